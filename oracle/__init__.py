@@ -1,0 +1,321 @@
+"""Python access to the plain FP64 CPU oracle (``psd_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke``
+and by the CPU-baseline leg of ``bench.py``.  The product package never
+imports this module.  Arrays are numpy float64, C-contiguous, x fastest
+(numpy shape (n, n) or (n, n, n) with the last axis = x).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "psd_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, single thread)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-o", tmp, _SRC,
+                               "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Prob(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int), ("L", ctypes.c_double),
+                ("order", ctypes.c_int), ("p", ctypes.c_double), ("s", ctypes.c_double),
+                ("eps", ctypes.c_double), ("lam", ctypes.c_double)]
+
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER(Prob)
+        sig = {
+            "orc_vgrad": (None, [P, _dp, _dp]),
+            "orc_vgrad_axis": (None, [P, ctypes.c_int, _dp, _dp]),
+            "orc_vdiv_axis": (None, [P, ctypes.c_int, _dp, _dp]),
+            "orc_vdiv": (None, [P, _dp, _dp]),
+            "orc_lap": (None, [P, _dp, _dp]),
+            "orc_plap": (None, [P, _dp, _dp]),
+            "orc_plap_lin": (None, [P, _dp, _dp, _dp]),
+            "orc_dft1": (None, [ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_int]),
+            "orc_fft1": (None, [ctypes.c_int, _dp, _dp, ctypes.c_int]),
+            "orc_fftn": (None, [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int, ctypes.c_int]),
+            "orc_symbol_neglap": (None, [P, _dp]),
+            "orc_symbol_precond": (None, [P, _dp]),
+            "orc_precond": (None, [P, _dp, _dp]),
+            "orc_T": (None, [P, _dp, _dp]),
+            "orc_ip": (ctypes.c_double, [P, _dp, _dp]),
+            "orc_maxabs": (ctypes.c_double, [P, _dp]),
+            "orc_N4": (None, [P, _dp, _dp]),
+            "orc_energy4": (ctypes.c_double, [P, _dp, _dp]),
+            "orc_residual4": (None, [P, _dp, _dp, _dp]),
+            "orc_residual6": (None, [P, _dp, _dp, _dp, _dp]),
+            "orc_energy6": (ctypes.c_double, [P, _dp, _dp, _dp]),
+            "orc_w_from_u": (None, [P, _dp, _dp, _dp, _dp]),
+            "orc_mixed_residuals": (None, [P, _dp, _dp, _dp, _dp, _dp, _dp]),
+            "orc_ls_coeffs4": (None, [P, _dp, _dp, _dp, _dp]),
+            "orc_q_eval": (None, [P, _dp, _dp, _dp, _dp, ctypes.c_double, _dp, _dp]),
+            "orc_root_cubic": (ctypes.c_double, [_dp, ctypes.POINTER(ctypes.c_int)]),
+            "orc_solve": (ctypes.c_int, [P, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int,
+                                         _dp, _dp]),
+            "orc_hessvec": (None, [P, _dp, _dp, _dp]),
+            "orc_dN_dparams": (None, [P, _dp, _dp, _dp]),
+            "orc_adjoint": (ctypes.c_int, [P, _dp, _dp, ctypes.c_double, ctypes.c_int, _dp, _dp,
+                                           _dp]),
+            "orc_cholesky_solve": (ctypes.c_int, [ctypes.c_int, _dp, _dp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_dp)
+
+
+def _arr(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Problem:
+    """Problem statement (Sec. 1 and Sec. 5): dim, n, L, order, p, s, eps, lam."""
+
+    def __init__(self, dim: int, n: int, L: float, order: int = 4, p: float = 4.0,
+                 s: float = 0.01, eps: float = 0.1, lam: float = 0.0):
+        self.dim, self.n, self.L, self.order = dim, n, L, order
+        self.p, self.s, self.eps, self.lam = p, s, eps, lam
+        self._c = Prob(dim, n, L, order, p, s, eps, lam)
+
+    @property
+    def shape(self) -> Tuple[int, ...]:
+        return (self.n,) * self.dim
+
+    @property
+    def h(self) -> float:
+        return self.L / self.n
+
+    @property
+    def hd(self) -> float:
+        return self.h ** self.dim
+
+    def replace(self, **kw) -> "Problem":
+        d = dict(dim=self.dim, n=self.n, L=self.L, order=self.order, p=self.p, s=self.s,
+                 eps=self.eps, lam=self.lam)
+        d.update(kw)
+        return Problem(**d)
+
+    # -- operators ---------------------------------------------------------
+    def _unary(self, name, v):
+        v = _arr(v)
+        out = np.empty_like(v)
+        getattr(_load(), name)(ctypes.byref(self._c), _ptr(v), _ptr(out))
+        return out
+
+    def lap(self, v):
+        return self._unary("orc_lap", v)
+
+    def plap(self, v):
+        return self._unary("orc_plap", v)
+
+    def N4(self, u):
+        return self._unary("orc_N4", u)
+
+    def precond(self, r):
+        return self._unary("orc_precond", r)
+
+    def T(self, z):
+        return self._unary("orc_T", z)
+
+    def vgrad(self, v):
+        v = _arr(v)
+        out = np.empty((self.dim,) + v.shape)
+        _load().orc_vgrad(ctypes.byref(self._c), _ptr(v), _ptr(out))
+        return out
+
+    def vgrad_axis(self, axis: int, v):
+        v = _arr(v)
+        out = np.empty_like(v)
+        _load().orc_vgrad_axis(ctypes.byref(self._c), axis, _ptr(v), _ptr(out))
+        return out
+
+    def vdiv_axis(self, axis: int, v):
+        v = _arr(v)
+        out = np.empty_like(v)
+        _load().orc_vdiv_axis(ctypes.byref(self._c), axis, _ptr(v), _ptr(out))
+        return out
+
+    def vdiv(self, F):
+        F = _arr(F)
+        out = np.empty(F.shape[1:])
+        _load().orc_vdiv(ctypes.byref(self._c), _ptr(F), _ptr(out))
+        return out
+
+    def plap_lin(self, u, xi):
+        u, xi = _arr(u), _arr(xi)
+        out = np.empty_like(u)
+        _load().orc_plap_lin(ctypes.byref(self._c), _ptr(u), _ptr(xi), _ptr(out))
+        return out
+
+    def symbol_neglap(self):
+        out = np.empty(self.shape)
+        _load().orc_symbol_neglap(ctypes.byref(self._c), _ptr(out))
+        return out
+
+    def symbol_precond(self):
+        out = np.empty(self.shape)
+        _load().orc_symbol_precond(ctypes.byref(self._c), _ptr(out))
+        return out
+
+    def ip(self, a, b) -> float:
+        return _load().orc_ip(ctypes.byref(self._c), _ptr(_arr(a)), _ptr(_arr(b)))
+
+    def residual(self, f, u, g=None):
+        f, u = _arr(f), _arr(u)
+        out = np.empty_like(u)
+        if self.order == 4:
+            _load().orc_residual4(ctypes.byref(self._c), _ptr(f), _ptr(u), _ptr(out))
+        else:
+            _load().orc_residual6(ctypes.byref(self._c), _ptr(f), _ptr(_arr(g)), _ptr(u),
+                                  _ptr(out))
+        return out
+
+    def energy(self, f, u, g=None) -> float:
+        f, u = _arr(f), _arr(u)
+        if self.order == 4:
+            return _load().orc_energy4(ctypes.byref(self._c), _ptr(f), _ptr(u))
+        return _load().orc_energy6(ctypes.byref(self._c), _ptr(f), _ptr(_arr(g)), _ptr(u))
+
+    def w_from_u(self, f, g, u):
+        out = np.empty_like(_arr(u))
+        _load().orc_w_from_u(ctypes.byref(self._c), _ptr(_arr(f)), _ptr(_arr(g)),
+                             _ptr(_arr(u)), _ptr(out))
+        return out
+
+    def mixed_residuals(self, f, g, u, w):
+        r1 = np.empty_like(_arr(u))
+        r2 = np.empty_like(r1)
+        _load().orc_mixed_residuals(ctypes.byref(self._c), _ptr(_arr(f)), _ptr(_arr(g)),
+                                    _ptr(_arr(u)), _ptr(_arr(w)), _ptr(r1), _ptr(r2))
+        return r1, r2
+
+    def ls_coeffs4(self, u, d, r):
+        c = np.empty(4)
+        _load().orc_ls_coeffs4(ctypes.byref(self._c), _ptr(_arr(u)), _ptr(_arr(d)),
+                               _ptr(_arr(r)), _ptr(c))
+        return c
+
+    def q_eval(self, f, u, d, alpha, g=None):
+        q = ctypes.c_double()
+        dq = ctypes.c_double()
+        _load().orc_q_eval(ctypes.byref(self._c), _ptr(_arr(f)),
+                           _ptr(_arr(g)) if g is not None else None, _ptr(_arr(u)),
+                           _ptr(_arr(d)), float(alpha), ctypes.byref(q), ctypes.byref(dq))
+        return q.value, dq.value
+
+    def solve(self, f, u0=None, g=None, tol: float = 1e-10, max_iter: int = 500,
+              history: bool = False):
+        """Run the PSD loop.  Returns dict(u, w, iters, res_inf, res_l2, energy, hist)."""
+        f = _arr(f)
+        if u0 is None:
+            u = np.zeros_like(f)
+            if self.order == 6:
+                u += float(np.mean(g))
+        else:
+            u = _arr(u0).copy()
+        w = np.empty_like(f) if self.order == 6 else None
+        hist = np.zeros((max_iter, 4)) if history else None
+        stats = np.zeros(3)
+        k = _load().orc_solve(ctypes.byref(self._c), _ptr(f),
+                              _ptr(_arr(g)) if g is not None else None, _ptr(u), _ptr(w),
+                              float(tol), int(max_iter), _ptr(hist), _ptr(stats))
+        if k < 0:
+            raise RuntimeError(f"oracle solve failed with status {k}")
+        return dict(u=u, w=w, iters=k, res_inf=stats[0], res_l2=stats[1], energy=stats[2],
+                    hist=hist[:k] if history else None)
+
+    def hessvec(self, u, xi):
+        out = np.empty_like(_arr(u))
+        _load().orc_hessvec(ctypes.byref(self._c), _ptr(_arr(u)), _ptr(_arr(xi)), _ptr(out))
+        return out
+
+    def dN_dparams(self, u):
+        ds = np.empty_like(_arr(u))
+        de = np.empty_like(ds)
+        _load().orc_dN_dparams(ctypes.byref(self._c), _ptr(_arr(u)), _ptr(ds), _ptr(de))
+        return ds, de
+
+    def adjoint(self, u, gu, rtol: float = 1e-13, max_iter: int = 1000):
+        lam = np.empty_like(_arr(u))
+        js = ctypes.c_double()
+        je = ctypes.c_double()
+        it = _load().orc_adjoint(ctypes.byref(self._c), _ptr(_arr(u)), _ptr(_arr(gu)),
+                                 float(rtol), int(max_iter), _ptr(lam), ctypes.byref(js),
+                                 ctypes.byref(je))
+        if it < 0:
+            raise RuntimeError("oracle adjoint failed")
+        return dict(dJdf=lam, dJds=js.value, dJdeps=je.value, iters=it)
+
+
+def root_cubic(c) -> Tuple[float, int]:
+    c = _arr(c)
+    ev = ctypes.c_int()
+    x = _load().orc_root_cubic(_ptr(c), ctypes.byref(ev))
+    return x, ev.value
+
+
+def dft1(x: np.ndarray, sign: int = -1) -> np.ndarray:
+    x = np.asarray(x, dtype=np.complex128)
+    n = len(x)
+    xr, xi = _arr(x.real), _arr(x.imag)
+    yr, yi = np.empty(n), np.empty(n)
+    _load().orc_dft1(n, _ptr(xr), _ptr(xi), _ptr(yr), _ptr(yi), sign)
+    return yr + 1j * yi
+
+
+def fft1(x: np.ndarray, sign: int = -1) -> np.ndarray:
+    x = np.asarray(x, dtype=np.complex128)
+    xr, xi = _arr(x.real).copy(), _arr(x.imag).copy()
+    _load().orc_fft1(len(x), _ptr(xr), _ptr(xi), sign)
+    return xr + 1j * xi
+
+
+def fftn(x: np.ndarray, sign: int = -1, naive: bool = False) -> np.ndarray:
+    x = np.asarray(x, dtype=np.complex128)
+    dim = x.ndim
+    n = x.shape[0]
+    assert all(s == n for s in x.shape)
+    xr, xi = _arr(x.real).copy(), _arr(x.imag).copy()
+    _load().orc_fftn(dim, n, _ptr(xr), _ptr(xi), sign, 1 if naive else 0)
+    return xr + 1j * xi
+
+
+def cholesky_solve(A: np.ndarray, b: np.ndarray) -> np.ndarray:
+    A = _arr(A).copy()
+    x = _arr(b).copy()
+    st = _load().orc_cholesky_solve(len(x), _ptr(A), _ptr(x))
+    if st != 0:
+        raise RuntimeError("matrix not SPD")
+    return x
