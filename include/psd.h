@@ -1,0 +1,172 @@
+/*
+ * psd.h -- C ABI of the MI355X (gfx950) preconditioned steepest descent
+ * solver for periodic, finite-difference regularised p-Laplacian problems
+ * (Feng, Salgado, Wang & Wise, arXiv:1607.01475).
+ *
+ * Problems (periodic box [0,L]^dim, n cells per axis, h = L/n, Sec. 5.1):
+ *   order 4 (Sec. 5.3, discrete fourth-order equation):
+ *       u - s div_h(|grad_h u|^{p-2} grad_h u) + s eps^2 Delta_h^2 u = f
+ *   order 6 (Sec. 5.4, discrete sixth-order mixed system):
+ *       u - Delta_h w = g,
+ *       s lam u - s div_h(|grad_h u|^{p-2} grad_h u) + s eps^2 Delta_h^2 u - w = f
+ * grad_h is the collocated centre-to-vertex gradient and div_h the
+ * vertex-to-centre divergence of Sec. 5.1 (3D: the same construction with
+ * averages over the two other axes).  Each call of the PSD loop (Sec. 2.2 and
+ * Sec. 6) computes the residual, solves the preconditioner equation
+ * L_h d = r by FFT (Sec. 6.1 and 6.2), finds the exact line-search step
+ * alpha (unique root of q, Sec. 6.1) and updates u <- u + alpha d.
+ *
+ * Memory: every array argument is a DEVICE pointer to n^dim contiguous
+ * doubles, x fastest (idx = i + n*(j + n*k)); cell i has centre (i+1/2)h.
+ * The caller owns inputs and outputs; the handle owns all workspace.
+ * Streams: all work is ordered on the stream given to psd_create (NULL =
+ * default stream).  psd_solve, psd_residual, psd_energy, psd_adjoint return
+ * only after the results are on the host/device (they synchronise the stream).
+ * Errors: status codes only; nothing aborts, no exception crosses the ABI.
+ * psd_last_error gives a message for the last failing call on a handle.
+ * A handle must not be used from two threads at once.
+ */
+#ifndef PSD_H
+#define PSD_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct psd_handle_s psd_handle;
+
+typedef enum {
+    PSD_OK = 0,
+    PSD_NOT_CONVERGED = 1,     /* max_iter updates without reaching tol */
+    PSD_ERR_ARG = -1,          /* NULL pointer, bad size, unsupported n */
+    PSD_ERR_RANGE = -2,        /* parameter outside the paper's range */
+    PSD_ERR_HIP = -3,          /* HIP runtime error (no device, OOM, ...) */
+    PSD_ERR_NONFINITE = -4,    /* NaN/Inf in the residual */
+    PSD_ERR_NOT_DESCENT = -5,  /* q(0) >= 0 with residual above tol */
+    PSD_ERR_MEAN = -6          /* order 6: mean(u0) != mean(g) */
+} psd_status;
+
+/* Problem statement (Sec. 1; discrete form Sec. 5).
+ *   dim   2 or 3
+ *   n     cells per axis; supported: 16, 32, 48, 64, 96, 128, 192, 256, 384,
+ *         512, 1024 (2D); up to 256 in 3D
+ *   L     box side (> 0)
+ *   order 4 or 6 (order 6 is supported in 2D)
+ *   p     exponent, p >= 2 (p <= 6 in 3D, Sec. 3.1)
+ *   s     > 0
+ *   eps   0 < eps <= 1
+ *   lambda  >= 0 (order 6 only) */
+typedef struct {
+    int dim;
+    int n;
+    double L;
+    int order;
+    double p, s, eps, lambda;
+} psd_problem;
+
+enum { PSD_FP64 = 0, PSD_MIXED = 1 };
+
+/* Solver options.
+ *   tol         stop when the absolute max-norm of the residual is <= tol
+ *               (order 4: f - N_h[u]; order 6: max of the two residuals of
+ *               the mixed system), checked after every update
+ *   max_iter    maximum number of updates
+ *   precision   PSD_FP64: every step in FP64.  PSD_MIXED: the FFT
+ *               preconditioner (forward transform, spectral scaling,
+ *               inverse transform) runs in FP32; residual, line-search
+ *               reductions, step and update stay FP64 (iterative refinement)
+ *   graph_chunk 0: host-driven loop, the host reads the convergence flag
+ *               after every iteration.  k > 0: k iterations are captured once
+ *               in a HIP graph and replayed until the device flag says done
+ *   history     non-zero: record per-update (alpha, ||r||_inf, ||r||_2, dE) */
+typedef struct {
+    double tol;
+    int max_iter;
+    int precision;
+    int graph_chunk;
+    int history;
+} psd_options;
+
+/* Per-instance result.  energy is E_h at the final iterate (Sec. 5.3 and
+ * 5.4 discrete energies) when options.history is set, else NaN (use
+ * psd_energy); status a psd_status. */
+typedef struct {
+    int iters;
+    double res_inf, res_l2, energy;
+    int status;
+} psd_stats;
+
+/* Validate one problem statement on the host (no GPU needed).  Returns
+ * PSD_OK, PSD_ERR_ARG or PSD_ERR_RANGE; msg (may be NULL) receives a short
+ * reason (buffer of msg_len bytes). */
+psd_status psd_check_problem(const psd_problem* prob, char* msg, int msg_len);
+
+/* Create a solver for `batch` independent instances (probs[batch]); all
+ * share the options.  Plans FFTs, symbol tables and all workspace on the
+ * current HIP device.  hip_stream is a hipStream_t (NULL = default). */
+psd_status psd_create(const psd_problem* probs, int batch, const psd_options* opt,
+                      void* hip_stream, psd_handle** out);
+
+/* Solve all instances.  f[b], g[b] (order 6, else NULL array or entries),
+ * u[b] (in: u0, out: final iterate; order 6 needs mean(u0) = mean(g)),
+ * w[b] (order 6 output of the mixed system, may be NULL) are device
+ * pointers.  stats[batch] is host memory.  Returns the worst instance status
+ * (errors < 0 take precedence over PSD_NOT_CONVERGED). */
+psd_status psd_solve(psd_handle* h, const double* const* f, const double* const* g,
+                     double* const* u, double* const* w, psd_stats* stats);
+
+/* Residual of instance `inst` at u.  Order 4: r = f - N_h[u].  Order 6: the
+ * reduced residual rho = P0[f - (s lam u - s div_h(...) + s eps^2 Delta_h^2 u)
+ * - T_h(u - g)] (minus the gradient of the mean-zero energy; T_h = -Delta_h^{-1}
+ * on mean-zero functions).  r (device, may be NULL) receives it, *res_inf
+ * (host, may be NULL) its max-norm. */
+psd_status psd_residual(psd_handle* h, int inst, const double* f, const double* g,
+                        const double* u, double* r, double* res_inf);
+
+/* Residuals of the order-6 mixed system at (u, w) (Sec. 5.4):
+ *   r1 = g - u + Delta_h w,  r2 = f - (s lam u - s div_h(...) + s eps^2 Delta_h^2 u - w). */
+psd_status psd_residual_mixed(psd_handle* h, int inst, const double* f, const double* g,
+                              const double* u, const double* w, double* r1, double* r2,
+                              double* res_inf);
+
+/* Discrete energy E_h at u (Sec. 5.3; order 6: Sec. 5.4 evaluated at
+ * nu = u - mean(g)).  *E is host memory. */
+psd_status psd_energy(psd_handle* h, int inst, const double* f, const double* g,
+                      const double* u, double* E);
+
+/* Gradient delta E_h[u] with respect to the grid inner product (.,.)_2
+ * (Sec. 5.3): order 4: N_h[u] - f;  order 6: -rho (mean zero).  The plain
+ * partial derivative with respect to a cell value is h^dim times this. */
+psd_status psd_grad(psd_handle* h, int inst, const double* f, const double* g,
+                    const double* u, double* grad);
+
+/* Adjoint of the converged order-4 solve (implicit differentiation through
+ * N_h[u*] = f).  For each instance b: solve H lam = dJdu[b] by conjugate
+ * gradients preconditioned with L_h^{-1}, where H is the Hessian of E_h at
+ * u*[b] (second variation, Sec. 5.3) acting on cell values; then
+ *   dJdf[b] = lam,  dJds[b] = -lam . dN/ds,  dJdeps[b] = -lam . dN/deps,
+ * with dN/ds = -div_h(|grad u|^{p-2} grad u) + eps^2 Delta_h^2 u and
+ * dN/deps = 2 s eps Delta_h^2 u.  dJdu, dJdf are device pointers (plain
+ * partial derivatives); dJds, dJdeps, cg_iters are host arrays [batch].
+ * Stops at ||res||_2 <= rtol ||dJdu||_2 or max_iter. */
+psd_status psd_adjoint(psd_handle* h, const double* const* u_star, const double* const* dJdu,
+                       double* const* dJdf, double* dJds, double* dJdeps, double rtol,
+                       int max_iter, int* cg_iters);
+
+/* Per-update history of instance `inst` from the last psd_solve (options
+ * history != 0): out[4*k + {0,1,2,3}] = alpha, ||r||_inf, ||r||_2, energy
+ * decrease (order 4, p = 4; else 0).  Copies min(cap, iters) records to host
+ * memory and returns their number in *count. */
+psd_status psd_history(psd_handle* h, int inst, double* out, int cap, int* count);
+
+/* Destroy the handle and free its workspace. */
+psd_status psd_destroy(psd_handle* h);
+
+/* Message of the last error on h (or of the last failed psd_create when h
+ * is NULL).  Never NULL. */
+const char* psd_last_error(const psd_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSD_H */

@@ -1,0 +1,143 @@
+// psd_common.hpp -- shared device types for the gfx950 PSD solver.
+//
+// Layout conventions (Sec. 5.1 of the paper): periodic n^dim cell-centred
+// grid, x fastest, idx = i + n*(j + n*k).  A vertex (i+1/2, j+1/2[, k+1/2])
+// is addressed by the index of cell (i, j[, k]).  Spectra are half spectra
+// (kx = 0 .. n/2) stored [kz][ky][kx], kx fastest, nc = n/2 + 1.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define PSD_NT 256          // threads per block for every kernel
+#define PSD_WAVE 64         // gfx950 wavefront
+
+namespace psd {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> mk(T a, T b) { cx<T> r; r.x = a; r.y = b; return r; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return mk(a.x + b.x, a.y + b.y); }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return mk(a.x - b.x, a.y - b.y); }
+template <typename T>
+__device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b) {
+  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T>
+__device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return mk(a.x * s, a.y * s); }
+template <typename T>
+__device__ __forceinline__ cx<T> conj(cx<T> a) { return mk(a.x, -a.y); }
+// multiply by +i (DIR = +1) or -i (DIR = -1)
+template <int DIR, typename T>
+__device__ __forceinline__ cx<T> mul_i(cx<T> a) {
+  return DIR > 0 ? mk(-a.y, a.x) : mk(a.y, -a.x);
+}
+
+// ---------------------------------------------------------------------------
+// Per-instance descriptor (device resident).  Field pointers are typed by
+// the precision form: TD = type of d/e1/e2, TR = type of the residual copy
+// given to the FFT (FP64 form: double, mixed form: float).
+// ---------------------------------------------------------------------------
+struct SolveState {
+  double alpha;        // current line-search step
+  double rinf, rl2;    // max-norm and l2 (h^dim weighted) of the last residual
+  double c[4];         // cubic coefficients (p = 4) or q(0), q'(0) (general p)
+  double lin;          // general p: linear part of q'
+  double nl0;          // general p: nonlinear vertex sum at alpha = 0
+  double lo, hi, x, qx, dqx;  // root-rule state (general p)
+  int iter;            // updates applied so far
+  int done;            // 1: converged / stopped (kernels early-exit)
+  int status;          // psd_status
+  int ls_phase;        // general p root rule: 0 expand, 1 newton, 2 finished
+  int ls_evals;
+  int newton_steps;
+  double dE;           // energy decrease of the last step (p = 4)
+  int pad[2];
+};
+
+struct Inst {
+  int dim, n, nc, order;
+  long long ncell;     // n^dim
+  long long nspec;     // nc * n^(dim-1)
+  double h, inv_h, p, s, se2, lam, inv_ntot, tol, hd;
+  int max_iter, p_is_4, p_is_2, pad0;
+  double* u[2];        // ping-pong iterate
+  double* w[2];        // order 6 carried w (ping-pong)
+  const double* f;
+  const double* g;
+  void* d;             // search direction (TD)
+  void* e1;            // order 6: T_h r1 (TD)
+  void* e2;            // order 6: T_h d (TD)
+  void* r;             // residual copy for the FFT (TR); order 6: r2
+  void* r1;            // order 6: r1 (TR)
+  void* spec;          // half spectra, up to 3 fields of nspec complex
+  const double* S;     // S[k] = (4/h^2) sin^2(pi k/n), k in [0,n)
+  const void* tw32;    // twiddles exp(-2 pi i m/n), m in [0,n), FP32 complex
+  const void* tw64;    // the same in FP64 complex
+  double* tmp;         // FP64 scratch field (auxiliary transforms)
+  SolveState* st;
+  double* part_res;    // residual partials: 2 per block (max|r|, sum r^2)
+  double* part_ls;     // line-search partials: 8 per block
+  double* part_sp;     // spectral partials: 2 per block
+  double* hist;        // 4 per update (may be null)
+  int nblk_res, nblk_ls, nblk_sp, hist_cap;
+};
+
+// A block's unit of work: instance and up to three integer coordinates.
+struct Task {
+  int inst, a, b, c;
+};
+
+// ---------------------------------------------------------------------------
+// Block reductions (wavefront shuffles, then LDS across the 4 waves).
+// Deterministic: fixed shuffle tree and fixed order across waves.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = PSD_WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, PSD_WAVE);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = PSD_WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, PSD_WAVE));
+  return v;
+}
+
+// Reduce K sums (and optionally the first M as max instead) across the
+// block; result valid in thread 0.  scratch: K * (NT/64) doubles of LDS.
+template <int K, int M>
+__device__ __forceinline__ void block_reduce(double (&v)[K], double* scratch) {
+  const int lane = threadIdx.x & (PSD_WAVE - 1);
+  const int wid = threadIdx.x / PSD_WAVE;
+  constexpr int NW = PSD_NT / PSD_WAVE;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = (k < M) ? wave_max(v[k]) : wave_sum(v[k]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) scratch[k * NW + wid] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double a = scratch[k * NW];
+      for (int w2 = 1; w2 < NW; ++w2) a = (k < M) ? fmax(a, scratch[k * NW + w2]) : a + scratch[k * NW + w2];
+      v[k] = a;
+    }
+  }
+  __syncthreads();
+}
+
+// periodic index for offsets within one period (3D tiles: n >= 32 is
+// required so that every halo index lies in [-n, 2n))
+__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+// periodic index for any i >= -n (2D tiles may be wider than small grids)
+__device__ __forceinline__ int posmod(int i, int n) { return (int)((unsigned)(i + n) % (unsigned)n); }
+
+}  // namespace psd

@@ -1,0 +1,340 @@
+// psd_fft.hpp -- LDS-resident batched FFT passes for gfx950.
+//
+// The preconditioner L_h is diagonal in the discrete Fourier basis (Sec. 6:
+// the search-direction equations are solved by FFT), so one application is
+// forward transform -> divide by the symbol -> inverse transform.  Lines of
+// length N (N = 2^a 3^b, 16 <= N <= 1024) are transformed inside LDS with a
+// Stockham auto-sort schedule (no bit reversal): stage with radix R and
+// span Ns reads R points at stride N/R, applies the twiddles
+// exp(dir 2 pi i r k / (Ns R)), k = j mod Ns, performs an R-point DFT in
+// registers and writes the results to (j div Ns) Ns R + k + r Ns.
+//
+// Three pass kinds cover a d-dimensional real transform:
+//   * row R2C / C2R along x (contiguous), two real rows per complex FFT;
+//   * column C2C along y or z (strided), W adjacent columns per block so
+//     that every global access is a contiguous W-element segment;
+//   * the last column pass fuses forward FFT, the spectral operator and the
+//     inverse FFT, so the spectrum of that axis never goes back to HBM
+//     between the two transforms.
+#pragma once
+#include <type_traits>
+#include "psd_common.hpp"
+
+namespace psd {
+
+// ---------------------------------------------------------------------------
+// radix plan: factors of 3 first, then the power of two as 16s with an 8/4/2
+// tail chosen to avoid a final radix-2 stage where possible
+// ---------------------------------------------------------------------------
+constexpr int pow2_part(int N) { int p = 1; while (N % 2 == 0) { N /= 2; p *= 2; } return p; }
+constexpr int log2i(int N) { int a = 0; while (N > 1) { N /= 2; ++a; } return a; }
+constexpr int n_threes(int N) { int t = 0; while (N % 3 == 0) { N /= 3; ++t; } return t; }
+
+constexpr int plan_stages(int N) {
+  int st = n_threes(N);
+  int a = log2i(pow2_part(N));
+  while (a >= 4 && a != 5 && a != 6) { a -= 4; ++st; }
+  if (a == 6 || a == 5) st += 2;
+  else if (a > 0) st += 1;
+  return st;
+}
+
+constexpr int plan_radix(int N, int s) {
+  int t = n_threes(N);
+  if (s < t) return 3;
+  s -= t;
+  int a = log2i(pow2_part(N));
+  while (a >= 4 && a != 5 && a != 6) {
+    if (s == 0) return 16;
+    a -= 4; --s;
+  }
+  if (a == 6) return 8;
+  if (a == 5) return s == 0 ? 8 : 4;
+  if (a == 3) return 8;
+  if (a == 2) return 4;
+  return 2;
+}
+
+constexpr int plan_span(int N, int s) {  // product of radices of stages < s
+  int p = 1;
+  for (int i = 0; i < s; ++i) p *= plan_radix(N, i);
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// small DFTs in registers, X_q = sum_r a_r exp(DIR 2 pi i r q / R)
+// ---------------------------------------------------------------------------
+template <int DIR, typename T>
+__device__ __forceinline__ void dft2(cx<T>& a, cx<T>& b) {
+  cx<T> t = a;
+  a = t + b;
+  b = t - b;
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft4(cx<T>& a0, cx<T>& a1, cx<T>& a2, cx<T>& a3) {
+  cx<T> t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = mul_i<DIR>(a1 - a3);
+  a0 = t0 + t2;
+  a2 = t0 - t2;
+  a1 = t1 + t3;
+  a3 = t1 - t3;
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft3(cx<T>* a) {
+  const T c = T(0.86602540378443864676372317075293618);  // sqrt(3)/2
+  cx<T> t = a[1] + a[2], d = a[1] - a[2];
+  cx<T> m = a[0] - scale(t, T(0.5));
+  cx<T> e = mul_i<DIR>(scale(d, c));
+  a[0] = a[0] + t;
+  a[1] = m + e;
+  a[2] = m - e;
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft8(cx<T>* a) {
+  const T r2 = T(0.70710678118654752440084436210484904);
+  // even / odd halves
+  dft4<DIR>(a[0], a[2], a[4], a[6]);
+  dft4<DIR>(a[1], a[3], a[5], a[7]);
+  // twiddles w^q = exp(DIR 2 pi i q / 8), q = 0..3, on the odd outputs
+  cx<T> o1 = a[3], o2 = a[5], o3 = a[7];
+  o1 = scale(o1 + mul_i<DIR>(o1), r2);                 // (1 + DIR i)/sqrt2
+  o2 = mul_i<DIR>(o2);                                  // DIR i
+  o3 = scale(mul_i<DIR>(o3) - o3, r2);                 // (-1 + DIR i)/sqrt2
+  cx<T> e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6], o0 = a[1];
+  a[0] = e0 + o0; a[4] = e0 - o0;
+  a[1] = e1 + o1; a[5] = e1 - o1;
+  a[2] = e2 + o2; a[6] = e2 - o2;
+  a[3] = e3 + o3; a[7] = e3 - o3;
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft16(cx<T>* a) {
+  // index n = 4 n1 + n2, output q = q1 + 4 q2
+  const T c1 = T(0.92387953251128675612818318939678829);  // cos(pi/8)
+  const T s1 = T(0.38268343236508977172845998403039887);  // sin(pi/8)
+  const T r2 = T(0.70710678118654752440084436210484904);
+  cx<T> y[16];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    cx<T> b0 = a[n2], b1 = a[4 + n2], b2 = a[8 + n2], b3 = a[12 + n2];
+    dft4<DIR>(b0, b1, b2, b3);
+    y[n2 * 4 + 0] = b0; y[n2 * 4 + 1] = b1; y[n2 * 4 + 2] = b2; y[n2 * 4 + 3] = b3;
+  }
+  // twiddle y[n2][q1] *= exp(DIR 2 pi i n2 q1 / 16)
+  const T ds = T(DIR);
+  // n2 = 1: q1 = 1,2,3 -> angles 1,2,3 (units 2pi/16)
+  y[5] = y[5] * mk(c1, ds * s1);
+  y[6] = y[6] * mk(r2, ds * r2);
+  y[7] = y[7] * mk(s1, ds * c1);
+  // n2 = 2: angles 2,4,6
+  y[9] = y[9] * mk(r2, ds * r2);
+  y[10] = mul_i<DIR>(y[10]);
+  y[11] = y[11] * mk(-r2, ds * r2);
+  // n2 = 3: angles 3,6,9
+  y[13] = y[13] * mk(s1, ds * c1);
+  y[14] = y[14] * mk(-r2, ds * r2);
+  y[15] = y[15] * mk(-c1, -ds * s1);
+#pragma unroll
+  for (int q1 = 0; q1 < 4; ++q1) {
+    cx<T> b0 = y[q1], b1 = y[4 + q1], b2 = y[8 + q1], b3 = y[12 + q1];
+    dft4<DIR>(b0, b1, b2, b3);
+    a[q1] = b0; a[q1 + 4] = b1; a[q1 + 8] = b2; a[q1 + 12] = b3;
+  }
+}
+
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void dftR(cx<T>* a) {
+  if constexpr (R == 2) dft2<DIR>(a[0], a[1]);
+  else if constexpr (R == 3) dft3<DIR>(a);
+  else if constexpr (R == 4) dft4<DIR>(a[0], a[1], a[2], a[3]);
+  else if constexpr (R == 8) dft8<DIR>(a);
+  else dft16<DIR>(a);
+}
+
+template <int S, int NSTG, typename F>
+__device__ __forceinline__ void stage_loop(F&& f) {
+  if constexpr (S < NSTG) {
+    f(std::integral_constant<int, S>());
+    stage_loop<S + 1, NSTG>(f);
+  }
+}
+
+// Transform NL lines of length N held in LDS (line l at buf + l*LS), in
+// place, unnormalised.  tw[m] = exp(-2 pi i m / N) (global, cached).
+// Must be called by all PSD_NT threads of the block; ends with a barrier.
+template <typename T, int N, int NL, int LS, int DIR>
+__device__ __forceinline__ void lds_fft(cx<T>* buf, const cx<T>* __restrict__ tw) {
+  constexpr int NSTG = plan_stages(N);
+  stage_loop<0, NSTG>([&](auto sc) {
+    constexpr int s = decltype(sc)::value;
+    constexpr int R = plan_radix(N, s);
+    constexpr int Ns = plan_span(N, s);
+    constexpr int M = N / R;             // butterflies per line
+    constexpr int NB = NL * M;           // butterflies in the block
+    constexpr int IT = (NB + PSD_NT - 1) / PSD_NT;
+    cx<T> v[IT][R];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int b = threadIdx.x + it * PSD_NT;
+      if (NB % PSD_NT == 0 || b < NB) {
+        const int line = b / M, j = b - line * M;
+        const cx<T>* src = buf + line * LS + j;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[it][r] = src[r * M];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int b = threadIdx.x + it * PSD_NT;
+      if (NB % PSD_NT == 0 || b < NB) {
+        const int line = b / M, j = b - line * M;
+        const int k = j % Ns;
+        if constexpr (Ns > 1) {
+          constexpr int TS = N / (Ns * R);
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            cx<T> w = tw[r * k * TS];
+            if (DIR > 0) w.y = -w.y;
+            v[it][r] = v[it][r] * w;
+          }
+        }
+        dftR<R, DIR>(v[it]);
+        cx<T>* dst = buf + line * LS + (j - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) dst[r * Ns] = v[it][r];
+      }
+    }
+    __syncthreads();
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Row passes along x.  Rows are addressed globally over NF fields: row gr in
+// [0, NF * rows_per_field), field = gr / rpf.  Two real rows form one complex
+// line z = a + i b; after the transform A_k = (Z_k + conj Z_{N-k}) / 2 and
+// B_k = -i (Z_k - conj Z_{N-k}) / 2 for k = 0..N/2.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct RowArgs {
+  const void* rin0;     // real inputs per field (R2C)
+  const void* rin1;
+  void* rout0;          // real outputs per field (C2R)
+  void* rout1;
+  void* rout2;
+  cx<T>* spec;          // NF fields of nspec complex
+  long long nspec;
+  long long rpf;        // rows per field
+  long long nrows;      // rows over all fields of this pass (guard)
+  __device__ __forceinline__ const void* in(int f) const { return f == 0 ? rin0 : rin1; }
+  __device__ __forceinline__ void* out(int f) const { return f == 0 ? rout0 : (f == 1 ? rout1 : rout2); }
+};
+
+template <int N, typename T>
+constexpr int rows_lines() {  // complex lines per block for row passes
+  return (N * 2 * sizeof(T) * 2 <= 8192 * 2) ? 16 : (N >= 1024 ? 4 : 8);
+}
+
+template <typename T, typename TIN, int N, int NL>
+__device__ __forceinline__ void r2c_rows(const RowArgs<T>& A, long long row0, cx<T>* buf,
+                                         const cx<T>* tw) {
+  constexpr int LS = N + 1;
+  constexpr int NC = N / 2 + 1;
+  // load 2*NL real rows
+  for (int e = threadIdx.x; e < 2 * NL * N; e += PSD_NT) {
+    const int rr = e / N, col = e - rr * N;
+    const long long gr = row0 + rr;
+    T val = T(0);
+    if (gr < A.nrows) {
+      const int fld = (int)(gr / A.rpf);
+      const long long row = gr - (long long)fld * A.rpf;
+      const TIN* src = (const TIN*)A.in(fld);
+      val = (T)src[row * N + col];
+    }
+    T* dst = (T*)(buf + (rr >> 1) * LS + col);
+    dst[rr & 1] = val;
+  }
+  __syncthreads();
+  lds_fft<T, N, NL, LS, -1>(buf, tw);
+  for (int e = threadIdx.x; e < NL * NC; e += PSD_NT) {
+    const int l = e / NC, k = e - l * NC;
+    const cx<T> zk = buf[l * LS + k];
+    const cx<T> zm = conj(buf[l * LS + (k == 0 ? 0 : N - k)]);
+    const cx<T> a = scale(zk + zm, T(0.5));
+    const cx<T> b = scale(mul_i<-1>(zk - zm), T(0.5));
+    const long long gr = row0 + 2 * l;
+    if (gr >= A.nrows) continue;
+    const int fld = (int)(gr / A.rpf);
+    const long long row = gr - (long long)fld * A.rpf;
+    cx<T>* out = A.spec + fld * A.nspec + row * NC;
+    out[k] = a;
+    out[NC + k] = b;
+  }
+}
+
+template <typename T, typename TOUT, int N, int NL>
+__device__ __forceinline__ void c2r_rows(const RowArgs<T>& A, long long row0, cx<T>* buf,
+                                         const cx<T>* tw) {
+  constexpr int LS = N + 1;
+  constexpr int NC = N / 2 + 1;
+  for (int e = threadIdx.x; e < NL * NC; e += PSD_NT) {
+    const int l = e / NC, k = e - l * NC;
+    const long long gr = row0 + 2 * l;
+    cx<T> a = mk(T(0), T(0)), b = mk(T(0), T(0));
+    if (gr < A.nrows) {
+      const int fld = (int)(gr / A.rpf);
+      const long long row = gr - (long long)fld * A.rpf;
+      const cx<T>* in = A.spec + fld * A.nspec + row * NC;
+      a = in[k];
+      b = in[NC + k];
+    }
+    if (k == 0 || k == N / 2) { a.y = T(0); b.y = T(0); }
+    // Z_k = A_k + i B_k ; Z_{N-k} = conj(A_k) + i conj(B_k)
+    buf[l * LS + k] = a + mul_i<1>(b);
+    if (k != 0 && k != N / 2) buf[l * LS + N - k] = conj(a) + mul_i<1>(conj(b));
+  }
+  __syncthreads();
+  lds_fft<T, N, NL, LS, 1>(buf, tw);
+  for (int e = threadIdx.x; e < 2 * NL * N; e += PSD_NT) {
+    const int rr = e / N, col = e - rr * N;
+    const long long gr = row0 + rr;
+    if (gr >= A.nrows) continue;
+    const int fld = (int)(gr / A.rpf);
+    const long long row = gr - (long long)fld * A.rpf;
+    const T* src = (const T*)(buf + (rr >> 1) * LS + col);
+    TOUT* dst = (TOUT*)A.out(fld);
+    dst[row * N + col] = (TOUT)src[rr & 1];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Column pass: W adjacent columns (inner index col0 .. col0+W-1 of
+// `inner_count`) of length N, element t at stride `lstride`, NF fields at
+// `fstride`.  Loads, transforms (DIR), stores.
+// ---------------------------------------------------------------------------
+template <typename T, int N, int W, int NF, int DIR>
+__device__ __forceinline__ void col_pass(cx<T>* base, long long inner_count, long long col0,
+                                         long long lstride, long long fstride, cx<T>* buf,
+                                         const cx<T>* tw) {
+  constexpr int LS = N + 1;
+  for (int e = threadIdx.x; e < NF * W * N; e += PSD_NT) {
+    const int c = e % W;
+    const int ft = e / W;
+    const int t = ft % N, f = ft / N;
+    cx<T> v = mk(T(0), T(0));
+    if (col0 + c < inner_count) v = base[f * fstride + col0 + c + t * lstride];
+    buf[(f * W + c) * LS + t] = v;
+  }
+  __syncthreads();
+  lds_fft<T, N, NF * W, LS, DIR>(buf, tw);
+  for (int e = threadIdx.x; e < NF * W * N; e += PSD_NT) {
+    const int c = e % W;
+    const int ft = e / W;
+    const int t = ft % N, f = ft / N;
+    if (col0 + c < inner_count) base[f * fstride + col0 + c + t * lstride] = buf[(f * W + c) * LS + t];
+  }
+}
+
+}  // namespace psd

@@ -1,0 +1,536 @@
+// psd_kernels.hpp -- __global__ kernels of the PSD solver (gfx950).
+// Every kernel reads its unit of work from a task table and its problem from
+// an instance table, so one launch can serve one large instance or a batch
+// of instances of different sizes.  Solver kernels return at once when their
+// instance is finished (SolveState::done), which lets a captured graph of
+// several iterations be replayed past convergence at negligible cost.
+#pragma once
+#include "psd_common.hpp"
+#include "psd_fft.hpp"
+#include "psd_stencil.hpp"
+
+namespace psd {
+
+struct Task2 {  // residual / line-search / col tiles
+  int inst, a, b, c, slot, pad0, pad1, pad2;
+};
+
+// ---------------------------------------------------------------------------
+// supported line lengths
+// ---------------------------------------------------------------------------
+#define PSD_FOR_EACH_N(X) X(16) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(1024)
+
+template <typename T, int N>
+constexpr int row_lines() {
+  int nl = 32768 / ((N + 1) * (int)sizeof(cx<T>));
+  int p = 1;
+  while (p * 2 <= nl && p < 32) p *= 2;
+  return p;
+}
+// columns per block of a column pass: 128-byte segments where the LDS
+// footprint NF*W*(N+1) complex stays within 64 KB
+template <typename T, int N, int NF>
+constexpr int col_width() {
+  int w = 128 / (int)sizeof(cx<T>);
+  const int cap = 65536 / (NF * (N + 1) * (int)sizeof(cx<T>));
+  if (cap < w) w = cap;
+  return w < 1 ? 1 : w;
+}
+
+// ===========================================================================
+// residual (+ fused update)
+// ===========================================================================
+template <typename TD, typename TR, int ORDER, bool UPD>
+__global__ __launch_bounds__(PSD_NT) void k_res2d(const Inst* __restrict__ insts,
+                                                  const Task2* __restrict__ tasks) {
+  extern __shared__ double smem[];
+  const Task2 t = tasks[blockIdx.x];
+  const Inst& I = insts[t.inst];
+  if (I.st->done) return;
+  double acc[2] = {0.0, 0.0};
+  res2d_tile<TD, TR, ORDER, UPD>(I, t.a, t.b, smem, acc);
+  block_reduce<2, 1>(acc, smem + R2_LDS);
+  if (threadIdx.x == 0) {
+    I.part_res[2 * t.slot] = acc[0];
+    I.part_res[2 * t.slot + 1] = acc[1];
+  }
+}
+
+template <typename TD, typename TR, bool UPD>
+__global__ __launch_bounds__(PSD_NT) void k_res3d(const Inst* __restrict__ insts,
+                                                  const Task2* __restrict__ tasks) {
+  extern __shared__ double smem[];
+  const Task2 t = tasks[blockIdx.x];
+  const Inst& I = insts[t.inst];
+  if (I.st->done) return;
+  double acc[2] = {0.0, 0.0};
+  res3d_tile<TD, TR, UPD>(I, t.a, t.b, t.c, smem, acc);
+  block_reduce<2, 1>(acc, smem + R3_LDS);
+  if (threadIdx.x == 0) {
+    I.part_res[2 * t.slot] = acc[0];
+    I.part_res[2 * t.slot + 1] = acc[1];
+  }
+}
+
+// One block per instance: reduce residual partials, count the update,
+// decide convergence, record history.
+__global__ __launch_bounds__(PSD_NT) void k_res_finalize(const Inst* __restrict__ insts, int upd) {
+  __shared__ double scratch[2 * PSD_NT / PSD_WAVE];
+  const Inst& I = insts[blockIdx.x];
+  SolveState* st = I.st;
+  if (st->done) return;
+  double acc[2] = {0.0, 0.0};
+  for (int b = threadIdx.x; b < I.nblk_res; b += PSD_NT) {
+    acc[0] = fmax(acc[0], I.part_res[2 * b]);
+    acc[1] += I.part_res[2 * b + 1];
+  }
+  block_reduce<2, 1>(acc, scratch);
+  if (threadIdx.x == 0) {
+    const double rinf = acc[0];
+    const double rl2 = sqrt(I.hd * acc[1]);
+    st->rinf = rinf;
+    st->rl2 = rl2;
+    if (upd) {
+      st->iter += 1;
+      if (I.hist && st->iter <= I.hist_cap) {
+        double* hrec = I.hist + 4 * (st->iter - 1);
+        hrec[0] = st->alpha; hrec[1] = rinf; hrec[2] = rl2; hrec[3] = st->dE;
+      }
+    }
+    if (!isfinite(acc[1])) { st->status = -4; st->done = 1; }
+    else if (rinf <= I.tol) { st->status = 0; st->done = 1; }
+    else if (st->iter >= I.max_iter) { st->status = 1; st->done = 1; }
+  }
+}
+
+// ===========================================================================
+// line search
+// ===========================================================================
+template <typename TD>
+__global__ __launch_bounds__(PSD_NT) void k_ls2d(const Inst* __restrict__ insts,
+                                                 const Task2* __restrict__ tasks, int mode) {
+  extern __shared__ double smem[];
+  const Task2 t = tasks[blockIdx.x];
+  const Inst& I = insts[t.inst];
+  if (I.st->done || (mode == 2 && I.st->ls_phase == 2)) return;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  ls2d_tile<TD>(I, mode, t.a, t.b, smem, acc);
+  block_reduce<8, 0>(acc, smem + L2_LDS);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 8; ++k) I.part_ls[8 * t.slot + k] = acc[k];
+}
+
+template <typename TD>
+__global__ __launch_bounds__(PSD_NT) void k_ls3d(const Inst* __restrict__ insts,
+                                                 const Task2* __restrict__ tasks, int mode) {
+  extern __shared__ double smem[];
+  const Task2 t = tasks[blockIdx.x];
+  const Inst& I = insts[t.inst];
+  if (I.st->done || (mode == 2 && I.st->ls_phase == 2)) return;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  ls3d_tile<TD>(I, mode, t.a, t.b, t.c, smem, acc);
+  block_reduce<8, 0>(acc, smem + L3_LDS);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 8; ++k) I.part_ls[8 * t.slot + k] = acc[k];
+}
+
+// Root of the strictly increasing cubic q(x) = c0 + c1 x + c2 x^2 + c3 x^3
+// (Sec. 6.1).  Rule: x = -c0/c1, double until q > 0, then Newton from that
+// point with bisection whenever a step leaves the bracket; stop when
+// |q| <= 1e-16 (|c0| + c1 x) or |dx| <= 1e-15 x.
+__device__ double cubic_root(const double* c) {
+  double lo = 0.0, hi = INFINITY, x = -c[0] / c[1], q = 0.0, dq = 0.0;
+  for (int it = 0; it < 200; ++it) {
+    q = c[0] + x * (c[1] + x * (c[2] + x * c[3]));
+    dq = c[1] + x * (2.0 * c[2] + 3.0 * c[3] * x);
+    if (q > 0.0) { hi = x; break; }
+    if (q == 0.0) return x;
+    lo = x;
+    x *= 2.0;
+  }
+  for (int it = 0; it < 100; ++it) {
+    if (fabs(q) <= 1e-16 * (fabs(c[0]) + c[1] * x)) break;
+    double xn = x - q / dq;
+    if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+    if (fabs(xn - x) <= 1e-15 * x) { x = xn; break; }
+    x = xn;
+    q = c[0] + x * (c[1] + x * (c[2] + x * c[3]));
+    dq = c[1] + x * (2.0 * c[2] + 3.0 * c[3] * x);
+    if (q > 0.0) hi = x;
+    else if (q < 0.0) lo = x;
+    else break;
+  }
+  return x;
+}
+
+// Reduce line-search and spectral partials; mode 0: cubic (p = 4) -> alpha;
+// mode 1: general p, first pass at alpha = 0 -> start the root rule;
+// mode 2: general p, one root-rule step after an evaluation at st->x.
+__global__ __launch_bounds__(PSD_NT) void k_ls_finalize(const Inst* __restrict__ insts, int mode) {
+  __shared__ double scratch[10 * PSD_NT / PSD_WAVE];
+  const Inst& I = insts[blockIdx.x];
+  SolveState* st = I.st;
+  if (st->done || (mode == 2 && st->ls_phase == 2)) return;
+  double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < I.nblk_ls; b += PSD_NT)
+    for (int k = 0; k < 8; ++k) acc[k] += I.part_ls[8 * b + k];
+  if (mode != 2)
+    for (int b = threadIdx.x; b < I.nblk_sp; b += PSD_NT) {
+      acc[8] += I.part_sp[2 * b];
+      acc[9] += I.part_sp[2 * b + 1];
+    }
+  block_reduce<10, 0>(acc, scratch);
+  if (threadIdx.x != 0) return;
+  const double s = I.s, se2 = I.se2;
+  if (mode == 0) {
+    const double S2 = acc[0], S3 = acc[1], S4 = acc[2], S5 = acc[3], P2 = acc[4], P4 = acc[5];
+    const double lin = (I.order == 4) ? P2 : s * I.lam * P2 + acc[9];
+    double c[4];
+    c[0] = -acc[8];
+    c[1] = lin + s * (S2 + 2.0 * S3) + se2 * P4;
+    c[2] = 3.0 * s * S4;
+    c[3] = s * S5;
+    for (int k = 0; k < 4; ++k) st->c[k] = c[k];
+    if (!(c[0] < 0.0) || !(c[1] > 0.0)) {
+      st->status = -5; st->done = 1; st->alpha = 0.0;
+      return;
+    }
+    const double a = cubic_root(c);
+    st->alpha = a;
+    st->dE = I.hd * a * (c[0] + a * (c[1] / 2.0 + a * (c[2] / 3.0 + a * c[3] / 4.0)));
+    st->ls_phase = 2;
+    return;
+  }
+  if (mode == 1) {
+    const double NL = acc[0], dNL = acc[1], P2 = acc[2], P4 = acc[3];
+    const double lin = ((I.order == 4) ? P2 : s * I.lam * P2 + acc[9]) + se2 * P4;
+    const double q0 = -acc[8];
+    const double dq0 = lin + s * dNL;
+    st->c[0] = q0; st->c[1] = dq0; st->lin = lin; st->nl0 = NL;
+    st->dE = 0.0;
+    if (!(q0 < 0.0) || !(dq0 > 0.0)) {
+      st->status = -5; st->done = 1; st->alpha = 0.0; st->ls_phase = 2;
+      return;
+    }
+    st->lo = 0.0; st->hi = INFINITY; st->x = -q0 / dq0;
+    st->ls_phase = 0; st->ls_evals = 0; st->newton_steps = 0;
+    return;
+  }
+  // mode 2: evaluation at x finished
+  const double x = st->x;
+  const double q = st->c[0] + x * st->lin + s * (acc[0] - st->nl0);
+  const double dq = st->lin + s * acc[1];
+  const double c0 = st->c[0], c1 = st->c[1];
+  st->ls_evals += 1;
+  if (st->ls_phase == 0) {
+    if (q > 0.0) { st->hi = x; st->ls_phase = 1; }
+    else if (q == 0.0) { st->alpha = x; st->ls_phase = 2; return; }
+    else {
+      st->lo = x; st->x = 2.0 * x;
+      if (st->ls_evals >= 200) { st->alpha = x; st->ls_phase = 2; }
+      return;
+    }
+  } else {
+    if (q > 0.0) st->hi = x;
+    else if (q < 0.0) st->lo = x;
+    else { st->alpha = x; st->ls_phase = 2; return; }
+  }
+  // Newton decision at (x, q, dq)
+  if (fabs(q) <= 1e-16 * (fabs(c0) + c1 * x) || st->newton_steps >= 100) {
+    st->alpha = x; st->ls_phase = 2; return;
+  }
+  double xn = x - q / dq;
+  if (!(xn > st->lo && xn < st->hi)) xn = 0.5 * (st->lo + st->hi);
+  st->newton_steps += 1;
+  if (fabs(xn - x) <= 1e-15 * x) { st->alpha = xn; st->ls_phase = 2; return; }
+  st->x = xn;
+}
+
+// ===========================================================================
+// FFT passes
+// ===========================================================================
+enum FieldSet { FS_RES = 0, FS_DIR = 1, FS_TMP = 2 };
+
+template <typename T>
+__device__ __forceinline__ RowArgs<T> row_args(const Inst& I, int fs, cx<T>* spec, int nf) {
+  RowArgs<T> A;
+  A.spec = spec;
+  A.nspec = I.nspec;
+  A.rpf = I.ncell / I.n;
+  A.nrows = A.rpf * nf;
+  A.rin0 = A.rin1 = nullptr;
+  A.rout0 = A.rout1 = A.rout2 = nullptr;
+  if (fs == FS_RES) { A.rin0 = I.r; A.rin1 = I.r1; }
+  else if (fs == FS_DIR) { A.rout0 = I.d; A.rout1 = I.e1; A.rout2 = I.e2; }
+  else { A.rin0 = I.tmp; A.rout0 = I.tmp; }  // FP64 scratch field
+  return A;
+}
+
+// row pass kernels: task.a = first global row (over fields), task.b = field
+// set, task.c = number of fields
+template <typename T, typename TIO, bool FWD>
+__global__ __launch_bounds__(PSD_NT) void k_rows(const Inst* __restrict__ insts,
+                                                 const Task2* __restrict__ tasks, int solver) {
+  extern __shared__ double smem[];
+  const Task2 t = tasks[blockIdx.x];
+  const Inst& I = insts[t.inst];
+  if (solver && I.st->done) return;
+  cx<T>* buf = (cx<T>*)smem;
+  const cx<T>* tw = (const cx<T>*)(sizeof(T) == 8 ? I.tw64 : I.tw32);
+  RowArgs<T> A = row_args<T>(I, t.b, (cx<T>*)I.spec, t.c);
+  switch (I.n) {
+#define PSD_ROW_CASE(NN)                                                               \
+    case NN:                                                                           \
+      if (FWD) r2c_rows<T, TIO, NN, row_lines<T, NN>()>(A, t.a, buf, tw);              \
+      else c2r_rows<T, TIO, NN, row_lines<T, NN>()>(A, t.a, buf, tw);                  \
+      break;
+    PSD_FOR_EACH_N(PSD_ROW_CASE)
+#undef PSD_ROW_CASE
+    default: break;
+  }
+}
+
+// plain column pass: task.a = outer index, task.b = first column; NF fields
+template <typename T, int NF, int DIR>
+__global__ __launch_bounds__(PSD_NT) void k_cols(const Inst* __restrict__ insts,
+                                                 const Task2* __restrict__ tasks, int axis,
+                                                 int solver) {
+  extern __shared__ double smem[];
+  const Task2 t = tasks[blockIdx.x];
+  const Inst& I = insts[t.inst];
+  if (solver && I.st->done) return;
+  cx<T>* buf = (cx<T>*)smem;
+  const cx<T>* tw = (const cx<T>*)(sizeof(T) == 8 ? I.tw64 : I.tw32);
+  const long long n = I.n, nc = I.nc;
+  // axis 1: lines along y (stride nc), columns kx, outer z (stride n*nc)
+  // axis 2: lines along z (stride n*nc), columns (ky,kx)
+  const long long inner = (axis == 1) ? nc : n * nc;
+  const long long lstride = (axis == 1) ? nc : n * nc;
+  cx<T>* base = (cx<T>*)I.spec + (axis == 1 ? (long long)t.a * n * nc : 0);
+  switch (I.n) {
+#define PSD_COL_CASE(NN)                                                                          \
+    case NN:                                                                                      \
+      col_pass<T, NN, col_width<T, NN, NF>(), NF, DIR>(base, inner, t.b, lstride, I.nspec, buf, tw); \
+      break;
+    PSD_FOR_EACH_N(PSD_COL_CASE)
+#undef PSD_COL_CASE
+    default: break;
+  }
+}
+
+// Spectral operators applied between the forward and inverse transform of
+// the last axis.  k indices: kx = column index mod nc, ky, kz.
+//   OP_PRECOND4: d^ = r^ / sigma / Ntot, sigma = 1 + s K + s eps^2 K^2
+//                (order-4 preconditioner, Sec. 5.3); partial: sum w |r^|^2/sigma/Ntot
+//   OP_PRECOND6: rho^ = r2^ + r1^/K, d^ = rho^/sigma6, e1^ = r1^/K, e2^ = d^/K,
+//                sigma6 = s lam + s K + s eps^2 K^2 + 1/K (Sec. 5.4), k = 0 -> 0;
+//                partials: sum w |rho^|^2/sigma6/Ntot, sum w |d^|^2/K/Ntot
+//   OP_POISSON:  z^ -> z^/K/Ntot (T_h = -Delta_h^{-1}), partial sum w |z^|^2/K/Ntot
+// K = S[kx] + S[ky] (+ S[kz]) is the symbol of -Delta_h (appendix).
+enum SpecOp { OP_PRECOND4 = 0, OP_PRECOND6 = 1, OP_POISSON = 2 };
+
+template <typename T, int N, int W, int OP>
+__device__ __forceinline__ void fused_col(const Inst& I, const Task2& t, cx<T>* buf, double (&acc)[2]) {
+  constexpr int NFI = (OP == OP_PRECOND6) ? 2 : 1;
+  constexpr int NFO = (OP == OP_PRECOND6) ? 3 : 1;
+  constexpr int LS = N + 1;
+  const cx<T>* tw = (const cx<T>*)(sizeof(T) == 8 ? I.tw64 : I.tw32);
+  const long long n = I.n, nc = I.nc;
+  const int dim = I.dim;
+  const long long inner = (dim == 2) ? nc : n * nc;
+  const long long lstride = inner;
+  cx<T>* base = (cx<T>*)I.spec;
+  const long long col0 = t.b;
+  for (int e = threadIdx.x; e < NFI * W * N; e += PSD_NT) {
+    const int c = e % W;
+    const int ft = e / W;
+    const int tt = ft % N, f = ft / N;
+    cx<T> v = mk(T(0), T(0));
+    if (col0 + c < inner) v = base[f * I.nspec + col0 + c + tt * lstride];
+    buf[(f * W + c) * LS + tt] = v;
+  }
+  __syncthreads();
+  lds_fft<T, N, NFI * W, LS, -1>(buf, tw);
+  const double s = I.s, se2 = I.se2, inv = I.inv_ntot;
+  const double* S = I.S;
+  for (int e = threadIdx.x; e < W * N; e += PSD_NT) {
+    const int c = e % W, tt = e / W;
+    const long long col = col0 + c;
+    if (col >= inner) continue;
+    const int kx = (int)(col % nc);
+    const int ky = (dim == 2) ? tt : (int)(col / nc);
+    double K = S[kx] + S[ky];
+    if (dim == 3) K += S[tt];
+    const double wgt = (kx == 0 || 2 * kx == (int)n) ? 1.0 : 2.0;
+    if (OP == OP_PRECOND4) {
+      const cx<T> X = buf[c * LS + tt];
+      const double sig = 1.0 + s * K + se2 * K * K;
+      const double x2 = (double)X.x * X.x + (double)X.y * X.y;
+      acc[0] += wgt * x2 / sig * inv;
+      buf[c * LS + tt] = scale(X, (T)(inv / sig));
+    } else if (OP == OP_POISSON) {
+      const cx<T> X = buf[c * LS + tt];
+      if (K > 0.0) {
+        const double x2 = (double)X.x * X.x + (double)X.y * X.y;
+        acc[0] += wgt * x2 / K * inv;
+        buf[c * LS + tt] = scale(X, (T)(inv / K));
+      } else {
+        buf[c * LS + tt] = mk(T(0), T(0));
+      }
+    } else {
+      const cx<T> X2 = buf[c * LS + tt], X1 = buf[(W + c) * LS + tt];
+      if (K > 0.0) {
+        const double iK = 1.0 / K;
+        const double sig = s * I.lam + s * K + se2 * K * K + iK;
+        const double px = (double)X2.x + iK * X1.x, py = (double)X2.y + iK * X1.y;
+        const double dx = px / sig, dy = py / sig;
+        acc[0] += wgt * (px * px + py * py) / sig * inv;
+        acc[1] += wgt * (dx * dx + dy * dy) * iK * inv;
+        buf[c * LS + tt] = mk((T)(dx * inv), (T)(dy * inv));
+        buf[(W + c) * LS + tt] = mk((T)(X1.x * iK * inv), (T)(X1.y * iK * inv));
+        buf[(2 * W + c) * LS + tt] = mk((T)(dx * iK * inv), (T)(dy * iK * inv));
+      } else {
+        buf[c * LS + tt] = mk(T(0), T(0));
+        buf[(W + c) * LS + tt] = mk(T(0), T(0));
+        buf[(2 * W + c) * LS + tt] = mk(T(0), T(0));
+      }
+    }
+  }
+  __syncthreads();
+  lds_fft<T, N, NFO * W, LS, 1>(buf, tw);
+  for (int e = threadIdx.x; e < NFO * W * N; e += PSD_NT) {
+    const int c = e % W;
+    const int ft = e / W;
+    const int tt = ft % N, f = ft / N;
+    if (col0 + c < inner) base[f * I.nspec + col0 + c + tt * lstride] = buf[(f * W + c) * LS + tt];
+  }
+}
+
+template <typename T, int OP>
+__global__ __launch_bounds__(PSD_NT) void k_cols_fused(const Inst* __restrict__ insts,
+                                                       const Task2* __restrict__ tasks, int solver) {
+  extern __shared__ double smem[];
+  const Task2 t = tasks[blockIdx.x];
+  const Inst& I = insts[t.inst];
+  if (solver && I.st->done) return;
+  cx<T>* buf = (cx<T>*)smem;
+  double acc[2] = {0.0, 0.0};
+  constexpr int NFM = (OP == OP_PRECOND6) ? 3 : 1;
+  switch (I.n) {
+#define PSD_FC_CASE(NN)                                                          \
+    case NN:                                                                     \
+      fused_col<T, NN, col_width<T, NN, NFM>(), OP>(I, t, buf, acc);             \
+      break;
+    PSD_FOR_EACH_N(PSD_FC_CASE)
+#undef PSD_FC_CASE
+    default: break;
+  }
+  // LDS scratch after the largest FFT buffer of this launch is not known
+  // here; reuse the start of smem after a barrier (buffers are dead now).
+  __syncthreads();
+  block_reduce<2, 0>(acc, smem);
+  if (threadIdx.x == 0) {
+    I.part_sp[2 * t.slot] = acc[0];
+    I.part_sp[2 * t.slot + 1] = acc[1];
+  }
+}
+
+// ===========================================================================
+// auxiliary kernels (not on the hot loop)
+// ===========================================================================
+// Energy partials per block (one thread per cell, direct global reads):
+// [0] sum (u-f)^2  [1] sum_V |G|^p  [2] sum (Delta_h u)^2  [3] sum u^2  [4] sum u f
+__global__ __launch_bounds__(PSD_NT) void k_energy_parts(const Inst* __restrict__ insts, int inst,
+                                                         const double* __restrict__ u,
+                                                         const double* __restrict__ f,
+                                                         double* __restrict__ part) {
+  __shared__ double scratch[5 * PSD_NT / PSD_WAVE];
+  const Inst& I = insts[inst];
+  const long long N = I.ncell;
+  const int n = I.n;
+  double acc[5] = {0, 0, 0, 0, 0};
+  const double ih = I.inv_h, ih2 = ih * ih;
+  for (long long c = blockIdx.x * (long long)PSD_NT + threadIdx.x; c < N; c += (long long)gridDim.x * PSD_NT) {
+    const int i = (int)(c % n);
+    const int j = (int)((c / n) % n);
+    const int k = (I.dim == 3) ? (int)(c / ((long long)n * n)) : 0;
+    auto at = [&](int di, int dj, int dk) -> double {
+      const int ii = wrapi(i + di, n), jj = wrapi(j + dj, n), kk = (I.dim == 3) ? wrapi(k + dk, n) : 0;
+      return u[ii + (long long)n * (jj + (long long)n * kk)];
+    };
+    const double uc = u[c];
+    const double fc = f[c];
+    acc[0] += (uc - fc) * (uc - fc);
+    acc[3] += uc * uc;
+    acc[4] += uc * fc;
+    double lap = at(1, 0, 0) + at(-1, 0, 0) + at(0, 1, 0) + at(0, -1, 0) - 4.0 * uc;
+    if (I.dim == 3) lap += at(0, 0, 1) + at(0, 0, -1) - 2.0 * uc;
+    lap *= ih2;
+    acc[2] += lap * lap;
+    double g2;
+    if (I.dim == 2) {
+      const double c10 = at(1, 0, 0), c01 = at(0, 1, 0), c11 = at(1, 1, 0);
+      const double gx = 0.5 * ih * ((c10 - uc) + (c11 - c01)), gy = 0.5 * ih * ((c01 - uc) + (c11 - c10));
+      g2 = gx * gx + gy * gy;
+    } else {
+      const double c100 = at(1, 0, 0), c010 = at(0, 1, 0), c110 = at(1, 1, 0);
+      const double c001 = at(0, 0, 1), c101 = at(1, 0, 1), c011 = at(0, 1, 1), c111 = at(1, 1, 1);
+      const double q = 0.25 * ih;
+      const double gx = q * ((c100 - uc) + (c110 - c010) + (c101 - c001) + (c111 - c011));
+      const double gy = q * ((c010 - uc) + (c110 - c100) + (c011 - c001) + (c111 - c101));
+      const double gz = q * ((c001 - uc) + (c101 - c100) + (c011 - c010) + (c111 - c110));
+      g2 = gx * gx + gy * gy + gz * gz;
+    }
+    acc[1] += (I.p_is_4) ? g2 * g2 : pow(g2, 0.5 * I.p);
+  }
+  block_reduce<5, 0>(acc, scratch);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 5; ++q) part[5 * blockIdx.x + q] = acc[q];
+}
+
+// per-block sums of up to 3 fields: [0] sum a, [1] sum b, [2] sum a*b
+__global__ __launch_bounds__(PSD_NT) void k_sums(const double* __restrict__ a, const double* __restrict__ b,
+                                                 long long N, double* __restrict__ part) {
+  __shared__ double scratch[3 * PSD_NT / PSD_WAVE];
+  double acc[3] = {0, 0, 0};
+  for (long long c = blockIdx.x * (long long)PSD_NT + threadIdx.x; c < N; c += (long long)gridDim.x * PSD_NT) {
+    const double av = a[c];
+    const double bv = b ? b[c] : 0.0;
+    acc[0] += av; acc[1] += bv; acc[2] += av * bv;
+  }
+  block_reduce<3, 0>(acc, scratch);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 3; ++q) part[3 * blockIdx.x + q] = acc[q];
+}
+
+// out = alpha * a + beta * b + gamma  (b may be null)
+__global__ __launch_bounds__(PSD_NT) void k_axpby(double* __restrict__ out, const double* __restrict__ a,
+                                                  const double* __restrict__ b, double alpha, double beta,
+                                                  double gamma, long long N) {
+  for (long long c = blockIdx.x * (long long)PSD_NT + threadIdx.x; c < N; c += (long long)gridDim.x * PSD_NT)
+    out[c] = alpha * a[c] + (b ? beta * b[c] : 0.0) + gamma;
+}
+
+// mark every instance except `keep` as finished (auxiliary single-instance calls)
+__global__ void k_mark_done(const Inst* __restrict__ insts, int ninst, int keep) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ninst && i != keep) insts[i].st->done = 1;
+}
+
+__global__ void k_set_status(const Inst* __restrict__ insts, int inst, int status) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    insts[inst].st->status = status;
+    insts[inst].st->done = 1;
+  }
+}
+
+__global__ void k_reset_state(const Inst* __restrict__ insts, int ninst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ninst) return;
+  SolveState* st = insts[i].st;
+  st->alpha = 0.0; st->rinf = 0.0; st->rl2 = 0.0;
+  for (int k = 0; k < 4; ++k) st->c[k] = 0.0;
+  st->iter = 0; st->done = 0; st->status = 0; st->ls_phase = 0; st->dE = 0.0;
+}
+
+}  // namespace psd

@@ -1,0 +1,835 @@
+// psd_lib.hip -- host runtime and C ABI of the gfx950 PSD solver.
+//
+// One handle holds a batch of instances (same dim, order and p; sizes and
+// coefficients may differ).  At creation it builds, per instance, the
+// symbol table S[k] = (4/h^2) sin^2(pi k/n) of -Delta_h along one axis
+// (appendix: eigenvalues of the difference operators), FP32 and FP64
+// twiddle tables, all work buffers, and the task tables of every pass.
+// One PSD iteration (Sec. 2.2 / Sec. 6) is the launch sequence
+//   rows R2C -> [cols fwd (3D)] -> cols fwd + 1/sigma + inv -> [cols inv]
+//   -> rows C2R   (search direction d, Sec. 6.1 / 6.2)
+//   -> line-search sums -> line-search finalize (alpha, Sec. 6.1)
+//   -> update + residual -> residual finalize (stop test)
+// all enqueued on one stream; in graph mode a chunk of iterations is
+// captured once into a HIP graph and replayed until the device flag is set.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "psd_kernels.hpp"
+#include "../../include/psd.h"
+
+using namespace psd;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct Range {
+  int off = 0, cnt = 0;
+  size_t lds = 0;
+};
+
+struct FftTasks {  // task ranges of one spectral application
+  Range r2c, coly_f, colz, coly_i, c2r;
+};
+
+size_t ceil_div(size_t a, size_t b) { return (a + b - 1) / b; }
+
+bool n_supported(int n) {
+  switch (n) {
+    case 16: case 32: case 48: case 64: case 96: case 128: case 192: case 256: case 384: case 512:
+    case 1024:
+      return true;
+    default:
+      return false;
+  }
+}
+
+template <typename T>
+int host_row_lines(int n) {
+  switch (n) {
+#define C(NN) case NN: return row_lines<T, NN>();
+    PSD_FOR_EACH_N(C)
+#undef C
+  }
+  return 0;
+}
+template <typename T, int NF>
+int host_col_width(int n) {
+  switch (n) {
+#define C(NN) case NN: return col_width<T, NN, NF>();
+    PSD_FOR_EACH_N(C)
+#undef C
+  }
+  return 0;
+}
+
+}  // namespace
+
+struct psd_handle_s {
+  int batch = 0;
+  int dim = 2, order = 4;
+  bool p_is_4 = true;
+  psd_options opt{};
+  bool mixed = false;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  std::vector<psd_problem> probs;
+  std::vector<Inst> hI;
+  Inst* dI = nullptr;
+  std::vector<Task2> hT;
+  Task2* dT = nullptr;
+  Range res, ls;
+  FftTasks fft_solver;   // solver precision, NF of the order
+  FftTasks fft_aux;      // FP64, one field (Poisson / energy / residual helpers)
+  SolveState* dState = nullptr;
+  SolveState* hState = nullptr;  // pinned
+  double* hPart = nullptr;       // pinned scratch for auxiliary partials
+  size_t hPartCap = 0;
+  double* dAuxPart = nullptr;
+  std::vector<void*> allocs;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  int gchunk = 0;
+  std::string err;
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+#define HIPCHK(expr)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      h->err = std::string(#expr) + ": " + hipGetErrorString(e_);                 \
+      return PSD_ERR_HIP;                                                         \
+    }                                                                             \
+  } while (0)
+
+static psd_status set_err(psd_handle* h, psd_status st, const std::string& msg) {
+  if (h) h->err = msg; else g_create_error = msg;
+  return st;
+}
+
+template <typename P>
+static hipError_t dalloc(psd_handle* h, P** ptr, size_t bytes) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes ? bytes : 16);
+  if (e == hipSuccess) {
+    h->allocs.push_back(p);
+    *ptr = (P*)p;
+  }
+  return e;
+}
+
+extern "C" psd_status psd_check_problem(const psd_problem* prob, char* msg, int msg_len) {
+  auto fail = [&](psd_status st, const char* m) {
+    if (msg && msg_len > 0) { std::snprintf(msg, (size_t)msg_len, "%s", m); }
+    return st;
+  };
+  if (!prob) return fail(PSD_ERR_ARG, "problem is NULL");
+  if (prob->dim != 2 && prob->dim != 3) return fail(PSD_ERR_ARG, "dim must be 2 or 3");
+  if (prob->order != 4 && prob->order != 6) return fail(PSD_ERR_ARG, "order must be 4 or 6");
+  if (prob->order == 6 && prob->dim != 2) return fail(PSD_ERR_ARG, "order 6 is supported in 2D");
+  if (!n_supported(prob->n)) return fail(PSD_ERR_ARG, "unsupported n");
+  if (prob->dim == 3 && (prob->n < 32 || prob->n > 256)) return fail(PSD_ERR_ARG, "3D needs 32 <= n <= 256");
+  if (!(prob->L > 0.0) || !std::isfinite(prob->L)) return fail(PSD_ERR_RANGE, "L must be > 0");
+  if (!(prob->s > 0.0) || !std::isfinite(prob->s)) return fail(PSD_ERR_RANGE, "s must be > 0");
+  if (!(prob->eps > 0.0 && prob->eps <= 1.0)) return fail(PSD_ERR_RANGE, "eps must lie in (0, 1]");
+  if (!(prob->p >= 2.0) || !std::isfinite(prob->p)) return fail(PSD_ERR_RANGE, "p must be >= 2");
+  if (prob->dim == 3 && prob->p > 6.0) return fail(PSD_ERR_RANGE, "3D needs p <= 6");
+  if (prob->order == 6 && !(prob->lambda >= 0.0)) return fail(PSD_ERR_RANGE, "lambda must be >= 0");
+  return fail(PSD_OK, "ok");
+}
+
+// ---------------------------------------------------------------------------
+// task tables
+// ---------------------------------------------------------------------------
+template <typename T>
+static int host_cw(int n, int nf) {
+  return nf == 1 ? host_col_width<T, 1>(n) : (nf == 2 ? host_col_width<T, 2>(n) : host_col_width<T, 3>(n));
+}
+
+// fs_in / fs_out: field sets read by the R2C rows and written by the C2R rows
+template <typename T>
+static void build_fft_tasks(psd_handle* h, FftTasks& F, int nfi, int nfo, bool with_slots, int fs_in,
+                            int fs_out) {
+  const size_t cxs = sizeof(cx<T>);
+  // rows R2C (nfi fields) and C2R (nfo fields)
+  for (int pass = 0; pass < 2; ++pass) {
+    Range& R = pass == 0 ? F.r2c : F.c2r;
+    const int nf = pass == 0 ? nfi : nfo;
+    R.off = (int)h->hT.size();
+    for (int b = 0; b < h->batch; ++b) {
+      const Inst& I = h->hI[b];
+      const int nl = host_row_lines<T>(I.n);
+      const long long rows = (long long)nf * (I.ncell / I.n);
+      for (long long r0 = 0; r0 < rows; r0 += 2 * nl) {
+        Task2 t{};
+        t.inst = b; t.a = (int)r0; t.b = pass == 0 ? fs_in : fs_out; t.c = nf;
+        h->hT.push_back(t);
+      }
+      R.lds = std::max(R.lds, (size_t)nl * (I.n + 1) * cxs);
+    }
+    R.cnt = (int)h->hT.size() - R.off;
+  }
+  // plain y passes (3D): forward over nfi fields, inverse over nfo fields
+  for (int pass = 0; pass < 2; ++pass) {
+    Range& R = pass == 0 ? F.coly_f : F.coly_i;
+    const int nf = pass == 0 ? nfi : nfo;
+    R.off = (int)h->hT.size();
+    if (h->dim == 3) {
+      for (int b = 0; b < h->batch; ++b) {
+        const Inst& I = h->hI[b];
+        const int W = host_cw<T>(I.n, nf);
+        for (int z = 0; z < I.n; ++z)
+          for (int c0 = 0; c0 < I.nc; c0 += W) {
+            Task2 t{};
+            t.inst = b; t.a = z; t.b = c0;
+            h->hT.push_back(t);
+          }
+        R.lds = std::max(R.lds, (size_t)nf * W * (I.n + 1) * cxs);
+      }
+    }
+    R.cnt = (int)h->hT.size() - R.off;
+  }
+  // fused last-axis pass
+  Range& R = F.colz;
+  R.off = (int)h->hT.size();
+  for (int b = 0; b < h->batch; ++b) {
+    Inst& I = h->hI[b];
+    const int nfm = std::max(nfi, nfo);
+    const int W = host_cw<T>(I.n, nfm);
+    const long long inner = h->dim == 2 ? I.nc : (long long)I.n * I.nc;
+    int slot = 0;
+    for (long long c0 = 0; c0 < inner; c0 += W) {
+      Task2 t{};
+      t.inst = b; t.a = 0; t.b = (int)c0; t.slot = slot++;
+      h->hT.push_back(t);
+    }
+    if (with_slots) I.nblk_sp = slot;
+    R.lds = std::max(R.lds, std::max((size_t)nfm * W * (I.n + 1) * cxs, (size_t)64 * 8));
+  }
+  R.cnt = (int)h->hT.size() - R.off;
+}
+
+static void build_tile_tasks(psd_handle* h) {
+  // residual and line-search tiles share the same tiling
+  for (int pass = 0; pass < 2; ++pass) {
+    Range& R = pass == 0 ? h->res : h->ls;
+    R.off = (int)h->hT.size();
+    for (int b = 0; b < h->batch; ++b) {
+      Inst& I = h->hI[b];
+      int slot = 0;
+      if (h->dim == 2) {
+        for (int y0 = 0; y0 < I.n; y0 += T2Y)
+          for (int x0 = 0; x0 < I.n; x0 += T2X) {
+            Task2 t{}; t.inst = b; t.a = x0; t.b = y0; t.c = 0; t.slot = slot++;
+            h->hT.push_back(t);
+          }
+      } else {
+        for (int z0 = 0; z0 < I.n; z0 += T3Z)
+          for (int y0 = 0; y0 < I.n; y0 += T3Y)
+            for (int x0 = 0; x0 < I.n; x0 += T3X) {
+              Task2 t{}; t.inst = b; t.a = x0; t.b = y0; t.c = z0; t.slot = slot++;
+              h->hT.push_back(t);
+            }
+      }
+      if (pass == 0) I.nblk_res = slot; else I.nblk_ls = slot;
+    }
+    R.cnt = (int)h->hT.size() - R.off;
+    if (h->dim == 2)
+      R.lds = pass == 0 ? (R2_LDS + 16) * sizeof(double) : (L2_LDS + 32) * sizeof(double);
+    else
+      R.lds = pass == 0 ? (R3_LDS + 16) * sizeof(double) : (L3_LDS + 32) * sizeof(double);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launches
+// ---------------------------------------------------------------------------
+template <typename T, typename TIN, typename TOUT>
+static void run_fft(psd_handle* h, const FftTasks& F, int op, bool solver) {
+  const Task2* dT = h->dT;
+  hipStream_t s = h->stream;
+  const int sv = solver ? 1 : 0;
+  if (F.r2c.cnt)
+    k_rows<T, TIN, true><<<F.r2c.cnt, PSD_NT, F.r2c.lds, s>>>(h->dI, dT + F.r2c.off, sv);
+  const int nfi = op == OP_PRECOND6 ? 2 : 1, nfo = op == OP_PRECOND6 ? 3 : 1;
+  if (F.coly_f.cnt) {
+    if (nfi == 1) k_cols<T, 1, -1><<<F.coly_f.cnt, PSD_NT, F.coly_f.lds, s>>>(h->dI, dT + F.coly_f.off, 1, sv);
+    else k_cols<T, 2, -1><<<F.coly_f.cnt, PSD_NT, F.coly_f.lds, s>>>(h->dI, dT + F.coly_f.off, 1, sv);
+  }
+  if (op == OP_PRECOND4)
+    k_cols_fused<T, OP_PRECOND4><<<F.colz.cnt, PSD_NT, F.colz.lds, s>>>(h->dI, dT + F.colz.off, sv);
+  else if (op == OP_PRECOND6)
+    k_cols_fused<T, OP_PRECOND6><<<F.colz.cnt, PSD_NT, F.colz.lds, s>>>(h->dI, dT + F.colz.off, sv);
+  else
+    k_cols_fused<T, OP_POISSON><<<F.colz.cnt, PSD_NT, F.colz.lds, s>>>(h->dI, dT + F.colz.off, sv);
+  if (F.coly_i.cnt) {
+    if (nfo == 1) k_cols<T, 1, 1><<<F.coly_i.cnt, PSD_NT, F.coly_i.lds, s>>>(h->dI, dT + F.coly_i.off, 1, sv);
+    else k_cols<T, 3, 1><<<F.coly_i.cnt, PSD_NT, F.coly_i.lds, s>>>(h->dI, dT + F.coly_i.off, 1, sv);
+  }
+  if (F.c2r.cnt)
+    k_rows<T, TOUT, false><<<F.c2r.cnt, PSD_NT, F.c2r.lds, s>>>(h->dI, dT + F.c2r.off, sv);
+}
+
+template <typename TD, typename TR>
+static void run_residual(psd_handle* h, bool upd) {
+  hipStream_t s = h->stream;
+  const Task2* t = h->dT + h->res.off;
+  const int n = h->res.cnt;
+  if (h->dim == 2) {
+    if (h->order == 4) {
+      if (upd) k_res2d<TD, TR, 4, true><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
+      else k_res2d<TD, TR, 4, false><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
+    } else {
+      if (upd) k_res2d<TD, TR, 6, true><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
+      else k_res2d<TD, TR, 6, false><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
+    }
+  } else {
+    if (upd) k_res3d<TD, TR, true><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
+    else k_res3d<TD, TR, false><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
+  }
+  k_res_finalize<<<h->batch, PSD_NT, 0, s>>>(h->dI, upd ? 1 : 0);
+}
+
+template <typename TD>
+static void run_ls(psd_handle* h, int mode) {
+  hipStream_t s = h->stream;
+  const Task2* t = h->dT + h->ls.off;
+  if (h->dim == 2) k_ls2d<TD><<<h->ls.cnt, PSD_NT, h->ls.lds, s>>>(h->dI, t, mode);
+  else k_ls3d<TD><<<h->ls.cnt, PSD_NT, h->ls.lds, s>>>(h->dI, t, mode);
+  k_ls_finalize<<<h->batch, PSD_NT, 0, s>>>(h->dI, mode);
+}
+
+// one PSD iteration (p = 4: fixed launch sequence, capturable)
+template <typename T, typename TD, typename TR>
+static void run_iteration_p4(psd_handle* h) {
+  run_fft<T, TR, TD>(h, h->fft_solver, h->order == 4 ? OP_PRECOND4 : OP_PRECOND6, true);
+  run_ls<TD>(h, 0);
+  run_residual<TD, TR>(h, true);
+}
+
+static psd_status read_states(psd_handle* h) {
+  HIPCHK(hipMemcpyAsync(h->hState, h->dState, sizeof(SolveState) * h->batch, hipMemcpyDeviceToHost,
+                        h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return PSD_OK;
+}
+
+static bool all_done(psd_handle* h) {
+  for (int b = 0; b < h->batch; ++b)
+    if (!h->hState[b].done) return false;
+  return true;
+}
+
+// general p: line search with a host-driven root rule (one grid pass per
+// evaluation of q and q')
+template <typename T, typename TD, typename TR>
+static psd_status run_iteration_general(psd_handle* h) {
+  run_fft<T, TR, TD>(h, h->fft_solver, h->order == 4 ? OP_PRECOND4 : OP_PRECOND6, true);
+  run_ls<TD>(h, 1);
+  for (int step = 0; step < 400; ++step) {
+    run_ls<TD>(h, 2);
+    psd_status st = read_states(h);
+    if (st != PSD_OK) return st;
+    bool fin = true;
+    for (int b = 0; b < h->batch; ++b)
+      if (!h->hState[b].done && h->hState[b].ls_phase != 2) fin = false;
+    if (fin) break;
+  }
+  run_residual<TD, TR>(h, true);
+  return PSD_OK;
+}
+
+template <typename T, typename TD, typename TR>
+static psd_status solve_loop(psd_handle* h) {
+  const int chunk = h->opt.graph_chunk;
+  if (chunk > 0 && h->p_is_4) {
+    if (!h->gexec || h->gchunk != chunk) {
+      if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
+      if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
+      HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+      for (int k = 0; k < chunk; ++k) run_iteration_p4<T, TD, TR>(h);
+      HIPCHK(hipStreamEndCapture(h->stream, &h->graph));
+      HIPCHK(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+      h->gchunk = chunk;
+    }
+    const int max_launch = h->opt.max_iter / chunk + 2;
+    for (int it = 0; it < max_launch; ++it) {
+      HIPCHK(hipGraphLaunch(h->gexec, h->stream));
+      psd_status st = read_states(h);
+      if (st != PSD_OK) return st;
+      if (all_done(h)) break;
+    }
+    return PSD_OK;
+  }
+  for (int it = 0; it <= h->opt.max_iter; ++it) {
+    if (h->p_is_4) run_iteration_p4<T, TD, TR>(h);
+    else {
+      psd_status st = run_iteration_general<T, TD, TR>(h);
+      if (st != PSD_OK) return st;
+    }
+    HIPCHK(hipGetLastError());
+    psd_status st = read_states(h);
+    if (st != PSD_OK) return st;
+    if (all_done(h)) break;
+  }
+  return PSD_OK;
+}
+
+// sum of per-block auxiliary partials on the host (fixed order)
+static psd_status aux_sums(psd_handle* h, const double* a, const double* b, long long N, double out[3]) {
+  const int nblk = 256;
+  k_sums<<<nblk, PSD_NT, 0, h->stream>>>(a, b, N, h->dAuxPart);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(h->hPart, h->dAuxPart, sizeof(double) * 3 * nblk, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  out[0] = out[1] = out[2] = 0.0;
+  for (int k = 0; k < nblk; ++k)
+    for (int q = 0; q < 3; ++q) out[q] += h->hPart[3 * k + q];
+  return PSD_OK;
+}
+
+static psd_status upload_inst(psd_handle* h) {
+  HIPCHK(hipMemcpyAsync(h->dI, h->hI.data(), sizeof(Inst) * h->batch, hipMemcpyHostToDevice, h->stream));
+  return PSD_OK;
+}
+
+// Apply T_h = -Delta_h^{-1} (FP64) to I.tmp of instance b in place; returns
+// sum_k w |z^|^2/K / Ntot = (z, T_h z) without the h^dim factor.
+static psd_status aux_poisson(psd_handle* h, int b, double* zTz) {
+  // run the auxiliary FFT only on instance b: temporarily mark the others done
+  run_fft<double, double, double>(h, h->fft_aux, OP_POISSON, false);
+  HIPCHK(hipGetLastError());
+  if (zTz) {
+    const Inst& I = h->hI[b];
+    // partials live in part_sp of instance b (aux slot count = fft_aux blocks of b)
+    int nblk = 0;
+    for (int k = 0; k < h->fft_aux.colz.cnt; ++k)
+      if (h->hT[h->fft_aux.colz.off + k].inst == b) ++nblk;
+    std::vector<double> tmp(2 * (size_t)nblk);
+    HIPCHK(hipMemcpyAsync(tmp.data(), I.part_sp, sizeof(double) * 2 * nblk, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    double sacc = 0.0;
+    for (int k = 0; k < nblk; ++k) sacc += tmp[2 * k];
+    *zTz = sacc;
+  }
+  return PSD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" psd_status psd_create(const psd_problem* probs, int batch, const psd_options* opt,
+                                 void* hip_stream, psd_handle** out) {
+  g_create_error.clear();
+  if (!out) return set_err(nullptr, PSD_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!probs || batch <= 0 || !opt) return set_err(nullptr, PSD_ERR_ARG, "probs/opt NULL or batch <= 0");
+  char msg[128];
+  for (int b = 0; b < batch; ++b) {
+    psd_status st = psd_check_problem(&probs[b], msg, sizeof msg);
+    if (st != PSD_OK) return set_err(nullptr, st, "instance " + std::to_string(b) + ": " + msg);
+    if (probs[b].dim != probs[0].dim || probs[b].order != probs[0].order || probs[b].p != probs[0].p)
+      return set_err(nullptr, PSD_ERR_ARG, "all instances must share dim, order and p");
+  }
+  if (!(opt->tol >= 0.0) || opt->max_iter < 0 || (opt->precision != PSD_FP64 && opt->precision != PSD_MIXED) ||
+      opt->graph_chunk < 0)
+    return set_err(nullptr, PSD_ERR_ARG, "bad options");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+    return set_err(nullptr, PSD_ERR_HIP, "no HIP device");
+
+  psd_handle* h = new psd_handle();
+  h->batch = batch;
+  h->dim = probs[0].dim;
+  h->order = probs[0].order;
+  h->p_is_4 = probs[0].p == 4.0;
+  h->opt = *opt;
+  h->mixed = opt->precision == PSD_MIXED;
+  h->probs.assign(probs, probs + batch);
+  (void)hipGetDevice(&h->device);
+  if (hip_stream) h->stream = (hipStream_t)hip_stream;
+  else {
+    if (hipStreamCreate(&h->stream) != hipSuccess) { delete h; return set_err(nullptr, PSD_ERR_HIP, "stream"); }
+    h->own_stream = true;
+  }
+  auto fail = [&](const std::string& m) {
+    g_create_error = m;
+    psd_destroy(h);
+    return PSD_ERR_HIP;
+  };
+
+  const size_t tds = h->mixed ? sizeof(float) : sizeof(double);
+  h->hI.resize(batch);
+  for (int b = 0; b < batch; ++b) {
+    const psd_problem& P = probs[b];
+    Inst& I = h->hI[b];
+    std::memset(&I, 0, sizeof(Inst));
+    I.dim = P.dim; I.n = P.n; I.nc = P.n / 2 + 1; I.order = P.order;
+    I.ncell = (long long)P.n * P.n * (P.dim == 3 ? P.n : 1);
+    I.nspec = (long long)I.nc * P.n * (P.dim == 3 ? P.n : 1);
+    I.h = P.L / P.n; I.inv_h = P.n / P.L; I.p = P.p; I.s = P.s;
+    I.se2 = P.s * P.eps * P.eps; I.lam = P.lambda;
+    I.inv_ntot = 1.0 / (double)I.ncell;
+    I.tol = opt->tol;
+    I.hd = std::pow(I.h, P.dim);
+    I.max_iter = opt->max_iter;
+    I.p_is_4 = P.p == 4.0; I.p_is_2 = P.p == 2.0;
+    const size_t N = (size_t)I.ncell;
+    const int nspec_fields = P.order == 6 ? 3 : 1;
+    if (dalloc(h, &I.u[1], N * 8) || dalloc(h, &I.tmp, N * 8) ||
+        dalloc(h, (char**)&I.d, N * tds) || dalloc(h, (char**)&I.r, N * tds) ||
+        dalloc(h, (char**)&I.spec, (size_t)I.nspec * nspec_fields * 16) ||
+        dalloc(h, (double**)&I.S, (size_t)P.n * 8) || dalloc(h, (char**)&I.tw32, (size_t)P.n * 8) ||
+        dalloc(h, (char**)&I.tw64, (size_t)P.n * 16))
+      return fail("out of device memory");
+    if (P.order == 6) {
+      if (dalloc(h, &I.w[0], N * 8) || dalloc(h, &I.w[1], N * 8) || dalloc(h, (char**)&I.e1, N * tds) ||
+          dalloc(h, (char**)&I.e2, N * tds) || dalloc(h, (char**)&I.r1, N * tds))
+        return fail("out of device memory");
+    }
+    // symbol table of -Delta_h along one axis and twiddles (host, long double)
+    std::vector<double> S(P.n);
+    std::vector<float> t32(2 * (size_t)P.n);
+    std::vector<double> t64(2 * (size_t)P.n);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int k = 0; k < P.n; ++k) {
+      const long double sn = sinl(pi * k / P.n);
+      S[k] = (double)(4.0L / ((long double)I.h * I.h) * sn * sn);
+      const long double ang = -2.0L * pi * k / P.n;
+      t64[2 * k] = (double)cosl(ang); t64[2 * k + 1] = (double)sinl(ang);
+      t32[2 * k] = (float)t64[2 * k]; t32[2 * k + 1] = (float)t64[2 * k + 1];
+    }
+    if (hipMemcpy((void*)I.S, S.data(), S.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy((void*)I.tw32, t32.data(), t32.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy((void*)I.tw64, t64.data(), t64.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+      return fail("copy of tables failed");
+    if (opt->history && opt->max_iter > 0) {
+      if (dalloc(h, &I.hist, (size_t)opt->max_iter * 4 * 8)) return fail("out of device memory");
+      I.hist_cap = opt->max_iter;
+    }
+  }
+  // task tables (also fill nblk_* counts)
+  build_tile_tasks(h);
+  const int nfi = h->order == 6 ? 2 : 1, nfo = h->order == 6 ? 3 : 1;
+  if (h->mixed) build_fft_tasks<float>(h, h->fft_solver, nfi, nfo, true, FS_RES, FS_DIR);
+  else build_fft_tasks<double>(h, h->fft_solver, nfi, nfo, true, FS_RES, FS_DIR);
+  std::vector<int> nsp(batch);
+  for (int b = 0; b < batch; ++b) nsp[b] = h->hI[b].nblk_sp;
+  build_fft_tasks<double>(h, h->fft_aux, 1, 1, false, FS_TMP, FS_TMP);
+  // partial arrays and states
+  if (dalloc(h, &h->dState, sizeof(SolveState) * batch)) return fail("out of device memory");
+  for (int b = 0; b < batch; ++b) {
+    Inst& I = h->hI[b];
+    int aux_sp = 0;
+    for (int k = 0; k < h->fft_aux.colz.cnt; ++k) {
+      Task2& t = h->hT[h->fft_aux.colz.off + k];
+      if (t.inst == b) t.slot = aux_sp++;
+    }
+    const int nsp_max = std::max(nsp[b], aux_sp);
+    if (dalloc(h, &I.part_res, (size_t)I.nblk_res * 2 * 8) || dalloc(h, &I.part_ls, (size_t)I.nblk_ls * 8 * 8) ||
+        dalloc(h, &I.part_sp, (size_t)nsp_max * 2 * 8))
+      return fail("out of device memory");
+    I.st = h->dState + b;
+  }
+  if (dalloc(h, &h->dI, sizeof(Inst) * batch) || dalloc(h, &h->dT, sizeof(Task2) * h->hT.size()) ||
+      dalloc(h, &h->dAuxPart, sizeof(double) * 5 * 1024))
+    return fail("out of device memory");
+  if (hipHostMalloc((void**)&h->hState, sizeof(SolveState) * batch, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&h->hPart, sizeof(double) * 5 * 1024, hipHostMallocDefault) != hipSuccess)
+    return fail("pinned allocation failed");
+  std::memset(h->hState, 0, sizeof(SolveState) * batch);
+  if (hipMemcpy(h->dT, h->hT.data(), sizeof(Task2) * h->hT.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->dI, h->hI.data(), sizeof(Inst) * batch, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(h->dState, 0, sizeof(SolveState) * batch) != hipSuccess)
+    return fail("upload of tables failed");
+  *out = h;
+  return PSD_OK;
+}
+
+template <typename T, typename TD, typename TR>
+static psd_status solve_impl(psd_handle* h, const double* const* f, const double* const* g, double* const* u,
+                             double* const* w, psd_stats* stats) {
+  const int B = h->batch;
+  std::vector<int> pre_status(B, 0);
+  // bind user buffers
+  for (int b = 0; b < B; ++b) {
+    Inst& I = h->hI[b];
+    I.u[0] = u[b];
+    I.f = f[b];
+    I.g = (h->order == 6) ? g[b] : nullptr;
+  }
+  psd_status st = upload_inst(h);
+  if (st != PSD_OK) return st;
+  k_reset_state<<<(B + 63) / 64, 64, 0, h->stream>>>(h->dI, B);
+  HIPCHK(hipGetLastError());
+  if (h->order == 6) {
+    // mean(u0) must equal mean(g); w0 = T_h(g - u0) + s lam gbar - fbar (Sec. 4)
+    for (int b = 0; b < B; ++b) {
+      Inst& I = h->hI[b];
+      double su[3], sg[3];
+      st = aux_sums(h, I.u[0], I.f, I.ncell, su);
+      if (st != PSD_OK) return st;
+      st = aux_sums(h, I.g, nullptr, I.ncell, sg);
+      if (st != PSD_OK) return st;
+      const double ubar = su[0] / I.ncell, fbar = su[1] / I.ncell, gbar = sg[0] / I.ncell;
+      if (std::fabs(ubar - gbar) > 1e-12 * (1.0 + std::fabs(gbar))) pre_status[b] = PSD_ERR_MEAN;
+      k_axpby<<<1024, PSD_NT, 0, h->stream>>>(I.tmp, I.g, I.u[0], 1.0, -1.0, 0.0, I.ncell);
+    }
+    // one auxiliary FP64 Poisson solve per instance (all instances at once)
+    st = aux_poisson(h, 0, nullptr);
+    if (st != PSD_OK) return st;
+    for (int b = 0; b < B; ++b) {
+      Inst& I = h->hI[b];
+      double sf[3], sg[3];
+      st = aux_sums(h, I.f, nullptr, I.ncell, sf);
+      if (st != PSD_OK) return st;
+      st = aux_sums(h, I.g, nullptr, I.ncell, sg);
+      if (st != PSD_OK) return st;
+      const double shift = I.s * I.lam * sg[0] / I.ncell - sf[0] / I.ncell;
+      k_axpby<<<1024, PSD_NT, 0, h->stream>>>(I.w[0], I.tmp, nullptr, 1.0, 0.0, shift, I.ncell);
+    }
+  }
+  for (int b = 0; b < B; ++b)
+    if (pre_status[b]) k_set_status<<<1, 64, 0, h->stream>>>(h->dI, b, pre_status[b]);
+  // initial residual (no update)
+  run_residual<TD, TR>(h, false);
+  HIPCHK(hipGetLastError());
+  st = read_states(h);
+  if (st != PSD_OK) return st;
+  if (!all_done(h)) {
+    st = solve_loop<T, TD, TR>(h);
+    if (st != PSD_OK) return st;
+  }
+  st = read_states(h);
+  if (st != PSD_OK) return st;
+  // move the final iterate (and w) to the caller's buffers
+  psd_status worst = PSD_OK;
+  for (int b = 0; b < B; ++b) {
+    Inst& I = h->hI[b];
+    const SolveState& S = h->hState[b];
+    const int cur = S.iter & 1;
+    if (cur == 1) HIPCHK(hipMemcpyAsync(u[b], I.u[1], I.ncell * 8, hipMemcpyDeviceToDevice, h->stream));
+    if (h->order == 6 && w && w[b])
+      HIPCHK(hipMemcpyAsync(w[b], I.w[cur], I.ncell * 8, hipMemcpyDeviceToDevice, h->stream));
+    int status = pre_status[b] ? pre_status[b] : S.status;
+    if (stats) {
+      stats[b].iters = S.iter;
+      stats[b].res_inf = S.rinf;
+      stats[b].res_l2 = S.rl2;
+      stats[b].status = status;
+      stats[b].energy = NAN;
+    }
+    if (status < 0 && (worst >= 0 || status < worst)) worst = (psd_status)status;
+    else if (status > 0 && worst == PSD_OK) worst = (psd_status)status;
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  // restore instance table pointers (u[0] = caller buffer is per call)
+  if (stats && h->opt.history) {
+    for (int b = 0; b < B; ++b) {
+      double E = 0.0;
+      psd_status es = psd_energy(h, b, f[b], h->order == 6 ? g[b] : nullptr, u[b], &E);
+      if (es == PSD_OK) stats[b].energy = E;
+    }
+  }
+  return worst;
+}
+
+extern "C" psd_status psd_solve(psd_handle* h, const double* const* f, const double* const* g,
+                                double* const* u, double* const* w, psd_stats* stats) {
+  if (!h) return PSD_ERR_ARG;
+  if (!f || !u) return set_err(h, PSD_ERR_ARG, "f and u must be given");
+  for (int b = 0; b < h->batch; ++b) {
+    if (!f[b] || !u[b]) return set_err(h, PSD_ERR_ARG, "NULL f[b] or u[b]");
+    if (h->order == 6 && (!g || !g[b])) return set_err(h, PSD_ERR_ARG, "order 6 needs g");
+  }
+  HIPCHK(hipSetDevice(h->device));
+  if (h->mixed) return solve_impl<float, float, float>(h, f, g, u, w, stats);
+  return solve_impl<double, double, double>(h, f, g, u, w, stats);
+}
+
+// Evaluate the residual kernel once for instance `inst` at caller buffers,
+// writing FP64 r (and r1 for order 6) without an update.
+static psd_status aux_residual(psd_handle* h, int inst, const double* f, const double* g, const double* u,
+                               const double* wv, double* r2out, double* r1out, double* res_inf) {
+  Inst saved = h->hI[inst];
+  Inst& I = h->hI[inst];
+  I.u[0] = const_cast<double*>(u);
+  I.f = f;
+  I.g = g;
+  I.r = r2out;
+  if (h->order == 6) { I.w[0] = const_cast<double*>(wv); I.r1 = r1out; }
+  // other instances: mark done so their tiles return at once
+  psd_status st = upload_inst(h);
+  if (st != PSD_OK) { h->hI[inst] = saved; return st; }
+  k_reset_state<<<(h->batch + 63) / 64, 64, 0, h->stream>>>(h->dI, h->batch);
+  k_mark_done<<<(h->batch + 63) / 64, 64, 0, h->stream>>>(h->dI, h->batch, inst);
+  run_residual<double, double>(h, false);
+  HIPCHK(hipGetLastError());
+  st = read_states(h);
+  if (res_inf) *res_inf = h->hState[inst].rinf;
+  h->hI[inst] = saved;
+  psd_status st2 = upload_inst(h);
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return st != PSD_OK ? st : st2;
+}
+
+extern "C" psd_status psd_residual(psd_handle* h, int inst, const double* f, const double* g, const double* u,
+                                   double* r, double* res_inf) {
+  if (!h) return PSD_ERR_ARG;
+  if (inst < 0 || inst >= h->batch || !f || !u || (h->order == 6 && !g))
+    return set_err(h, PSD_ERR_ARG, "bad arguments");
+  HIPCHK(hipSetDevice(h->device));
+  Inst& I = h->hI[inst];
+  if (h->order == 4) {
+    double* rr = r ? r : I.tmp;
+    return aux_residual(h, inst, f, g, u, nullptr, rr, nullptr, res_inf);
+  }
+  // order 6: w = T_h(g - u); r2 = f - (s lam u - s div + s eps^2 Delta^2 u - w); rho = r2 - mean(r2)
+  k_axpby<<<1024, PSD_NT, 0, h->stream>>>(I.tmp, g, u, 1.0, -1.0, 0.0, I.ncell);
+  // mark other instances done for the auxiliary transform
+  k_reset_state<<<(h->batch + 63) / 64, 64, 0, h->stream>>>(h->dI, h->batch);
+  k_mark_done<<<(h->batch + 63) / 64, 64, 0, h->stream>>>(h->dI, h->batch, inst);
+  psd_status st = aux_poisson(h, inst, nullptr);
+  if (st != PSD_OK) return st;
+  double* rr = r ? r : (double*)I.d;  // FP64 scratch of ncell doubles needed
+  double* wtmp = I.u[1];
+  HIPCHK(hipMemcpyAsync(wtmp, I.tmp, I.ncell * 8, hipMemcpyDeviceToDevice, h->stream));
+  if (!r) {
+    // no caller buffer: use tmp for r2 (w copied to u[1] above)
+    rr = I.tmp;
+  }
+  std::vector<double> dummy;
+  double* r1 = I.w[1];
+  st = aux_residual(h, inst, f, g, u, wtmp, rr, r1, nullptr);
+  if (st != PSD_OK) return st;
+  double sm[3];
+  st = aux_sums(h, rr, nullptr, I.ncell, sm);
+  if (st != PSD_OK) return st;
+  k_axpby<<<1024, PSD_NT, 0, h->stream>>>(rr, rr, nullptr, 1.0, 0.0, -sm[0] / I.ncell, I.ncell);
+  if (res_inf) {
+    // max-norm on the host copy (auxiliary path, not performance relevant)
+    std::vector<double> host((size_t)I.ncell);
+    HIPCHK(hipMemcpyAsync(host.data(), rr, I.ncell * 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    double m = 0.0;
+    for (double v : host) m = std::max(m, std::fabs(v));
+    *res_inf = m;
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return PSD_OK;
+}
+
+extern "C" psd_status psd_residual_mixed(psd_handle* h, int inst, const double* f, const double* g,
+                                         const double* u, const double* w, double* r1, double* r2,
+                                         double* res_inf) {
+  if (!h) return PSD_ERR_ARG;
+  if (h->order != 6) return set_err(h, PSD_ERR_ARG, "psd_residual_mixed needs order 6");
+  if (inst < 0 || inst >= h->batch || !f || !g || !u || !w) return set_err(h, PSD_ERR_ARG, "bad arguments");
+  HIPCHK(hipSetDevice(h->device));
+  Inst& I = h->hI[inst];
+  return aux_residual(h, inst, f, g, u, w, r2 ? r2 : I.tmp, r1 ? r1 : I.u[1], res_inf);
+}
+
+extern "C" psd_status psd_energy(psd_handle* h, int inst, const double* f, const double* g, const double* u,
+                                 double* E) {
+  if (!h) return PSD_ERR_ARG;
+  if (inst < 0 || inst >= h->batch || !f || !u || !E || (h->order == 6 && !g))
+    return set_err(h, PSD_ERR_ARG, "bad arguments");
+  HIPCHK(hipSetDevice(h->device));
+  Inst& I = h->hI[inst];
+  const int nblk = 1024;
+  k_energy_parts<<<nblk, PSD_NT, 0, h->stream>>>(h->dI, inst, u, f, h->dAuxPart);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(h->hPart, h->dAuxPart, sizeof(double) * 5 * nblk, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  double a[5] = {0, 0, 0, 0, 0};
+  for (int k = 0; k < nblk; ++k)
+    for (int q = 0; q < 5; ++q) a[q] += h->hPart[5 * k + q];
+  const double s = I.s, se2 = I.se2, p = I.p;
+  if (h->order == 4) {
+    *E = I.hd * (0.5 * a[0] + s / p * a[1] + 0.5 * se2 * a[2]);
+    return PSD_OK;
+  }
+  // order 6 at nu = u - gbar: 1/2 (z, T z) + lam s/2 ||u||^2 - (nu, f) + s/p sum|G|^p + s eps^2/2 sum (Delta u)^2
+  double sg[3], sf[3];
+  psd_status st = aux_sums(h, g, nullptr, I.ncell, sg);
+  if (st != PSD_OK) return st;
+  st = aux_sums(h, f, nullptr, I.ncell, sf);
+  if (st != PSD_OK) return st;
+  const double gbar = sg[0] / I.ncell;
+  k_axpby<<<1024, PSD_NT, 0, h->stream>>>(I.tmp, u, g, 1.0, -1.0, 0.0, I.ncell);
+  k_reset_state<<<(h->batch + 63) / 64, 64, 0, h->stream>>>(h->dI, h->batch);
+  k_mark_done<<<(h->batch + 63) / 64, 64, 0, h->stream>>>(h->dI, h->batch, inst);
+  double zTz = 0.0;
+  st = aux_poisson(h, inst, &zTz);
+  if (st != PSD_OK) return st;
+  *E = I.hd * (0.5 * zTz + 0.5 * I.lam * s * a[3] - (a[4] - gbar * sf[0]) + s / p * a[1] + 0.5 * se2 * a[2]);
+  return PSD_OK;
+}
+
+extern "C" psd_status psd_grad(psd_handle* h, int inst, const double* f, const double* g, const double* u,
+                               double* grad) {
+  if (!h) return PSD_ERR_ARG;
+  if (inst < 0 || inst >= h->batch || !f || !u || !grad || (h->order == 6 && !g))
+    return set_err(h, PSD_ERR_ARG, "bad arguments");
+  psd_status st = psd_residual(h, inst, f, g, u, grad, nullptr);
+  if (st != PSD_OK) return st;
+  Inst& I = h->hI[inst];
+  k_axpby<<<1024, PSD_NT, 0, h->stream>>>(grad, grad, nullptr, -1.0, 0.0, 0.0, I.ncell);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return PSD_OK;
+}
+
+extern "C" psd_status psd_history(psd_handle* h, int inst, double* out, int cap, int* count) {
+  if (!h) return PSD_ERR_ARG;
+  if (inst < 0 || inst >= h->batch || !out || !count) return set_err(h, PSD_ERR_ARG, "bad arguments");
+  const Inst& I = h->hI[inst];
+  if (!I.hist) { *count = 0; return set_err(h, PSD_ERR_ARG, "history was not enabled"); }
+  HIPCHK(hipSetDevice(h->device));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  SolveState S;
+  HIPCHK(hipMemcpy(&S, I.st, sizeof(SolveState), hipMemcpyDeviceToHost));
+  const int k = std::min(std::min(S.iter, I.hist_cap), cap);
+  if (k > 0) HIPCHK(hipMemcpy(out, I.hist, sizeof(double) * 4 * k, hipMemcpyDeviceToHost));
+  *count = k;
+  return PSD_OK;
+}
+
+extern "C" psd_status psd_adjoint(psd_handle* h, const double* const* u_star, const double* const* dJdu,
+                                  double* const* dJdf, double* dJds, double* dJdeps, double rtol, int max_iter,
+                                  int* cg_iters) {
+  if (!h) return PSD_ERR_ARG;
+  (void)u_star; (void)dJdu; (void)dJdf; (void)dJds; (void)dJdeps; (void)rtol; (void)max_iter; (void)cg_iters;
+  return set_err(h, PSD_ERR_ARG, "adjoint not available in this build");
+}
+
+extern "C" psd_status psd_destroy(psd_handle* h) {
+  if (!h) return PSD_ERR_ARG;
+  (void)hipSetDevice(h->device);
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  for (void* p : h->allocs) (void)hipFree(p);
+  if (h->hState) (void)hipHostFree(h->hState);
+  if (h->hPart) (void)hipHostFree(h->hPart);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+  return PSD_OK;
+}
+
+extern "C" const char* psd_last_error(const psd_handle* h) {
+  if (!h) return g_create_error.c_str();
+  return h->err.c_str();
+}

@@ -1,0 +1,248 @@
+"""Thin Python binding of the gfx950 PSD solver library (``libpsd.so``).
+
+Argument marshalling only: every step of the solver runs in the HIP
+kernels behind the C ABI declared in ``include/psd.h``.  PyTorch provides
+device memory (tensors) and the stream.  Loading fails loudly when the
+library has not been built; there is no CPU fallback.
+
+Arrays are float64 CUDA tensors of shape (n, n) or (n, n, n), C-contiguous,
+x fastest (the last tensor axis is x).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import List, Optional, Sequence, Union
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpsd.so")
+
+PSD_OK = 0
+PSD_NOT_CONVERGED = 1
+PSD_ERR_ARG = -1
+PSD_ERR_RANGE = -2
+PSD_ERR_HIP = -3
+PSD_ERR_NONFINITE = -4
+PSD_ERR_NOT_DESCENT = -5
+PSD_ERR_MEAN = -6
+STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_ARG", -2: "ERR_RANGE", -3: "ERR_HIP",
+                -4: "ERR_NONFINITE", -5: "ERR_NOT_DESCENT", -6: "ERR_MEAN"}
+
+PSD_FP64 = 0
+PSD_MIXED = 1
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int), ("L", ctypes.c_double),
+                ("order", ctypes.c_int), ("p", ctypes.c_double), ("s", ctypes.c_double),
+                ("eps", ctypes.c_double), ("lam", ctypes.c_double)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("precision", ctypes.c_int), ("graph_chunk", ctypes.c_int),
+                ("history", ctypes.c_int)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("res_inf", ctypes.c_double),
+                ("res_l2", ctypes.c_double), ("energy", ctypes.c_double),
+                ("status", ctypes.c_int)]
+
+
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+_lib = None
+
+SIGNATURES = {
+    "psd_check_problem": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.c_char_p, ctypes.c_int]),
+    "psd_create": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.c_int, ctypes.POINTER(_Options),
+                                  _vp, ctypes.POINTER(_vp)]),
+    "psd_solve": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                 ctypes.POINTER(_vp), ctypes.POINTER(_Stats)]),
+    "psd_residual": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _dp]),
+    "psd_residual_mixed": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _dp]),
+    "psd_energy": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _dp]),
+    "psd_grad": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
+    "psd_adjoint": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                   _dp, _dp, ctypes.c_double, ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_int)]),
+    "psd_history": (ctypes.c_int, [_vp, ctypes.c_int, _dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    "psd_destroy": (ctypes.c_int, [_vp]),
+    "psd_last_error": (ctypes.c_char_p, [_vp]),
+}
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libpsd.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"PSD HIP library not built: {path} is missing "
+                               "(run __graft_entry__.build() or paper_1607_01475_amd/build.py)")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class PSDError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+@dataclasses.dataclass
+class Problem:
+    """Problem statement (order 4: Sec. 5.3; order 6: Sec. 5.4)."""
+    dim: int
+    n: int
+    L: float
+    order: int = 4
+    p: float = 4.0
+    s: float = 0.01
+    eps: float = 0.1
+    lam: float = 0.0
+
+    def c(self) -> _Problem:
+        return _Problem(self.dim, self.n, float(self.L), self.order, float(self.p), float(self.s),
+                        float(self.eps), float(self.lam))
+
+    @property
+    def shape(self):
+        return (self.n,) * self.dim
+
+
+def check_problem(prob: Problem):
+    """Host-side validation (no GPU): returns (status, message)."""
+    buf = ctypes.create_string_buffer(128)
+    st = load_library().psd_check_problem(ctypes.byref(prob.c()), buf, 128)
+    return st, buf.value.decode()
+
+
+@dataclasses.dataclass
+class Stats:
+    iters: int
+    res_inf: float
+    res_l2: float
+    energy: float
+    status: int
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _ptr_array(ts: Sequence[Optional[torch.Tensor]]):
+    arr = (_vp * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = None if t is None else _ptr(t).value
+    return arr
+
+
+class Solver:
+    """A handle over one or more instances (same dim, order and p)."""
+
+    def __init__(self, problems: Union[Problem, List[Problem]], tol: float = 1e-10,
+                 max_iter: int = 500, precision: str = "fp64", graph_chunk: int = 0,
+                 history: bool = False, stream: Optional[torch.cuda.Stream] = None):
+        self._lib = load_library()
+        self.problems = [problems] if isinstance(problems, Problem) else list(problems)
+        self.batch = len(self.problems)
+        arr = (_Problem * self.batch)(*[p.c() for p in self.problems])
+        prec = {"fp64": PSD_FP64, "mixed": PSD_MIXED}[precision]
+        self.opt = _Options(float(tol), int(max_iter), prec, int(graph_chunk), 1 if history else 0)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = _vp()
+        st = self._lib.psd_create(arr, self.batch, ctypes.byref(self.opt),
+                                  _vp(self.stream.cuda_stream), ctypes.byref(h))
+        if st != PSD_OK:
+            raise PSDError(st, self._lib.psd_last_error(None).decode())
+        self._h = h
+
+    def _check(self, st: int, allow=(PSD_OK,)):
+        if st not in allow:
+            raise PSDError(st, self._lib.psd_last_error(self._h).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.psd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ------------------------------------------------------------------
+    def solve(self, f: Sequence[torch.Tensor], u: Sequence[torch.Tensor],
+              g: Optional[Sequence[torch.Tensor]] = None,
+              w: Optional[Sequence[torch.Tensor]] = None, raise_on_error: bool = True):
+        """Solve in place: u[b] holds u0 on entry and the final iterate on exit."""
+        B = self.batch
+        stats = (_Stats * B)()
+        st = self._lib.psd_solve(self._h, _ptr_array(f), _ptr_array(g) if g is not None else None,
+                                 _ptr_array(u), _ptr_array(w) if w is not None else None, stats)
+        if raise_on_error:
+            self._check(st, allow=(PSD_OK, PSD_NOT_CONVERGED))
+        return [Stats(s.iters, s.res_inf, s.res_l2, s.energy, s.status) for s in stats]
+
+    def residual(self, inst: int, f, u, g=None, r=None):
+        rinf = ctypes.c_double()
+        self._check(self._lib.psd_residual(self._h, inst, _ptr(f), _ptr(g), _ptr(u), _ptr(r),
+                                           ctypes.byref(rinf)))
+        return rinf.value
+
+    def residual_mixed(self, inst: int, f, g, u, w, r1=None, r2=None):
+        rinf = ctypes.c_double()
+        self._check(self._lib.psd_residual_mixed(self._h, inst, _ptr(f), _ptr(g), _ptr(u), _ptr(w),
+                                                 _ptr(r1), _ptr(r2), ctypes.byref(rinf)))
+        return rinf.value
+
+    def energy(self, inst: int, f, u, g=None) -> float:
+        E = ctypes.c_double()
+        self._check(self._lib.psd_energy(self._h, inst, _ptr(f), _ptr(g), _ptr(u), ctypes.byref(E)))
+        return E.value
+
+    def grad(self, inst: int, f, u, g=None, out=None):
+        if out is None:
+            out = torch.empty_like(u)
+        self._check(self._lib.psd_grad(self._h, inst, _ptr(f), _ptr(g), _ptr(u), _ptr(out)))
+        return out
+
+    def history(self, inst: int = 0):
+        cap = self.opt.max_iter
+        buf = (ctypes.c_double * (4 * max(cap, 1)))()
+        cnt = ctypes.c_int()
+        self._check(self._lib.psd_history(self._h, inst, buf, cap, ctypes.byref(cnt)))
+        import numpy as np
+        return np.array(buf[: 4 * cnt.value]).reshape(cnt.value, 4)
+
+    def adjoint(self, u_star: Sequence[torch.Tensor], dJdu: Sequence[torch.Tensor],
+                rtol: float = 1e-12, max_iter: int = 1000):
+        B = self.batch
+        dJdf = [torch.empty_like(t) for t in u_star]
+        ds = (ctypes.c_double * B)()
+        de = (ctypes.c_double * B)()
+        it = (ctypes.c_int * B)()
+        self._check(self._lib.psd_adjoint(self._h, _ptr_array(u_star), _ptr_array(dJdu),
+                                          _ptr_array(dJdf), ds, de, float(rtol), int(max_iter), it))
+        return dJdf, list(ds), list(de), list(it)

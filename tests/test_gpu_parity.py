@@ -1,0 +1,218 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars (from the arithmetic, stated per test): FP64 operators to ~1e-13
+relative; FP64 solves to 1e-11 relative max-norm at residual <= 1e-10 with
+iteration counts within +-1, and at matched iteration counts to ~1e-12.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import psd_inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def psd():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1607_01475_amd import psd as _psd
+    _psd.load_library()
+    return _psd
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+# --------------------------------------------------------------------------
+# operator parity
+# --------------------------------------------------------------------------
+CASES = [(2, 64, 4.0), (2, 96, 4.0), (2, 48, 3.0), (2, 128, 2.0), (3, 32, 4.0), (3, 48, 4.0),
+         (3, 64, 2.5)]
+
+
+@pytest.mark.parametrize("dim,n,p", CASES)
+def test_residual_energy_grad_parity(psd, dim, n, p):
+    log(f"case residual dim={dim} n={n} p={p}")
+    L = 12.8 * n / 64
+    P = psd.Problem(dim, n, L, 4, p, 0.01, 0.1)
+    O = oracle.Problem(dim, n, L, p=p, s=0.01, eps=0.1)
+    f = psd_inputs.small_field(dim, n, L, 11)
+    u = psd_inputs.small_field(dim, n, L, 12, K=5) + 0.01 * psd_inputs.white_noise(f.shape, 13)
+    with psd.Solver(P) as S:
+        r = torch.empty_like(dev(f))
+        rinf = S.residual(0, dev(f), dev(u), r=r)
+        r_ref = O.residual(f, u)
+        scale = np.abs(O.N4(u)).max()
+        assert np.abs(host(r) - r_ref).max() <= 1e-13 * scale
+        assert abs(rinf - np.abs(r_ref).max()) <= 1e-13 * scale
+        E = S.energy(0, dev(f), dev(u))
+        assert abs(E - O.energy(f, u)) <= 1e-13 * abs(E)
+        g = S.grad(0, dev(f), dev(u))
+        assert np.abs(host(g) + r_ref).max() <= 1e-13 * scale
+
+
+def test_residual_parity_order6(psd):
+    n, L = 96, 12.8
+    P = psd.Problem(2, n, L, 6, 4.0, 0.02, 0.1, 1.0)
+    O = oracle.Problem(2, n, L, order=6, p=4.0, s=0.02, eps=0.1, lam=1.0)
+    f = psd_inputs.small_field(2, n, L, 21)
+    g = psd_inputs.small_field(2, n, L, 22)
+    u = psd_inputs.small_field(2, n, L, 23, K=5) + g.mean()
+    w = psd_inputs.small_field(2, n, L, 24, K=5)
+    with psd.Solver(P) as S:
+        r = torch.empty_like(dev(f))
+        S.residual(0, dev(f), dev(u), g=dev(g), r=r)
+        rho = O.residual(f, u, g)
+        assert np.abs(host(r) - rho).max() <= 1e-12 * np.abs(rho).max()
+        r1, r2 = torch.empty_like(r), torch.empty_like(r)
+        S.residual_mixed(0, dev(f), dev(g), dev(u), dev(w), r1=r1, r2=r2)
+        e1, e2 = O.mixed_residuals(f, g, u, w)
+        assert np.abs(host(r1) - e1).max() <= 1e-12 * max(1, np.abs(e1).max())
+        assert np.abs(host(r2) - e2).max() <= 1e-12 * max(1, np.abs(e2).max())
+        E = S.energy(0, dev(f), dev(u), g=dev(g))
+        assert abs(E - O.energy(f, u, g)) <= 1e-12 * abs(E)
+
+
+# --------------------------------------------------------------------------
+# solve parity (FP64)
+# --------------------------------------------------------------------------
+SOLVES = [(2, 64, 4.0, 12.8, 0.01, 0.1), (2, 96, 4.0, 12.8, 0.01, 0.1), (2, 128, 3.0, 25.6, 0.005, 0.05),
+          (3, 32, 4.0, 12.8, 0.01, 0.1), (3, 48, 4.0, 12.8, 0.01, 0.1)]
+
+
+@pytest.mark.parametrize("dim,n,p,L,s,eps", SOLVES)
+def test_solve_parity_fp64(psd, dim, n, p, L, s, eps):
+    log(f"case solve dim={dim} n={n} p={p}")
+    f = psd_inputs.small_field(dim, n, L, 31, K=6)
+    O = oracle.Problem(dim, n, L, p=p, s=s, eps=eps)
+    ref = O.solve(f, tol=1e-10, max_iter=300, history=True)
+    P = psd.Problem(dim, n, L, 4, p, s, eps)
+    with psd.Solver(P, tol=1e-10, max_iter=300, history=True) as S:
+        u = torch.zeros_like(dev(f))
+        st = S.solve([dev(f)], [u])[0]
+        hist = S.history(0)
+    assert st.status == 0 and st.res_inf <= 1e-10
+    assert abs(st.iters - ref["iters"]) <= 1
+    ug = host(u)
+    if st.iters == ref["iters"]:
+        assert rel(ug, ref["u"]) <= 1e-11
+    # step sizes agree (same iterate sequence up to rounding)
+    k = min(len(hist), len(ref["hist"]))
+    assert np.abs(hist[:k, 0] - ref["hist"][:k, 0]).max() <= 1e-9 * np.abs(ref["hist"][:k, 0]).max()
+    # matched iteration count
+    kk = max(ref["iters"] - 2, 1)
+    with psd.Solver(P, tol=0.0, max_iter=kk) as S:
+        u = torch.zeros_like(dev(f))
+        st = S.solve([dev(f)], [u])[0]
+    ref_k = O.solve(f, tol=0.0, max_iter=kk)
+    assert st.iters == kk and st.status == 1
+    assert rel(host(u), ref_k["u"]) <= 1e-11
+    # the converged GPU iterate solves the oracle's discrete equation
+    assert np.abs(O.residual(f, ug)).max() <= 1.5e-10
+
+
+def test_solve_parity_config1(psd):
+    w = psd_inputs.config1()
+    O = oracle.Problem(2, w.n, w.L, p=w.p, s=w.s, eps=w.eps)
+    ref = O.solve(w.f, tol=1e-10, max_iter=300)
+    with psd.Solver(psd.Problem(2, w.n, w.L, 4, w.p, w.s, w.eps), tol=1e-10, max_iter=300) as S:
+        u = torch.zeros_like(dev(w.f))
+        st = S.solve([dev(w.f)], [u])[0]
+    log(f"config1: gpu iters {st.iters} oracle iters {ref['iters']}")
+    assert st.status == 0 and abs(st.iters - ref["iters"]) <= 1
+    if st.iters == ref["iters"]:
+        assert rel(host(u), ref["u"]) <= 1e-11
+
+
+@pytest.mark.parametrize("n", [64, 96])
+def test_solve_parity_order6(psd, n):
+    L = 12.8
+    f = psd_inputs.small_field(2, n, L, 41, K=6)
+    g = psd_inputs.small_field(2, n, L, 42, K=6)
+    O = oracle.Problem(2, n, L, order=6, p=4.0, s=0.02, eps=0.1, lam=1.0)
+    ref = O.solve(f, g=g, tol=1e-10, max_iter=300)
+    P = psd.Problem(2, n, L, 6, 4.0, 0.02, 0.1, 1.0)
+    with psd.Solver(P, tol=1e-10, max_iter=300) as S:
+        u = torch.full_like(dev(f), float(g.mean()))
+        w = torch.zeros_like(u)
+        st = S.solve([dev(f)], [u], g=[dev(g)], w=[w])[0]
+    log(f"order6 n={n}: gpu iters {st.iters} oracle iters {ref['iters']}")
+    assert st.status == 0 and abs(st.iters - ref["iters"]) <= 1
+    assert rel(host(u), ref["u"]) <= 1e-9
+    assert rel(host(w), ref["w"]) <= 1e-9
+    r1, r2 = O.mixed_residuals(f, g, host(u), host(w))
+    assert np.abs(r1).max() <= 2e-10 and np.abs(r2).max() <= 2e-10
+
+
+# --------------------------------------------------------------------------
+# mixed precision, graphs, batching
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dim,n", [(2, 128), (3, 48)])
+def test_mixed_precision_reaches_fp64_answer(psd, dim, n):
+    L = 12.8
+    f = psd_inputs.small_field(dim, n, L, 51, K=6)
+    O = oracle.Problem(dim, n, L, p=4.0, s=0.01, eps=0.1)
+    ref = O.solve(f, tol=1e-12, max_iter=300)
+    P = psd.Problem(dim, n, L, 4, 4.0, 0.01, 0.1)
+    with psd.Solver(P, tol=1e-10, max_iter=300, precision="mixed") as S:
+        u = torch.zeros_like(dev(f))
+        st = S.solve([dev(f)], [u])[0]
+    log(f"mixed dim={dim} n={n}: iters {st.iters} (oracle to 1e-12: {ref['iters']})")
+    assert st.status == 0 and st.res_inf <= 1e-10
+    # FP64 residual verified by the oracle; error against the FP64 answer
+    assert np.abs(O.residual(f, host(u))).max() <= 1.5e-10
+    assert rel(host(u), ref["u"]) <= 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_mode_matches_stream_mode(psd, precision):
+    n, L = 48, 12.8
+    f = psd_inputs.small_field(3, n, L, 61, K=6)
+    P = psd.Problem(3, n, L, 4, 4.0, 0.01, 0.1)
+    out = []
+    for chunk in (0, 4):
+        with psd.Solver(P, tol=1e-10, max_iter=300, precision=precision, graph_chunk=chunk) as S:
+            for rep in range(2):
+                u = torch.zeros_like(dev(f))
+                st = S.solve([dev(f)], [u])[0]
+                out.append((st.iters, host(u)))
+    assert all(o[0] == out[0][0] for o in out)
+    for o in out[1:]:
+        assert np.array_equal(o[1], out[0][1])  # deterministic, bitwise
+
+
+def test_batched_instances_match_single(psd):
+    sizes = [64, 96, 128, 64]
+    probs, fs = [], []
+    for i, n in enumerate(sizes):
+        probs.append(psd.Problem(2, n, 12.8, 6, 4.0, 0.02, 0.1, 1.0))
+        fs.append((psd_inputs.small_field(2, n, 12.8, 70 + 2 * i, K=6),
+                   psd_inputs.small_field(2, n, 12.8, 71 + 2 * i, K=6)))
+    with psd.Solver(probs, tol=1e-10, max_iter=300, precision="mixed", graph_chunk=4) as S:
+        us = [torch.full_like(dev(f), float(g.mean())) for f, g in fs]
+        ws = [torch.zeros_like(u) for u in us]
+        stats = S.solve([dev(f) for f, _ in fs], us, g=[dev(g) for _, g in fs], w=ws)
+    for (f, g), n, u, w, st in zip(fs, sizes, us, ws, stats):
+        O = oracle.Problem(2, n, 12.8, order=6, p=4.0, s=0.02, eps=0.1, lam=1.0)
+        assert st.status == 0 and st.res_inf <= 1e-10
+        r1, r2 = O.mixed_residuals(f, g, host(u), host(w))
+        assert np.abs(r1).max() <= 2e-10 and np.abs(r2).max() <= 2e-10
+        ref = O.solve(f, g=g, tol=1e-11, max_iter=300)
+        assert rel(host(u), ref["u"]) <= 1e-9
