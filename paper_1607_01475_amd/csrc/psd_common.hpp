@@ -57,6 +57,7 @@ struct SolveState {
   int ls_evals;
   int newton_steps;
   double dE;           // energy decrease of the last step (p = 4)
+  double mean[3];      // order 6: means of d, e1, e2 removed in the update
   int pad[2];
 };
 
@@ -84,8 +85,10 @@ struct Inst {
   double* part_res;    // residual partials: 2 per block (max|r|, sum r^2)
   double* part_ls;     // line-search partials: 8 per block
   double* part_sp;     // spectral partials: 2 per block
+  double* part_c2r;    // sums of the inverse-transform outputs: 3 per block
   double* hist;        // 4 per update (may be null)
   int nblk_res, nblk_ls, nblk_sp, hist_cap;
+  int nblk_c2r, pad1;
 };
 
 // A block's unit of work: instance and up to three integer coordinates.

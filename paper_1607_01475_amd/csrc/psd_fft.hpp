@@ -274,9 +274,10 @@ __device__ __forceinline__ void r2c_rows(const RowArgs<T>& A, long long row0, cx
   }
 }
 
+// fsum[f] accumulates the sum of the values written to output field f
 template <typename T, typename TOUT, int N, int NL>
 __device__ __forceinline__ void c2r_rows(const RowArgs<T>& A, long long row0, cx<T>* buf,
-                                         const cx<T>* tw) {
+                                         const cx<T>* tw, double (&fsum)[3]) {
   constexpr int LS = N + 1;
   constexpr int NC = N / 2 + 1;
   for (int e = threadIdx.x; e < NL * NC; e += PSD_NT) {
@@ -305,7 +306,12 @@ __device__ __forceinline__ void c2r_rows(const RowArgs<T>& A, long long row0, cx
     const long long row = gr - (long long)fld * A.rpf;
     const T* src = (const T*)(buf + (rr >> 1) * LS + col);
     TOUT* dst = (TOUT*)A.out(fld);
-    dst[row * N + col] = (TOUT)src[rr & 1];
+    const TOUT val = (TOUT)src[rr & 1];
+    dst[row * N + col] = val;
+    const double dv = (double)val;
+    fsum[0] += fld == 0 ? dv : 0.0;
+    fsum[1] += fld == 1 ? dv : 0.0;
+    fsum[2] += fld == 2 ? dv : 0.0;
   }
 }
 

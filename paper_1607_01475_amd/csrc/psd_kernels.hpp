@@ -180,6 +180,20 @@ __global__ __launch_bounds__(PSD_NT) void k_ls_finalize(const Inst* __restrict__
       acc[9] += I.part_sp[2 * b + 1];
     }
   block_reduce<10, 0>(acc, scratch);
+  if (I.order == 6 && mode != 2) {
+    // means of d, e1, e2 (FP32 round-off of the inverse transform leaves a
+    // tiny mean that the preconditioner never corrects); the update removes them
+    double ms[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < I.nblk_c2r; b += PSD_NT)
+      for (int q = 0; q < 3; ++q) ms[q] += I.part_c2r[3 * b + q];
+    block_reduce<3, 0>(ms, scratch);
+    if (threadIdx.x == 0) {
+      for (int q = 0; q < 3; ++q) st->mean[q] = ms[q] * I.inv_ntot;
+      // sum (d - dbar)^2 = sum d^2 - N dbar^2
+      const double corr = (double)I.ncell * st->mean[0] * st->mean[0];
+      if (mode == 0) acc[4] -= corr; else acc[2] -= corr;
+    }
+  }
   if (threadIdx.x != 0) return;
   const double s = I.s, se2 = I.se2;
   if (mode == 0) {
@@ -278,15 +292,22 @@ __global__ __launch_bounds__(PSD_NT) void k_rows(const Inst* __restrict__ insts,
   cx<T>* buf = (cx<T>*)smem;
   const cx<T>* tw = (const cx<T>*)(sizeof(T) == 8 ? I.tw64 : I.tw32);
   RowArgs<T> A = row_args<T>(I, t.b, (cx<T>*)I.spec, t.c);
+  double fsum[3] = {0.0, 0.0, 0.0};
   switch (I.n) {
 #define PSD_ROW_CASE(NN)                                                               \
     case NN:                                                                           \
       if (FWD) r2c_rows<T, TIO, NN, row_lines<T, NN>()>(A, t.a, buf, tw);              \
-      else c2r_rows<T, TIO, NN, row_lines<T, NN>()>(A, t.a, buf, tw);                  \
+      else c2r_rows<T, TIO, NN, row_lines<T, NN>()>(A, t.a, buf, tw, fsum);            \
       break;
     PSD_FOR_EACH_N(PSD_ROW_CASE)
 #undef PSD_ROW_CASE
     default: break;
+  }
+  if (!FWD && solver && I.order == 6) {
+    __syncthreads();
+    block_reduce<3, 0>(fsum, smem);
+    if (threadIdx.x == 0)
+      for (int q = 0; q < 3; ++q) I.part_c2r[3 * t.slot + q] = fsum[q];
   }
 }
 
@@ -531,6 +552,7 @@ __global__ void k_reset_state(const Inst* __restrict__ insts, int ninst) {
   st->alpha = 0.0; st->rinf = 0.0; st->rl2 = 0.0;
   for (int k = 0; k < 4; ++k) st->c[k] = 0.0;
   st->iter = 0; st->done = 0; st->status = 0; st->ls_phase = 0; st->dE = 0.0;
+  st->mean[0] = st->mean[1] = st->mean[2] = 0.0;
 }
 
 }  // namespace psd

@@ -171,11 +171,13 @@ static void build_fft_tasks(psd_handle* h, FftTasks& F, int nfi, int nfo, bool w
       const Inst& I = h->hI[b];
       const int nl = host_row_lines<T>(I.n);
       const long long rows = (long long)nf * (I.ncell / I.n);
+      int slot = 0;
       for (long long r0 = 0; r0 < rows; r0 += 2 * nl) {
         Task2 t{};
-        t.inst = b; t.a = (int)r0; t.b = pass == 0 ? fs_in : fs_out; t.c = nf;
+        t.inst = b; t.a = (int)r0; t.b = pass == 0 ? fs_in : fs_out; t.c = nf; t.slot = slot++;
         h->hT.push_back(t);
       }
+      if (pass == 1 && with_slots) h->hI[b].nblk_c2r = slot;
       R.lds = std::max(R.lds, (size_t)nl * (I.n + 1) * cxs);
     }
     R.cnt = (int)h->hT.size() - R.off;
@@ -538,7 +540,7 @@ extern "C" psd_status psd_create(const psd_problem* probs, int batch, const psd_
     }
     const int nsp_max = std::max(nsp[b], aux_sp);
     if (dalloc(h, &I.part_res, (size_t)I.nblk_res * 2 * 8) || dalloc(h, &I.part_ls, (size_t)I.nblk_ls * 8 * 8) ||
-        dalloc(h, &I.part_sp, (size_t)nsp_max * 2 * 8))
+        dalloc(h, &I.part_sp, (size_t)nsp_max * 2 * 8) || dalloc(h, &I.part_c2r, (size_t)I.nblk_c2r * 3 * 8))
       return fail("out of device memory");
     I.st = h->dState + b;
   }

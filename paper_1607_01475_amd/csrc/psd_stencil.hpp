@@ -43,6 +43,8 @@ __device__ void res2d_tile(const Inst& I, int x0, int y0, double* lds, double (&
   const SolveState* st = I.st;
   const int cur = st->iter & 1;
   const double alpha = UPD ? st->alpha : 0.0;
+  // order 6: d, e1, e2 are mean-zero in exact arithmetic; remove the round-off mean
+  const double dbar = (ORDER == 6) ? st->mean[0] : 0.0;
   const double* __restrict__ u = I.u[cur];
   const TD* __restrict__ d = (const TD*)I.d;
   double* v = lds;
@@ -57,10 +59,11 @@ __device__ void res2d_tile(const Inst& I, int x0, int y0, double* lds, double (&
     const int gx = posmod(x0 - 2 + ex, n), gy = posmod(y0 - 2 + ey, n);
     const long long gi = gx + (long long)n * gy;
     double val = u[gi];
-    if (UPD) val += alpha * (double)d[gi];
+    if (UPD) val += alpha * ((double)d[gi] - dbar);
     v[e] = val;
   }
   if (ORDER == 6) {
+    const double e1bar = st->mean[1], e2bar = st->mean[2];
     const double* __restrict__ w = I.w[cur];
     const TD* __restrict__ e1 = (const TD*)I.e1;
     const TD* __restrict__ e2 = (const TD*)I.e2;
@@ -69,7 +72,7 @@ __device__ void res2d_tile(const Inst& I, int x0, int y0, double* lds, double (&
       const int gx = posmod(x0 - 1 + ex, n), gy = posmod(y0 - 1 + ey, n);
       const long long gi = gx + (long long)n * gy;
       double val = w[gi];
-      if (UPD) val += (double)e1[gi] - alpha * (double)e2[gi];
+      if (UPD) val += ((double)e1[gi] - e1bar) - alpha * ((double)e2[gi] - e2bar);
       wl[e] = val;
     }
   }
