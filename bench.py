@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Benchmark of the gfx950 PSD solver on the 3D p=4 workload (256^3).
+
+One step = one complete PSD solve (residual -> FFT preconditioner -> line
+search -> update, repeated until ||f - N_h[u]||_inf <= 1e-10) from u0 = 0 on
+a seeded synthetic right-hand side shaped like the paper's thin-film
+workloads.  Two forms are timed: the plain FP64 GPU form (host-driven loop)
+and the mixed-precision graph-captured form (FP32 FFT preconditioner, FP64
+residual/line search/update, 4 iterations per HIP graph replay).  `value` is
+the PSD iterations per second of the mixed graph form; both forms'
+time-to-1e-10 are reported.
+
+Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(pass_name: str, n: int, dim: int, mixed: bool) -> float:
+    """Algorithmic HBM bytes of one launch of a pass (one instance).
+
+    Every field is read or written once per launch; spectra are half
+    spectra of nc = n/2+1 complex per x-row."""
+    N = n ** dim
+    nc = n // 2 + 1
+    spec = nc * n ** (dim - 1)
+    fr = 4 if mixed else 8           # residual copy / direction element
+    cs = 8 if mixed else 16          # spectrum element
+    table = {
+        "rows_r2c": fr * N + cs * spec,
+        "cols_fwd": 2 * cs * spec,
+        "cols_fused": 2 * cs * spec,
+        "cols_inv": 2 * cs * spec,
+        "rows_c2r": cs * spec + fr * N,
+        "ls": 8 * N + fr * N,
+        "res": 8 * N + fr * N + 8 * N + 8 * N + fr * N,  # read u, d, f; write u, r
+    }
+    return float(table.get(pass_name, 0.0))
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in ("psd_common.hpp", "psd_fft.hpp", "psd_stencil.hpp", "psd_kernels.hpp", "psd_lib.hip"):
+        with open(os.path.join(ROOT, "paper_1607_01475_amd", "csrc", rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel: str, workload: str):
+    """HBM bytes per launch from committed rocprofv3 --pmc counters, or None
+    when they are missing or were taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+        rec = data.get(f"{workload}:{kernel}")
+        if not rec or rec.get("source_hash") != source_hash():
+            return None
+        return float(rec["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def run_form(psd, torch, P, f, precision, chunk, steps, warmup, tol=1e-10):
+    S = psd.Solver(P, tol=tol, max_iter=500, precision=precision, graph_chunk=chunk, profile=True)
+    fd = f
+    u = torch.zeros_like(fd)
+    for _ in range(warmup):
+        u.zero_()
+        S.solve([fd], [u])
+    torch.cuda.synchronize()
+    times, iters = [], []
+    agg = {}
+    for _ in range(steps):
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = S.solve([fd], [u])[0]
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        iters.append(st.iters)
+        if st.status != 0:
+            raise RuntimeError(f"solve did not converge: {st}")
+        for k, (ms, cnt) in S.pass_times().items():
+            a = agg.setdefault(k, [0.0, 0])
+            a[0] += ms
+            a[1] += cnt
+    S.close()
+    return dict(times=times, iters=iters, passes=agg, u=u.clone(), res_inf=st.res_inf)
+
+
+def cpu_baseline(f_np, n, L, p, s, eps):
+    """Time one PSD iteration of the plain FP64 CPU oracle on the same
+    256^3 workload: preconditioner application, line-search coefficients and
+    the residual of the updated iterate (the three steps of one iteration)."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    O = oracle.Problem(3, n, L, p=p, s=s, eps=eps)
+    u = np.zeros_like(f_np)
+    r = O.residual(f_np, u)          # state at the start of the iteration (not timed)
+    t0 = time.perf_counter()
+    d = O.precond(r)
+    c = O.ls_coeffs4(u, d, r)
+    alpha, _ = oracle.root_cubic(c)
+    u = u + alpha * d
+    r = O.residual(f_np, u)
+    dt = time.perf_counter() - t0
+    return dict(value=1.0 / dt, unit="PSD iters/s", cores=1, kind="oracle",
+                sample=f"one PSD iteration (preconditioner, line-search coefficients, update and "
+                       f"residual) of the single-threaded C oracle at {n}^3, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="fp64,mixed")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this solver runs on one GPU; multi-GPU runs are not part of "
+                                   "this build (run with --gpus 1)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import psd_inputs
+    from paper_1607_01475_amd import psd
+
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    psd.load_library()
+    w = psd_inputs.config3(args.n)
+    log(f"bench: workload {w.name} n={w.n} p={w.p} s={w.s} eps={w.eps}")
+    f = torch.from_numpy(w.f).to("cuda")
+    P = psd.Problem(3, w.n, w.L, 4, w.p, w.s, w.eps)
+
+    res = {}
+    forms = args.forms.split(",")
+    if "fp64" in forms:
+        log("bench: FP64 form (host-driven loop)")
+        res["fp64"] = run_form(psd, torch, P, f, "fp64", 0, args.steps, args.warmup)
+    if "mixed" in forms:
+        log("bench: mixed form (FP32 FFT, FP64 residual, HIP graph chunk 4)")
+        res["mixed"] = run_form(psd, torch, P, f, "mixed", 4, args.steps, args.warmup)
+    head = res.get("mixed", res.get("fp64"))
+    head_mixed = "mixed" in res
+    t_med = float(np.median(head["times"]))
+    it_med = float(np.median(head["iters"]))
+    total_t = float(np.sum(head["times"]))
+    total_it = float(np.sum(head["iters"]))
+    value = total_it / total_t
+
+    # dominant kernel of the headline form and its roofline
+    passes = head["passes"]
+    dom = max((k for k in passes if kernel_bytes(k, w.n, 3, head_mixed) > 0),
+              key=lambda k: passes[k][0])
+    ms_tot, cnt = passes[dom]
+    avg_s = ms_tot / 1e3 / max(cnt, 1)
+    nbytes = kernel_bytes(dom, w.n, 3, head_mixed)
+    achieved = nbytes / avg_s / 1e9
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": traffic_for(dom, "c3_256"),
+            "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": nbytes}
+    per_pass = {k: {"avg_us": round(v[0] * 1e3 / max(v[1], 1), 2), "launches": v[1],
+                    "GBps": round(kernel_bytes(k, w.n, 3, head_mixed) / (v[0] / 1e3 / max(v[1], 1)) / 1e9, 1)
+                    if v[1] and kernel_bytes(k, w.n, 3, head_mixed) else None}
+                for k, v in passes.items()}
+
+    extra = {}
+    if "fp64" in res and "mixed" in res:
+        ua, ub = res["fp64"]["u"], res["mixed"]["u"]
+        extra["mixed_vs_fp64_rel_err"] = float((ub - ua).abs().max() / ua.abs().max())
+        extra["speedup_time_to_tol"] = float(np.median(res["fp64"]["times"]) / t_med)
+    for k, r in res.items():
+        extra[f"{k}_time_to_1e-10_ms"] = round(1e3 * float(np.median(r["times"])), 3)
+        extra[f"{k}_iters"] = int(np.median(r["iters"]))
+        extra[f"{k}_iters_per_s"] = round(float(np.sum(r["iters"]) / np.sum(r["times"])), 2)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("bench: CPU oracle baseline (one iteration at full size)")
+        cpu = cpu_baseline(w.f, w.n, w.L, w.p, w.s, w.eps)
+
+    out = {
+        "metric": "time-to-1e-10 residual & PSD iters/s, 256³ p=4: mixed/batched vs FP64 GPU",
+        "value": round(value, 3),
+        "unit": "PSD iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * t_med, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 (f32 FFT preconditioner)" if head_mixed else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"3D fourth-order PSD, p=4, {w.n}^3, [0,12.8]^3, s=0.01, eps=0.1, "
+                               f"tol 1e-10, seeded Fourier field |k|<=12",
+                   "form": "mixed precision + HIP graph (chunk 4)" if head_mixed else "fp64",
+                   "iters_per_solve": it_med},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "passes": per_pass,
+        **extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

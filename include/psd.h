@@ -78,13 +78,16 @@ enum { PSD_FP64 = 0, PSD_MIXED = 1 };
  *   graph_chunk 0: host-driven loop, the host reads the convergence flag
  *               after every iteration.  k > 0: k iterations are captured once
  *               in a HIP graph and replayed until the device flag says done
- *   history     non-zero: record per-update (alpha, ||r||_inf, ||r||_2, dE) */
+ *   history     non-zero: record per-update (alpha, ||r||_inf, ||r||_2, dE)
+ *   profile     non-zero: per-pass kernel timing of psd_solve (psd_pass_times) */
 typedef struct {
     double tol;
     int max_iter;
     int precision;
     int graph_chunk;
     int history;
+    int profile;   /* non-zero: time every kernel launch with HIP events on the
+                      solver stream (see psd_pass_times) */
 } psd_options;
 
 /* Per-instance result.  energy is E_h at the final iterate (Sec. 5.3 and
@@ -158,6 +161,27 @@ psd_status psd_adjoint(psd_handle* h, const double* const* u_star, const double*
  * decrease (order 4, p = 4; else 0).  Copies min(cap, iters) records to host
  * memory and returns their number in *count. */
 psd_status psd_history(psd_handle* h, int inst, double* out, int cap, int* count);
+
+/* Kernel passes of one PSD iteration, in launch order (psd_pass_times). */
+enum {
+    PSD_PASS_ROWS_R2C = 0,   /* x-axis real-to-complex rows */
+    PSD_PASS_COLS_FWD = 1,   /* y-axis forward columns (3D) */
+    PSD_PASS_COLS_FUSED = 2, /* last axis: forward, 1/sigma, inverse */
+    PSD_PASS_COLS_INV = 3,   /* y-axis inverse columns (3D) */
+    PSD_PASS_ROWS_C2R = 4,   /* x-axis complex-to-real rows -> d */
+    PSD_PASS_LS = 5,         /* line-search sums */
+    PSD_PASS_LS_FIN = 6,     /* line-search reduction and root */
+    PSD_PASS_RES = 7,        /* update + residual */
+    PSD_PASS_RES_FIN = 8,    /* residual reduction and stop test */
+    PSD_NPASS = 9
+};
+
+/* Per-pass kernel time of the last psd_solve made with options.profile set:
+ * ms[k] = summed duration (HIP events on the solver stream) of the launches
+ * of pass k that did work, launches[k] = their number; launches after
+ * convergence (early exits inside a replayed graph) are excluded.  Arrays
+ * of PSD_NPASS entries, host memory. */
+psd_status psd_pass_times(psd_handle* h, double* ms, int* launches);
 
 /* Destroy the handle and free its workspace. */
 psd_status psd_destroy(psd_handle* h);

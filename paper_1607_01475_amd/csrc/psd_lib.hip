@@ -99,6 +99,14 @@ struct psd_handle_s {
   hipGraph_t graph = nullptr;
   int gchunk = 0;
   std::string err;
+  // profiling: events around every pass launch, in launch order
+  struct ProfRec { int pass; int iter_slot; hipEvent_t a, b; };
+  std::vector<ProfRec> prof;        // records of the current launch sequence
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  int prof_iter_slot = -1;          // iteration index within a graph chunk (-1: none)
+  double pass_ms[PSD_NPASS] = {0};
+  int pass_n[PSD_NPASS] = {0};
 };
 
 // ---------------------------------------------------------------------------
@@ -127,6 +135,49 @@ static hipError_t dalloc(psd_handle* h, P** ptr, size_t bytes) {
     *ptr = (P*)p;
   }
   return e;
+}
+
+// ---------------------------------------------------------------------------
+// per-pass profiling with HIP events on the solver stream
+// ---------------------------------------------------------------------------
+static hipEvent_t prof_event(psd_handle* h) {
+  if (h->ev_used == h->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->ev_pool.push_back(e);
+  }
+  return h->ev_pool[h->ev_used++];
+}
+
+struct ProfScope {
+  psd_handle* h;
+  int pass;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(psd_handle* hh, int p) : h(hh), pass(p) {
+    if (!h->opt.profile || pass < 0) return;
+    a = prof_event(h);
+    b = prof_event(h);
+    if (a && b) (void)hipEventRecord(a, h->stream);
+  }
+  ~ProfScope() {
+    if (!h->opt.profile || pass < 0 || !a || !b) return;
+    (void)hipEventRecord(b, h->stream);
+    h->prof.push_back({pass, h->prof_iter_slot, a, b});
+  }
+};
+
+// Fold the recorded events into the per-pass totals (stream synchronised).
+// iters_real: number of leading graph iterations that did work (-1: all).
+static void prof_collect(psd_handle* h, int iters_real, bool keep_records) {
+  for (const auto& r : h->prof) {
+    if (iters_real >= 0 && r.iter_slot >= iters_real) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      h->pass_ms[r.pass] += ms;
+      h->pass_n[r.pass] += 1;
+    }
+  }
+  if (!keep_records) { h->prof.clear(); h->ev_used = 0; }
 }
 
 extern "C" psd_status psd_check_problem(const psd_problem* prob, char* msg, int msg_len) {
@@ -262,25 +313,35 @@ static void run_fft(psd_handle* h, const FftTasks& F, int op, bool solver) {
   const Task2* dT = h->dT;
   hipStream_t s = h->stream;
   const int sv = solver ? 1 : 0;
-  if (F.r2c.cnt)
+  const bool pr = solver;  // auxiliary transforms are not profiled
+  if (F.r2c.cnt) {
+    ProfScope ps(h, pr ? PSD_PASS_ROWS_R2C : -1);
     k_rows<T, TIN, true><<<F.r2c.cnt, PSD_NT, F.r2c.lds, s>>>(h->dI, dT + F.r2c.off, sv);
+  }
   const int nfi = op == OP_PRECOND6 ? 2 : 1, nfo = op == OP_PRECOND6 ? 3 : 1;
   if (F.coly_f.cnt) {
+    ProfScope ps(h, pr ? PSD_PASS_COLS_FWD : -1);
     if (nfi == 1) k_cols<T, 1, -1><<<F.coly_f.cnt, PSD_NT, F.coly_f.lds, s>>>(h->dI, dT + F.coly_f.off, 1, sv);
     else k_cols<T, 2, -1><<<F.coly_f.cnt, PSD_NT, F.coly_f.lds, s>>>(h->dI, dT + F.coly_f.off, 1, sv);
   }
-  if (op == OP_PRECOND4)
-    k_cols_fused<T, OP_PRECOND4><<<F.colz.cnt, PSD_NT, F.colz.lds, s>>>(h->dI, dT + F.colz.off, sv);
-  else if (op == OP_PRECOND6)
-    k_cols_fused<T, OP_PRECOND6><<<F.colz.cnt, PSD_NT, F.colz.lds, s>>>(h->dI, dT + F.colz.off, sv);
-  else
-    k_cols_fused<T, OP_POISSON><<<F.colz.cnt, PSD_NT, F.colz.lds, s>>>(h->dI, dT + F.colz.off, sv);
+  {
+    ProfScope ps(h, pr ? PSD_PASS_COLS_FUSED : -1);
+    if (op == OP_PRECOND4)
+      k_cols_fused<T, OP_PRECOND4><<<F.colz.cnt, PSD_NT, F.colz.lds, s>>>(h->dI, dT + F.colz.off, sv);
+    else if (op == OP_PRECOND6)
+      k_cols_fused<T, OP_PRECOND6><<<F.colz.cnt, PSD_NT, F.colz.lds, s>>>(h->dI, dT + F.colz.off, sv);
+    else
+      k_cols_fused<T, OP_POISSON><<<F.colz.cnt, PSD_NT, F.colz.lds, s>>>(h->dI, dT + F.colz.off, sv);
+  }
   if (F.coly_i.cnt) {
+    ProfScope ps(h, pr ? PSD_PASS_COLS_INV : -1);
     if (nfo == 1) k_cols<T, 1, 1><<<F.coly_i.cnt, PSD_NT, F.coly_i.lds, s>>>(h->dI, dT + F.coly_i.off, 1, sv);
     else k_cols<T, 3, 1><<<F.coly_i.cnt, PSD_NT, F.coly_i.lds, s>>>(h->dI, dT + F.coly_i.off, 1, sv);
   }
-  if (F.c2r.cnt)
+  if (F.c2r.cnt) {
+    ProfScope ps(h, pr ? PSD_PASS_ROWS_C2R : -1);
     k_rows<T, TOUT, false><<<F.c2r.cnt, PSD_NT, F.c2r.lds, s>>>(h->dI, dT + F.c2r.off, sv);
+  }
 }
 
 template <typename TD, typename TR>
@@ -288,18 +349,22 @@ static void run_residual(psd_handle* h, bool upd) {
   hipStream_t s = h->stream;
   const Task2* t = h->dT + h->res.off;
   const int n = h->res.cnt;
-  if (h->dim == 2) {
-    if (h->order == 4) {
-      if (upd) k_res2d<TD, TR, 4, true><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
-      else k_res2d<TD, TR, 4, false><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
+  {
+    ProfScope ps(h, upd ? PSD_PASS_RES : -1);
+    if (h->dim == 2) {
+      if (h->order == 4) {
+        if (upd) k_res2d<TD, TR, 4, true><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
+        else k_res2d<TD, TR, 4, false><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
+      } else {
+        if (upd) k_res2d<TD, TR, 6, true><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
+        else k_res2d<TD, TR, 6, false><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
+      }
     } else {
-      if (upd) k_res2d<TD, TR, 6, true><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
-      else k_res2d<TD, TR, 6, false><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
+      if (upd) k_res3d<TD, TR, true><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
+      else k_res3d<TD, TR, false><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
     }
-  } else {
-    if (upd) k_res3d<TD, TR, true><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
-    else k_res3d<TD, TR, false><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
   }
+  ProfScope ps(h, upd ? PSD_PASS_RES_FIN : -1);
   k_res_finalize<<<h->batch, PSD_NT, 0, s>>>(h->dI, upd ? 1 : 0);
 }
 
@@ -307,8 +372,12 @@ template <typename TD>
 static void run_ls(psd_handle* h, int mode) {
   hipStream_t s = h->stream;
   const Task2* t = h->dT + h->ls.off;
-  if (h->dim == 2) k_ls2d<TD><<<h->ls.cnt, PSD_NT, h->ls.lds, s>>>(h->dI, t, mode);
-  else k_ls3d<TD><<<h->ls.cnt, PSD_NT, h->ls.lds, s>>>(h->dI, t, mode);
+  {
+    ProfScope ps(h, PSD_PASS_LS);
+    if (h->dim == 2) k_ls2d<TD><<<h->ls.cnt, PSD_NT, h->ls.lds, s>>>(h->dI, t, mode);
+    else k_ls3d<TD><<<h->ls.cnt, PSD_NT, h->ls.lds, s>>>(h->dI, t, mode);
+  }
+  ProfScope ps(h, PSD_PASS_LS_FIN);
   k_ls_finalize<<<h->batch, PSD_NT, 0, s>>>(h->dI, mode);
 }
 
@@ -359,17 +428,31 @@ static psd_status solve_loop(psd_handle* h) {
     if (!h->gexec || h->gchunk != chunk) {
       if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
       if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
+      h->prof.clear();
+      h->ev_used = 0;
       HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-      for (int k = 0; k < chunk; ++k) run_iteration_p4<T, TD, TR>(h);
+      for (int k = 0; k < chunk; ++k) {
+        h->prof_iter_slot = k;
+        run_iteration_p4<T, TD, TR>(h);
+      }
+      h->prof_iter_slot = -1;
       HIPCHK(hipStreamEndCapture(h->stream, &h->graph));
       HIPCHK(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
       h->gchunk = chunk;
     }
     const int max_launch = h->opt.max_iter / chunk + 2;
     for (int it = 0; it < max_launch; ++it) {
+      std::vector<int> before(h->batch);
+      for (int b = 0; b < h->batch; ++b) before[b] = h->hState[b].iter;
       HIPCHK(hipGraphLaunch(h->gexec, h->stream));
       psd_status st = read_states(h);
       if (st != PSD_OK) return st;
+      if (h->opt.profile) {
+        // leading iterations of this replay that did work (largest over instances)
+        int real = 0;
+        for (int b = 0; b < h->batch; ++b) real = std::max(real, h->hState[b].iter - before[b]);
+        prof_collect(h, std::min(chunk, real), true);
+      }
       if (all_done(h)) break;
     }
     return PSD_OK;
@@ -383,6 +466,7 @@ static psd_status solve_loop(psd_handle* h) {
     HIPCHK(hipGetLastError());
     psd_status st = read_states(h);
     if (st != PSD_OK) return st;
+    if (h->opt.profile) prof_collect(h, -1, false);
     if (all_done(h)) break;
   }
   return PSD_OK;
@@ -564,6 +648,8 @@ static psd_status solve_impl(psd_handle* h, const double* const* f, const double
                              double* const* w, psd_stats* stats) {
   const int B = h->batch;
   std::vector<int> pre_status(B, 0);
+  for (int k = 0; k < PSD_NPASS; ++k) { h->pass_ms[k] = 0.0; h->pass_n[k] = 0; }
+  if (!h->gexec) { h->prof.clear(); h->ev_used = 0; }
   // bind user buffers
   for (int b = 0; b < B; ++b) {
     Inst& I = h->hI[b];
@@ -817,6 +903,13 @@ extern "C" psd_status psd_adjoint(psd_handle* h, const double* const* u_star, co
   return set_err(h, PSD_ERR_ARG, "adjoint not available in this build");
 }
 
+extern "C" psd_status psd_pass_times(psd_handle* h, double* ms, int* launches) {
+  if (!h) return PSD_ERR_ARG;
+  if (!ms || !launches) return set_err(h, PSD_ERR_ARG, "NULL output");
+  for (int k = 0; k < PSD_NPASS; ++k) { ms[k] = h->pass_ms[k]; launches[k] = h->pass_n[k]; }
+  return PSD_OK;
+}
+
 extern "C" psd_status psd_destroy(psd_handle* h) {
   if (!h) return PSD_ERR_ARG;
   (void)hipSetDevice(h->device);
@@ -824,6 +917,7 @@ extern "C" psd_status psd_destroy(psd_handle* h) {
   if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
   if (h->graph) (void)hipGraphDestroy(h->graph);
   for (void* p : h->allocs) (void)hipFree(p);
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   if (h->hState) (void)hipHostFree(h->hState);
   if (h->hPart) (void)hipHostFree(h->hPart);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);

@@ -34,6 +34,9 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_ARG", -2: "ERR_RANGE", -3:
 PSD_FP64 = 0
 PSD_MIXED = 1
 
+PASS_NAMES = ["rows_r2c", "cols_fwd", "cols_fused", "cols_inv", "rows_c2r", "ls", "ls_fin",
+              "res", "res_fin"]
+
 
 class _Problem(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int), ("L", ctypes.c_double),
@@ -44,7 +47,7 @@ class _Problem(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("precision", ctypes.c_int), ("graph_chunk", ctypes.c_int),
-                ("history", ctypes.c_int)]
+                ("history", ctypes.c_int), ("profile", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -71,6 +74,7 @@ SIGNATURES = {
                                    _dp, _dp, ctypes.c_double, ctypes.c_int,
                                    ctypes.POINTER(ctypes.c_int)]),
     "psd_history": (ctypes.c_int, [_vp, ctypes.c_int, _dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    "psd_pass_times": (ctypes.c_int, [_vp, _dp, ctypes.POINTER(ctypes.c_int)]),
     "psd_destroy": (ctypes.c_int, [_vp]),
     "psd_last_error": (ctypes.c_char_p, [_vp]),
 }
@@ -155,13 +159,15 @@ class Solver:
 
     def __init__(self, problems: Union[Problem, List[Problem]], tol: float = 1e-10,
                  max_iter: int = 500, precision: str = "fp64", graph_chunk: int = 0,
-                 history: bool = False, stream: Optional[torch.cuda.Stream] = None):
+                 history: bool = False, profile: bool = False,
+                 stream: Optional[torch.cuda.Stream] = None):
         self._lib = load_library()
         self.problems = [problems] if isinstance(problems, Problem) else list(problems)
         self.batch = len(self.problems)
         arr = (_Problem * self.batch)(*[p.c() for p in self.problems])
         prec = {"fp64": PSD_FP64, "mixed": PSD_MIXED}[precision]
-        self.opt = _Options(float(tol), int(max_iter), prec, int(graph_chunk), 1 if history else 0)
+        self.opt = _Options(float(tol), int(max_iter), prec, int(graph_chunk), 1 if history else 0,
+                            1 if profile else 0)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = _vp()
         st = self._lib.psd_create(arr, self.batch, ctypes.byref(self.opt),
@@ -235,6 +241,13 @@ class Solver:
         self._check(self._lib.psd_history(self._h, inst, buf, cap, ctypes.byref(cnt)))
         import numpy as np
         return np.array(buf[: 4 * cnt.value]).reshape(cnt.value, 4)
+
+    def pass_times(self):
+        """{pass name: (total ms, launches)} of the last solve (profile=True)."""
+        ms = (ctypes.c_double * len(PASS_NAMES))()
+        cnt = (ctypes.c_int * len(PASS_NAMES))()
+        self._check(self._lib.psd_pass_times(self._h, ms, cnt))
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(PASS_NAMES)}
 
     def adjoint(self, u_star: Sequence[torch.Tensor], dJdu: Sequence[torch.Tensor],
                 rtol: float = 1e-12, max_iter: int = 1000):
