@@ -176,11 +176,10 @@ enum {
     PSD_NPASS = 9
 };
 
-/* Per-pass kernel time of the last psd_solve made with options.profile set:
- * ms[k] = summed duration (HIP events on the solver stream) of the launches
- * of pass k that did work, launches[k] = their number; launches after
- * convergence (early exits inside a replayed graph) are excluded.  Arrays
- * of PSD_NPASS entries, host memory. */
+/* Per-pass kernel time of the last psd_solve made with options.profile set
+ * and graph_chunk = 0: ms[k] = summed duration (HIP events on the solver
+ * stream) of the launches of pass k, launches[k] = their number (all zero in
+ * graph mode).  Arrays of PSD_NPASS entries, host memory. */
 psd_status psd_pass_times(psd_handle* h, double* ms, int* launches);
 
 /* Destroy the handle and free its workspace. */

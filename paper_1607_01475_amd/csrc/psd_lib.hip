@@ -153,8 +153,11 @@ struct ProfScope {
   psd_handle* h;
   int pass;
   hipEvent_t a = nullptr, b = nullptr;
+  // Events are recorded only in host-driven (stream) mode: elapsed times of
+  // events recorded through captured graph nodes are not available.
   ProfScope(psd_handle* hh, int p) : h(hh), pass(p) {
-    if (!h->opt.profile || pass < 0) return;
+    if (!h->opt.profile || h->prof_iter_slot >= 0) pass = -1;
+    if (pass < 0) return;
     a = prof_event(h);
     b = prof_event(h);
     if (a && b) (void)hipEventRecord(a, h->stream);
@@ -442,17 +445,10 @@ static psd_status solve_loop(psd_handle* h) {
     }
     const int max_launch = h->opt.max_iter / chunk + 2;
     for (int it = 0; it < max_launch; ++it) {
-      std::vector<int> before(h->batch);
-      for (int b = 0; b < h->batch; ++b) before[b] = h->hState[b].iter;
       HIPCHK(hipGraphLaunch(h->gexec, h->stream));
       psd_status st = read_states(h);
       if (st != PSD_OK) return st;
-      if (h->opt.profile) {
-        // leading iterations of this replay that did work (largest over instances)
-        int real = 0;
-        for (int b = 0; b < h->batch; ++b) real = std::max(real, h->hState[b].iter - before[b]);
-        prof_collect(h, std::min(chunk, real), true);
-      }
+
       if (all_done(h)) break;
     }
     return PSD_OK;
