@@ -137,6 +137,8 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="fp64,mixed")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 512 MiB device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs on one GPU; multi-GPU runs are not part of "
@@ -151,6 +153,12 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
     psd.load_library()
+    if args.copy_calibration:
+        a = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     w = psd_inputs.config3(args.n)
     log(f"bench: workload {w.name} n={w.n} p={w.p} s={w.s} eps={w.eps}")
     f = torch.from_numpy(w.f).to("cuda")

@@ -87,6 +87,13 @@ struct Inst {
   double* part_sp;     // spectral partials: 2 per block
   double* part_c2r;    // sums of the inverse-transform outputs: 3 per block
   double* hist;        // 4 per update (may be null)
+  // adjoint (conjugate gradients on the Hessian of E_h at u*)
+  const double* adj_us;   // u*
+  const double* adj_g;    // right-hand side dJ/du
+  double* adj_lam;        // solution (= dJ/df)
+  double* adj_r;          // CG residual
+  double* adj_p;          // CG direction
+  double* adj_Hp;         // Hessian times direction
   int nblk_res, nblk_ls, nblk_sp, hist_cap;
   int nblk_c2r, pad1;
 };

@@ -242,19 +242,38 @@ __device__ __forceinline__ void r2c_rows(const RowArgs<T>& A, long long row0, cx
                                          const cx<T>* tw) {
   constexpr int LS = N + 1;
   constexpr int NC = N / 2 + 1;
-  // load 2*NL real rows
-  for (int e = threadIdx.x; e < 2 * NL * N; e += PSD_NT) {
-    const int rr = e / N, col = e - rr * N;
+  // load 2*NL real rows: VEC consecutive values per thread and load, all
+  // loads of the block issued before the first LDS store
+  constexpr int VEC = 16 / (int)sizeof(TIN);
+  constexpr int NV = 2 * NL * N / VEC;                 // vector loads per block
+  constexpr int IT = (NV + PSD_NT - 1) / PSD_NT;
+  static_assert(N % VEC == 0, "row length must be a multiple of the vector width");
+  struct alignas(16) V { TIN x[VEC]; };
+  V regs[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = threadIdx.x + it * PSD_NT;
+    const int rr = (e * VEC) / N;
     const long long gr = row0 + rr;
-    T val = T(0);
-    if (gr < A.nrows) {
+    if ((NV % PSD_NT == 0 || e < NV) && gr < A.nrows) {
+      const int col = e * VEC - rr * N;
       const int fld = (int)(gr / A.rpf);
       const long long row = gr - (long long)fld * A.rpf;
-      const TIN* src = (const TIN*)A.in(fld);
-      val = (T)src[row * N + col];
+      regs[it] = *(const V*)((const TIN*)A.in(fld) + row * N + col);
+    } else {
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) regs[it].x[q] = TIN(0);
     }
-    T* dst = (T*)(buf + (rr >> 1) * LS + col);
-    dst[rr & 1] = val;
+  }
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = threadIdx.x + it * PSD_NT;
+    if (NV % PSD_NT == 0 || e < NV) {
+      const int rr = (e * VEC) / N, col = e * VEC - rr * N;
+      T* dst = (T*)(buf + (rr >> 1) * LS + col) + (rr & 1);
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) dst[2 * q] = (T)regs[it].x[q];
+    }
   }
   __syncthreads();
   lds_fft<T, N, NL, LS, -1>(buf, tw);
@@ -280,17 +299,30 @@ __device__ __forceinline__ void c2r_rows(const RowArgs<T>& A, long long row0, cx
                                          const cx<T>* tw, double (&fsum)[3]) {
   constexpr int LS = N + 1;
   constexpr int NC = N / 2 + 1;
-  for (int e = threadIdx.x; e < NL * NC; e += PSD_NT) {
+  constexpr int NE = NL * NC;
+  constexpr int IT = (NE + PSD_NT - 1) / PSD_NT;
+  cx<T> ra[IT], rb[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = threadIdx.x + it * PSD_NT;
     const int l = e / NC, k = e - l * NC;
     const long long gr = row0 + 2 * l;
-    cx<T> a = mk(T(0), T(0)), b = mk(T(0), T(0));
-    if (gr < A.nrows) {
+    ra[it] = mk(T(0), T(0));
+    rb[it] = mk(T(0), T(0));
+    if ((NE % PSD_NT == 0 || e < NE) && gr < A.nrows) {
       const int fld = (int)(gr / A.rpf);
       const long long row = gr - (long long)fld * A.rpf;
       const cx<T>* in = A.spec + fld * A.nspec + row * NC;
-      a = in[k];
-      b = in[NC + k];
+      ra[it] = in[k];
+      rb[it] = in[NC + k];
     }
+  }
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = threadIdx.x + it * PSD_NT;
+    if (!(NE % PSD_NT == 0 || e < NE)) continue;
+    const int l = e / NC, k = e - l * NC;
+    cx<T> a = ra[it], b = rb[it];
     if (k == 0 || k == N / 2) { a.y = T(0); b.y = T(0); }
     // Z_k = A_k + i B_k ; Z_{N-k} = conj(A_k) + i conj(B_k)
     buf[l * LS + k] = a + mul_i<1>(b);
@@ -298,20 +330,58 @@ __device__ __forceinline__ void c2r_rows(const RowArgs<T>& A, long long row0, cx
   }
   __syncthreads();
   lds_fft<T, N, NL, LS, 1>(buf, tw);
-  for (int e = threadIdx.x; e < 2 * NL * N; e += PSD_NT) {
-    const int rr = e / N, col = e - rr * N;
+  constexpr int VEC = 16 / (int)sizeof(TOUT);
+  constexpr int NV = 2 * NL * N / VEC;
+  struct alignas(16) V { TOUT x[VEC]; };
+  for (int e = threadIdx.x; e < NV; e += PSD_NT) {
+    const int rr = (e * VEC) / N, col = e * VEC - rr * N;
     const long long gr = row0 + rr;
     if (gr >= A.nrows) continue;
     const int fld = (int)(gr / A.rpf);
     const long long row = gr - (long long)fld * A.rpf;
-    const T* src = (const T*)(buf + (rr >> 1) * LS + col);
-    TOUT* dst = (TOUT*)A.out(fld);
-    const TOUT val = (TOUT)src[rr & 1];
-    dst[row * N + col] = val;
-    const double dv = (double)val;
-    fsum[0] += fld == 0 ? dv : 0.0;
-    fsum[1] += fld == 1 ? dv : 0.0;
-    fsum[2] += fld == 2 ? dv : 0.0;
+    const T* src = (const T*)(buf + (rr >> 1) * LS + col) + (rr & 1);
+    V out;
+    double part = 0.0;
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) {
+      out.x[q] = (TOUT)src[2 * q];
+      part += (double)out.x[q];
+    }
+    *(V*)((TOUT*)A.out(fld) + row * N + col) = out;
+    fsum[0] += fld == 0 ? part : 0.0;
+    fsum[1] += fld == 1 ? part : 0.0;
+    fsum[2] += fld == 2 ? part : 0.0;
+  }
+}
+
+// Load NF fields of W adjacent columns of length N into LDS lines
+// (f*W + c), every load of the block issued before the first LDS store.
+template <typename T, int N, int W, int NF>
+__device__ __forceinline__ void col_load(const cx<T>* base, long long inner_count, long long col0,
+                                         long long lstride, long long fstride, cx<T>* buf) {
+  constexpr int LS = N + 1;
+  constexpr int NE = NF * W * N;
+  constexpr int IT = (NE + PSD_NT - 1) / PSD_NT;
+  cx<T> regs[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = threadIdx.x + it * PSD_NT;
+    const int c = e % W;
+    const int ft = e / W;
+    const int t = ft % N, f = ft / N;
+    regs[it] = mk(T(0), T(0));
+    if ((NE % PSD_NT == 0 || e < NE) && col0 + c < inner_count)
+      regs[it] = base[f * fstride + col0 + c + t * lstride];
+  }
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = threadIdx.x + it * PSD_NT;
+    if (NE % PSD_NT == 0 || e < NE) {
+      const int c = e % W;
+      const int ft = e / W;
+      const int t = ft % N, f = ft / N;
+      buf[(f * W + c) * LS + t] = regs[it];
+    }
   }
 }
 
@@ -325,14 +395,7 @@ __device__ __forceinline__ void col_pass(cx<T>* base, long long inner_count, lon
                                          long long lstride, long long fstride, cx<T>* buf,
                                          const cx<T>* tw) {
   constexpr int LS = N + 1;
-  for (int e = threadIdx.x; e < NF * W * N; e += PSD_NT) {
-    const int c = e % W;
-    const int ft = e / W;
-    const int t = ft % N, f = ft / N;
-    cx<T> v = mk(T(0), T(0));
-    if (col0 + c < inner_count) v = base[f * fstride + col0 + c + t * lstride];
-    buf[(f * W + c) * LS + t] = v;
-  }
+  col_load<T, N, W, NF>(base, inner_count, col0, lstride, fstride, buf);
   __syncthreads();
   lds_fft<T, N, NF * W, LS, DIR>(buf, tw);
   for (int e = threadIdx.x; e < NF * W * N; e += PSD_NT) {

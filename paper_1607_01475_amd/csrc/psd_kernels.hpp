@@ -362,14 +362,7 @@ __device__ __forceinline__ void fused_col(const Inst& I, const Task2& t, cx<T>* 
   const long long lstride = inner;
   cx<T>* base = (cx<T>*)I.spec;
   const long long col0 = t.b;
-  for (int e = threadIdx.x; e < NFI * W * N; e += PSD_NT) {
-    const int c = e % W;
-    const int ft = e / W;
-    const int tt = ft % N, f = ft / N;
-    cx<T> v = mk(T(0), T(0));
-    if (col0 + c < inner) v = base[f * I.nspec + col0 + c + tt * lstride];
-    buf[(f * W + c) * LS + tt] = v;
-  }
+  col_load<T, N, W, NFI>(base, inner, col0, lstride, I.nspec, buf);
   __syncthreads();
   lds_fft<T, N, NFI * W, LS, -1>(buf, tw);
   const double s = I.s, se2 = I.se2, inv = I.inv_ntot;
@@ -530,6 +523,199 @@ __global__ __launch_bounds__(PSD_NT) void k_axpby(double* __restrict__ out, cons
                                                   double gamma, long long N) {
   for (long long c = blockIdx.x * (long long)PSD_NT + threadIdx.x; c < N; c += (long long)gridDim.x * PSD_NT)
     out[c] = alpha * a[c] + (b ? beta * b[c] : 0.0) + gamma;
+}
+
+// ===========================================================================
+// adjoint: conjugate gradients on H lam = dJ/du (H = Hessian of E_h at u*,
+// second variation of Sec. 5.3), preconditioned by L_h^{-1} (FFT passes).
+// Flexible (Polak-Ribiere) beta, so an FP32 preconditioner is allowed:
+//   beta = z+.(r+ - r)/(r.z) = -alpha (z+.Hp)/(r.z).
+// SolveState reuse: c[0] = r.z, c[1] = p.Hp, c[2] = r.r, alpha, x = beta,
+// hi = stop threshold on r.r, iter = CG iterations.
+// ===========================================================================
+template <typename TD, typename TR>
+__global__ __launch_bounds__(PSD_NT) void k_hess2d(const Inst* __restrict__ insts,
+                                                   const Task2* __restrict__ tasks) {
+  extern __shared__ double smem[];
+  const Task2 t = tasks[blockIdx.x];
+  const Inst& I = insts[t.inst];
+  if (I.st->done) return;
+  double acc[2] = {0.0, 0.0};
+  res2d_tile<TD, TR, 4, false, true>(I, t.a, t.b, smem, acc);
+  block_reduce<2, 1>(acc, smem + R2_LDS);
+  if (threadIdx.x == 0) {
+    I.part_res[2 * t.slot] = 0.0;
+    I.part_res[2 * t.slot + 1] = acc[1];
+  }
+}
+
+template <typename TR>
+__global__ __launch_bounds__(PSD_NT) void k_hess3d(const Inst* __restrict__ insts,
+                                                   const Task2* __restrict__ tasks) {
+  extern __shared__ double smem[];
+  const Task2 t = tasks[blockIdx.x];
+  const Inst& I = insts[t.inst];
+  if (I.st->done) return;
+  double acc[2] = {0.0, 0.0};
+  res3d_tile<double, TR, false, true>(I, t.a, t.b, t.c, smem, acc);
+  block_reduce<2, 1>(acc, smem + R3H_LDS);
+  if (threadIdx.x == 0) {
+    I.part_res[2 * t.slot] = 0.0;
+    I.part_res[2 * t.slot + 1] = acc[1];
+  }
+}
+
+// Vector steps over the cells of one instance; block b handles a contiguous
+// chunk and writes one partial sum to part_res[2b+1].
+//   op 0: lam = 0, r = g, rTR = g;            partial g.g
+//   op 1: lam += alpha p, r -= alpha Hp, rTR = r;  partial r.r
+//   op 2: partial z.Hp
+//   op 3: p = z (first) ; op 4: p = z + beta p
+template <typename TD, typename TR>
+__global__ __launch_bounds__(PSD_NT) void k_cg_vec(const Inst* __restrict__ insts, int inst, int op) {
+  __shared__ double scratch[2 * PSD_NT / PSD_WAVE];
+  const Inst& I = insts[inst];
+  const SolveState* st = I.st;
+  if (st->done) return;
+  const long long N = I.ncell;
+  const long long chunk = (N + gridDim.x - 1) / gridDim.x;
+  const long long c0 = blockIdx.x * chunk;
+  const long long c1 = c0 + chunk < N ? c0 + chunk : N;
+  const double alpha = st->alpha, beta = st->x;
+  double acc[2] = {0.0, 0.0};
+  const TD* z = (const TD*)I.d;
+  TR* rtr = (TR*)I.r;
+  for (long long c = c0 + threadIdx.x; c < c1; c += PSD_NT) {
+    if (op == 0) {
+      const double g = I.adj_g[c];
+      I.adj_lam[c] = 0.0;
+      I.adj_r[c] = g;
+      rtr[c] = (TR)g;
+      acc[1] += g * g;
+    } else if (op == 1) {
+      I.adj_lam[c] += alpha * I.adj_p[c];
+      const double r = I.adj_r[c] - alpha * I.adj_Hp[c];
+      I.adj_r[c] = r;
+      rtr[c] = (TR)r;
+      acc[1] += r * r;
+    } else if (op == 2) {
+      acc[1] += (double)z[c] * I.adj_Hp[c];
+    } else if (op == 3) {
+      I.adj_p[c] = (double)z[c];
+    } else {
+      I.adj_p[c] = (double)z[c] + beta * I.adj_p[c];
+    }
+  }
+  if (op <= 2) {
+    block_reduce<2, 1>(acc, scratch);
+    if (threadIdx.x == 0) I.part_res[2 * blockIdx.x + 1] = acc[1];
+  }
+}
+
+// One block per instance.  mode 0: threshold from g.g; 1: r.z from the
+// spectral partials; 2: alpha = r.z / p.Hp; 3: r.r and stop test; 4: beta.
+__global__ __launch_bounds__(PSD_NT) void k_cg_fin(const Inst* __restrict__ insts, int mode, int nblk_vec,
+                                                   double rtol2) {
+  __shared__ double scratch[2 * PSD_NT / PSD_WAVE];
+  const Inst& I = insts[blockIdx.x];
+  SolveState* st = I.st;
+  if (st->done) return;
+  double acc[2] = {0.0, 0.0};
+  if (mode == 1 || mode == 4)
+    for (int b = threadIdx.x; b < I.nblk_sp; b += PSD_NT) acc[0] += I.part_sp[2 * b];
+  const int nb = (mode == 2 || nblk_vec < 0) ? I.nblk_res : nblk_vec;
+  if (mode != 1)
+    for (int b = threadIdx.x; b < nb; b += PSD_NT) acc[1] += I.part_res[2 * b + 1];
+  block_reduce<2, 0>(acc, scratch);
+  if (threadIdx.x != 0) return;
+  if (mode == 0) {
+    st->hi = rtol2 * acc[1];
+    st->c[2] = acc[1];
+    if (!(acc[1] > 0.0)) st->done = 1;   // zero right-hand side: lam = 0
+  } else if (mode == 1) {
+    st->c[0] = acc[0];
+  } else if (mode == 2) {
+    st->c[1] = acc[1];
+    if (!(acc[1] > 0.0)) { st->status = -5; st->done = 1; return; }
+    st->alpha = st->c[0] / acc[1];
+  } else if (mode == 3) {
+    st->c[2] = acc[1];
+    st->iter += 1;
+    if (!isfinite(acc[1])) { st->status = -4; st->done = 1; }
+    else if (acc[1] <= st->hi) st->done = 1;
+    else if (st->iter >= I.max_iter) { st->status = 1; st->done = 1; }
+  } else {
+    const double rz_new = acc[0];
+    st->x = -st->alpha * acc[1] / st->c[0];
+    st->c[0] = rz_new;
+  }
+}
+
+// Parameter sensitivities of N_h at u* weighted by lam (one thread per cell,
+// direct reads):  part[2b] = sum lam (-plap u* + eps^2 Delta_h^2 u*),
+// part[2b+1] = sum lam Delta_h^2 u*.
+__device__ __forceinline__ double at3(const double* u, int n, int dim, int i, int j, int k) {
+  i = wrapi(i, n); j = wrapi(j, n);
+  k = dim == 3 ? wrapi(k, n) : 0;
+  return u[i + (long long)n * (j + (long long)n * k)];
+}
+
+__global__ __launch_bounds__(PSD_NT) void k_param_sens(const Inst* __restrict__ insts, int inst,
+                                                       double* __restrict__ part) {
+  __shared__ double scratch[2 * PSD_NT / PSD_WAVE];
+  const Inst& I = insts[inst];
+  const double* u = I.adj_us;
+  const int n = I.n, dim = I.dim;
+  const double ih = I.inv_h, ih2 = ih * ih;
+  double acc[2] = {0.0, 0.0};
+  for (long long c = blockIdx.x * (long long)PSD_NT + threadIdx.x; c < I.ncell; c += (long long)gridDim.x * PSD_NT) {
+    const int i = (int)(c % n), j = (int)((c / n) % n), k = dim == 3 ? (int)(c / ((long long)n * n)) : 0;
+    auto lap = [&](int a, int b, int e) {
+      double v = at3(u, n, dim, a + 1, b, e) + at3(u, n, dim, a - 1, b, e) + at3(u, n, dim, a, b + 1, e) +
+                 at3(u, n, dim, a, b - 1, e) - 4.0 * at3(u, n, dim, a, b, e);
+      if (dim == 3) v += at3(u, n, dim, a, b, e + 1) + at3(u, n, dim, a, b, e - 1) - 2.0 * at3(u, n, dim, a, b, e);
+      return v * ih2;
+    };
+    double l2 = lap(i + 1, j, k) + lap(i - 1, j, k) + lap(i, j + 1, k) + lap(i, j - 1, k) - 4.0 * lap(i, j, k);
+    if (dim == 3) l2 += lap(i, j, k + 1) + lap(i, j, k - 1) - 2.0 * lap(i, j, k);
+    l2 *= ih2;
+    // p-Laplacian: fluxes at the 4 (2D) or 8 (3D) vertices around the cell
+    double div = 0.0;
+    const int nz = dim == 3 ? 2 : 1;
+    for (int cz = 0; cz < nz; ++cz)
+      for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) {
+          // vertex (i - 1 + cx + 1/2, j - 1 + cy + 1/2, k - 1 + cz + 1/2): lower cell corner
+          const int vi = i - 1 + cx, vj = j - 1 + cy, vk = dim == 3 ? k - 1 + cz : 0;
+          double gx, gy, gz = 0.0;
+          if (dim == 2) {
+            const double c00 = at3(u, n, 2, vi, vj, 0), c10 = at3(u, n, 2, vi + 1, vj, 0);
+            const double c01 = at3(u, n, 2, vi, vj + 1, 0), c11 = at3(u, n, 2, vi + 1, vj + 1, 0);
+            gx = 0.5 * ih * ((c10 - c00) + (c11 - c01));
+            gy = 0.5 * ih * ((c01 - c00) + (c11 - c10));
+          } else {
+            const double c000 = at3(u, n, 3, vi, vj, vk), c100 = at3(u, n, 3, vi + 1, vj, vk);
+            const double c010 = at3(u, n, 3, vi, vj + 1, vk), c110 = at3(u, n, 3, vi + 1, vj + 1, vk);
+            const double c001 = at3(u, n, 3, vi, vj, vk + 1), c101 = at3(u, n, 3, vi + 1, vj, vk + 1);
+            const double c011 = at3(u, n, 3, vi, vj + 1, vk + 1), c111 = at3(u, n, 3, vi + 1, vj + 1, vk + 1);
+            const double q = 0.25 * ih;
+            gx = q * ((c100 - c000) + (c110 - c010) + (c101 - c001) + (c111 - c011));
+            gy = q * ((c010 - c000) + (c110 - c100) + (c011 - c001) + (c111 - c101));
+            gz = q * ((c001 - c000) + (c101 - c100) + (c011 - c010) + (c111 - c110));
+          }
+          const double rr = flux_r(gx * gx + gy * gy + gz * gz, I.p, I.p_is_4, I.p_is_2);
+          // divergence weights: +-1/(2h) (2D) or +-1/(4h) (3D) per component
+          const double w = dim == 2 ? 0.5 * ih : 0.25 * ih;
+          div += w * ((cx ? 1.0 : -1.0) * rr * gx + (cy ? 1.0 : -1.0) * rr * gy +
+                      (dim == 3 ? (cz ? 1.0 : -1.0) * rr * gz : 0.0));
+        }
+    const double lam = I.adj_lam[c];
+    const double e2 = I.se2 / I.s;
+    acc[0] += lam * (-div + e2 * l2);
+    acc[1] += lam * l2;
+  }
+  block_reduce<2, 0>(acc, scratch);
+  if (threadIdx.x == 0) { part[2 * blockIdx.x] = acc[0]; part[2 * blockIdx.x + 1] = acc[1]; }
 }
 
 // mark every instance except `keep` as finished (auxiliary single-instance calls)

@@ -98,6 +98,7 @@ struct psd_handle_s {
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
   int gchunk = 0;
+  bool adj_alloc = false;
   std::string err;
   // profiling: events around every pass launch, in launch order
   struct ProfRec { int pass; int iter_slot; hipEvent_t a, b; };
@@ -891,12 +892,104 @@ extern "C" psd_status psd_history(psd_handle* h, int inst, double* out, int cap,
   return PSD_OK;
 }
 
+template <typename T, typename TD, typename TR>
+static psd_status adjoint_impl(psd_handle* h, const double* const* u_star, const double* const* dJdu,
+                               double* const* dJdf, double* dJds, double* dJdeps, double rtol, int max_iter,
+                               int* cg_iters) {
+  const int B = h->batch;
+  hipStream_t s = h->stream;
+  std::vector<Inst> saved = h->hI;
+  for (int b = 0; b < B; ++b) {
+    Inst& I = h->hI[b];
+    if (!h->adj_alloc) {
+      if (dalloc(h, &I.adj_r, I.ncell * 8) || dalloc(h, &I.adj_p, I.ncell * 8) || dalloc(h, &I.adj_Hp, I.ncell * 8))
+        return set_err(h, PSD_ERR_HIP, "out of device memory");
+    }
+    I.adj_us = u_star[b];
+    I.adj_g = dJdu[b];
+    I.adj_lam = dJdf[b];
+    I.max_iter = max_iter;
+  }
+  h->adj_alloc = true;
+  // keep the buffers for later calls
+  for (int b = 0; b < B; ++b) {
+    saved[b].adj_r = h->hI[b].adj_r; saved[b].adj_p = h->hI[b].adj_p; saved[b].adj_Hp = h->hI[b].adj_Hp;
+  }
+  psd_status st = upload_inst(h);
+  if (st != PSD_OK) return st;
+  k_reset_state<<<(B + 63) / 64, 64, 0, s>>>(h->dI, B);
+  const double rtol2 = rtol * rtol;
+  auto vec = [&](int op) {
+    for (int b = 0; b < B; ++b)
+      k_cg_vec<TD, TR><<<h->hI[b].nblk_res, PSD_NT, 0, s>>>(h->dI, b, op);
+  };
+  // nblk_vec = nblk_res (vector kernels use one block per residual tile count)
+  const int nbv = 0;  // per-instance block count read from Inst in k_cg_fin
+  (void)nbv;
+  auto fin = [&](int mode) {
+    // vector partial counts equal nblk_res for every instance
+    k_cg_fin<<<B, PSD_NT, 0, s>>>(h->dI, mode, -1, rtol2);
+  };
+  vec(0);
+  fin(0);
+  run_fft<T, TR, TD>(h, h->fft_solver, OP_PRECOND4, true);
+  fin(1);
+  vec(3);
+  const Task2* tt = h->dT + h->res.off;
+  for (int it = 0; it < max_iter; ++it) {
+    if (h->dim == 2) k_hess2d<TD, TR><<<h->res.cnt, PSD_NT, (R2_LDS + 16) * sizeof(double), s>>>(h->dI, tt);
+    else k_hess3d<TR><<<h->res.cnt, PSD_NT, (R3H_LDS + 16) * sizeof(double), s>>>(h->dI, tt);
+    fin(2);
+    vec(1);
+    fin(3);
+    HIPCHK(hipGetLastError());
+    st = read_states(h);
+    if (st != PSD_OK) return st;
+    if (all_done(h)) break;
+    run_fft<T, TR, TD>(h, h->fft_solver, OP_PRECOND4, true);
+    vec(2);
+    fin(4);
+    vec(4);
+  }
+  st = read_states(h);
+  if (st != PSD_OK) return st;
+  psd_status worst = PSD_OK;
+  // sensitivities to s and eps (one pass per instance)
+  const int nblk = 1024;
+  for (int b = 0; b < B; ++b) {
+    const Inst& I = h->hI[b];
+    const SolveState& S = h->hState[b];
+    if (cg_iters) cg_iters[b] = S.iter;
+    if (S.status < 0) worst = (psd_status)S.status;
+    else if (S.status > 0 && worst == PSD_OK) worst = PSD_NOT_CONVERGED;
+    k_param_sens<<<nblk, PSD_NT, 0, s>>>(h->dI, b, h->dAuxPart);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(h->hPart, h->dAuxPart, sizeof(double) * 2 * nblk, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double a0 = 0.0, a1 = 0.0;
+    for (int k = 0; k < nblk; ++k) { a0 += h->hPart[2 * k]; a1 += h->hPart[2 * k + 1]; }
+    // dN/ds = -plap(u*) + eps^2 Delta_h^2 u*,  dN/deps = 2 s eps Delta_h^2 u*
+    const double eps = std::sqrt(I.se2 / I.s);
+    if (dJds) dJds[b] = -a0;
+    if (dJdeps) dJdeps[b] = -2.0 * I.s * eps * a1;
+  }
+  h->hI = saved;
+  st = upload_inst(h);
+  HIPCHK(hipStreamSynchronize(s));
+  return st != PSD_OK ? st : worst;
+}
+
 extern "C" psd_status psd_adjoint(psd_handle* h, const double* const* u_star, const double* const* dJdu,
                                   double* const* dJdf, double* dJds, double* dJdeps, double rtol, int max_iter,
                                   int* cg_iters) {
   if (!h) return PSD_ERR_ARG;
-  (void)u_star; (void)dJdu; (void)dJdf; (void)dJds; (void)dJdeps; (void)rtol; (void)max_iter; (void)cg_iters;
-  return set_err(h, PSD_ERR_ARG, "adjoint not available in this build");
+  if (h->order != 4) return set_err(h, PSD_ERR_ARG, "the adjoint is available for order 4");
+  if (!u_star || !dJdu || !dJdf || max_iter <= 0 || !(rtol >= 0.0)) return set_err(h, PSD_ERR_ARG, "bad arguments");
+  for (int b = 0; b < h->batch; ++b)
+    if (!u_star[b] || !dJdu[b] || !dJdf[b]) return set_err(h, PSD_ERR_ARG, "NULL instance pointer");
+  HIPCHK(hipSetDevice(h->device));
+  if (h->mixed) return adjoint_impl<float, float, float>(h, u_star, dJdu, dJdf, dJds, dJdeps, rtol, max_iter, cg_iters);
+  return adjoint_impl<double, double, double>(h, u_star, dJdu, dJdf, dJds, dJdeps, rtol, max_iter, cg_iters);
 }
 
 extern "C" psd_status psd_pass_times(psd_handle* h, double* ms, int* launches) {

@@ -27,6 +27,22 @@ __device__ __forceinline__ double flux_r(double g2, double p, int p_is_4, int p_
   return g2 > 0.0 ? pow(g2, 0.5 * (p - 2.0)) : 0.0;
 }
 
+// Linearised flux of the second variation (Sec. 5.3) at a vertex:
+//   F = |a|^{p-2} b + (p-2) |a|^{p-4} (a.b) a,  a = grad u*, b = grad xi;
+// the second term is 0 where a = 0 (and for p = 2).
+__device__ __forceinline__ void flux_lin(const Inst& I, double ax, double ay, double az, double bx,
+                                         double by, double bz, double& fx, double& fy, double& fz) {
+  const double a2 = ax * ax + ay * ay + az * az, ab = ax * bx + ay * by + az * bz;
+  double r2, r4;
+  if (I.p_is_4) { r2 = a2; r4 = 2.0; }
+  else if (I.p_is_2) { r2 = 1.0; r4 = 0.0; }
+  else if (a2 == 0.0) { r2 = 0.0; r4 = 0.0; }
+  else { r2 = pow(a2, 0.5 * (I.p - 2.0)); r4 = (I.p - 2.0) * r2 / a2; }
+  fx = r2 * bx + r4 * ab * ax;
+  fy = r2 * by + r4 * ab * ay;
+  fz = r2 * bz + r4 * ab * az;
+}
+
 // ===========================================================================
 // 2D residual tile (order 4 or 6)
 // ===========================================================================
@@ -37,7 +53,9 @@ constexpr int R2_LW = T2X + 2, R2_LH = T2Y + 2;
 constexpr int R2_FW = T2X + 1, R2_FH = T2Y + 1;
 constexpr int R2_LDS = R2_VW * R2_VH + R2_LW * R2_LH + 2 * R2_FW * R2_FH + R2_LW * R2_LH;
 
-template <typename TD, typename TR, int ORDER, bool UPD>
+// HESS: Hessian-vector product H xi = xi - s div(F_lin) + s eps^2 Delta_h^2 xi
+// with xi = I.adj_p and u* = I.adj_us (written to I.adj_Hp; acc[1] = sum xi H xi).
+template <typename TD, typename TR, int ORDER, bool UPD, bool HESS = false>
 __device__ void res2d_tile(const Inst& I, int x0, int y0, double* lds, double (&acc)[2]) {
   const int n = I.n;
   const SolveState* st = I.st;
@@ -45,7 +63,7 @@ __device__ void res2d_tile(const Inst& I, int x0, int y0, double* lds, double (&
   const double alpha = UPD ? st->alpha : 0.0;
   // order 6: d, e1, e2 are mean-zero in exact arithmetic; remove the round-off mean
   const double dbar = (ORDER == 6) ? st->mean[0] : 0.0;
-  const double* __restrict__ u = I.u[cur];
+  const double* __restrict__ u = HESS ? I.adj_p : I.u[cur];
   const TD* __restrict__ d = (const TD*)I.d;
   double* v = lds;
   double* lap = v + R2_VW * R2_VH;
@@ -62,7 +80,14 @@ __device__ void res2d_tile(const Inst& I, int x0, int y0, double* lds, double (&
     if (UPD) val += alpha * ((double)d[gi] - dbar);
     v[e] = val;
   }
-  if (ORDER == 6) {
+  if (HESS) {  // u* on the tile plus a 1-cell ring (vertex gradients)
+    for (int e = threadIdx.x; e < R2_LW * R2_LH; e += PSD_NT) {
+      const int ey = e / R2_LW, ex = e - ey * R2_LW;
+      const int gx = posmod(x0 - 1 + ex, n), gy = posmod(y0 - 1 + ey, n);
+      wl[e] = I.adj_us[gx + (long long)n * gy];
+    }
+  }
+  if (ORDER == 6 && !HESS) {
     const double e1bar = st->mean[1], e2bar = st->mean[2];
     const double* __restrict__ w = I.w[cur];
     const TD* __restrict__ e1 = (const TD*)I.e1;
@@ -90,9 +115,20 @@ __device__ void res2d_tile(const Inst& I, int x0, int y0, double* lds, double (&
     const double c00 = v[c], c10 = v[c + 1], c01 = v[c + R2_VW], c11 = v[c + R2_VW + 1];
     const double gx = 0.5 * ih * ((c10 - c00) + (c11 - c01));
     const double gy = 0.5 * ih * ((c01 - c00) + (c11 - c10));
-    const double rr = flux_r(gx * gx + gy * gy, I.p, I.p_is_4, I.p_is_2);
-    Fx[e] = rr * gx;
-    Fy[e] = rr * gy;
+    if (HESS) {
+      const int cw = fy * R2_LW + fx;  // cell (i, j) of the vertex in the u* region
+      const double s00 = wl[cw], s10 = wl[cw + 1], s01 = wl[cw + R2_LW], s11 = wl[cw + R2_LW + 1];
+      const double ax = 0.5 * ih * ((s10 - s00) + (s11 - s01));
+      const double ay = 0.5 * ih * ((s01 - s00) + (s11 - s10));
+      double fxv, fyv, fzv;
+      flux_lin(I, ax, ay, 0.0, gx, gy, 0.0, fxv, fyv, fzv);
+      Fx[e] = fxv;
+      Fy[e] = fyv;
+    } else {
+      const double rr = flux_r(gx * gx + gy * gy, I.p, I.p_is_4, I.p_is_2);
+      Fx[e] = rr * gx;
+      Fy[e] = rr * gy;
+    }
   }
   __syncthreads();
   const double s = I.s, se2 = I.se2;
@@ -108,7 +144,11 @@ __device__ void res2d_tile(const Inst& I, int x0, int y0, double* lds, double (&
     const int lc = (ty + 1) * R2_LW + tx + 1;
     const double l2 = (lap[lc - 1] + lap[lc + 1] + lap[lc - R2_LW] + lap[lc + R2_LW] - 4.0 * lap[lc]) * ih2;
     const double vc = v[(ty + 2) * R2_VW + tx + 2];
-    if (ORDER == 4) {
+    if (HESS) {
+      const double hx = vc - s * div + se2 * l2;
+      I.adj_Hp[gi] = hx;
+      acc[1] += vc * hx;
+    } else if (ORDER == 4) {
       const double r = I.f[gi] - (vc - s * div + se2 * l2);
       ((TR*)I.r)[gi] = (TR)r;
       if (UPD) uo[gi] = vc;
@@ -129,114 +169,255 @@ __device__ void res2d_tile(const Inst& I, int x0, int y0, double* lds, double (&
 }
 
 // ===========================================================================
-// 3D residual: (T3X x T3Y) column tile marching T3Z planes in z.
-// Ring buffers: v 4 planes (halo 2), lap 3 planes (halo 1), F 2 vertex planes.
+// 3D residual: a T3X x T3Y column tile marching T3Z planes in z.
+// Each thread owns one (x, y) column: its values of v = u + alpha d and of
+// Delta_h v at the planes in flight stay in registers; LDS holds the xy-halo
+// of 3 v planes (halo 2), 2 planes of Delta_h v (halo 1) and one vertex plane
+// of fluxes stored as A = Fx + Fy, B = Fx - Fy, C = Fz, from which each
+// thread forms the partial divergence of its cell for that vertex plane:
+//   P = A(i,j) - A(i-1,j-1) + B(i,j-1) - B(i-1,j),  Q = sum of C over the 4
+// vertices, and div = (P_below + P_above + Q_above - Q_below) / (4h).
+// The global loads of plane k+3 are issued before plane k is computed.
 // ===========================================================================
 constexpr int R3_VW = T3X + 4, R3_VH = T3Y + 4, R3_VP = R3_VW * R3_VH;
 constexpr int R3_LW = T3X + 2, R3_LH = T3Y + 2, R3_LP = R3_LW * R3_LH;
 constexpr int R3_FW = T3X + 1, R3_FH = T3Y + 1, R3_FP = R3_FW * R3_FH;
-constexpr int R3_LDS = 4 * R3_VP + 3 * R3_LP + 2 * 3 * R3_FP;
+constexpr int R3_VRING = R3_VP - T3X * T3Y;   // 176 halo cells of a v plane
+constexpr int R3_LRING = R3_LP - T3X * T3Y;   // 84 halo cells of a Laplacian plane
+constexpr int R3_FRING = R3_FP - T3X * T3Y;   // 41 halo vertices of a flux plane
+constexpr int R3_LDS = 3 * R3_VP + 2 * R3_LP + 3 * R3_FP;
+constexpr int R3H_LDS = R3_LDS + 3 * R3_VP;   // Hessian mode: 3 more planes (u*)
+static_assert(R3_VRING <= PSD_NT && R3_LRING <= PSD_NT && R3_FRING <= PSD_NT, "ring sizes");
+
+// position in the v plane buffer of halo cell number t (0 <= t < R3_VRING)
+__device__ __forceinline__ int r3_vring_pos(int t) {
+  if (t < 4 * R3_VW) {                          // rows 0, 1, VH-2, VH-1
+    const int r = t / R3_VW, ex = t - r * R3_VW;
+    const int ey = r < 2 ? r : r + (R3_VH - 4);
+    return ey * R3_VW + ex;
+  }
+  const int q = t - 4 * R3_VW;                  // columns 0, 1, VW-2, VW-1 of rows 2..VH-3
+  const int ey = 2 + (q >> 2), c = q & 3;
+  const int ex = c < 2 ? c : c + (R3_VW - 4);
+  return ey * R3_VW + ex;
+}
+// position in the Laplacian plane buffer of halo cell number t (< R3_LRING)
+__device__ __forceinline__ int r3_lring_pos(int t) {
+  if (t < 2 * R3_LW) {
+    const int r = t / R3_LW, lx = t - r * R3_LW;
+    return (r == 0 ? 0 : R3_LH - 1) * R3_LW + lx;
+  }
+  const int q = t - 2 * R3_LW;
+  const int ly = 1 + (q >> 1);
+  return ly * R3_LW + ((q & 1) ? R3_LW - 1 : 0);
+}
+// position in the flux plane buffer of halo vertex number t (< R3_FRING)
+__device__ __forceinline__ int r3_fring_pos(int t) {
+  if (t < R3_FW) return t;                      // row y0-1
+  return (t - R3_FW + 1) * R3_FW;               // column x0-1, rows 1..FH-1
+}
+
+template <typename TD>
+struct R3Prefetch {
+  double u_own, u_ring;
+  TD d_own, d_ring;
+};
 
 template <typename TD, bool UPD>
-__device__ __forceinline__ void r3_load_plane(const Inst& I, const double* __restrict__ u,
-                                              const TD* __restrict__ d, double alpha, int x0, int y0,
-                                              int z, double* vp) {
-  const int n = I.n;
+__device__ __forceinline__ void r3_fetch(const double* __restrict__ u, const TD* __restrict__ d, int n,
+                                         int x0, int y0, int z, int ring_ey, int ring_ex,
+                                         R3Prefetch<TD>& pf) {
   const long long zo = (long long)wrapi(z, n) * n * n;
-  for (int e = threadIdx.x; e < R3_VP; e += PSD_NT) {
-    const int ey = e / R3_VW, ex = e - ey * R3_VW;
-    const int gx = wrapi(x0 - 2 + ex, n), gy = wrapi(y0 - 2 + ey, n);
-    const long long gi = zo + gx + (long long)n * gy;
-    double val = u[gi];
-    if (UPD) val += alpha * (double)d[gi];
-    vp[e] = val;
+  const int tx = threadIdx.x % T3X, ty = threadIdx.x / T3X;
+  const long long go = zo + wrapi(x0 + tx, n) + (long long)n * wrapi(y0 + ty, n);
+  pf.u_own = u[go];
+  if (UPD) pf.d_own = d[go];
+  if (threadIdx.x < R3_VRING) {
+    const long long gr = zo + wrapi(x0 - 2 + ring_ex, n) + (long long)n * wrapi(y0 - 2 + ring_ey, n);
+    pf.u_ring = u[gr];
+    if (UPD) pf.d_ring = d[gr];
   }
 }
 
-__device__ __forceinline__ void r3_lap_plane(const double* vm, const double* v0, const double* vp,
-                                             double* lp, double ih2) {
-  for (int e = threadIdx.x; e < R3_LP; e += PSD_NT) {
-    const int ly = e / R3_LW, lx = e - ly * R3_LW;
-    const int c = (ly + 1) * R3_VW + lx + 1;
-    lp[e] = (v0[c - 1] + v0[c + 1] + v0[c - R3_VW] + v0[c + R3_VW] + vm[c] + vp[c] - 6.0 * v0[c]) * ih2;
-  }
+// flux at one vertex from the 8 surrounding cell values; stores A, B, C
+__device__ __forceinline__ void r3_vertex_flux(const Inst& I, double qh, double c000, double c100,
+                                               double c010, double c110, double c001, double c101,
+                                               double c011, double c111, double& A, double& B,
+                                               double& C) {
+  const double gx = qh * ((c100 - c000) + (c110 - c010) + (c101 - c001) + (c111 - c011));
+  const double gy = qh * ((c010 - c000) + (c110 - c100) + (c011 - c001) + (c111 - c101));
+  const double gz = qh * ((c001 - c000) + (c101 - c100) + (c011 - c010) + (c111 - c110));
+  const double rr = flux_r(gx * gx + gy * gy + gz * gz, I.p, I.p_is_4, I.p_is_2);
+  const double fx = rr * gx, fy = rr * gy;
+  A = fx + fy;
+  B = fx - fy;
+  C = rr * gz;
 }
 
-// fluxes at vertex plane between cell planes v0 (lower) and v1 (upper)
-__device__ __forceinline__ void r3_flux_plane(const Inst& I, const double* v0, const double* v1,
-                                              double* F, double qh) {
-  for (int e = threadIdx.x; e < R3_FP; e += PSD_NT) {
-    const int fy = e / R3_FW, fx = e - fy * R3_FW;
-    const int c = (fy + 1) * R3_VW + fx + 1;
-    const double c000 = v0[c], c100 = v0[c + 1], c010 = v0[c + R3_VW], c110 = v0[c + R3_VW + 1];
-    const double c001 = v1[c], c101 = v1[c + 1], c011 = v1[c + R3_VW], c111 = v1[c + R3_VW + 1];
-    const double gx = qh * ((c100 - c000) + (c110 - c010) + (c101 - c001) + (c111 - c011));
-    const double gy = qh * ((c010 - c000) + (c110 - c100) + (c011 - c001) + (c111 - c101));
-    const double gz = qh * ((c001 - c000) + (c101 - c100) + (c011 - c010) + (c111 - c110));
-    const double rr = flux_r(gx * gx + gy * gy + gz * gz, I.p, I.p_is_4, I.p_is_2);
-    F[e] = rr * gx;
-    F[R3_FP + e] = rr * gy;
-    F[2 * R3_FP + e] = rr * gz;
-  }
+// HESS: Hessian-vector product (see res2d_tile); the "d" stream carries u*.
+// linearised flux at a vertex: c*** cells of xi, s*** cells of u*
+__device__ __forceinline__ void r3_vertex_flux_lin(
+    const Inst& I, double qh, double c000, double c100, double c010, double c110, double c001,
+    double c101, double c011, double c111, double s000, double s100, double s010, double s110,
+    double s001, double s101, double s011, double s111, double& A, double& B, double& C) {
+  const double bx = qh * ((c100 - c000) + (c110 - c010) + (c101 - c001) + (c111 - c011));
+  const double by = qh * ((c010 - c000) + (c110 - c100) + (c011 - c001) + (c111 - c101));
+  const double bz = qh * ((c001 - c000) + (c101 - c100) + (c011 - c010) + (c111 - c110));
+  const double ax = qh * ((s100 - s000) + (s110 - s010) + (s101 - s001) + (s111 - s011));
+  const double ay = qh * ((s010 - s000) + (s110 - s100) + (s011 - s001) + (s111 - s101));
+  const double az = qh * ((s001 - s000) + (s101 - s100) + (s011 - s010) + (s111 - s110));
+  double fx, fy, fz;
+  flux_lin(I, ax, ay, az, bx, by, bz, fx, fy, fz);
+  A = fx + fy;
+  B = fx - fy;
+  C = fz;
 }
 
-template <typename TD, typename TR, bool UPD>
+template <typename TD, typename TR, bool UPD, bool HESS = false>
 __device__ void res3d_tile(const Inst& I, int x0, int y0, int z0, double* lds, double (&acc)[2]) {
+  static_assert(!(HESS && UPD), "no update in Hessian mode");
+  static_assert(!HESS || sizeof(TD) == 8, "u* is FP64");
+  constexpr bool LOADD = UPD || HESS;
   const int n = I.n;
   const SolveState* st = I.st;
   const int cur = st->iter & 1;
   const double alpha = UPD ? st->alpha : 0.0;
-  const double* __restrict__ u = I.u[cur];
+  const double* __restrict__ u = HESS ? I.adj_p : I.u[cur];
   double* __restrict__ uo = I.u[cur ^ 1];
-  const TD* __restrict__ d = (const TD*)I.d;
-  double* vb = lds;                    // 4 planes
-  double* lb = vb + 4 * R3_VP;         // 3 planes
-  double* fb = lb + 3 * R3_LP;         // 2 vertex planes x 3 components
+  const TD* __restrict__ d = HESS ? (const TD*)I.adj_us : (const TD*)I.d;
+  double* sb = lds + R3_LDS;           // Hessian mode: 3 planes of u*
+  double* vb = lds;                    // 3 v planes
+  double* lb = vb + 3 * R3_VP;         // 2 Laplacian planes
+  double* fA = lb + 2 * R3_LP;         // one vertex plane: A, B, C
+  double* fB = fA + R3_FP;
+  double* fC = fB + R3_FP;
   const double ih = I.inv_h, ih2 = ih * ih, qh = 0.25 * ih;
   const double s = I.s, se2 = I.se2;
   const int z1 = min(z0 + T3Z, n);
-  // prologue: v planes z0-2 .. z0+1, lap z0-1, z0, flux plane z0-1
-  for (int q = -2; q <= 1; ++q) r3_load_plane<TD, UPD>(I, u, d, alpha, x0, y0, z0 + q, vb + ((z0 + q + 8) & 3) * R3_VP);
-  __syncthreads();
-  for (int q = -1; q <= 0; ++q)
-    r3_lap_plane(vb + ((z0 + q - 1 + 8) & 3) * R3_VP, vb + ((z0 + q + 8) & 3) * R3_VP,
-                 vb + ((z0 + q + 1 + 8) & 3) * R3_VP, lb + ((z0 + q + 3) % 3) * R3_LP, ih2);
-  r3_flux_plane(I, vb + ((z0 - 1 + 8) & 3) * R3_VP, vb + ((z0 + 8) & 3) * R3_VP,
-                fb + ((z0 - 1 + 2) & 1) * 3 * R3_FP, qh);
-  __syncthreads();  // the first in-loop load reuses the slot of plane z0-2
-  const int tx = threadIdx.x % T3X, ty = threadIdx.x / T3X;
+  const int tid = threadIdx.x;
+  const int tx = tid % T3X, ty = tid / T3X;
+  const int vown = (ty + 2) * R3_VW + tx + 2;      // own cell in a v plane
+  const int lown = (ty + 1) * R3_LW + tx + 1;      // own cell in a Laplacian plane
+  const int fown = (ty + 1) * R3_FW + tx + 1;      // own vertex (i+1/2, j+1/2)
+  const int vring = tid < R3_VRING ? r3_vring_pos(tid) : 0;
+  const int ring_ey = vring / R3_VW, ring_ex = vring - ring_ey * R3_VW;
+  const int lring = tid < R3_LRING ? r3_lring_pos(tid) : 0;
+  const int fring = tid < R3_FRING ? r3_fring_pos(tid) : 0;
   const int gx = x0 + tx, gy = y0 + ty;
   const bool own = gx < n && gy < n;
-  for (int k = z0; k < z1; ++k) {
-    r3_load_plane<TD, UPD>(I, u, d, alpha, x0, y0, k + 2, vb + ((k + 2) & 3) * R3_VP);
+
+  // own-column registers: v at planes j, j+1, j+2; Laplacian at j-1, j, j+1;
+  // Hessian mode: u* at planes j, j+1, j+2
+  double vc0 = 0.0, vc1 = 0.0, vc2 = 0.0, lm = 0.0, l0 = 0.0, lp = 0.0;
+  double sc0 = 0.0, sc1 = 0.0, sc2 = 0.0;
+  double P_old = 0.0, Q_old = 0.0;
+  R3Prefetch<TD> pf;
+  // planes z0-2 and z0-1 go straight to LDS; plane z0 is prefetched
+  for (int q = -2; q <= -1; ++q) {
+    r3_fetch<TD, LOADD>(u, d, n, x0, y0, z0 + q, ring_ey, ring_ex, pf);
+    const int sl = ((z0 + q + 6) % 3) * R3_VP;
+    const double vo = UPD ? pf.u_own + alpha * (double)pf.d_own : pf.u_own;
+    vb[sl + vown] = vo;
+    if (tid < R3_VRING) vb[sl + vring] = UPD ? pf.u_ring + alpha * (double)pf.d_ring : pf.u_ring;
+    vc1 = vc2;
+    vc2 = vo;
+    if (HESS) {
+      sb[sl + vown] = (double)pf.d_own;
+      if (tid < R3_VRING) sb[sl + vring] = (double)pf.d_ring;
+      sc1 = sc2;
+      sc2 = (double)pf.d_own;
+    }
+  }
+  r3_fetch<TD, LOADD>(u, d, n, x0, y0, z0, ring_ey, ring_ex, pf);
+
+  for (int j = z0 - 2; j < z1; ++j) {
+    // store plane j+2 (prefetched), then prefetch plane j+3
+    double* vn = vb + ((j + 2 + 6) % 3) * R3_VP;
+    const double vo = UPD ? pf.u_own + alpha * (double)pf.d_own : pf.u_own;
+    vn[vown] = vo;
+    if (tid < R3_VRING) vn[vring] = UPD ? pf.u_ring + alpha * (double)pf.d_ring : pf.u_ring;
+    vc0 = vc1; vc1 = vc2; vc2 = vo;
+    if (HESS) {
+      double* sn = sb + ((j + 2 + 6) % 3) * R3_VP;
+      sn[vown] = (double)pf.d_own;
+      if (tid < R3_VRING) sn[vring] = (double)pf.d_ring;
+      sc0 = sc1; sc1 = sc2; sc2 = (double)pf.d_own;
+    }
+    if (j + 1 < z1) r3_fetch<TD, LOADD>(u, d, n, x0, y0, j + 3, ring_ey, ring_ex, pf);
     __syncthreads();
-    r3_lap_plane(vb + (k & 3) * R3_VP, vb + ((k + 1) & 3) * R3_VP, vb + ((k + 2) & 3) * R3_VP,
-                 lb + ((k + 1) % 3) * R3_LP, ih2);
-    r3_flux_plane(I, vb + (k & 3) * R3_VP, vb + ((k + 1) & 3) * R3_VP, fb + ((k + 2) & 1) * 3 * R3_FP, qh);
+    const double* v0 = vb + ((j + 6) % 3) * R3_VP;       // plane j
+    const double* v1 = vb + ((j + 1 + 6) % 3) * R3_VP;   // plane j+1
+    const double* v2 = vn;                                // plane j+2
+    // Laplacian of plane j+1: own cell (z neighbours from registers) and ring
+    double* ln = lb + ((j + 1 + 2) & 1) * R3_LP;
+    {
+      const int c = vown;
+      const double lap = (v1[c - 1] + v1[c + 1] + v1[c - R3_VW] + v1[c + R3_VW] + vc0 + vc2 - 6.0 * vc1) * ih2;
+      ln[lown] = lap;
+      lm = l0; l0 = lp; lp = lap;
+      if (tid < R3_LRING) {
+        const int ly = lring / R3_LW, lx = lring - ly * R3_LW;
+        const int cc = (ly + 1) * R3_VW + lx + 1;
+        ln[lring] = (v1[cc - 1] + v1[cc + 1] + v1[cc - R3_VW] + v1[cc + R3_VW] + v0[cc] + v2[cc] - 6.0 * v1[cc]) * ih2;
+      }
+    }
+    // fluxes at vertex plane j+1/2 (cells j, j+1) and the partial divergence
+    double A_own = 0.0, C_own = 0.0;
+    if (j >= z0 - 1) {
+      const double* s0 = sb + ((j + 6) % 3) * R3_VP;
+      const double* s1 = sb + ((j + 1 + 6) % 3) * R3_VP;
+      {
+        const int c = vown;  // own vertex: cell (i, j) of the vertex is the own cell
+        double A, B, C;
+        if (HESS)
+          r3_vertex_flux_lin(I, qh, vc0, v0[c + 1], v0[c + R3_VW], v0[c + R3_VW + 1], vc1, v1[c + 1],
+                             v1[c + R3_VW], v1[c + R3_VW + 1], sc0, s0[c + 1], s0[c + R3_VW],
+                             s0[c + R3_VW + 1], sc1, s1[c + 1], s1[c + R3_VW], s1[c + R3_VW + 1], A, B, C);
+        else
+          r3_vertex_flux(I, qh, vc0, v0[c + 1], v0[c + R3_VW], v0[c + R3_VW + 1], vc1, v1[c + 1],
+                         v1[c + R3_VW], v1[c + R3_VW + 1], A, B, C);
+        fA[fown] = A; fB[fown] = B; fC[fown] = C;
+        A_own = A; C_own = C;
+      }
+      if (tid < R3_FRING) {
+        const int fy = fring / R3_FW, fx = fring - fy * R3_FW;
+        const int c = (fy + 1) * R3_VW + fx + 1;
+        double A, B, C;
+        if (HESS)
+          r3_vertex_flux_lin(I, qh, v0[c], v0[c + 1], v0[c + R3_VW], v0[c + R3_VW + 1], v1[c], v1[c + 1],
+                             v1[c + R3_VW], v1[c + R3_VW + 1], s0[c], s0[c + 1], s0[c + R3_VW],
+                             s0[c + R3_VW + 1], s1[c], s1[c + 1], s1[c + R3_VW], s1[c + R3_VW + 1], A, B, C);
+        else
+          r3_vertex_flux(I, qh, v0[c], v0[c + 1], v0[c + R3_VW], v0[c + R3_VW + 1], v1[c], v1[c + 1],
+                         v1[c + R3_VW], v1[c + R3_VW + 1], A, B, C);
+        fA[fring] = A; fB[fring] = B; fC[fring] = C;
+      }
+    }
     __syncthreads();
-    if (own) {
-      const double* F0 = fb + ((k + 1) & 1) * 3 * R3_FP;  // vertex plane k-1/2
-      const double* F1 = fb + ((k + 2) & 1) * 3 * R3_FP;  // vertex plane k+1/2
-      const int fc = (ty + 1) * R3_FW + tx + 1;
-      const int fx = fc - 1, fy = fc - R3_FW, fxy = fc - R3_FW - 1;
-      const double* Fx0 = F0; const double* Fy0 = F0 + R3_FP; const double* Fz0 = F0 + 2 * R3_FP;
-      const double* Fx1 = F1; const double* Fy1 = F1 + R3_FP; const double* Fz1 = F1 + 2 * R3_FP;
-      const double dx = (Fx1[fc] - Fx1[fx]) + (Fx1[fy] - Fx1[fxy]) + (Fx0[fc] - Fx0[fx]) + (Fx0[fy] - Fx0[fxy]);
-      const double dy = (Fy1[fc] - Fy1[fy]) + (Fy1[fx] - Fy1[fxy]) + (Fy0[fc] - Fy0[fy]) + (Fy0[fx] - Fy0[fxy]);
-      const double dz = (Fz1[fc] - Fz0[fc]) + (Fz1[fx] - Fz0[fx]) + (Fz1[fy] - Fz0[fy]) + (Fz1[fxy] - Fz0[fxy]);
-      const double div = qh * (dx + dy + dz);
-      const double* lm = lb + ((k + 2) % 3) * R3_LP;  // plane k-1
-      const double* l0 = lb + (k % 3) * R3_LP;
-      const double* lp = lb + ((k + 1) % 3) * R3_LP;
-      const int lc = (ty + 1) * R3_LW + tx + 1;
-      const double l2 = (l0[lc - 1] + l0[lc + 1] + l0[lc - R3_LW] + l0[lc + R3_LW] + lm[lc] + lp[lc] - 6.0 * l0[lc]) * ih2;
-      const double vc = vb[(k & 3) * R3_VP + (ty + 2) * R3_VW + tx + 2];
-      const long long gi = gx + (long long)n * (gy + (long long)n * k);
-      const double r = I.f[gi] - (vc - s * div + se2 * l2);
-      ((TR*)I.r)[gi] = (TR)r;
-      if (UPD) uo[gi] = vc;
-      acc[0] = fmax(acc[0], fabs(r));
-      acc[1] += r * r;
+    if (j >= z0 - 1) {
+      const int fx = fown - 1, fy = fown - R3_FW, fxy = fown - R3_FW - 1;
+      const double P = A_own - fA[fxy] + fB[fy] - fB[fx];
+      const double Q = C_own + fC[fx] + fC[fy] + fC[fxy];
+      if (j >= z0 && own) {
+        // output plane j: v(j) = vc0, Laplacian planes j-1, j, j+1 = lm, l0, lp
+        const double div = qh * (P + P_old + Q - Q_old);
+        const double* lc = lb + ((j + 2) & 1) * R3_LP;   // Laplacian plane j
+        const double l2 = (lc[lown - 1] + lc[lown + 1] + lc[lown - R3_LW] + lc[lown + R3_LW] + lm + lp - 6.0 * l0) * ih2;
+        const long long gi = gx + (long long)n * (gy + (long long)n * j);
+        if (HESS) {
+          const double hx = vc0 - s * div + se2 * l2;
+          I.adj_Hp[gi] = hx;
+          acc[1] += vc0 * hx;
+        } else {
+          const double r = I.f[gi] - (vc0 - s * div + se2 * l2);
+          ((TR*)I.r)[gi] = (TR)r;
+          if (UPD) uo[gi] = vc0;
+          acc[0] = fmax(acc[0], fabs(r));
+          acc[1] += r * r;
+        }
+      }
+      P_old = P;
+      Q_old = Q;
     }
   }
 }
@@ -309,21 +490,32 @@ __device__ void ls2d_tile(const Inst& I, int mode, int x0, int y0, double* lds, 
   }
 }
 
+// 3D line-search sums: the same column tiling; own-column u (planes k,
+// k+1) and d (planes k-1, k, k+1) in registers, xy-halo of 3 planes of u and
+// d in LDS (halo 1), loads of plane k+2 issued before plane k is reduced.
 constexpr int L3_W = T3X + 2, L3_H = T3Y + 2, L3_P = L3_W * L3_H;
-constexpr int L3_LDS = 6 * L3_P;  // u: 3 planes, d: 3 planes
+constexpr int L3_RING = L3_P - T3X * T3Y;   // 84
+constexpr int L3_LDS = 6 * L3_P;            // u: 3 planes, d: 3 planes
 
 template <typename TD>
-__device__ __forceinline__ void l3_load(const Inst& I, const double* __restrict__ u,
-                                        const TD* __restrict__ d, int x0, int y0, int z,
-                                        double* up, double* dp) {
-  const int n = I.n;
+struct L3Prefetch {
+  double u_own, u_ring;
+  TD d_own, d_ring;
+};
+
+template <typename TD>
+__device__ __forceinline__ void l3_fetch(const double* __restrict__ u, const TD* __restrict__ d, int n,
+                                         int x0, int y0, int z, int ring_ey, int ring_ex,
+                                         L3Prefetch<TD>& pf) {
   const long long zo = (long long)wrapi(z, n) * n * n;
-  for (int e = threadIdx.x; e < L3_P; e += PSD_NT) {
-    const int ey = e / L3_W, ex = e - ey * L3_W;
-    const int gx = wrapi(x0 - 1 + ex, n), gy = wrapi(y0 - 1 + ey, n);
-    const long long gi = zo + gx + (long long)n * gy;
-    up[e] = u[gi];
-    dp[e] = (double)d[gi];
+  const int tx = threadIdx.x % T3X, ty = threadIdx.x / T3X;
+  const long long go = zo + wrapi(x0 + tx, n) + (long long)n * wrapi(y0 + ty, n);
+  pf.u_own = u[go];
+  pf.d_own = d[go];
+  if (threadIdx.x < L3_RING) {
+    const long long gr = zo + wrapi(x0 - 1 + ring_ex, n) + (long long)n * wrapi(y0 - 1 + ring_ey, n);
+    pf.u_ring = u[gr];
+    pf.d_ring = d[gr];
   }
 }
 
@@ -339,24 +531,44 @@ __device__ void ls3d_tile(const Inst& I, int mode, int x0, int y0, int z0, doubl
   double* db = lds + 3 * L3_P;
   const double qh = 0.25 * I.inv_h, ih2 = I.inv_h * I.inv_h;
   const int z1 = min(z0 + T3Z, n);
-  l3_load<TD>(I, u, d, x0, y0, z0 - 1, ub + ((z0 + 2) % 3) * L3_P, db + ((z0 + 2) % 3) * L3_P);
-  l3_load<TD>(I, u, d, x0, y0, z0, ub + (z0 % 3) * L3_P, db + (z0 % 3) * L3_P);
-  const int tx = threadIdx.x % T3X, ty = threadIdx.x / T3X;
+  const int tid = threadIdx.x;
+  const int tx = tid % T3X, ty = tid / T3X;
   const bool own = x0 + tx < n && y0 + ty < n;
-  const int c = (ty + 1) * L3_W + tx + 1;
+  const int c = (ty + 1) * L3_W + tx + 1;           // own cell in a plane buffer
+  const int ring = tid < L3_RING ? r3_lring_pos(tid) : 0;   // same ring shape as a Laplacian plane
+  const int ring_ey = ring / L3_W, ring_ex = ring - ring_ey * L3_W;
+  double uc0 = 0.0, uc1 = 0.0, dm = 0.0, dc0 = 0.0, dc1 = 0.0;
+  L3Prefetch<TD> pf;
+  for (int q = -1; q <= 0; ++q) {
+    l3_fetch<TD>(u, d, n, x0, y0, z0 + q, ring_ey, ring_ex, pf);
+    const int sl = ((z0 + q + 3) % 3) * L3_P;
+    ub[sl + c] = pf.u_own;
+    db[sl + c] = (double)pf.d_own;
+    if (tid < L3_RING) { ub[sl + ring] = pf.u_ring; db[sl + ring] = (double)pf.d_ring; }
+    uc0 = uc1; uc1 = pf.u_own;
+    dm = dc0; dc0 = dc1; dc1 = (double)pf.d_own;
+  }
+  // now uc1 = u(z0), dc0 = d(z0-1), dc1 = d(z0)
+  l3_fetch<TD>(u, d, n, x0, y0, z0 + 1, ring_ey, ring_ex, pf);
   for (int k = z0; k < z1; ++k) {
-    l3_load<TD>(I, u, d, x0, y0, k + 1, ub + ((k + 1) % 3) * L3_P, db + ((k + 1) % 3) * L3_P);
+    const int sn = ((k + 1 + 3) % 3) * L3_P;
+    ub[sn + c] = pf.u_own;
+    db[sn + c] = (double)pf.d_own;
+    if (tid < L3_RING) { ub[sn + ring] = pf.u_ring; db[sn + ring] = (double)pf.d_ring; }
+    uc0 = uc1; uc1 = pf.u_own;
+    dm = dc0; dc0 = dc1; dc1 = (double)pf.d_own;
+    if (k + 1 < z1) l3_fetch<TD>(u, d, n, x0, y0, k + 2, ring_ey, ring_ex, pf);
     __syncthreads();
     if (own) {
-      const double* u0 = ub + (k % 3) * L3_P;
-      const double* u1 = ub + ((k + 1) % 3) * L3_P;
-      const double* d0 = db + (k % 3) * L3_P;
-      const double* d1 = db + ((k + 1) % 3) * L3_P;
-      const double* dm = db + ((k + 2) % 3) * L3_P;
-      const double a000 = u0[c], a100 = u0[c + 1], a010 = u0[c + L3_W], a110 = u0[c + L3_W + 1];
-      const double a001 = u1[c], a101 = u1[c + 1], a011 = u1[c + L3_W], a111 = u1[c + L3_W + 1];
-      const double b000 = d0[c], b100 = d0[c + 1], b010 = d0[c + L3_W], b110 = d0[c + L3_W + 1];
-      const double b001 = d1[c], b101 = d1[c + 1], b011 = d1[c + L3_W], b111 = d1[c + L3_W + 1];
+      const double* u0 = ub + ((k + 3) % 3) * L3_P;
+      const double* u1 = ub + sn;
+      const double* d0 = db + ((k + 3) % 3) * L3_P;
+      const double* d1 = db + sn;
+      const double a100 = u0[c + 1], a010 = u0[c + L3_W], a110 = u0[c + L3_W + 1];
+      const double a101 = u1[c + 1], a011 = u1[c + L3_W], a111 = u1[c + L3_W + 1];
+      const double b100 = d0[c + 1], b010 = d0[c + L3_W], b110 = d0[c + L3_W + 1];
+      const double b101 = d1[c + 1], b011 = d1[c + L3_W], b111 = d1[c + L3_W + 1];
+      const double a000 = uc0, a001 = uc1, b000 = dc0, b001 = dc1;
       const double ax = qh * ((a100 - a000) + (a110 - a010) + (a101 - a001) + (a111 - a011));
       const double ay = qh * ((a010 - a000) + (a110 - a100) + (a011 - a001) + (a111 - a101));
       const double az = qh * ((a001 - a000) + (a101 - a100) + (a011 - a010) + (a111 - a110));
@@ -364,11 +576,10 @@ __device__ void ls3d_tile(const Inst& I, int mode, int x0, int y0, int z0, doubl
       const double by = qh * ((b010 - b000) + (b110 - b100) + (b011 - b001) + (b111 - b101));
       const double bz = qh * ((b001 - b000) + (b101 - b100) + (b011 - b010) + (b111 - b110));
       ls_vertex(mode, I.p, alpha, ax, ay, az, bx, by, bz, acc);
-      const double ld = (d0[c - 1] + d0[c + 1] + d0[c - L3_W] + d0[c + L3_W] + dm[c] + d1[c] - 6.0 * b000) * ih2;
+      const double ld = (d0[c - 1] + d0[c + 1] + d0[c - L3_W] + d0[c + L3_W] + dm + dc1 - 6.0 * dc0) * ih2;
       if (mode == 0) { acc[4] += b000 * b000; acc[5] += ld * ld; }
       else { acc[2] += b000 * b000; acc[3] += ld * ld; }
     }
-    __syncthreads();
   }
 }
 

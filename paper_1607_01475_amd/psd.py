@@ -259,3 +259,50 @@ class Solver:
         self._check(self._lib.psd_adjoint(self._h, _ptr_array(u_star), _ptr_array(dJdu),
                                           _ptr_array(dJdf), ds, de, float(rtol), int(max_iter), it))
         return dJdf, list(ds), list(de), list(it)
+
+
+class PSDSolveFn(torch.autograd.Function):
+    """u* = PSD solve of N_h[u] = f (order 4) with an implicit adjoint.
+
+    forward(f, s, eps, solver): f has shape (B, n, ..) for a solver of batch B
+    (or (n, ..) when B = 1); s and eps are 0-d tensors that must equal the
+    solver's problem values (they are inputs so that autograd can return
+    their gradients).  backward solves H lam = dJ/du by the library's
+    preconditioned conjugate gradients (psd_adjoint): dJ/df = lam,
+    dJ/ds = -lam.dN/ds, dJ/deps = -lam.dN/deps; no solver trajectory is kept.
+    """
+
+    @staticmethod
+    def forward(ctx, f, s, eps, solver, adj_rtol=1e-12, adj_max_iter=500):
+        for P in solver.problems:
+            if abs(P.s - float(s)) > 1e-15 * abs(P.s) or abs(P.eps - float(eps)) > 1e-15 * abs(P.eps):
+                raise ValueError("s and eps must match the solver's problems")
+        batched = f.dim() == solver.problems[0].dim + 1
+        fs = list(f.detach().contiguous()) if batched else [f.detach().contiguous()]
+        us = [torch.zeros_like(x) for x in fs]
+        stats = solver.solve(fs, us)
+        for st in stats:
+            if st.status != PSD_OK:
+                raise PSDError(st.status, "forward solve did not converge")
+        u = torch.stack(us) if batched else us[0]
+        ctx.solver, ctx.batched = solver, batched
+        ctx.adj_rtol, ctx.adj_max_iter = adj_rtol, adj_max_iter
+        ctx.save_for_backward(u)
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        (u,) = ctx.saved_tensors
+        us = list(u) if ctx.batched else [u]
+        gs = list(grad_u.contiguous()) if ctx.batched else [grad_u.contiguous()]
+        gs = [g.contiguous() for g in gs]
+        dJdf, ds, de, _ = ctx.solver.adjoint(us, gs, rtol=ctx.adj_rtol, max_iter=ctx.adj_max_iter)
+        gf = torch.stack(dJdf) if ctx.batched else dJdf[0]
+        dev = grad_u.device
+        return (gf, torch.tensor(sum(ds), dtype=torch.float64, device=dev),
+                torch.tensor(sum(de), dtype=torch.float64, device=dev), None, None, None)
+
+
+def solve_differentiable(f, s, eps, solver, adj_rtol=1e-12, adj_max_iter=500):
+    """Functional form of PSDSolveFn.apply."""
+    return PSDSolveFn.apply(f, s, eps, solver, adj_rtol, adj_max_iter)
