@@ -79,7 +79,8 @@ enum { PSD_FP64 = 0, PSD_MIXED = 1 };
  *               after every iteration.  k > 0: k iterations are captured once
  *               in a HIP graph and replayed until the device flag says done
  *   history     non-zero: record per-update (alpha, ||r||_inf, ||r||_2, dE)
- *   profile     non-zero: per-pass kernel timing of psd_solve (psd_pass_times) */
+ *   profile     non-zero: per-pass kernel timing of psd_solve (psd_pass_times)
+ *   autotune    non-zero: pick stencil tilings by timing at creation */
 typedef struct {
     double tol;
     int max_iter;
@@ -88,6 +89,10 @@ typedef struct {
     int history;
     int profile;   /* non-zero: time every kernel launch with HIP events on the
                       solver stream (see psd_pass_times) */
+    int autotune;  /* non-zero: at psd_create, time the stencil-kernel tilings
+                      (3D z-chunk 8/16/32/64, natural or XCD-grouped block order)
+                      on this handle's buffers and keep the fastest; results are
+                      cached in the file named by PSD_TUNE_CACHE when set */
 } psd_options;
 
 /* Per-instance result.  energy is E_h at the final iterate (Sec. 5.3 and
@@ -181,6 +186,11 @@ enum {
  * stream) of the launches of pass k, launches[k] = their number (all zero in
  * graph mode).  Arrays of PSD_NPASS entries, host memory. */
 psd_status psd_pass_times(psd_handle* h, double* ms, int* launches);
+
+/* Tiling chosen for the stencil kernels (after autotuning or defaults):
+ * out[0..3] = z-chunk of the residual, z-chunk of the line search,
+ * XCD-grouped order of the residual (0/1), of the line search (0/1). */
+psd_status psd_tuning(const psd_handle* h, int* out4);
 
 /* Destroy the handle and free its workspace. */
 psd_status psd_destroy(psd_handle* h);

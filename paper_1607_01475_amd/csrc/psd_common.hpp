@@ -95,7 +95,10 @@ struct Inst {
   double* adj_p;          // CG direction
   double* adj_Hp;         // Hessian times direction
   int nblk_res, nblk_ls, nblk_sp, hist_cap;
-  int nblk_c2r, pad1;
+  int nblk_c2r;
+  int zchunk_res;      // 3D: z-planes marched per residual block (tuned)
+  int zchunk_ls;       // 3D: z-planes marched per line-search block (tuned)
+  int pad1;
 };
 
 // A block's unit of work: instance and up to three integer coordinates.

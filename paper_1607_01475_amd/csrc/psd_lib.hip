@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -99,6 +100,10 @@ struct psd_handle_s {
   hipGraph_t graph = nullptr;
   int gchunk = 0;
   bool adj_alloc = false;
+  // tuning (autotuner or defaults)
+  int tune_zc_res = T3Z, tune_zc_ls = T3Z;
+  bool tune_xcd_res = false, tune_xcd_ls = false;
+  size_t dT_cap = 0;
   std::string err;
   // profiling: events around every pass launch, in launch order
   struct ProfRec { int pass; int iter_slot; hipEvent_t a, b; };
@@ -277,10 +282,26 @@ static void build_fft_tasks(psd_handle* h, FftTasks& F, int nfi, int nfo, bool w
   R.cnt = (int)h->hT.size() - R.off;
 }
 
+// XCD-aware order of a launch's task list: MI355X hands workgroup i to XCD
+// (i mod 8); with this permutation XCD x receives a contiguous run of the
+// natural (spatial) order, so tiles that share halos share an L2.
+static void xcd_permute(std::vector<Task2>& v, size_t off, size_t cnt) {
+  if (cnt < 16) return;
+  std::vector<Task2> nat(v.begin() + off, v.begin() + off + cnt);
+  const size_t q = cnt / 8, r = cnt % 8;
+  for (size_t i = 0; i < cnt; ++i) {
+    const size_t x = i % 8, k = i / 8;
+    const size_t start = x * q + std::min(x, r);
+    v[off + i] = nat[start + k];
+  }
+}
+
 static void build_tile_tasks(psd_handle* h) {
-  // residual and line-search tiles share the same tiling
+  // residual and line-search tiles: same (x, y) tiling, own z-chunk and order
   for (int pass = 0; pass < 2; ++pass) {
     Range& R = pass == 0 ? h->res : h->ls;
+    const int zc = pass == 0 ? h->tune_zc_res : h->tune_zc_ls;
+    const bool xcd = pass == 0 ? h->tune_xcd_res : h->tune_xcd_ls;
     R.off = (int)h->hT.size();
     for (int b = 0; b < h->batch; ++b) {
       Inst& I = h->hI[b];
@@ -292,20 +313,40 @@ static void build_tile_tasks(psd_handle* h) {
             h->hT.push_back(t);
           }
       } else {
-        for (int z0 = 0; z0 < I.n; z0 += T3Z)
+        const int z = std::min(zc, I.n);
+        for (int z0 = 0; z0 < I.n; z0 += z)
           for (int y0 = 0; y0 < I.n; y0 += T3Y)
             for (int x0 = 0; x0 < I.n; x0 += T3X) {
               Task2 t{}; t.inst = b; t.a = x0; t.b = y0; t.c = z0; t.slot = slot++;
               h->hT.push_back(t);
             }
+        if (pass == 0) I.zchunk_res = z; else I.zchunk_ls = z;
       }
       if (pass == 0) I.nblk_res = slot; else I.nblk_ls = slot;
     }
     R.cnt = (int)h->hT.size() - R.off;
+    if (xcd) xcd_permute(h->hT, R.off, R.cnt);
     if (h->dim == 2)
       R.lds = pass == 0 ? (R2_LDS + 16) * sizeof(double) : (L2_LDS + 32) * sizeof(double);
     else
       R.lds = pass == 0 ? (R3_LDS + 16) * sizeof(double) : (L3_LDS + 32) * sizeof(double);
+  }
+}
+
+// Build every task table (tiles with the current tuning, FFT passes of the
+// solver precision and the FP64 auxiliary transforms) into h->hT.
+// nsp_aux[b] receives the auxiliary spectral block count of instance b.
+static void build_all_tasks(psd_handle* h, std::vector<int>& nsp_aux) {
+  h->hT.clear();
+  build_tile_tasks(h);
+  const int nfi = h->order == 6 ? 2 : 1, nfo = h->order == 6 ? 3 : 1;
+  if (h->mixed) build_fft_tasks<float>(h, h->fft_solver, nfi, nfo, true, FS_RES, FS_DIR);
+  else build_fft_tasks<double>(h, h->fft_solver, nfi, nfo, true, FS_RES, FS_DIR);
+  build_fft_tasks<double>(h, h->fft_aux, 1, 1, false, FS_TMP, FS_TMP);
+  nsp_aux.assign(h->batch, 0);
+  for (int k = 0; k < h->fft_aux.colz.cnt; ++k) {
+    Task2& t = h->hT[h->fft_aux.colz.off + k];
+    t.slot = nsp_aux[t.inst]++;
   }
 }
 
@@ -510,6 +551,128 @@ static psd_status aux_poisson(psd_handle* h, int b, double* zTz) {
 }
 
 // ---------------------------------------------------------------------------
+// autotuner: stencil tilings timed on the handle's own buffers
+// ---------------------------------------------------------------------------
+static std::string tune_key(psd_handle* h) {
+  hipDeviceProp_t prop;
+  std::string arch = "gfx";
+  if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) arch = prop.gcnArchName;
+  std::string k = arch + " d" + std::to_string(h->dim) + " o" + std::to_string(h->order) +
+                  (h->mixed ? " mixed" : " fp64") + " n";
+  for (int b = 0; b < h->batch; ++b) k += (b ? "," : "") + std::to_string(h->hI[b].n);
+  if (k.size() > 200) k = k.substr(0, 200) + " b" + std::to_string(h->batch);
+  return k;
+}
+
+static bool tune_cache_read(psd_handle* h, const std::string& key) {
+  const char* path = std::getenv("PSD_TUNE_CACHE");
+  if (!path) return false;
+  FILE* fp = std::fopen(path, "r");
+  if (!fp) return false;
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof line, fp)) {
+    std::string l(line);
+    const size_t bar = l.find('|');
+    if (bar == std::string::npos || l.substr(0, bar) != key) continue;
+    int a, b, c, d;
+    if (std::sscanf(l.c_str() + bar + 1, "%d %d %d %d", &a, &b, &c, &d) == 4) {
+      h->tune_zc_res = a; h->tune_zc_ls = b; h->tune_xcd_res = c != 0; h->tune_xcd_ls = d != 0;
+      found = true;
+    }
+  }
+  std::fclose(fp);
+  return found;
+}
+
+static void tune_cache_write(psd_handle* h, const std::string& key) {
+  const char* path = std::getenv("PSD_TUNE_CACHE");
+  if (!path) return;
+  FILE* fp = std::fopen(path, "a");
+  if (!fp) return;
+  std::fprintf(fp, "%s|%d %d %d %d\n", key.c_str(), h->tune_zc_res, h->tune_zc_ls, (int)h->tune_xcd_res,
+               (int)h->tune_xcd_ls);
+  std::fclose(fp);
+}
+
+static psd_status upload_tasks(psd_handle* h) {
+  if (h->hT.size() > h->dT_cap) return set_err(h, PSD_ERR_ARG, "task table exceeds its capacity");
+  HIPCHK(hipMemcpyAsync(h->dT, h->hT.data(), sizeof(Task2) * h->hT.size(), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(h->dI, h->hI.data(), sizeof(Inst) * h->batch, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return PSD_OK;
+}
+
+template <typename TD, typename TR>
+static psd_status autotune_impl(psd_handle* h) {
+  const std::string key = tune_key(h);
+  std::vector<int> nsp_aux;
+  if (tune_cache_read(h, key)) {
+    build_all_tasks(h, nsp_aux);
+    return upload_tasks(h);
+  }
+  // scratch bindings: u[0] -> tmp (zeroed), f -> tmp; d, r zeroed
+  std::vector<Inst> saved = h->hI;
+  for (int b = 0; b < h->batch; ++b) {
+    Inst& I = h->hI[b];
+    HIPCHK(hipMemsetAsync(I.tmp, 0, I.ncell * 8, h->stream));
+    HIPCHK(hipMemsetAsync(I.d, 0, I.ncell * (h->mixed ? 4 : 8), h->stream));
+    HIPCHK(hipMemsetAsync(I.u[1], 0, I.ncell * 8, h->stream));
+    I.u[0] = I.tmp;
+    I.f = I.tmp;
+    if (h->order == 6) {
+      HIPCHK(hipMemsetAsync(I.w[0], 0, I.ncell * 8, h->stream));
+      HIPCHK(hipMemsetAsync(I.w[1], 0, I.ncell * 8, h->stream));
+      HIPCHK(hipMemsetAsync(I.e1, 0, I.ncell * (h->mixed ? 4 : 8), h->stream));
+      HIPCHK(hipMemsetAsync(I.e2, 0, I.ncell * (h->mixed ? 4 : 8), h->stream));
+      I.g = I.tmp;
+    }
+  }
+  std::vector<int> zcs = {8, 16, 32, 64};
+  if (h->dim == 2) zcs = {T3Z};
+  const int save_prof = h->opt.profile;
+  h->opt.profile = 1;
+  double best_res = 1e300, best_ls = 1e300;
+  int bz_res = T3Z, bz_ls = T3Z;
+  bool bx_res = false, bx_ls = false;
+  for (int zc : zcs) {
+    for (int xcd = 0; xcd < 2; ++xcd) {
+      h->tune_zc_res = h->tune_zc_ls = zc;
+      h->tune_xcd_res = h->tune_xcd_ls = xcd != 0;
+      build_all_tasks(h, nsp_aux);
+      psd_status st = upload_tasks(h);
+      if (st != PSD_OK) return st;
+      for (int k = 0; k < PSD_NPASS; ++k) { h->pass_ms[k] = 0.0; h->pass_n[k] = 0; }
+      for (int rep = 0; rep < 4; ++rep) {
+        k_reset_state<<<(h->batch + 63) / 64, 64, 0, h->stream>>>(h->dI, h->batch);
+        run_ls<TD>(h, 0);
+        k_reset_state<<<(h->batch + 63) / 64, 64, 0, h->stream>>>(h->dI, h->batch);
+        run_residual<TD, TR>(h, true);
+        HIPCHK(hipStreamSynchronize(h->stream));
+        if (rep == 0) { h->prof.clear(); h->ev_used = 0; continue; }  // warm-up
+        prof_collect(h, -1, false);
+      }
+      HIPCHK(hipGetLastError());
+      const double tr = h->pass_ms[PSD_PASS_RES], tl = h->pass_ms[PSD_PASS_LS];
+      if (tr < best_res) { best_res = tr; bz_res = zc; bx_res = xcd != 0; }
+      if (tl < best_ls) { best_ls = tl; bz_ls = zc; bx_ls = xcd != 0; }
+    }
+  }
+  h->opt.profile = save_prof;
+  h->tune_zc_res = bz_res; h->tune_zc_ls = bz_ls;
+  h->tune_xcd_res = bx_res; h->tune_xcd_ls = bx_ls;
+  h->hI = saved;
+  build_all_tasks(h, nsp_aux);
+  for (int k = 0; k < PSD_NPASS; ++k) { h->pass_ms[k] = 0.0; h->pass_n[k] = 0; }
+  psd_status st = upload_tasks(h);
+  if (st != PSD_OK) return st;
+  HIPCHK(hipMemsetAsync(h->dState, 0, sizeof(SolveState) * h->batch, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  tune_cache_write(h, key);
+  return PSD_OK;
+}
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" psd_status psd_create(const psd_problem* probs, int batch, const psd_options* opt,
@@ -602,30 +765,27 @@ extern "C" psd_status psd_create(const psd_problem* probs, int batch, const psd_
       I.hist_cap = opt->max_iter;
     }
   }
-  // task tables (also fill nblk_* counts)
-  build_tile_tasks(h);
-  const int nfi = h->order == 6 ? 2 : 1, nfo = h->order == 6 ? 3 : 1;
-  if (h->mixed) build_fft_tasks<float>(h, h->fft_solver, nfi, nfo, true, FS_RES, FS_DIR);
-  else build_fft_tasks<double>(h, h->fft_solver, nfi, nfo, true, FS_RES, FS_DIR);
-  std::vector<int> nsp(batch);
-  for (int b = 0; b < batch; ++b) nsp[b] = h->hI[b].nblk_sp;
-  build_fft_tasks<double>(h, h->fft_aux, 1, 1, false, FS_TMP, FS_TMP);
+  // task tables: capacities from the finest z-chunk any tuning may pick
+  std::vector<int> nsp_aux;
+  h->tune_zc_res = h->tune_zc_ls = 8;
+  build_all_tasks(h, nsp_aux);
+  h->dT_cap = h->hT.size();
+  std::vector<int> cap_res(batch), cap_ls(batch);
+  for (int b = 0; b < batch; ++b) { cap_res[b] = h->hI[b].nblk_res; cap_ls[b] = h->hI[b].nblk_ls; }
+  h->tune_zc_res = h->tune_zc_ls = T3Z;
+  build_all_tasks(h, nsp_aux);
   // partial arrays and states
   if (dalloc(h, &h->dState, sizeof(SolveState) * batch)) return fail("out of device memory");
   for (int b = 0; b < batch; ++b) {
     Inst& I = h->hI[b];
-    int aux_sp = 0;
-    for (int k = 0; k < h->fft_aux.colz.cnt; ++k) {
-      Task2& t = h->hT[h->fft_aux.colz.off + k];
-      if (t.inst == b) t.slot = aux_sp++;
-    }
-    const int nsp_max = std::max(nsp[b], aux_sp);
-    if (dalloc(h, &I.part_res, (size_t)I.nblk_res * 2 * 8) || dalloc(h, &I.part_ls, (size_t)I.nblk_ls * 8 * 8) ||
+    const int nsp_max = std::max(I.nblk_sp, nsp_aux[b]);
+    const int nres = std::max(cap_res[b], 1024);   // vector kernels use up to nblk_res blocks
+    if (dalloc(h, &I.part_res, (size_t)nres * 2 * 8) || dalloc(h, &I.part_ls, (size_t)cap_ls[b] * 8 * 8) ||
         dalloc(h, &I.part_sp, (size_t)nsp_max * 2 * 8) || dalloc(h, &I.part_c2r, (size_t)I.nblk_c2r * 3 * 8))
       return fail("out of device memory");
     I.st = h->dState + b;
   }
-  if (dalloc(h, &h->dI, sizeof(Inst) * batch) || dalloc(h, &h->dT, sizeof(Task2) * h->hT.size()) ||
+  if (dalloc(h, &h->dI, sizeof(Inst) * batch) || dalloc(h, &h->dT, sizeof(Task2) * h->dT_cap) ||
       dalloc(h, &h->dAuxPart, sizeof(double) * 5 * 1024))
     return fail("out of device memory");
   if (hipHostMalloc((void**)&h->hState, sizeof(SolveState) * batch, hipHostMallocDefault) != hipSuccess ||
@@ -636,7 +796,22 @@ extern "C" psd_status psd_create(const psd_problem* probs, int batch, const psd_
       hipMemcpy(h->dI, h->hI.data(), sizeof(Inst) * batch, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(h->dState, 0, sizeof(SolveState) * batch) != hipSuccess)
     return fail("upload of tables failed");
+  if (opt->autotune) {
+    psd_status st = h->mixed ? autotune_impl<float, float>(h) : autotune_impl<double, double>(h);
+    if (st != PSD_OK) {
+      std::string m = "autotune: " + h->err;
+      psd_destroy(h);
+      return set_err(nullptr, st, m);
+    }
+  }
   *out = h;
+  return PSD_OK;
+}
+
+extern "C" psd_status psd_tuning(const psd_handle* h, int* out4) {
+  if (!h || !out4) return PSD_ERR_ARG;
+  out4[0] = h->tune_zc_res; out4[1] = h->tune_zc_ls;
+  out4[2] = h->tune_xcd_res ? 1 : 0; out4[3] = h->tune_xcd_ls ? 1 : 0;
   return PSD_OK;
 }
 

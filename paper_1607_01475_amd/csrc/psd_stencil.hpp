@@ -19,7 +19,7 @@ namespace psd {
 // tile shapes
 constexpr int T2X = 64, T2Y = 8;     // 2D: 512 cells, 2 per thread
 constexpr int T3X = 32, T3Y = 8;     // 3D: one (x,y) column per thread
-constexpr int T3Z = 16;              // 3D: planes marched per block
+constexpr int T3Z = 16;              // 3D: default planes marched per block
 
 __device__ __forceinline__ double flux_r(double g2, double p, int p_is_4, int p_is_2) {
   if (p_is_4) return g2;
@@ -293,7 +293,7 @@ __device__ void res3d_tile(const Inst& I, int x0, int y0, int z0, double* lds, d
   double* fC = fB + R3_FP;
   const double ih = I.inv_h, ih2 = ih * ih, qh = 0.25 * ih;
   const double s = I.s, se2 = I.se2;
-  const int z1 = min(z0 + T3Z, n);
+  const int z1 = min(z0 + I.zchunk_res, n);
   const int tid = threadIdx.x;
   const int tx = tid % T3X, ty = tid / T3X;
   const int vown = (ty + 2) * R3_VW + tx + 2;      // own cell in a v plane
@@ -530,7 +530,7 @@ __device__ void ls3d_tile(const Inst& I, int mode, int x0, int y0, int z0, doubl
   double* ub = lds;
   double* db = lds + 3 * L3_P;
   const double qh = 0.25 * I.inv_h, ih2 = I.inv_h * I.inv_h;
-  const int z1 = min(z0 + T3Z, n);
+  const int z1 = min(z0 + I.zchunk_ls, n);
   const int tid = threadIdx.x;
   const int tx = tid % T3X, ty = tid / T3X;
   const bool own = x0 + tx < n && y0 + ty < n;

@@ -47,7 +47,8 @@ class _Problem(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("precision", ctypes.c_int), ("graph_chunk", ctypes.c_int),
-                ("history", ctypes.c_int), ("profile", ctypes.c_int)]
+                ("history", ctypes.c_int), ("profile", ctypes.c_int),
+                ("autotune", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -75,6 +76,7 @@ SIGNATURES = {
                                    ctypes.POINTER(ctypes.c_int)]),
     "psd_history": (ctypes.c_int, [_vp, ctypes.c_int, _dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "psd_pass_times": (ctypes.c_int, [_vp, _dp, ctypes.POINTER(ctypes.c_int)]),
+    "psd_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
     "psd_destroy": (ctypes.c_int, [_vp]),
     "psd_last_error": (ctypes.c_char_p, [_vp]),
 }
@@ -159,7 +161,7 @@ class Solver:
 
     def __init__(self, problems: Union[Problem, List[Problem]], tol: float = 1e-10,
                  max_iter: int = 500, precision: str = "fp64", graph_chunk: int = 0,
-                 history: bool = False, profile: bool = False,
+                 history: bool = False, profile: bool = False, autotune: bool = False,
                  stream: Optional[torch.cuda.Stream] = None):
         self._lib = load_library()
         self.problems = [problems] if isinstance(problems, Problem) else list(problems)
@@ -167,7 +169,7 @@ class Solver:
         arr = (_Problem * self.batch)(*[p.c() for p in self.problems])
         prec = {"fp64": PSD_FP64, "mixed": PSD_MIXED}[precision]
         self.opt = _Options(float(tol), int(max_iter), prec, int(graph_chunk), 1 if history else 0,
-                            1 if profile else 0)
+                            1 if profile else 0, 1 if autotune else 0)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = _vp()
         st = self._lib.psd_create(arr, self.batch, ctypes.byref(self.opt),
@@ -241,6 +243,12 @@ class Solver:
         self._check(self._lib.psd_history(self._h, inst, buf, cap, ctypes.byref(cnt)))
         import numpy as np
         return np.array(buf[: 4 * cnt.value]).reshape(cnt.value, 4)
+
+    def tuning(self):
+        """(z-chunk residual, z-chunk line search, XCD order residual, XCD order line search)."""
+        out = (ctypes.c_int * 4)()
+        self._check(self._lib.psd_tuning(self._h, out))
+        return tuple(out)
 
     def pass_times(self):
         """{pass name: (total ms, launches)} of the last solve (profile=True)."""

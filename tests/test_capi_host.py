@@ -65,7 +65,7 @@ def test_create_without_gpu_fails_cleanly(psd):
     import ctypes
     lib = psd.load_library()
     P = (psd._Problem * 1)(psd.Problem(2, 64, 12.8).c())
-    opt = psd._Options(1e-10, 10, 0, 0, 0, 0)
+    opt = psd._Options(1e-10, 10, 0, 0, 0, 0, 0)
     h = ctypes.c_void_p()
     st = lib.psd_create(P, 1, ctypes.byref(opt), None, ctypes.byref(h))
     assert st == psd.PSD_ERR_HIP

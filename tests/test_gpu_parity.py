@@ -223,3 +223,20 @@ def test_batched_instances_match_single(psd):
         assert np.abs(r1).max() <= 2e-10 and np.abs(r2).max() <= 2e-10
         ref = O.solve(f, g=g, tol=1e-11, max_iter=300)
         assert rel(host(u), ref["u"]) <= 1e-9
+
+
+def test_autotuned_tiling_gives_same_solution(psd):
+    n, L = 64, 12.8
+    f = psd_inputs.small_field(3, n, L, 101, K=6)
+    P = psd.Problem(3, n, L, 4, 4.0, 0.01, 0.1)
+    res = []
+    for tune in (False, True):
+        with psd.Solver(P, tol=1e-10, max_iter=300, precision="mixed", autotune=tune) as S:
+            t = S.tuning()
+            assert t[0] in (8, 16, 32, 64) and t[1] in (8, 16, 32, 64)
+            u = torch.zeros_like(dev(f))
+            st = S.solve([dev(f)], [u])[0]
+            res.append((st.iters, host(u), t))
+    log(f"autotune: tuning {res[1][2]}")
+    assert abs(res[0][0] - res[1][0]) <= 1
+    assert rel(res[1][1], res[0][1]) <= 1e-10
