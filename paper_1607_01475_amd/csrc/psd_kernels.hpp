@@ -80,6 +80,7 @@ __global__ __launch_bounds__(PSD_NT) void k_res_finalize(const Inst* __restrict_
   SolveState* st = I.st;
   if (st->done) return;
   double acc[2] = {0.0, 0.0};
+#pragma unroll 8
   for (int b = threadIdx.x; b < I.nblk_res; b += PSD_NT) {
     acc[0] = fmax(acc[0], I.part_res[2 * b]);
     acc[1] += I.part_res[2 * b + 1];
@@ -172,9 +173,12 @@ __global__ __launch_bounds__(PSD_NT) void k_ls_finalize(const Inst* __restrict__
   SolveState* st = I.st;
   if (st->done || (mode == 2 && st->ls_phase == 2)) return;
   double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 4
   for (int b = threadIdx.x; b < I.nblk_ls; b += PSD_NT)
+#pragma unroll
     for (int k = 0; k < 8; ++k) acc[k] += I.part_ls[8 * b + k];
   if (mode != 2)
+#pragma unroll 4
     for (int b = threadIdx.x; b < I.nblk_sp; b += PSD_NT) {
       acc[8] += I.part_sp[2 * b];
       acc[9] += I.part_sp[2 * b + 1];
