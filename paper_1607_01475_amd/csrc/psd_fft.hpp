@@ -153,6 +153,13 @@ __device__ __forceinline__ void dftR(cx<T>* a) {
   else dft16<DIR>(a);
 }
 
+// LDS line layout: one padding element after every 16, so that the span-1
+// stage (R results per thread at stride R) does not hit the same banks from
+// consecutive lanes.  Element t of a line lives at pidx(t); a line occupies
+// fft_ls(N) elements.
+constexpr int fft_ls(int N) { return N + N / 16 + 1; }
+__device__ __forceinline__ int pidx(int t) { return t + (t >> 4); }
+
 template <int S, int NSTG, typename F>
 __device__ __forceinline__ void stage_loop(F&& f) {
   if constexpr (S < NSTG) {
@@ -161,7 +168,8 @@ __device__ __forceinline__ void stage_loop(F&& f) {
   }
 }
 
-// Transform NL lines of length N held in LDS (line l at buf + l*LS), in
+// Transform NL lines of length N held in LDS (line l at buf + l*LS, element
+// t at pidx(t)), in
 // place, unnormalised.  tw[m] = exp(-2 pi i m / N) (global, cached).
 // Must be called by all PSD_NT threads of the block; ends with a barrier.
 template <typename T, int N, int NL, int LS, int DIR>
@@ -180,9 +188,9 @@ __device__ __forceinline__ void lds_fft(cx<T>* buf, const cx<T>* __restrict__ tw
       const int b = threadIdx.x + it * PSD_NT;
       if (NB % PSD_NT == 0 || b < NB) {
         const int line = b / M, j = b - line * M;
-        const cx<T>* src = buf + line * LS + j;
+        const cx<T>* src = buf + line * LS;
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[it][r] = src[r * M];
+        for (int r = 0; r < R; ++r) v[it][r] = src[pidx(j + r * M)];
       }
     }
     __syncthreads();
@@ -202,9 +210,10 @@ __device__ __forceinline__ void lds_fft(cx<T>* buf, const cx<T>* __restrict__ tw
           }
         }
         dftR<R, DIR>(v[it]);
-        cx<T>* dst = buf + line * LS + (j - k) * R + k;
+        cx<T>* dst = buf + line * LS;
+        const int o = (j - k) * R + k;
 #pragma unroll
-        for (int r = 0; r < R; ++r) dst[r * Ns] = v[it][r];
+        for (int r = 0; r < R; ++r) dst[pidx(o + r * Ns)] = v[it][r];
       }
     }
     __syncthreads();
@@ -240,7 +249,7 @@ constexpr int rows_lines() {  // complex lines per block for row passes
 template <typename T, typename TIN, int N, int NL>
 __device__ __forceinline__ void r2c_rows(const RowArgs<T>& A, long long row0, cx<T>* buf,
                                          const cx<T>* tw) {
-  constexpr int LS = N + 1;
+  constexpr int LS = fft_ls(N);
   constexpr int NC = N / 2 + 1;
   // load 2*NL real rows: VEC consecutive values per thread and load, all
   // loads of the block issued before the first LDS store
@@ -270,7 +279,7 @@ __device__ __forceinline__ void r2c_rows(const RowArgs<T>& A, long long row0, cx
     const int e = threadIdx.x + it * PSD_NT;
     if (NV % PSD_NT == 0 || e < NV) {
       const int rr = (e * VEC) / N, col = e * VEC - rr * N;
-      T* dst = (T*)(buf + (rr >> 1) * LS + col) + (rr & 1);
+      T* dst = (T*)(buf + (rr >> 1) * LS + pidx(col)) + (rr & 1);
 #pragma unroll
       for (int q = 0; q < VEC; ++q) dst[2 * q] = (T)regs[it].x[q];
     }
@@ -279,8 +288,8 @@ __device__ __forceinline__ void r2c_rows(const RowArgs<T>& A, long long row0, cx
   lds_fft<T, N, NL, LS, -1>(buf, tw);
   for (int e = threadIdx.x; e < NL * NC; e += PSD_NT) {
     const int l = e / NC, k = e - l * NC;
-    const cx<T> zk = buf[l * LS + k];
-    const cx<T> zm = conj(buf[l * LS + (k == 0 ? 0 : N - k)]);
+    const cx<T> zk = buf[l * LS + pidx(k)];
+    const cx<T> zm = conj(buf[l * LS + pidx(k == 0 ? 0 : N - k)]);
     const cx<T> a = scale(zk + zm, T(0.5));
     const cx<T> b = scale(mul_i<-1>(zk - zm), T(0.5));
     const long long gr = row0 + 2 * l;
@@ -297,7 +306,7 @@ __device__ __forceinline__ void r2c_rows(const RowArgs<T>& A, long long row0, cx
 template <typename T, typename TOUT, int N, int NL>
 __device__ __forceinline__ void c2r_rows(const RowArgs<T>& A, long long row0, cx<T>* buf,
                                          const cx<T>* tw, double (&fsum)[3]) {
-  constexpr int LS = N + 1;
+  constexpr int LS = fft_ls(N);
   constexpr int NC = N / 2 + 1;
   constexpr int NE = NL * NC;
   constexpr int IT = (NE + PSD_NT - 1) / PSD_NT;
@@ -325,8 +334,8 @@ __device__ __forceinline__ void c2r_rows(const RowArgs<T>& A, long long row0, cx
     cx<T> a = ra[it], b = rb[it];
     if (k == 0 || k == N / 2) { a.y = T(0); b.y = T(0); }
     // Z_k = A_k + i B_k ; Z_{N-k} = conj(A_k) + i conj(B_k)
-    buf[l * LS + k] = a + mul_i<1>(b);
-    if (k != 0 && k != N / 2) buf[l * LS + N - k] = conj(a) + mul_i<1>(conj(b));
+    buf[l * LS + pidx(k)] = a + mul_i<1>(b);
+    if (k != 0 && k != N / 2) buf[l * LS + pidx(N - k)] = conj(a) + mul_i<1>(conj(b));
   }
   __syncthreads();
   lds_fft<T, N, NL, LS, 1>(buf, tw);
@@ -339,7 +348,7 @@ __device__ __forceinline__ void c2r_rows(const RowArgs<T>& A, long long row0, cx
     if (gr >= A.nrows) continue;
     const int fld = (int)(gr / A.rpf);
     const long long row = gr - (long long)fld * A.rpf;
-    const T* src = (const T*)(buf + (rr >> 1) * LS + col) + (rr & 1);
+    const T* src = (const T*)(buf + (rr >> 1) * LS + pidx(col)) + (rr & 1);
     V out;
     double part = 0.0;
 #pragma unroll
@@ -359,7 +368,7 @@ __device__ __forceinline__ void c2r_rows(const RowArgs<T>& A, long long row0, cx
 template <typename T, int N, int W, int NF>
 __device__ __forceinline__ void col_load(const cx<T>* base, long long inner_count, long long col0,
                                          long long lstride, long long fstride, cx<T>* buf) {
-  constexpr int LS = N + 1;
+  constexpr int LS = fft_ls(N);
   constexpr int NE = NF * W * N;
   constexpr int IT = (NE + PSD_NT - 1) / PSD_NT;
   cx<T> regs[IT];
@@ -380,7 +389,7 @@ __device__ __forceinline__ void col_load(const cx<T>* base, long long inner_coun
       const int c = e % W;
       const int ft = e / W;
       const int t = ft % N, f = ft / N;
-      buf[(f * W + c) * LS + t] = regs[it];
+      buf[(f * W + c) * LS + pidx(t)] = regs[it];
     }
   }
 }
@@ -394,7 +403,7 @@ template <typename T, int N, int W, int NF, int DIR>
 __device__ __forceinline__ void col_pass(cx<T>* base, long long inner_count, long long col0,
                                          long long lstride, long long fstride, cx<T>* buf,
                                          const cx<T>* tw) {
-  constexpr int LS = N + 1;
+  constexpr int LS = fft_ls(N);
   col_load<T, N, W, NF>(base, inner_count, col0, lstride, fstride, buf);
   __syncthreads();
   lds_fft<T, N, NF * W, LS, DIR>(buf, tw);
@@ -402,7 +411,7 @@ __device__ __forceinline__ void col_pass(cx<T>* base, long long inner_count, lon
     const int c = e % W;
     const int ft = e / W;
     const int t = ft % N, f = ft / N;
-    if (col0 + c < inner_count) base[f * fstride + col0 + c + t * lstride] = buf[(f * W + c) * LS + t];
+    if (col0 + c < inner_count) base[f * fstride + col0 + c + t * lstride] = buf[(f * W + c) * LS + pidx(t)];
   }
 }
 

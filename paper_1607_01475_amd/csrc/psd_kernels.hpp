@@ -22,17 +22,17 @@ struct Task2 {  // residual / line-search / col tiles
 
 template <typename T, int N>
 constexpr int row_lines() {
-  int nl = 32768 / ((N + 1) * (int)sizeof(cx<T>));
+  int nl = 32768 / (fft_ls(N) * (int)sizeof(cx<T>));
   int p = 1;
   while (p * 2 <= nl && p < 32) p *= 2;
   return p;
 }
 // columns per block of a column pass: 128-byte segments where the LDS
-// footprint NF*W*(N+1) complex stays within 64 KB
+// footprint NF*W*fft_ls(N) complex stays within 64 KB
 template <typename T, int N, int NF>
 constexpr int col_width() {
   int w = 128 / (int)sizeof(cx<T>);
-  const int cap = 65536 / (NF * (N + 1) * (int)sizeof(cx<T>));
+  const int cap = 65536 / (NF * fft_ls(N) * (int)sizeof(cx<T>));
   if (cap < w) w = cap;
   return w < 1 ? 1 : w;
 }
@@ -358,7 +358,7 @@ template <typename T, int N, int W, int OP>
 __device__ __forceinline__ void fused_col(const Inst& I, const Task2& t, cx<T>* buf, double (&acc)[2]) {
   constexpr int NFI = (OP == OP_PRECOND6) ? 2 : 1;
   constexpr int NFO = (OP == OP_PRECOND6) ? 3 : 1;
-  constexpr int LS = N + 1;
+  constexpr int LS = fft_ls(N);
   const cx<T>* tw = (const cx<T>*)(sizeof(T) == 8 ? I.tw64 : I.tw32);
   const long long n = I.n, nc = I.nc;
   const int dim = I.dim;
@@ -381,22 +381,22 @@ __device__ __forceinline__ void fused_col(const Inst& I, const Task2& t, cx<T>* 
     if (dim == 3) K += S[tt];
     const double wgt = (kx == 0 || 2 * kx == (int)n) ? 1.0 : 2.0;
     if (OP == OP_PRECOND4) {
-      const cx<T> X = buf[c * LS + tt];
+      const cx<T> X = buf[c * LS + pidx(tt)];
       const double sig = 1.0 + s * K + se2 * K * K;
       const double x2 = (double)X.x * X.x + (double)X.y * X.y;
       acc[0] += wgt * x2 / sig * inv;
-      buf[c * LS + tt] = scale(X, (T)(inv / sig));
+      buf[c * LS + pidx(tt)] = scale(X, (T)(inv / sig));
     } else if (OP == OP_POISSON) {
-      const cx<T> X = buf[c * LS + tt];
+      const cx<T> X = buf[c * LS + pidx(tt)];
       if (K > 0.0) {
         const double x2 = (double)X.x * X.x + (double)X.y * X.y;
         acc[0] += wgt * x2 / K * inv;
-        buf[c * LS + tt] = scale(X, (T)(inv / K));
+        buf[c * LS + pidx(tt)] = scale(X, (T)(inv / K));
       } else {
-        buf[c * LS + tt] = mk(T(0), T(0));
+        buf[c * LS + pidx(tt)] = mk(T(0), T(0));
       }
     } else {
-      const cx<T> X2 = buf[c * LS + tt], X1 = buf[(W + c) * LS + tt];
+      const cx<T> X2 = buf[c * LS + pidx(tt)], X1 = buf[(W + c) * LS + pidx(tt)];
       if (K > 0.0) {
         const double iK = 1.0 / K;
         const double sig = s * I.lam + s * K + se2 * K * K + iK;
@@ -404,13 +404,13 @@ __device__ __forceinline__ void fused_col(const Inst& I, const Task2& t, cx<T>* 
         const double dx = px / sig, dy = py / sig;
         acc[0] += wgt * (px * px + py * py) / sig * inv;
         acc[1] += wgt * (dx * dx + dy * dy) * iK * inv;
-        buf[c * LS + tt] = mk((T)(dx * inv), (T)(dy * inv));
-        buf[(W + c) * LS + tt] = mk((T)(X1.x * iK * inv), (T)(X1.y * iK * inv));
-        buf[(2 * W + c) * LS + tt] = mk((T)(dx * iK * inv), (T)(dy * iK * inv));
+        buf[c * LS + pidx(tt)] = mk((T)(dx * inv), (T)(dy * inv));
+        buf[(W + c) * LS + pidx(tt)] = mk((T)(X1.x * iK * inv), (T)(X1.y * iK * inv));
+        buf[(2 * W + c) * LS + pidx(tt)] = mk((T)(dx * iK * inv), (T)(dy * iK * inv));
       } else {
-        buf[c * LS + tt] = mk(T(0), T(0));
-        buf[(W + c) * LS + tt] = mk(T(0), T(0));
-        buf[(2 * W + c) * LS + tt] = mk(T(0), T(0));
+        buf[c * LS + pidx(tt)] = mk(T(0), T(0));
+        buf[(W + c) * LS + pidx(tt)] = mk(T(0), T(0));
+        buf[(2 * W + c) * LS + pidx(tt)] = mk(T(0), T(0));
       }
     }
   }
@@ -420,7 +420,7 @@ __device__ __forceinline__ void fused_col(const Inst& I, const Task2& t, cx<T>* 
     const int c = e % W;
     const int ft = e / W;
     const int tt = ft % N, f = ft / N;
-    if (col0 + c < inner) base[f * I.nspec + col0 + c + tt * lstride] = buf[(f * W + c) * LS + tt];
+    if (col0 + c < inner) base[f * I.nspec + col0 + c + tt * lstride] = buf[(f * W + c) * LS + pidx(tt)];
   }
 }
 
