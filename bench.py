@@ -80,7 +80,8 @@ def traffic_for(kernel: str, workload: str):
 def run_form(psd, torch, P, f, precision, chunk, steps, warmup, tol=1e-10):
     # per-kernel HIP-event timing is available in the host-driven loop only
     S = psd.Solver(P, tol=tol, max_iter=500, precision=precision, graph_chunk=chunk,
-                   profile=(chunk == 0))
+                   profile=(chunk == 0), autotune=True)
+    tuning = S.tuning()
     fd = f
     u = torch.zeros_like(fd)
     for _ in range(warmup):
@@ -104,7 +105,7 @@ def run_form(psd, torch, P, f, precision, chunk, steps, warmup, tol=1e-10):
             a[0] += ms
             a[1] += cnt
     S.close()
-    return dict(times=times, iters=iters, passes=agg, u=u.clone(), res_inf=st.res_inf)
+    return dict(times=times, iters=iters, passes=agg, u=u.clone(), res_inf=st.res_inf, tuning=tuning)
 
 
 def cpu_baseline(f_np, n, L, p, s, eps):
@@ -209,6 +210,7 @@ def main():
         extra[f"{k}_time_to_1e-10_ms"] = round(1e3 * float(np.median(r["times"])), 3)
         extra[f"{k}_iters"] = int(np.median(r["iters"]))
         extra[f"{k}_iters_per_s"] = round(float(np.sum(r["iters"]) / np.sum(r["times"])), 2)
+        extra[f"{k}_tiling"] = dict(zip(("zchunk_res", "zchunk_ls", "xcd_res", "xcd_ls"), r["tuning"]))
 
     cpu = None
     if not args.no_cpu_baseline:

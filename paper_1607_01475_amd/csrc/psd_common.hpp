@@ -3,7 +3,8 @@
 // Layout conventions (Sec. 5.1 of the paper): periodic n^dim cell-centred
 // grid, x fastest, idx = i + n*(j + n*k).  A vertex (i+1/2, j+1/2[, k+1/2])
 // is addressed by the index of cell (i, j[, k]).  Spectra are half spectra
-// (kx = 0 .. n/2) stored [kz][ky][kx], kx fastest, nc = n/2 + 1.
+// (kx = 0 .. n/2) stored [kz][ky][kx], kx fastest, nc = n/2 + 1 values in a
+// row padded to ncp (a multiple of 128 bytes) so that column tiles are aligned.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -64,7 +65,9 @@ struct SolveState {
 struct Inst {
   int dim, n, nc, order;
   long long ncell;     // n^dim
-  long long nspec;     // nc * n^(dim-1)
+  long long nspec;     // largest field stride of the spectrum buffer (complex elements)
+  int ncp32, ncp64;    // padded spectrum row strides (128-byte multiples) for FP32 / FP64
+  long long nspec32, nspec64;  // spectrum field strides = ncp * n^(dim-1)
   double h, inv_h, p, s, se2, lam, inv_ntot, tol, hd;
   int max_iter, p_is_4, p_is_2, pad0;
   double* u[2];        // ping-pong iterate

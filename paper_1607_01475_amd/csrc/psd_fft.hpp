@@ -234,7 +234,8 @@ struct RowArgs {
   void* rout1;
   void* rout2;
   cx<T>* spec;          // NF fields of nspec complex
-  long long nspec;
+  long long nspec;      // field stride (complex elements)
+  int ncp;              // row stride (complex elements, >= N/2 + 1)
   long long rpf;        // rows per field
   long long nrows;      // rows over all fields of this pass (guard)
   __device__ __forceinline__ const void* in(int f) const { return f == 0 ? rin0 : rin1; }
@@ -296,9 +297,9 @@ __device__ __forceinline__ void r2c_rows(const RowArgs<T>& A, long long row0, cx
     if (gr >= A.nrows) continue;
     const int fld = (int)(gr / A.rpf);
     const long long row = gr - (long long)fld * A.rpf;
-    cx<T>* out = A.spec + fld * A.nspec + row * NC;
+    cx<T>* out = A.spec + fld * A.nspec + row * A.ncp;
     out[k] = a;
-    out[NC + k] = b;
+    out[A.ncp + k] = b;
   }
 }
 
@@ -321,9 +322,9 @@ __device__ __forceinline__ void c2r_rows(const RowArgs<T>& A, long long row0, cx
     if ((NE % PSD_NT == 0 || e < NE) && gr < A.nrows) {
       const int fld = (int)(gr / A.rpf);
       const long long row = gr - (long long)fld * A.rpf;
-      const cx<T>* in = A.spec + fld * A.nspec + row * NC;
+      const cx<T>* in = A.spec + fld * A.nspec + row * A.ncp;
       ra[it] = in[k];
-      rb[it] = in[NC + k];
+      rb[it] = in[A.ncp + k];
     }
   }
 #pragma unroll

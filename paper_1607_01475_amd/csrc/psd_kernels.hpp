@@ -273,7 +273,8 @@ template <typename T>
 __device__ __forceinline__ RowArgs<T> row_args(const Inst& I, int fs, cx<T>* spec, int nf) {
   RowArgs<T> A;
   A.spec = spec;
-  A.nspec = I.nspec;
+  A.nspec = sizeof(T) == 8 ? I.nspec64 : I.nspec32;
+  A.ncp = sizeof(T) == 8 ? I.ncp64 : I.ncp32;
   A.rpf = I.ncell / I.n;
   A.nrows = A.rpf * nf;
   A.rin0 = A.rin1 = nullptr;
@@ -326,16 +327,18 @@ __global__ __launch_bounds__(PSD_NT) void k_cols(const Inst* __restrict__ insts,
   if (solver && I.st->done) return;
   cx<T>* buf = (cx<T>*)smem;
   const cx<T>* tw = (const cx<T>*)(sizeof(T) == 8 ? I.tw64 : I.tw32);
-  const long long n = I.n, nc = I.nc;
-  // axis 1: lines along y (stride nc), columns kx, outer z (stride n*nc)
-  // axis 2: lines along z (stride n*nc), columns (ky,kx)
-  const long long inner = (axis == 1) ? nc : n * nc;
-  const long long lstride = (axis == 1) ? nc : n * nc;
-  cx<T>* base = (cx<T>*)I.spec + (axis == 1 ? (long long)t.a * n * nc : 0);
+  const long long n = I.n;
+  const long long ncp = sizeof(T) == 8 ? I.ncp64 : I.ncp32;
+  const long long fstride = sizeof(T) == 8 ? I.nspec64 : I.nspec32;
+  // axis 1: lines along y (stride ncp), columns kx, outer z (stride n*ncp)
+  // axis 2: lines along z (stride n*ncp), columns (ky,kx)
+  const long long inner = (axis == 1) ? ncp : n * ncp;
+  const long long lstride = (axis == 1) ? ncp : n * ncp;
+  cx<T>* base = (cx<T>*)I.spec + (axis == 1 ? (long long)t.a * n * ncp : 0);
   switch (I.n) {
 #define PSD_COL_CASE(NN)                                                                          \
     case NN:                                                                                      \
-      col_pass<T, NN, col_width<T, NN, NF>(), NF, DIR>(base, inner, t.b, lstride, I.nspec, buf, tw); \
+      col_pass<T, NN, col_width<T, NN, NF>(), NF, DIR>(base, inner, t.b, lstride, fstride, buf, tw); \
       break;
     PSD_FOR_EACH_N(PSD_COL_CASE)
 #undef PSD_COL_CASE
@@ -361,12 +364,14 @@ __device__ __forceinline__ void fused_col(const Inst& I, const Task2& t, cx<T>* 
   constexpr int LS = fft_ls(N);
   const cx<T>* tw = (const cx<T>*)(sizeof(T) == 8 ? I.tw64 : I.tw32);
   const long long n = I.n, nc = I.nc;
+  const long long ncp = sizeof(T) == 8 ? I.ncp64 : I.ncp32;
+  const long long fstride = sizeof(T) == 8 ? I.nspec64 : I.nspec32;
   const int dim = I.dim;
-  const long long inner = (dim == 2) ? nc : n * nc;
+  const long long inner = (dim == 2) ? ncp : n * ncp;
   const long long lstride = inner;
   cx<T>* base = (cx<T>*)I.spec;
   const long long col0 = t.b;
-  col_load<T, N, W, NFI>(base, inner, col0, lstride, I.nspec, buf);
+  col_load<T, N, W, NFI>(base, inner, col0, lstride, fstride, buf);
   __syncthreads();
   lds_fft<T, N, NFI * W, LS, -1>(buf, tw);
   const double s = I.s, se2 = I.se2, inv = I.inv_ntot;
@@ -375,8 +380,13 @@ __device__ __forceinline__ void fused_col(const Inst& I, const Task2& t, cx<T>* 
     const int c = e % W, tt = e / W;
     const long long col = col0 + c;
     if (col >= inner) continue;
-    const int kx = (int)(col % nc);
-    const int ky = (dim == 2) ? tt : (int)(col / nc);
+    const int kx = (int)(col % ncp);
+    const int ky = (dim == 2) ? tt : (int)(col / ncp);
+    if (kx >= nc) {  // row padding: keep it zero, contribute nothing
+#pragma unroll
+      for (int f = 0; f < NFO; ++f) buf[(f * W + c) * LS + pidx(tt)] = mk(T(0), T(0));
+      continue;
+    }
     double K = S[kx] + S[ky];
     if (dim == 3) K += S[tt];
     const double wgt = (kx == 0 || 2 * kx == (int)n) ? 1.0 : 2.0;
@@ -420,7 +430,7 @@ __device__ __forceinline__ void fused_col(const Inst& I, const Task2& t, cx<T>* 
     const int c = e % W;
     const int ft = e / W;
     const int tt = ft % N, f = ft / N;
-    if (col0 + c < inner) base[f * I.nspec + col0 + c + tt * lstride] = buf[(f * W + c) * LS + pidx(tt)];
+    if (col0 + c < inner) base[f * fstride + col0 + c + tt * lstride] = buf[(f * W + c) * LS + pidx(tt)];
   }
 }
 

@@ -252,7 +252,7 @@ static void build_fft_tasks(psd_handle* h, FftTasks& F, int nfi, int nfo, bool w
         const Inst& I = h->hI[b];
         const int W = host_cw<T>(I.n, nf);
         for (int z = 0; z < I.n; ++z)
-          for (int c0 = 0; c0 < I.nc; c0 += W) {
+          for (int c0 = 0; c0 < (sizeof(T) == 8 ? I.ncp64 : I.ncp32); c0 += W) {
             Task2 t{};
             t.inst = b; t.a = z; t.b = c0;
             h->hT.push_back(t);
@@ -269,7 +269,8 @@ static void build_fft_tasks(psd_handle* h, FftTasks& F, int nfi, int nfo, bool w
     Inst& I = h->hI[b];
     const int nfm = std::max(nfi, nfo);
     const int W = host_cw<T>(I.n, nfm);
-    const long long inner = h->dim == 2 ? I.nc : (long long)I.n * I.nc;
+    const long long ncp = sizeof(T) == 8 ? I.ncp64 : I.ncp32;
+    const long long inner = h->dim == 2 ? ncp : (long long)I.n * ncp;
     int slot = 0;
     for (long long c0 = 0; c0 < inner; c0 += W) {
       Task2 t{};
@@ -723,7 +724,11 @@ extern "C" psd_status psd_create(const psd_problem* probs, int batch, const psd_
     std::memset(&I, 0, sizeof(Inst));
     I.dim = P.dim; I.n = P.n; I.nc = P.n / 2 + 1; I.order = P.order;
     I.ncell = (long long)P.n * P.n * (P.dim == 3 ? P.n : 1);
-    I.nspec = (long long)I.nc * P.n * (P.dim == 3 ? P.n : 1);
+    I.ncp32 = (I.nc + 15) / 16 * 16;   // 16 FP32 complex = 128 bytes
+    I.ncp64 = (I.nc + 7) / 8 * 8;      // 8 FP64 complex = 128 bytes
+    I.nspec32 = (long long)I.ncp32 * P.n * (P.dim == 3 ? P.n : 1);
+    I.nspec64 = (long long)I.ncp64 * P.n * (P.dim == 3 ? P.n : 1);
+    I.nspec = I.nspec64;
     I.h = P.L / P.n; I.inv_h = P.n / P.L; I.p = P.p; I.s = P.s;
     I.se2 = P.s * P.eps * P.eps; I.lam = P.lambda;
     I.inv_ntot = 1.0 / (double)I.ncell;
@@ -744,6 +749,8 @@ extern "C" psd_status psd_create(const psd_problem* probs, int batch, const psd_
           dalloc(h, (char**)&I.e2, N * tds) || dalloc(h, (char**)&I.r1, N * tds))
         return fail("out of device memory");
     }
+    if (hipMemset(I.spec, 0, (size_t)I.nspec * nspec_fields * 16) != hipSuccess)
+      return fail("memset of the spectrum buffer failed");
     // symbol table of -Delta_h along one axis and twiddles (host, long double)
     std::vector<double> S(P.n);
     std::vector<float> t32(2 * (size_t)P.n);
