@@ -160,6 +160,13 @@ __device__ __forceinline__ void dftR(cx<T>* a) {
 constexpr int fft_ls(int N) { return N + N / 16 + 1; }
 __device__ __forceinline__ int pidx(int t) { return t + (t >> 4); }
 
+// Copy the twiddle table exp(-2 pi i m/N), m < N, into LDS (dst); the
+// caller's next barrier publishes it.
+template <typename T, int N>
+__device__ __forceinline__ void stage_twiddles(cx<T>* dst, const cx<T>* __restrict__ tw) {
+  for (int i = threadIdx.x; i < N; i += PSD_NT) dst[i] = tw[i];
+}
+
 template <int S, int NSTG, typename F>
 __device__ __forceinline__ void stage_loop(F&& f) {
   if constexpr (S < NSTG) {
@@ -169,8 +176,8 @@ __device__ __forceinline__ void stage_loop(F&& f) {
 }
 
 // Transform NL lines of length N held in LDS (line l at buf + l*LS, element
-// t at pidx(t)), in
-// place, unnormalised.  tw[m] = exp(-2 pi i m / N) (global, cached).
+// t at pidx(t)), in place, unnormalised.  tw[m] = exp(-2 pi i m / N), staged
+// in LDS by the caller.
 // Must be called by all PSD_NT threads of the block; ends with a barrier.
 template <typename T, int N, int NL, int LS, int DIR>
 __device__ __forceinline__ void lds_fft(cx<T>* buf, const cx<T>* __restrict__ tw) {
@@ -259,6 +266,8 @@ __device__ __forceinline__ void r2c_rows(const RowArgs<T>& A, long long row0, cx
   constexpr int IT = (NV + PSD_NT - 1) / PSD_NT;
   static_assert(N % VEC == 0, "row length must be a multiple of the vector width");
   struct alignas(16) V { TIN x[VEC]; };
+  cx<T>* twl = buf + NL * LS;
+  stage_twiddles<T, N>(twl, tw);
   V regs[IT];
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
@@ -286,7 +295,7 @@ __device__ __forceinline__ void r2c_rows(const RowArgs<T>& A, long long row0, cx
     }
   }
   __syncthreads();
-  lds_fft<T, N, NL, LS, -1>(buf, tw);
+  lds_fft<T, N, NL, LS, -1>(buf, twl);
   for (int e = threadIdx.x; e < NL * NC; e += PSD_NT) {
     const int l = e / NC, k = e - l * NC;
     const cx<T> zk = buf[l * LS + pidx(k)];
@@ -311,6 +320,8 @@ __device__ __forceinline__ void c2r_rows(const RowArgs<T>& A, long long row0, cx
   constexpr int NC = N / 2 + 1;
   constexpr int NE = NL * NC;
   constexpr int IT = (NE + PSD_NT - 1) / PSD_NT;
+  cx<T>* twl = buf + NL * LS;
+  stage_twiddles<T, N>(twl, tw);
   cx<T> ra[IT], rb[IT];
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
@@ -339,7 +350,7 @@ __device__ __forceinline__ void c2r_rows(const RowArgs<T>& A, long long row0, cx
     if (k != 0 && k != N / 2) buf[l * LS + pidx(N - k)] = conj(a) + mul_i<1>(conj(b));
   }
   __syncthreads();
-  lds_fft<T, N, NL, LS, 1>(buf, tw);
+  lds_fft<T, N, NL, LS, 1>(buf, twl);
   constexpr int VEC = 16 / (int)sizeof(TOUT);
   constexpr int NV = 2 * NL * N / VEC;
   struct alignas(16) V { TOUT x[VEC]; };
@@ -405,9 +416,11 @@ __device__ __forceinline__ void col_pass(cx<T>* base, long long inner_count, lon
                                          long long lstride, long long fstride, cx<T>* buf,
                                          const cx<T>* tw) {
   constexpr int LS = fft_ls(N);
+  cx<T>* twl = buf + NF * W * LS;
+  stage_twiddles<T, N>(twl, tw);
   col_load<T, N, W, NF>(base, inner_count, col0, lstride, fstride, buf);
   __syncthreads();
-  lds_fft<T, N, NF * W, LS, DIR>(buf, tw);
+  lds_fft<T, N, NF * W, LS, DIR>(buf, twl);
   for (int e = threadIdx.x; e < NF * W * N; e += PSD_NT) {
     const int c = e % W;
     const int ft = e / W;

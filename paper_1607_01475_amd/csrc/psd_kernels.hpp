@@ -22,17 +22,17 @@ struct Task2 {  // residual / line-search / col tiles
 
 template <typename T, int N>
 constexpr int row_lines() {
-  int nl = 32768 / (fft_ls(N) * (int)sizeof(cx<T>));
+  int nl = 32768 / (fft_ls(N) * (int)sizeof(cx<T>));  // plus N twiddles
   int p = 1;
   while (p * 2 <= nl && p < 32) p *= 2;
   return p;
 }
 // columns per block of a column pass: 128-byte segments where the LDS
-// footprint NF*W*fft_ls(N) complex stays within 64 KB
+// footprint NF*W*fft_ls(N) complex plus N twiddles stays within 64 KB
 template <typename T, int N, int NF>
 constexpr int col_width() {
   int w = 128 / (int)sizeof(cx<T>);
-  const int cap = 65536 / (NF * fft_ls(N) * (int)sizeof(cx<T>));
+  const int cap = (65536 - N * (int)sizeof(cx<T>)) / (NF * fft_ls(N) * (int)sizeof(cx<T>));
   if (cap < w) w = cap;
   return w < 1 ? 1 : w;
 }
@@ -371,24 +371,44 @@ __device__ __forceinline__ void fused_col(const Inst& I, const Task2& t, cx<T>* 
   const long long lstride = inner;
   cx<T>* base = (cx<T>*)I.spec;
   const long long col0 = t.b;
+  constexpr int NLMAX = (NFI > NFO ? NFI : NFO) * W;
+  cx<T>* twl = buf + NLMAX * LS;
+  stage_twiddles<T, N>(twl, tw);
   col_load<T, N, W, NFI>(base, inner, col0, lstride, fstride, buf);
   __syncthreads();
-  lds_fft<T, N, NFI * W, LS, -1>(buf, tw);
+  lds_fft<T, N, NFI * W, LS, -1>(buf, twl);
   const double s = I.s, se2 = I.se2, inv = I.inv_ntot;
   const double* S = I.S;
+  // column of this thread (fixed when W divides the block size)
+  int c_fix = -1, kx_fix = 0, ky_fix = 0;
+  double Kc_fix = 0.0;
+  if (PSD_NT % W == 0) {
+    c_fix = threadIdx.x % W;
+    const int col = (int)col0 + c_fix;
+    kx_fix = col % (int)ncp;
+    ky_fix = col / (int)ncp;
+    Kc_fix = S[kx_fix < nc ? kx_fix : 0] + (dim == 3 ? S[ky_fix < n ? ky_fix : 0] : 0.0);
+  }
   for (int e = threadIdx.x; e < W * N; e += PSD_NT) {
-    const int c = e % W, tt = e / W;
-    const long long col = col0 + c;
+    const int c = (PSD_NT % W == 0) ? c_fix : e % W, tt = e / W;
+    const int col = (int)col0 + c;
     if (col >= inner) continue;
-    const int kx = (int)(col % ncp);
-    const int ky = (dim == 2) ? tt : (int)(col / ncp);
+    int kx, ky;
+    double K;
+    if (PSD_NT % W == 0) {
+      kx = kx_fix;
+      ky = (dim == 2) ? tt : ky_fix;
+      K = Kc_fix + S[tt];
+    } else {
+      kx = col % (int)ncp;
+      ky = (dim == 2) ? tt : col / (int)ncp;
+      K = S[kx < nc ? kx : 0] + S[ky] + (dim == 3 ? S[tt] : 0.0);
+    }
     if (kx >= nc) {  // row padding: keep it zero, contribute nothing
 #pragma unroll
       for (int f = 0; f < NFO; ++f) buf[(f * W + c) * LS + pidx(tt)] = mk(T(0), T(0));
       continue;
     }
-    double K = S[kx] + S[ky];
-    if (dim == 3) K += S[tt];
     const double wgt = (kx == 0 || 2 * kx == (int)n) ? 1.0 : 2.0;
     if (OP == OP_PRECOND4) {
       const cx<T> X = buf[c * LS + pidx(tt)];
@@ -425,7 +445,7 @@ __device__ __forceinline__ void fused_col(const Inst& I, const Task2& t, cx<T>* 
     }
   }
   __syncthreads();
-  lds_fft<T, N, NFO * W, LS, 1>(buf, tw);
+  lds_fft<T, N, NFO * W, LS, 1>(buf, twl);
   for (int e = threadIdx.x; e < NFO * W * N; e += PSD_NT) {
     const int c = e % W;
     const int ft = e / W;

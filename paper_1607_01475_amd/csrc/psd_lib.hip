@@ -238,7 +238,7 @@ static void build_fft_tasks(psd_handle* h, FftTasks& F, int nfi, int nfo, bool w
         h->hT.push_back(t);
       }
       if (pass == 1 && with_slots) h->hI[b].nblk_c2r = slot;
-      R.lds = std::max(R.lds, (size_t)nl * fft_ls(I.n) * cxs);
+      R.lds = std::max(R.lds, ((size_t)nl * fft_ls(I.n) + I.n) * cxs);
     }
     R.cnt = (int)h->hT.size() - R.off;
   }
@@ -257,7 +257,7 @@ static void build_fft_tasks(psd_handle* h, FftTasks& F, int nfi, int nfo, bool w
             t.inst = b; t.a = z; t.b = c0;
             h->hT.push_back(t);
           }
-        R.lds = std::max(R.lds, (size_t)nf * W * fft_ls(I.n) * cxs);
+        R.lds = std::max(R.lds, ((size_t)nf * W * fft_ls(I.n) + I.n) * cxs);
       }
     }
     R.cnt = (int)h->hT.size() - R.off;
@@ -278,7 +278,7 @@ static void build_fft_tasks(psd_handle* h, FftTasks& F, int nfi, int nfo, bool w
       h->hT.push_back(t);
     }
     if (with_slots) I.nblk_sp = slot;
-    R.lds = std::max(R.lds, std::max((size_t)nfm * W * fft_ls(I.n) * cxs, (size_t)64 * 8));
+    R.lds = std::max(R.lds, std::max(((size_t)nfm * W * fft_ls(I.n) + I.n) * cxs, (size_t)64 * 8));
   }
   R.cnt = (int)h->hT.size() - R.off;
 }

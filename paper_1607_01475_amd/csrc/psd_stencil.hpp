@@ -311,6 +311,8 @@ __device__ void res3d_tile(const Inst& I, int x0, int y0, int z0, double* lds, d
   double vc0 = 0.0, vc1 = 0.0, vc2 = 0.0, lm = 0.0, l0 = 0.0, lp = 0.0;
   double sc0 = 0.0, sc1 = 0.0, sc2 = 0.0;
   double P_old = 0.0, Q_old = 0.0;
+  double f_next = 0.0;                 // f at the own cell of the next output plane
+  const long long fcol = (long long)wrapi(gx, n) + (long long)n * wrapi(gy, n);
   R3Prefetch<TD> pf;
   // planes z0-2 and z0-1 go straight to LDS; plane z0 is prefetched
   for (int q = -2; q <= -1; ++q) {
@@ -344,6 +346,9 @@ __device__ void res3d_tile(const Inst& I, int x0, int y0, int z0, double* lds, d
       sc0 = sc1; sc1 = sc2; sc2 = (double)pf.d_own;
     }
     if (j + 1 < z1) r3_fetch<TD, LOADD>(u, d, n, x0, y0, j + 3, ring_ey, ring_ex, pf);
+    // the output of this step (plane j) needs f(j): load it one step ahead
+    const double f_cur = f_next;
+    if (!HESS && j + 1 >= z0 && j + 1 < z1) f_next = I.f[fcol + (long long)n * n * (j + 1)];
     __syncthreads();
     const double* v0 = vb + ((j + 6) % 3) * R3_VP;       // plane j
     const double* v1 = vb + ((j + 1 + 6) % 3) * R3_VP;   // plane j+1
@@ -409,7 +414,7 @@ __device__ void res3d_tile(const Inst& I, int x0, int y0, int z0, double* lds, d
           I.adj_Hp[gi] = hx;
           acc[1] += vc0 * hx;
         } else {
-          const double r = I.f[gi] - (vc0 - s * div + se2 * l2);
+          const double r = f_cur - (vc0 - s * div + se2 * l2);
           ((TR*)I.r)[gi] = (TR)r;
           if (UPD) uo[gi] = vc0;
           acc[0] = fmax(acc[0], fabs(r));
