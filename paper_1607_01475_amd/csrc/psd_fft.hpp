@@ -245,8 +245,18 @@ struct RowArgs {
   int ncp;              // row stride (complex elements, >= N/2 + 1)
   long long rpf;        // rows per field
   long long nrows;      // rows over all fields of this pass (guard)
-  __device__ __forceinline__ const void* in(int f) const { return f == 0 ? rin0 : rin1; }
-  __device__ __forceinline__ void* out(int f) const { return f == 0 ? rout0 : (f == 1 ? rout1 : rout2); }
+  // value selects (not lvalue selects), so that the struct stays in registers
+  __device__ __forceinline__ const void* in(int f) const {
+    const void* a = rin0;
+    const void* b = rin1;
+    return f == 0 ? a : b;
+  }
+  __device__ __forceinline__ void* out(int f) const {
+    void* a = rout0;
+    void* b = rout1;
+    void* c = rout2;
+    return f == 0 ? a : (f == 1 ? b : c);
+  }
 };
 
 template <int N, typename T>

@@ -56,8 +56,13 @@ __global__ __launch_bounds__(PSD_NT) void k_res2d(const Inst* __restrict__ insts
   }
 }
 
+// Register budget of the 3D residual: PSD_RES3D_WAVES waves per SIMD (4: at
+// most 128 VGPRs; the LDS tile allows six blocks per CU)
+#ifndef PSD_RES3D_WAVES
+#define PSD_RES3D_WAVES 4
+#endif
 template <typename TD, typename TR, bool UPD>
-__global__ __launch_bounds__(PSD_NT) void k_res3d(const Inst* __restrict__ insts,
+__global__ __launch_bounds__(PSD_NT) __attribute__((amdgpu_waves_per_eu(PSD_RES3D_WAVES))) void k_res3d(const Inst* __restrict__ insts,
                                                   const Task2* __restrict__ tasks) {
   extern __shared__ double smem[];
   const Task2 t = tasks[blockIdx.x];
@@ -107,29 +112,29 @@ __global__ __launch_bounds__(PSD_NT) void k_res_finalize(const Inst* __restrict_
 // ===========================================================================
 // line search
 // ===========================================================================
-template <typename TD>
+template <typename TD, int MODE>
 __global__ __launch_bounds__(PSD_NT) void k_ls2d(const Inst* __restrict__ insts,
-                                                 const Task2* __restrict__ tasks, int mode) {
+                                                 const Task2* __restrict__ tasks) {
   extern __shared__ double smem[];
   const Task2 t = tasks[blockIdx.x];
   const Inst& I = insts[t.inst];
-  if (I.st->done || (mode == 2 && I.st->ls_phase == 2)) return;
+  if (I.st->done || (MODE == 2 && I.st->ls_phase == 2)) return;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  ls2d_tile<TD>(I, mode, t.a, t.b, smem, acc);
+  ls2d_tile<TD, MODE>(I, t.a, t.b, smem, acc);
   block_reduce<8, 0>(acc, smem + L2_LDS);
   if (threadIdx.x == 0)
     for (int k = 0; k < 8; ++k) I.part_ls[8 * t.slot + k] = acc[k];
 }
 
-template <typename TD>
+template <typename TD, int MODE>
 __global__ __launch_bounds__(PSD_NT) void k_ls3d(const Inst* __restrict__ insts,
-                                                 const Task2* __restrict__ tasks, int mode) {
+                                                 const Task2* __restrict__ tasks) {
   extern __shared__ double smem[];
   const Task2 t = tasks[blockIdx.x];
   const Inst& I = insts[t.inst];
-  if (I.st->done || (mode == 2 && I.st->ls_phase == 2)) return;
+  if (I.st->done || (MODE == 2 && I.st->ls_phase == 2)) return;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  ls3d_tile<TD>(I, mode, t.a, t.b, t.c, smem, acc);
+  ls3d_tile<TD, MODE>(I, t.a, t.b, t.c, smem, acc);
   block_reduce<8, 0>(acc, smem + L3_LDS);
   if (threadIdx.x == 0)
     for (int k = 0; k < 8; ++k) I.part_ls[8 * t.slot + k] = acc[k];

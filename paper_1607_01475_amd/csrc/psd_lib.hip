@@ -420,8 +420,17 @@ static void run_ls(psd_handle* h, int mode) {
   const Task2* t = h->dT + h->ls.off;
   {
     ProfScope ps(h, PSD_PASS_LS);
-    if (h->dim == 2) k_ls2d<TD><<<h->ls.cnt, PSD_NT, h->ls.lds, s>>>(h->dI, t, mode);
-    else k_ls3d<TD><<<h->ls.cnt, PSD_NT, h->ls.lds, s>>>(h->dI, t, mode);
+    const int nb = h->ls.cnt;
+    const size_t lds = h->ls.lds;
+    if (h->dim == 2) {
+      if (mode == 0) k_ls2d<TD, 0><<<nb, PSD_NT, lds, s>>>(h->dI, t);
+      else if (mode == 1) k_ls2d<TD, 1><<<nb, PSD_NT, lds, s>>>(h->dI, t);
+      else k_ls2d<TD, 2><<<nb, PSD_NT, lds, s>>>(h->dI, t);
+    } else {
+      if (mode == 0) k_ls3d<TD, 0><<<nb, PSD_NT, lds, s>>>(h->dI, t);
+      else if (mode == 1) k_ls3d<TD, 1><<<nb, PSD_NT, lds, s>>>(h->dI, t);
+      else k_ls3d<TD, 2><<<nb, PSD_NT, lds, s>>>(h->dI, t);
+    }
   }
   ProfScope ps(h, PSD_PASS_LS_FIN);
   k_ls_finalize<<<h->batch, PSD_NT, 0, s>>>(h->dI, mode);

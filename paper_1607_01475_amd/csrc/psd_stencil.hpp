@@ -239,14 +239,28 @@ __device__ __forceinline__ void r3_fetch(const double* __restrict__ u, const TD*
   }
 }
 
-// flux at one vertex from the 8 surrounding cell values; stores A, B, C
-__device__ __forceinline__ void r3_vertex_flux(const Inst& I, double qh, double c000, double c100,
-                                               double c010, double c110, double c001, double c101,
-                                               double c011, double c111, double& A, double& B,
-                                               double& C) {
-  const double gx = qh * ((c100 - c000) + (c110 - c010) + (c101 - c001) + (c111 - c011));
-  const double gy = qh * ((c010 - c000) + (c110 - c100) + (c011 - c001) + (c111 - c101));
-  const double gz = qh * ((c001 - c000) + (c101 - c100) + (c011 - c010) + (c111 - c110));
+// Per-plane partial sums of the 2x2 cells (c00, c10, c01, c11) below or
+// above a vertex: the vertex gradient of Sec. 5.1 (3D form) between planes k
+// and k+1 is (ex_k + ex_k+1, ey_k + ey_k+1, sm_k+1 - sm_k) / (4h), so each
+// plane's partials are formed once and used by the two vertex planes that
+// touch it.
+struct VPart {
+  double ex, ey, sm;
+};
+__device__ __forceinline__ VPart vpart(double c00, double c10, double c01, double c11) {
+  VPart q;
+  q.ex = (c10 - c00) + (c11 - c01);
+  q.ey = (c01 - c00) + (c11 - c10);
+  q.sm = (c00 + c10) + (c01 + c11);
+  return q;
+}
+
+// flux at a vertex from its two plane partials, gradients kept scaled by 4h
+// (the flux is homogeneous of degree p-1; the factor (1/(4h))^p is applied
+// with the divergence).  Stores A = Fx + Fy, B = Fx - Fy, C = Fz.
+__device__ __forceinline__ void r3_flux(const Inst& I, const VPart& lo, const VPart& hi, double& A,
+                                        double& B, double& C) {
+  const double gx = lo.ex + hi.ex, gy = lo.ey + hi.ey, gz = hi.sm - lo.sm;
   const double rr = flux_r(gx * gx + gy * gy + gz * gz, I.p, I.p_is_4, I.p_is_2);
   const double fx = rr * gx, fy = rr * gy;
   A = fx + fy;
@@ -254,20 +268,13 @@ __device__ __forceinline__ void r3_vertex_flux(const Inst& I, double qh, double 
   C = rr * gz;
 }
 
-// HESS: Hessian-vector product (see res2d_tile); the "d" stream carries u*.
-// linearised flux at a vertex: c*** cells of xi, s*** cells of u*
-__device__ __forceinline__ void r3_vertex_flux_lin(
-    const Inst& I, double qh, double c000, double c100, double c010, double c110, double c001,
-    double c101, double c011, double c111, double s000, double s100, double s010, double s110,
-    double s001, double s101, double s011, double s111, double& A, double& B, double& C) {
-  const double bx = qh * ((c100 - c000) + (c110 - c010) + (c101 - c001) + (c111 - c011));
-  const double by = qh * ((c010 - c000) + (c110 - c100) + (c011 - c001) + (c111 - c101));
-  const double bz = qh * ((c001 - c000) + (c101 - c100) + (c011 - c010) + (c111 - c110));
-  const double ax = qh * ((s100 - s000) + (s110 - s010) + (s101 - s001) + (s111 - s011));
-  const double ay = qh * ((s010 - s000) + (s110 - s100) + (s011 - s001) + (s111 - s101));
-  const double az = qh * ((s001 - s000) + (s101 - s100) + (s011 - s010) + (s111 - s110));
+// HESS: linearised flux; lo/hi are partials of xi, slo/shi of u*
+__device__ __forceinline__ void r3_flux_lin(const Inst& I, const VPart& lo, const VPart& hi,
+                                            const VPart& slo, const VPart& shi, double& A,
+                                            double& B, double& C) {
   double fx, fy, fz;
-  flux_lin(I, ax, ay, az, bx, by, bz, fx, fy, fz);
+  flux_lin(I, slo.ex + shi.ex, slo.ey + shi.ey, shi.sm - slo.sm, lo.ex + hi.ex, lo.ey + hi.ey,
+           hi.sm - lo.sm, fx, fy, fz);
   A = fx + fy;
   B = fx - fy;
   C = fz;
@@ -292,6 +299,8 @@ __device__ void res3d_tile(const Inst& I, int x0, int y0, int z0, double* lds, d
   double* fB = fA + R3_FP;
   double* fC = fB + R3_FP;
   const double ih = I.inv_h, ih2 = ih * ih, qh = 0.25 * ih;
+  // (1/(4h))^p: the divergence's 1/(4h) times the flux's (1/(4h))^(p-1)
+  const double qhp = I.p_is_4 ? (qh * qh) * (qh * qh) : (I.p_is_2 ? qh * qh : pow(qh, I.p));
   const double s = I.s, se2 = I.se2;
   const int z1 = min(z0 + I.zchunk_res, n);
   const int tid = threadIdx.x;
@@ -303,14 +312,19 @@ __device__ void res3d_tile(const Inst& I, int x0, int y0, int z0, double* lds, d
   const int ring_ey = vring / R3_VW, ring_ex = vring - ring_ey * R3_VW;
   const int lring = tid < R3_LRING ? r3_lring_pos(tid) : 0;
   const int fring = tid < R3_FRING ? r3_fring_pos(tid) : 0;
+  // low-corner cell of the ring vertex in a v plane
+  const int fring_c = (fring / R3_FW + 1) * R3_VW + fring % R3_FW + 1;
   const int gx = x0 + tx, gy = y0 + ty;
   const bool own = gx < n && gy < n;
 
   // own-column registers: v at planes j, j+1, j+2; Laplacian at j-1, j, j+1;
   // Hessian mode: u* at planes j, j+1, j+2
   double vc0 = 0.0, vc1 = 0.0, vc2 = 0.0, lm = 0.0, l0 = 0.0, lp = 0.0;
-  double sc0 = 0.0, sc1 = 0.0, sc2 = 0.0;
+  double sc1 = 0.0, sc2 = 0.0;
   double P_old = 0.0, Q_old = 0.0;
+  // plane partials of the lower plane of the current vertex plane: own
+  // vertex and ring vertex, of v and (Hessian mode) u*
+  VPart po = {0.0, 0.0, 0.0}, pr = {0.0, 0.0, 0.0}, so = {0.0, 0.0, 0.0}, sr = {0.0, 0.0, 0.0};
   double f_next = 0.0;                 // f at the own cell of the next output plane
   const long long fcol = (long long)wrapi(gx, n) + (long long)n * wrapi(gy, n);
   R3Prefetch<TD> pf;
@@ -343,7 +357,7 @@ __device__ void res3d_tile(const Inst& I, int x0, int y0, int z0, double* lds, d
       double* sn = sb + ((j + 2 + 6) % 3) * R3_VP;
       sn[vown] = (double)pf.d_own;
       if (tid < R3_VRING) sn[vring] = (double)pf.d_ring;
-      sc0 = sc1; sc1 = sc2; sc2 = (double)pf.d_own;
+      sc1 = sc2; sc2 = (double)pf.d_own;
     }
     if (j + 1 < z1) r3_fetch<TD, LOADD>(u, d, n, x0, y0, j + 3, ring_ey, ring_ex, pf);
     // the output of this step (plane j) needs f(j): load it one step ahead
@@ -353,11 +367,14 @@ __device__ void res3d_tile(const Inst& I, int x0, int y0, int z0, double* lds, d
     const double* v0 = vb + ((j + 6) % 3) * R3_VP;       // plane j
     const double* v1 = vb + ((j + 1 + 6) % 3) * R3_VP;   // plane j+1
     const double* v2 = vn;                                // plane j+2
+    // own neighbours in plane j+1 (Laplacian and vertex partials)
+    const int c = vown;
+    const double xm = v1[c - 1], xp = v1[c + 1], ym = v1[c - R3_VW], yp = v1[c + R3_VW];
+    const double xyp = v1[c + R3_VW + 1];
     // Laplacian of plane j+1: own cell (z neighbours from registers) and ring
     double* ln = lb + ((j + 1 + 2) & 1) * R3_LP;
     {
-      const int c = vown;
-      const double lap = (v1[c - 1] + v1[c + 1] + v1[c - R3_VW] + v1[c + R3_VW] + vc0 + vc2 - 6.0 * vc1) * ih2;
+      const double lap = (xm + xp + ym + yp + vc0 + vc2 - 6.0 * vc1) * ih2;
       ln[lown] = lap;
       lm = l0; l0 = lp; lp = lap;
       if (tid < R3_LRING) {
@@ -366,38 +383,33 @@ __device__ void res3d_tile(const Inst& I, int x0, int y0, int z0, double* lds, d
         ln[lring] = (v1[cc - 1] + v1[cc + 1] + v1[cc - R3_VW] + v1[cc + R3_VW] + v0[cc] + v2[cc] - 6.0 * v1[cc]) * ih2;
       }
     }
+    // partials of plane j+1 for the own and the ring vertex
+    const VPart pn = vpart(vc1, xp, yp, xyp);
+    VPart prn = {0.0, 0.0, 0.0}, sn_own = {0.0, 0.0, 0.0}, srn = {0.0, 0.0, 0.0};
+    if (tid < R3_FRING)
+      prn = vpart(v1[fring_c], v1[fring_c + 1], v1[fring_c + R3_VW], v1[fring_c + R3_VW + 1]);
+    if (HESS) {
+      const double* s1 = sb + ((j + 1 + 6) % 3) * R3_VP;
+      sn_own = vpart(sc1, s1[c + 1], s1[c + R3_VW], s1[c + R3_VW + 1]);
+      if (tid < R3_FRING)
+        srn = vpart(s1[fring_c], s1[fring_c + 1], s1[fring_c + R3_VW], s1[fring_c + R3_VW + 1]);
+    }
     // fluxes at vertex plane j+1/2 (cells j, j+1) and the partial divergence
     double A_own = 0.0, C_own = 0.0;
     if (j >= z0 - 1) {
-      const double* s0 = sb + ((j + 6) % 3) * R3_VP;
-      const double* s1 = sb + ((j + 1 + 6) % 3) * R3_VP;
-      {
-        const int c = vown;  // own vertex: cell (i, j) of the vertex is the own cell
-        double A, B, C;
-        if (HESS)
-          r3_vertex_flux_lin(I, qh, vc0, v0[c + 1], v0[c + R3_VW], v0[c + R3_VW + 1], vc1, v1[c + 1],
-                             v1[c + R3_VW], v1[c + R3_VW + 1], sc0, s0[c + 1], s0[c + R3_VW],
-                             s0[c + R3_VW + 1], sc1, s1[c + 1], s1[c + R3_VW], s1[c + R3_VW + 1], A, B, C);
-        else
-          r3_vertex_flux(I, qh, vc0, v0[c + 1], v0[c + R3_VW], v0[c + R3_VW + 1], vc1, v1[c + 1],
-                         v1[c + R3_VW], v1[c + R3_VW + 1], A, B, C);
-        fA[fown] = A; fB[fown] = B; fC[fown] = C;
-        A_own = A; C_own = C;
-      }
+      double A, B, C;
+      if (HESS) r3_flux_lin(I, po, pn, so, sn_own, A, B, C);
+      else r3_flux(I, po, pn, A, B, C);
+      fA[fown] = A; fB[fown] = B; fC[fown] = C;
+      A_own = A; C_own = C;
       if (tid < R3_FRING) {
-        const int fy = fring / R3_FW, fx = fring - fy * R3_FW;
-        const int c = (fy + 1) * R3_VW + fx + 1;
-        double A, B, C;
-        if (HESS)
-          r3_vertex_flux_lin(I, qh, v0[c], v0[c + 1], v0[c + R3_VW], v0[c + R3_VW + 1], v1[c], v1[c + 1],
-                             v1[c + R3_VW], v1[c + R3_VW + 1], s0[c], s0[c + 1], s0[c + R3_VW],
-                             s0[c + R3_VW + 1], s1[c], s1[c + 1], s1[c + R3_VW], s1[c + R3_VW + 1], A, B, C);
-        else
-          r3_vertex_flux(I, qh, v0[c], v0[c + 1], v0[c + R3_VW], v0[c + R3_VW + 1], v1[c], v1[c + 1],
-                         v1[c + R3_VW], v1[c + R3_VW + 1], A, B, C);
+        if (HESS) r3_flux_lin(I, pr, prn, sr, srn, A, B, C);
+        else r3_flux(I, pr, prn, A, B, C);
         fA[fring] = A; fB[fring] = B; fC[fring] = C;
       }
     }
+    po = pn; pr = prn;
+    if (HESS) { so = sn_own; sr = srn; }
     __syncthreads();
     if (j >= z0 - 1) {
       const int fx = fown - 1, fy = fown - R3_FW, fxy = fown - R3_FW - 1;
@@ -405,7 +417,7 @@ __device__ void res3d_tile(const Inst& I, int x0, int y0, int z0, double* lds, d
       const double Q = C_own + fC[fx] + fC[fy] + fC[fxy];
       if (j >= z0 && own) {
         // output plane j: v(j) = vc0, Laplacian planes j-1, j, j+1 = lm, l0, lp
-        const double div = qh * (P + P_old + Q - Q_old);
+        const double div = qhp * (P + P_old + Q - Q_old);
         const double* lc = lb + ((j + 2) & 1) * R3_LP;   // Laplacian plane j
         const double l2 = (lc[lown - 1] + lc[lown + 1] + lc[lown - R3_LW] + lc[lown + R3_LW] + lm + lp - 6.0 * l0) * ih2;
         const long long gi = gx + (long long)n * (gy + (long long)n * j);
@@ -436,10 +448,11 @@ __device__ void res3d_tile(const Inst& I, int x0, int y0, int z0, double* lds, d
 // P2, P4.  Layout of the 8 partials: MODE 0: S2 S3 S4 S5 P2 P4 0 0;
 // MODE 1: NL dNL P2 P4 0 0 0 0.
 // ===========================================================================
-__device__ __forceinline__ void ls_vertex(int mode, double p, double alpha, double ax, double ay,
+template <int MODE>
+__device__ __forceinline__ void ls_vertex(double p, double alpha, double ax, double ay,
                                           double az, double bx, double by, double bz,
                                           double (&acc)[8]) {
-  if (mode == 0) {
+  if (MODE == 0) {
     const double a2 = ax * ax + ay * ay + az * az, b2 = bx * bx + by * by + bz * bz;
     const double ab = ax * bx + ay * by + az * bz;
     acc[0] += a2 * b2;
@@ -462,13 +475,13 @@ __device__ __forceinline__ void ls_vertex(int mode, double p, double alpha, doub
 constexpr int L2_W = T2X + 2, L2_H = T2Y + 2;
 constexpr int L2_LDS = 2 * L2_W * L2_H;
 
-template <typename TD>
-__device__ void ls2d_tile(const Inst& I, int mode, int x0, int y0, double* lds, double (&acc)[8]) {
+template <typename TD, int MODE>
+__device__ void ls2d_tile(const Inst& I, int x0, int y0, double* lds, double (&acc)[8]) {
   const int n = I.n;
   const SolveState* st = I.st;
   const double* __restrict__ u = I.u[st->iter & 1];
   const TD* __restrict__ d = (const TD*)I.d;
-  const double alpha = (mode == 2) ? st->x : 0.0;
+  const double alpha = (MODE == 2) ? st->x : 0.0;
   double* ul = lds;
   double* dl = lds + L2_W * L2_H;
   for (int e = threadIdx.x; e < L2_W * L2_H; e += PSD_NT) {
@@ -488,9 +501,9 @@ __device__ void ls2d_tile(const Inst& I, int mode, int x0, int y0, double* lds, 
     const double b00 = dl[c], b10 = dl[c + 1], b01 = dl[c + L2_W], b11 = dl[c + L2_W + 1];
     const double ax = hh * ((a10 - a00) + (a11 - a01)), ay = hh * ((a01 - a00) + (a11 - a10));
     const double bx = hh * ((b10 - b00) + (b11 - b01)), by = hh * ((b01 - b00) + (b11 - b10));
-    ls_vertex(mode, I.p, alpha, ax, ay, 0.0, bx, by, 0.0, acc);
+    ls_vertex<MODE>(I.p, alpha, ax, ay, 0.0, bx, by, 0.0, acc);
     const double ld = (dl[c - 1] + dl[c + 1] + dl[c - L2_W] + dl[c + L2_W] - 4.0 * b00) * ih2;
-    if (mode == 0) { acc[4] += b00 * b00; acc[5] += ld * ld; }
+    if (MODE == 0) { acc[4] += b00 * b00; acc[5] += ld * ld; }
     else { acc[2] += b00 * b00; acc[3] += ld * ld; }
   }
 }
@@ -524,17 +537,22 @@ __device__ __forceinline__ void l3_fetch(const double* __restrict__ u, const TD*
   }
 }
 
-template <typename TD>
-__device__ void ls3d_tile(const Inst& I, int mode, int x0, int y0, int z0, double* lds,
+// Vertex gradients from per-plane partial sums of the 2x2 cells around a
+// vertex column: for a plane, Ex = (c10 - c00) + (c11 - c01),
+// Ey = (c01 - c00) + (c11 - c10), Sm = c00 + c10 + c01 + c11; the gradient at
+// the vertex between planes k and k+1 is (Ex_k + Ex_k+1, Ey_k + Ey_k+1,
+// Sm_k+1 - Sm_k) / (4h).  The 1/(4h) factor is applied once to the sums.
+template <typename TD, int MODE>
+__device__ void ls3d_tile(const Inst& I, int x0, int y0, int z0, double* lds,
                           double (&acc)[8]) {
   const int n = I.n;
   const SolveState* st = I.st;
   const double* __restrict__ u = I.u[st->iter & 1];
   const TD* __restrict__ d = (const TD*)I.d;
-  const double alpha = (mode == 2) ? st->x : 0.0;
+  const double alpha = (MODE == 2) ? st->x : 0.0;
   double* ub = lds;
   double* db = lds + 3 * L3_P;
-  const double qh = 0.25 * I.inv_h, ih2 = I.inv_h * I.inv_h;
+  const double ih2 = I.inv_h * I.inv_h;
   const int z1 = min(z0 + I.zchunk_ls, n);
   const int tid = threadIdx.x;
   const int tx = tid % T3X, ty = tid / T3X;
@@ -542,49 +560,76 @@ __device__ void ls3d_tile(const Inst& I, int mode, int x0, int y0, int z0, doubl
   const int c = (ty + 1) * L3_W + tx + 1;           // own cell in a plane buffer
   const int ring = tid < L3_RING ? r3_lring_pos(tid) : 0;   // same ring shape as a Laplacian plane
   const int ring_ey = ring / L3_W, ring_ex = ring - ring_ey * L3_W;
-  double uc0 = 0.0, uc1 = 0.0, dm = 0.0, dc0 = 0.0, dc1 = 0.0;
+  double uc1 = 0.0, dm = 0.0, dc0 = 0.0, dc1 = 0.0;
+  // plane partials of u and d for the own vertex column (plane k), and the
+  // +x, +y neighbours of d in plane k (reused by the Laplacian of d)
+  double exu = 0.0, eyu = 0.0, smu = 0.0, exd = 0.0, eyd = 0.0, smd = 0.0;
+  double d10 = 0.0, d01 = 0.0;
+  double sacc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   L3Prefetch<TD> pf;
-  for (int q = -1; q <= 0; ++q) {
-    l3_fetch<TD>(u, d, n, x0, y0, z0 + q, ring_ey, ring_ex, pf);
-    const int sl = ((z0 + q + 3) % 3) * L3_P;
+  // plane z0-1 enters only through the own-column d (Laplacian along z)
+  dc0 = (double)d[(long long)wrapi(z0 - 1, n) * n * n + wrapi(x0 + tx, n) +
+                  (long long)n * wrapi(y0 + ty, n)];
+  {
+    l3_fetch<TD>(u, d, n, x0, y0, z0, ring_ey, ring_ex, pf);
+    const int sl = (z0 % 3) * L3_P;
     ub[sl + c] = pf.u_own;
     db[sl + c] = (double)pf.d_own;
     if (tid < L3_RING) { ub[sl + ring] = pf.u_ring; db[sl + ring] = (double)pf.d_ring; }
-    uc0 = uc1; uc1 = pf.u_own;
-    dm = dc0; dc0 = dc1; dc1 = (double)pf.d_own;
+    uc1 = pf.u_own;
+    dc1 = (double)pf.d_own;
   }
-  // now uc1 = u(z0), dc0 = d(z0-1), dc1 = d(z0)
+  // now uc1 = u(z0), dc0 = d(z0-1), dc1 = d(z0); partials of plane z0
+  __syncthreads();
+  {
+    const int s0 = (z0 % 3) * L3_P;
+    const double u10 = ub[s0 + c + 1], u01 = ub[s0 + c + L3_W], u11 = ub[s0 + c + L3_W + 1];
+    exu = (u10 - uc1) + (u11 - u01); eyu = (u01 - uc1) + (u11 - u10); smu = uc1 + u10 + u01 + u11;
+    d10 = db[s0 + c + 1]; d01 = db[s0 + c + L3_W];
+    const double e11 = db[s0 + c + L3_W + 1];
+    exd = (d10 - dc1) + (e11 - d01); eyd = (d01 - dc1) + (e11 - d10); smd = dc1 + d10 + d01 + e11;
+  }
   l3_fetch<TD>(u, d, n, x0, y0, z0 + 1, ring_ey, ring_ex, pf);
   for (int k = z0; k < z1; ++k) {
     const int sn = ((k + 1 + 3) % 3) * L3_P;
     ub[sn + c] = pf.u_own;
     db[sn + c] = (double)pf.d_own;
     if (tid < L3_RING) { ub[sn + ring] = pf.u_ring; db[sn + ring] = (double)pf.d_ring; }
-    uc0 = uc1; uc1 = pf.u_own;
+    uc1 = pf.u_own;
     dm = dc0; dc0 = dc1; dc1 = (double)pf.d_own;
     if (k + 1 < z1) l3_fetch<TD>(u, d, n, x0, y0, k + 2, ring_ey, ring_ex, pf);
     __syncthreads();
+    // partials of plane k+1
+    const double* u1 = ub + sn;
+    const double* d1 = db + sn;
+    const double u10 = u1[c + 1], u01 = u1[c + L3_W], u11 = u1[c + L3_W + 1];
+    const double exu1 = (u10 - uc1) + (u11 - u01), eyu1 = (u01 - uc1) + (u11 - u10);
+    const double smu1 = uc1 + u10 + u01 + u11;
+    const double n10 = d1[c + 1], n01 = d1[c + L3_W], n11 = d1[c + L3_W + 1];
+    const double exd1 = (n10 - dc1) + (n11 - n01), eyd1 = (n01 - dc1) + (n11 - n10);
+    const double smd1 = dc1 + n10 + n01 + n11;
     if (own) {
-      const double* u0 = ub + ((k + 3) % 3) * L3_P;
-      const double* u1 = ub + sn;
+      const double ax = exu + exu1, ay = eyu + eyu1, az = smu1 - smu;
+      const double bx = exd + exd1, by = eyd + eyd1, bz = smd1 - smd;
+      ls_vertex<MODE>(I.p, alpha, ax, ay, az, bx, by, bz, sacc);
       const double* d0 = db + ((k + 3) % 3) * L3_P;
-      const double* d1 = db + sn;
-      const double a100 = u0[c + 1], a010 = u0[c + L3_W], a110 = u0[c + L3_W + 1];
-      const double a101 = u1[c + 1], a011 = u1[c + L3_W], a111 = u1[c + L3_W + 1];
-      const double b100 = d0[c + 1], b010 = d0[c + L3_W], b110 = d0[c + L3_W + 1];
-      const double b101 = d1[c + 1], b011 = d1[c + L3_W], b111 = d1[c + L3_W + 1];
-      const double a000 = uc0, a001 = uc1, b000 = dc0, b001 = dc1;
-      const double ax = qh * ((a100 - a000) + (a110 - a010) + (a101 - a001) + (a111 - a011));
-      const double ay = qh * ((a010 - a000) + (a110 - a100) + (a011 - a001) + (a111 - a101));
-      const double az = qh * ((a001 - a000) + (a101 - a100) + (a011 - a010) + (a111 - a110));
-      const double bx = qh * ((b100 - b000) + (b110 - b010) + (b101 - b001) + (b111 - b011));
-      const double by = qh * ((b010 - b000) + (b110 - b100) + (b011 - b001) + (b111 - b101));
-      const double bz = qh * ((b001 - b000) + (b101 - b100) + (b011 - b010) + (b111 - b110));
-      ls_vertex(mode, I.p, alpha, ax, ay, az, bx, by, bz, acc);
-      const double ld = (d0[c - 1] + d0[c + 1] + d0[c - L3_W] + d0[c + L3_W] + dm + dc1 - 6.0 * dc0) * ih2;
-      if (mode == 0) { acc[4] += b000 * b000; acc[5] += ld * ld; }
-      else { acc[2] += b000 * b000; acc[3] += ld * ld; }
+      const double ld = (d0[c - 1] + d10 + d0[c - L3_W] + d01 + dm + dc1 - 6.0 * dc0) * ih2;
+      if (MODE == 0) { sacc[4] += dc0 * dc0; sacc[5] += ld * ld; }
+      else { sacc[2] += dc0 * dc0; sacc[3] += ld * ld; }
     }
+    exu = exu1; eyu = eyu1; smu = smu1;
+    exd = exd1; eyd = eyd1; smd = smd1;
+    d10 = n10; d01 = n01;
+  }
+  // vertex sums were taken with gradients scaled by 4h: undo once
+  const double qh = 0.25 * I.inv_h;
+  const double sc = (MODE == 0 || I.p_is_4) ? qh * qh * qh * qh : pow(qh, I.p);
+  if (MODE == 0) {
+    for (int q = 0; q < 4; ++q) acc[q] += sc * sacc[q];
+    acc[4] += sacc[4]; acc[5] += sacc[5];
+  } else {
+    acc[0] += sc * sacc[0]; acc[1] += sc * sacc[1];
+    acc[2] += sacc[2]; acc[3] += sacc[3];
   }
 }
 
