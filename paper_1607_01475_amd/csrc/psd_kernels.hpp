@@ -19,6 +19,8 @@ struct Task2 {  // residual / line-search / col tiles
 // supported line lengths
 // ---------------------------------------------------------------------------
 #define PSD_FOR_EACH_N(X) X(16) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(1024)
+// lengths of the 3D grids (y-axis column passes exist in 3D only)
+#define PSD_FOR_EACH_N3(X) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
 
 template <typename T, int N>
 constexpr int row_lines() {
@@ -291,8 +293,9 @@ __device__ __forceinline__ RowArgs<T> row_args(const Inst& I, int fs, cx<T>* spe
 }
 
 // row pass kernels: task.a = first global row (over fields), task.b = field
-// set, task.c = number of fields
-template <typename T, typename TIO, bool FWD>
+// set, task.c = number of fields.  One kernel per row length N: every block
+// of a launch works on instances with n = N.
+template <typename T, typename TIO, bool FWD, int N>
 __global__ __launch_bounds__(PSD_NT) void k_rows(const Inst* __restrict__ insts,
                                                  const Task2* __restrict__ tasks, int solver) {
   extern __shared__ double smem[];
@@ -303,16 +306,8 @@ __global__ __launch_bounds__(PSD_NT) void k_rows(const Inst* __restrict__ insts,
   const cx<T>* tw = (const cx<T>*)(sizeof(T) == 8 ? I.tw64 : I.tw32);
   RowArgs<T> A = row_args<T>(I, t.b, (cx<T>*)I.spec, t.c);
   double fsum[3] = {0.0, 0.0, 0.0};
-  switch (I.n) {
-#define PSD_ROW_CASE(NN)                                                               \
-    case NN:                                                                           \
-      if (FWD) r2c_rows<T, TIO, NN, row_lines<T, NN>()>(A, t.a, buf, tw);              \
-      else c2r_rows<T, TIO, NN, row_lines<T, NN>()>(A, t.a, buf, tw, fsum);            \
-      break;
-    PSD_FOR_EACH_N(PSD_ROW_CASE)
-#undef PSD_ROW_CASE
-    default: break;
-  }
+  if (FWD) r2c_rows<T, TIO, N, row_lines<T, N>()>(A, t.a, buf, tw);
+  else c2r_rows<T, TIO, N, row_lines<T, N>()>(A, t.a, buf, tw, fsum);
   if (!FWD && solver && I.order == 6) {
     __syncthreads();
     block_reduce<3, 0>(fsum, smem);
@@ -322,7 +317,7 @@ __global__ __launch_bounds__(PSD_NT) void k_rows(const Inst* __restrict__ insts,
 }
 
 // plain column pass: task.a = outer index, task.b = first column; NF fields
-template <typename T, int NF, int DIR>
+template <typename T, int NF, int DIR, int N>
 __global__ __launch_bounds__(PSD_NT) void k_cols(const Inst* __restrict__ insts,
                                                  const Task2* __restrict__ tasks, int axis,
                                                  int solver) {
@@ -332,7 +327,7 @@ __global__ __launch_bounds__(PSD_NT) void k_cols(const Inst* __restrict__ insts,
   if (solver && I.st->done) return;
   cx<T>* buf = (cx<T>*)smem;
   const cx<T>* tw = (const cx<T>*)(sizeof(T) == 8 ? I.tw64 : I.tw32);
-  const long long n = I.n;
+  const long long n = N;
   const long long ncp = sizeof(T) == 8 ? I.ncp64 : I.ncp32;
   const long long fstride = sizeof(T) == 8 ? I.nspec64 : I.nspec32;
   // axis 1: lines along y (stride ncp), columns kx, outer z (stride n*ncp)
@@ -340,15 +335,7 @@ __global__ __launch_bounds__(PSD_NT) void k_cols(const Inst* __restrict__ insts,
   const long long inner = (axis == 1) ? ncp : n * ncp;
   const long long lstride = (axis == 1) ? ncp : n * ncp;
   cx<T>* base = (cx<T>*)I.spec + (axis == 1 ? (long long)t.a * n * ncp : 0);
-  switch (I.n) {
-#define PSD_COL_CASE(NN)                                                                          \
-    case NN:                                                                                      \
-      col_pass<T, NN, col_width<T, NN, NF>(), NF, DIR>(base, inner, t.b, lstride, fstride, buf, tw); \
-      break;
-    PSD_FOR_EACH_N(PSD_COL_CASE)
-#undef PSD_COL_CASE
-    default: break;
-  }
+  col_pass<T, N, col_width<T, N, NF>(), NF, DIR>(base, inner, t.b, lstride, fstride, buf, tw);
 }
 
 // Spectral operators applied between the forward and inverse transform of
@@ -459,7 +446,7 @@ __device__ __forceinline__ void fused_col(const Inst& I, const Task2& t, cx<T>* 
   }
 }
 
-template <typename T, int OP>
+template <typename T, int OP, int N>
 __global__ __launch_bounds__(PSD_NT) void k_cols_fused(const Inst* __restrict__ insts,
                                                        const Task2* __restrict__ tasks, int solver) {
   extern __shared__ double smem[];
@@ -469,17 +456,8 @@ __global__ __launch_bounds__(PSD_NT) void k_cols_fused(const Inst* __restrict__ 
   cx<T>* buf = (cx<T>*)smem;
   double acc[2] = {0.0, 0.0};
   constexpr int NFM = (OP == OP_PRECOND6) ? 3 : 1;
-  switch (I.n) {
-#define PSD_FC_CASE(NN)                                                          \
-    case NN:                                                                     \
-      fused_col<T, NN, col_width<T, NN, NFM>(), OP>(I, t, buf, acc);             \
-      break;
-    PSD_FOR_EACH_N(PSD_FC_CASE)
-#undef PSD_FC_CASE
-    default: break;
-  }
-  // LDS scratch after the largest FFT buffer of this launch is not known
-  // here; reuse the start of smem after a barrier (buffers are dead now).
+  fused_col<T, N, col_width<T, N, NFM>(), OP>(I, t, buf, acc);
+  // the FFT buffers are dead after this barrier: reuse them for the reduction
   __syncthreads();
   block_reduce<2, 0>(acc, smem);
   if (threadIdx.x == 0) {

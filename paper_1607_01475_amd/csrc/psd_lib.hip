@@ -31,9 +31,16 @@ namespace {
 
 thread_local std::string g_create_error;
 
+// launch group of one transform length inside a pass
+struct NPart {
+  int n = 0, off = 0, cnt = 0;
+  size_t lds = 0;
+};
+
 struct Range {
   int off = 0, cnt = 0;
   size_t lds = 0;
+  std::vector<NPart> parts;   // FFT passes: tasks grouped by n, one launch per group
 };
 
 struct FftTasks {  // task ranges of one spectral application
@@ -222,23 +229,46 @@ template <typename T>
 static void build_fft_tasks(psd_handle* h, FftTasks& F, int nfi, int nfo, bool with_slots, int fs_in,
                             int fs_out) {
   const size_t cxs = sizeof(cx<T>);
+  F = FftTasks{};   // rebuilt after retiling: drop the previous launch groups
+  // distinct transform lengths, ascending: tasks of one length are contiguous
+  std::vector<int> ns;
+  for (int b = 0; b < h->batch; ++b) ns.push_back(h->hI[b].n);
+  std::sort(ns.begin(), ns.end());
+  ns.erase(std::unique(ns.begin(), ns.end()), ns.end());
+  auto open_part = [&](Range& R, int n) {
+    NPart p;
+    p.n = n;
+    p.off = (int)h->hT.size();
+    R.parts.push_back(p);
+  };
+  auto close_part = [&](Range& R, size_t lds) {
+    NPart& p = R.parts.back();
+    p.cnt = (int)h->hT.size() - p.off;
+    p.lds = lds;
+    R.lds = std::max(R.lds, lds);
+    if (p.cnt == 0) R.parts.pop_back();
+  };
   // rows R2C (nfi fields) and C2R (nfo fields)
   for (int pass = 0; pass < 2; ++pass) {
     Range& R = pass == 0 ? F.r2c : F.c2r;
     const int nf = pass == 0 ? nfi : nfo;
     R.off = (int)h->hT.size();
-    for (int b = 0; b < h->batch; ++b) {
-      const Inst& I = h->hI[b];
-      const int nl = host_row_lines<T>(I.n);
-      const long long rows = (long long)nf * (I.ncell / I.n);
-      int slot = 0;
-      for (long long r0 = 0; r0 < rows; r0 += 2 * nl) {
-        Task2 t{};
-        t.inst = b; t.a = (int)r0; t.b = pass == 0 ? fs_in : fs_out; t.c = nf; t.slot = slot++;
-        h->hT.push_back(t);
+    for (int n : ns) {
+      open_part(R, n);
+      const int nl = host_row_lines<T>(n);
+      for (int b = 0; b < h->batch; ++b) {
+        const Inst& I = h->hI[b];
+        if (I.n != n) continue;
+        const long long rows = (long long)nf * (I.ncell / I.n);
+        int slot = 0;
+        for (long long r0 = 0; r0 < rows; r0 += 2 * nl) {
+          Task2 t{};
+          t.inst = b; t.a = (int)r0; t.b = pass == 0 ? fs_in : fs_out; t.c = nf; t.slot = slot++;
+          h->hT.push_back(t);
+        }
+        if (pass == 1 && with_slots) h->hI[b].nblk_c2r = slot;
       }
-      if (pass == 1 && with_slots) h->hI[b].nblk_c2r = slot;
-      R.lds = std::max(R.lds, ((size_t)nl * fft_ls(I.n) + I.n) * cxs);
+      close_part(R, ((size_t)nl * fft_ls(n) + n) * cxs);
     }
     R.cnt = (int)h->hT.size() - R.off;
   }
@@ -248,16 +278,20 @@ static void build_fft_tasks(psd_handle* h, FftTasks& F, int nfi, int nfo, bool w
     const int nf = pass == 0 ? nfi : nfo;
     R.off = (int)h->hT.size();
     if (h->dim == 3) {
-      for (int b = 0; b < h->batch; ++b) {
-        const Inst& I = h->hI[b];
-        const int W = host_cw<T>(I.n, nf);
-        for (int z = 0; z < I.n; ++z)
-          for (int c0 = 0; c0 < (sizeof(T) == 8 ? I.ncp64 : I.ncp32); c0 += W) {
-            Task2 t{};
-            t.inst = b; t.a = z; t.b = c0;
-            h->hT.push_back(t);
-          }
-        R.lds = std::max(R.lds, ((size_t)nf * W * fft_ls(I.n) + I.n) * cxs);
+      for (int n : ns) {
+        open_part(R, n);
+        const int W = host_cw<T>(n, nf);
+        for (int b = 0; b < h->batch; ++b) {
+          const Inst& I = h->hI[b];
+          if (I.n != n) continue;
+          for (int z = 0; z < I.n; ++z)
+            for (int c0 = 0; c0 < (sizeof(T) == 8 ? I.ncp64 : I.ncp32); c0 += W) {
+              Task2 t{};
+              t.inst = b; t.a = z; t.b = c0;
+              h->hT.push_back(t);
+            }
+        }
+        close_part(R, ((size_t)nf * W * fft_ls(n) + n) * cxs);
       }
     }
     R.cnt = (int)h->hT.size() - R.off;
@@ -265,20 +299,24 @@ static void build_fft_tasks(psd_handle* h, FftTasks& F, int nfi, int nfo, bool w
   // fused last-axis pass
   Range& R = F.colz;
   R.off = (int)h->hT.size();
-  for (int b = 0; b < h->batch; ++b) {
-    Inst& I = h->hI[b];
-    const int nfm = std::max(nfi, nfo);
-    const int W = host_cw<T>(I.n, nfm);
-    const long long ncp = sizeof(T) == 8 ? I.ncp64 : I.ncp32;
-    const long long inner = h->dim == 2 ? ncp : (long long)I.n * ncp;
-    int slot = 0;
-    for (long long c0 = 0; c0 < inner; c0 += W) {
-      Task2 t{};
-      t.inst = b; t.a = 0; t.b = (int)c0; t.slot = slot++;
-      h->hT.push_back(t);
+  const int nfm = std::max(nfi, nfo);
+  for (int n : ns) {
+    open_part(R, n);
+    const int W = host_cw<T>(n, nfm);
+    for (int b = 0; b < h->batch; ++b) {
+      Inst& I = h->hI[b];
+      if (I.n != n) continue;
+      const long long ncp = sizeof(T) == 8 ? I.ncp64 : I.ncp32;
+      const long long inner = h->dim == 2 ? ncp : (long long)I.n * ncp;
+      int slot = 0;
+      for (long long c0 = 0; c0 < inner; c0 += W) {
+        Task2 t{};
+        t.inst = b; t.a = 0; t.b = (int)c0; t.slot = slot++;
+        h->hT.push_back(t);
+      }
+      if (with_slots) I.nblk_sp = slot;
     }
-    if (with_slots) I.nblk_sp = slot;
-    R.lds = std::max(R.lds, std::max(((size_t)nfm * W * fft_ls(I.n) + I.n) * cxs, (size_t)64 * 8));
+    close_part(R, std::max(((size_t)nfm * W * fft_ls(n) + n) * cxs, (size_t)64 * 8));
   }
   R.cnt = (int)h->hT.size() - R.off;
 }
@@ -354,39 +392,77 @@ static void build_all_tasks(psd_handle* h, std::vector<int>& nsp_aux) {
 // ---------------------------------------------------------------------------
 // launches
 // ---------------------------------------------------------------------------
+// one launch per transform length of the pass
+template <typename T, typename TIO, bool FWD>
+static void launch_rows(const Range& R, const Inst* dI, const Task2* dT, int sv, hipStream_t s) {
+  for (const NPart& p : R.parts) {
+    switch (p.n) {
+#define PSD_L(NN) \
+      case NN: k_rows<T, TIO, FWD, NN><<<p.cnt, PSD_NT, p.lds, s>>>(dI, dT + p.off, sv); break;
+      PSD_FOR_EACH_N(PSD_L)
+#undef PSD_L
+      default: break;
+    }
+  }
+}
+
+template <typename T, int NF, int DIR>
+static void launch_cols(const Range& R, const Inst* dI, const Task2* dT, int sv, hipStream_t s) {
+  for (const NPart& p : R.parts) {
+    switch (p.n) {
+#define PSD_L(NN) \
+      case NN: k_cols<T, NF, DIR, NN><<<p.cnt, PSD_NT, p.lds, s>>>(dI, dT + p.off, 1, sv); break;
+      PSD_FOR_EACH_N3(PSD_L)
+#undef PSD_L
+      default: break;
+    }
+  }
+}
+
+template <typename T, int OP>
+static void launch_fused(const Range& R, const Inst* dI, const Task2* dT, int sv, hipStream_t s) {
+  for (const NPart& p : R.parts) {
+    switch (p.n) {
+#define PSD_L(NN) \
+      case NN: k_cols_fused<T, OP, NN><<<p.cnt, PSD_NT, p.lds, s>>>(dI, dT + p.off, sv); break;
+      PSD_FOR_EACH_N(PSD_L)
+#undef PSD_L
+      default: break;
+    }
+  }
+}
+
 template <typename T, typename TIN, typename TOUT>
 static void run_fft(psd_handle* h, const FftTasks& F, int op, bool solver) {
   const Task2* dT = h->dT;
+  const Inst* dI = h->dI;
   hipStream_t s = h->stream;
   const int sv = solver ? 1 : 0;
   const bool pr = solver;  // auxiliary transforms are not profiled
   if (F.r2c.cnt) {
     ProfScope ps(h, pr ? PSD_PASS_ROWS_R2C : -1);
-    k_rows<T, TIN, true><<<F.r2c.cnt, PSD_NT, F.r2c.lds, s>>>(h->dI, dT + F.r2c.off, sv);
+    launch_rows<T, TIN, true>(F.r2c, dI, dT, sv, s);
   }
   const int nfi = op == OP_PRECOND6 ? 2 : 1, nfo = op == OP_PRECOND6 ? 3 : 1;
   if (F.coly_f.cnt) {
     ProfScope ps(h, pr ? PSD_PASS_COLS_FWD : -1);
-    if (nfi == 1) k_cols<T, 1, -1><<<F.coly_f.cnt, PSD_NT, F.coly_f.lds, s>>>(h->dI, dT + F.coly_f.off, 1, sv);
-    else k_cols<T, 2, -1><<<F.coly_f.cnt, PSD_NT, F.coly_f.lds, s>>>(h->dI, dT + F.coly_f.off, 1, sv);
+    if (nfi == 1) launch_cols<T, 1, -1>(F.coly_f, dI, dT, sv, s);
+    else launch_cols<T, 2, -1>(F.coly_f, dI, dT, sv, s);
   }
   {
     ProfScope ps(h, pr ? PSD_PASS_COLS_FUSED : -1);
-    if (op == OP_PRECOND4)
-      k_cols_fused<T, OP_PRECOND4><<<F.colz.cnt, PSD_NT, F.colz.lds, s>>>(h->dI, dT + F.colz.off, sv);
-    else if (op == OP_PRECOND6)
-      k_cols_fused<T, OP_PRECOND6><<<F.colz.cnt, PSD_NT, F.colz.lds, s>>>(h->dI, dT + F.colz.off, sv);
-    else
-      k_cols_fused<T, OP_POISSON><<<F.colz.cnt, PSD_NT, F.colz.lds, s>>>(h->dI, dT + F.colz.off, sv);
+    if (op == OP_PRECOND4) launch_fused<T, OP_PRECOND4>(F.colz, dI, dT, sv, s);
+    else if (op == OP_PRECOND6) launch_fused<T, OP_PRECOND6>(F.colz, dI, dT, sv, s);
+    else launch_fused<T, OP_POISSON>(F.colz, dI, dT, sv, s);
   }
   if (F.coly_i.cnt) {
     ProfScope ps(h, pr ? PSD_PASS_COLS_INV : -1);
-    if (nfo == 1) k_cols<T, 1, 1><<<F.coly_i.cnt, PSD_NT, F.coly_i.lds, s>>>(h->dI, dT + F.coly_i.off, 1, sv);
-    else k_cols<T, 3, 1><<<F.coly_i.cnt, PSD_NT, F.coly_i.lds, s>>>(h->dI, dT + F.coly_i.off, 1, sv);
+    if (nfo == 1) launch_cols<T, 1, 1>(F.coly_i, dI, dT, sv, s);
+    else launch_cols<T, 3, 1>(F.coly_i, dI, dT, sv, s);
   }
   if (F.c2r.cnt) {
     ProfScope ps(h, pr ? PSD_PASS_ROWS_C2R : -1);
-    k_rows<T, TOUT, false><<<F.c2r.cnt, PSD_NT, F.c2r.lds, s>>>(h->dI, dT + F.c2r.off, sv);
+    launch_rows<T, TOUT, false>(F.c2r, dI, dT, sv, s);
   }
 }
 
