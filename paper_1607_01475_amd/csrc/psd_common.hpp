@@ -3,8 +3,10 @@
 // Layout conventions (Sec. 5.1 of the paper): periodic n^dim cell-centred
 // grid, x fastest, idx = i + n*(j + n*k).  A vertex (i+1/2, j+1/2[, k+1/2])
 // is addressed by the index of cell (i, j[, k]).  Spectra are half spectra
-// (kx = 0 .. n/2) stored [kz][ky][kx], kx fastest, nc = n/2 + 1 values in a
-// row padded to ncp (a multiple of 128 bytes) so that column tiles are aligned.
+// (kx = 0 .. n/2).  A field holds the columns kx < n/2 as rows [kz][ky][kx],
+// kx fastest, row stride ncp (n/2 rounded up to 128 bytes), followed by the
+// Nyquist plane kx = n/2 stored [kz][ky] (offset nyq): every row is a whole
+// number of 128-byte lines and no padding column is ever read or written.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -66,8 +68,9 @@ struct Inst {
   int dim, n, nc, order;
   long long ncell;     // n^dim
   long long nspec;     // largest field stride of the spectrum buffer (complex elements)
-  int ncp32, ncp64;    // padded spectrum row strides (128-byte multiples) for FP32 / FP64
-  long long nspec32, nspec64;  // spectrum field strides = ncp * n^(dim-1)
+  int ncp32, ncp64;    // spectrum row strides (kx < n/2, 128-byte multiples) for FP32 / FP64
+  long long nspec32, nspec64;  // spectrum field strides (complex elements)
+  long long nyq32, nyq64;      // offset of the Nyquist plane in a field = ncp * n^(dim-1)
   double h, inv_h, p, s, se2, lam, inv_ntot, tol, hd;
   int max_iter, p_is_4, p_is_2, pad0;
   double* u[2];        // ping-pong iterate
@@ -126,11 +129,11 @@ __device__ __forceinline__ double wave_max(double v) {
 
 // Reduce K sums (and optionally the first M as max instead) across the
 // block; result valid in thread 0.  scratch: K * (NT/64) doubles of LDS.
-template <int K, int M>
+template <int K, int M, int NT = PSD_NT>
 __device__ __forceinline__ void block_reduce(double (&v)[K], double* scratch) {
   const int lane = threadIdx.x & (PSD_WAVE - 1);
   const int wid = threadIdx.x / PSD_WAVE;
-  constexpr int NW = PSD_NT / PSD_WAVE;
+  constexpr int NW = NT / PSD_WAVE;
 #pragma unroll
   for (int k = 0; k < K; ++k) v[k] = (k < M) ? wave_max(v[k]) : wave_sum(v[k]);
   __syncthreads();
@@ -148,6 +151,32 @@ __device__ __forceinline__ void block_reduce(double (&v)[K], double* scratch) {
     }
   }
   __syncthreads();
+}
+
+// Threads of the per-instance finalize kernels (one block per instance).
+constexpr int PSD_FIN_NT = 1024;
+
+// Accumulate K-wide block partials part[K*b + k], b < nblk, over the threads
+// of a PSD_FIN_NT block (the first M as max, the rest as sums).  Four slots
+// per thread are loaded before any is added, so the loads of a round are in
+// flight together.  The order of the additions is fixed.
+template <int K, int M>
+__device__ __forceinline__ void gather_parts(const double* __restrict__ part, int nblk,
+                                             double (&acc)[K]) {
+  constexpr int U = 4;
+  for (int b0 = 0; b0 < nblk; b0 += U * PSD_FIN_NT) {
+    double v[U][K];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int b = b0 + j * PSD_FIN_NT + (int)threadIdx.x;
+#pragma unroll
+      for (int k = 0; k < K; ++k) v[j][k] = b < nblk ? part[K * b + k] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+#pragma unroll
+      for (int k = 0; k < K; ++k) acc[k] = (k < M) ? fmax(acc[k], v[j][k]) : acc[k] + v[j][k];
+  }
 }
 
 // periodic index for offsets within one period (3D tiles: n >= 32 is

@@ -242,7 +242,8 @@ struct RowArgs {
   void* rout2;
   cx<T>* spec;          // NF fields of nspec complex
   long long nspec;      // field stride (complex elements)
-  int ncp;              // row stride (complex elements, >= N/2 + 1)
+  long long nyq;        // offset of the Nyquist plane (kx = N/2) in a field
+  int ncp;              // row stride of the columns kx < N/2 (complex elements)
   long long rpf;        // rows per field
   long long nrows;      // rows over all fields of this pass (guard)
   // value selects (not lvalue selects), so that the struct stays in registers
@@ -316,9 +317,12 @@ __device__ __forceinline__ void r2c_rows(const RowArgs<T>& A, long long row0, cx
     if (gr >= A.nrows) continue;
     const int fld = (int)(gr / A.rpf);
     const long long row = gr - (long long)fld * A.rpf;
-    cx<T>* out = A.spec + fld * A.nspec + row * A.ncp;
-    out[k] = a;
-    out[A.ncp + k] = b;
+    cx<T>* out = A.spec + fld * A.nspec;
+    // rows row, row+1: columns kx < N/2 in the row array, kx = N/2 in the Nyquist plane
+    const long long oa = (k < N / 2) ? row * A.ncp + k : A.nyq + row;
+    const long long ob = (k < N / 2) ? oa + A.ncp : oa + 1;
+    out[oa] = a;
+    out[ob] = b;
   }
 }
 
@@ -343,9 +347,11 @@ __device__ __forceinline__ void c2r_rows(const RowArgs<T>& A, long long row0, cx
     if ((NE % PSD_NT == 0 || e < NE) && gr < A.nrows) {
       const int fld = (int)(gr / A.rpf);
       const long long row = gr - (long long)fld * A.rpf;
-      const cx<T>* in = A.spec + fld * A.nspec + row * A.ncp;
-      ra[it] = in[k];
-      rb[it] = in[A.ncp + k];
+      const cx<T>* in = A.spec + fld * A.nspec;
+      const long long oa = (k < N / 2) ? row * A.ncp + k : A.nyq + row;
+      const long long ob = (k < N / 2) ? oa + A.ncp : oa + 1;
+      ra[it] = in[oa];
+      rb[it] = in[ob];
     }
   }
 #pragma unroll
@@ -385,30 +391,39 @@ __device__ __forceinline__ void c2r_rows(const RowArgs<T>& A, long long row0, cx
   }
 }
 
-// Load NF fields of W adjacent columns of length N into LDS lines
+// Columns of one column-pass block: column c < ncols starts at element
+// cbase + c * cstride of a field; element t of a column lies at + t * lstride
+// and field f at + f * fstride.
+struct ColSet {
+  long long cbase, cstride, lstride;
+  int ncols;
+};
+
+// Load NF fields of the block's columns of length N into LDS lines
 // (f*W + c), every load of the block issued before the first LDS store.
 template <typename T, int N, int W, int NF>
-__device__ __forceinline__ void col_load(const cx<T>* base, long long inner_count, long long col0,
-                                         long long lstride, long long fstride, cx<T>* buf) {
+__device__ __forceinline__ void col_load(const cx<T>* base, const ColSet& cs, long long fstride,
+                                         cx<T>* buf) {
   constexpr int LS = fft_ls(N);
   constexpr int NE = NF * W * N;
   constexpr int IT = (NE + PSD_NT - 1) / PSD_NT;
+  static_assert(PSD_NT % W == 0, "a thread keeps one column");
+  const int c = threadIdx.x % W;
+  const long long coff = cs.cbase + c * cs.cstride;
+  const bool live = c < cs.ncols;
   cx<T> regs[IT];
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int e = threadIdx.x + it * PSD_NT;
-    const int c = e % W;
     const int ft = e / W;
     const int t = ft % N, f = ft / N;
     regs[it] = mk(T(0), T(0));
-    if ((NE % PSD_NT == 0 || e < NE) && col0 + c < inner_count)
-      regs[it] = base[f * fstride + col0 + c + t * lstride];
+    if ((NE % PSD_NT == 0 || e < NE) && live) regs[it] = base[f * fstride + coff + t * cs.lstride];
   }
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int e = threadIdx.x + it * PSD_NT;
     if (NE % PSD_NT == 0 || e < NE) {
-      const int c = e % W;
       const int ft = e / W;
       const int t = ft % N, f = ft / N;
       buf[(f * W + c) * LS + pidx(t)] = regs[it];
@@ -416,27 +431,36 @@ __device__ __forceinline__ void col_load(const cx<T>* base, long long inner_coun
   }
 }
 
+// Store NF fields of the block's columns from LDS lines (f*W + c).
+template <typename T, int N, int W, int NF>
+__device__ __forceinline__ void col_store(cx<T>* base, const ColSet& cs, long long fstride,
+                                          const cx<T>* buf) {
+  constexpr int LS = fft_ls(N);
+  static_assert(PSD_NT % W == 0, "a thread keeps one column");
+  const int c = threadIdx.x % W;
+  if (c >= cs.ncols) return;
+  const long long coff = cs.cbase + c * cs.cstride;
+  for (int e = threadIdx.x; e < NF * W * N; e += PSD_NT) {
+    const int ft = e / W;
+    const int t = ft % N, f = ft / N;
+    base[f * fstride + coff + t * cs.lstride] = buf[(f * W + c) * LS + pidx(t)];
+  }
+}
+
 // ---------------------------------------------------------------------------
-// Column pass: W adjacent columns (inner index col0 .. col0+W-1 of
-// `inner_count`) of length N, element t at stride `lstride`, NF fields at
-// `fstride`.  Loads, transforms (DIR), stores.
+// Column pass: the block's columns (ColSet) of length N, NF fields.  Loads,
+// transforms (DIR), stores.
 // ---------------------------------------------------------------------------
 template <typename T, int N, int W, int NF, int DIR>
-__device__ __forceinline__ void col_pass(cx<T>* base, long long inner_count, long long col0,
-                                         long long lstride, long long fstride, cx<T>* buf,
+__device__ __forceinline__ void col_pass(cx<T>* base, const ColSet& cs, long long fstride, cx<T>* buf,
                                          const cx<T>* tw) {
   constexpr int LS = fft_ls(N);
   cx<T>* twl = buf + NF * W * LS;
   stage_twiddles<T, N>(twl, tw);
-  col_load<T, N, W, NF>(base, inner_count, col0, lstride, fstride, buf);
+  col_load<T, N, W, NF>(base, cs, fstride, buf);
   __syncthreads();
   lds_fft<T, N, NF * W, LS, DIR>(buf, twl);
-  for (int e = threadIdx.x; e < NF * W * N; e += PSD_NT) {
-    const int c = e % W;
-    const int ft = e / W;
-    const int t = ft % N, f = ft / N;
-    if (col0 + c < inner_count) base[f * fstride + col0 + c + t * lstride] = buf[(f * W + c) * LS + pidx(t)];
-  }
+  col_store<T, N, W, NF>(base, cs, fstride, buf);
 }
 
 }  // namespace psd

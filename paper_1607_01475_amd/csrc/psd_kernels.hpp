@@ -30,13 +30,14 @@ constexpr int row_lines() {
   return p;
 }
 // columns per block of a column pass: 128-byte segments where the LDS
-// footprint NF*W*fft_ls(N) complex plus N twiddles stays within 64 KB
+// footprint NF*W*fft_ls(N) complex plus N twiddles stays within 64 KB; a
+// power of two, so that a thread keeps one column
 template <typename T, int N, int NF>
 constexpr int col_width() {
   int w = 128 / (int)sizeof(cx<T>);
   const int cap = (65536 - N * (int)sizeof(cx<T>)) / (NF * fft_ls(N) * (int)sizeof(cx<T>));
-  if (cap < w) w = cap;
-  return w < 1 ? 1 : w;
+  while (w > cap && w > 1) w /= 2;
+  return w;
 }
 
 // ===========================================================================
@@ -81,18 +82,14 @@ __global__ __launch_bounds__(PSD_NT) __attribute__((amdgpu_waves_per_eu(PSD_RES3
 
 // One block per instance: reduce residual partials, count the update,
 // decide convergence, record history.
-__global__ __launch_bounds__(PSD_NT) void k_res_finalize(const Inst* __restrict__ insts, int upd) {
-  __shared__ double scratch[2 * PSD_NT / PSD_WAVE];
+__global__ __launch_bounds__(PSD_FIN_NT) void k_res_finalize(const Inst* __restrict__ insts, int upd) {
+  __shared__ double scratch[2 * PSD_FIN_NT / PSD_WAVE];
   const Inst& I = insts[blockIdx.x];
   SolveState* st = I.st;
   if (st->done) return;
   double acc[2] = {0.0, 0.0};
-#pragma unroll 8
-  for (int b = threadIdx.x; b < I.nblk_res; b += PSD_NT) {
-    acc[0] = fmax(acc[0], I.part_res[2 * b]);
-    acc[1] += I.part_res[2 * b + 1];
-  }
-  block_reduce<2, 1>(acc, scratch);
+  gather_parts<2, 1>(I.part_res, I.nblk_res, acc);
+  block_reduce<2, 1, PSD_FIN_NT>(acc, scratch);
   if (threadIdx.x == 0) {
     const double rinf = acc[0];
     const double rl2 = sqrt(I.hd * acc[1]);
@@ -174,30 +171,31 @@ __device__ double cubic_root(const double* c) {
 // Reduce line-search and spectral partials; mode 0: cubic (p = 4) -> alpha;
 // mode 1: general p, first pass at alpha = 0 -> start the root rule;
 // mode 2: general p, one root-rule step after an evaluation at st->x.
-__global__ __launch_bounds__(PSD_NT) void k_ls_finalize(const Inst* __restrict__ insts, int mode) {
-  __shared__ double scratch[10 * PSD_NT / PSD_WAVE];
+__global__ __launch_bounds__(PSD_FIN_NT) void k_ls_finalize(const Inst* __restrict__ insts, int mode) {
+  __shared__ double scratch[10 * PSD_FIN_NT / PSD_WAVE];
   const Inst& I = insts[blockIdx.x];
   SolveState* st = I.st;
   if (st->done || (mode == 2 && st->ls_phase == 2)) return;
   double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll 4
-  for (int b = threadIdx.x; b < I.nblk_ls; b += PSD_NT)
+  {
+    double a8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    gather_parts<8, 0>(I.part_ls, I.nblk_ls, a8);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) acc[k] += I.part_ls[8 * b + k];
-  if (mode != 2)
-#pragma unroll 4
-    for (int b = threadIdx.x; b < I.nblk_sp; b += PSD_NT) {
-      acc[8] += I.part_sp[2 * b];
-      acc[9] += I.part_sp[2 * b + 1];
-    }
-  block_reduce<10, 0>(acc, scratch);
+    for (int k = 0; k < 8; ++k) acc[k] = a8[k];
+  }
+  if (mode != 2) {
+    double a2[2] = {0.0, 0.0};
+    gather_parts<2, 0>(I.part_sp, I.nblk_sp, a2);
+    acc[8] = a2[0];
+    acc[9] = a2[1];
+  }
+  block_reduce<10, 0, PSD_FIN_NT>(acc, scratch);
   if (I.order == 6 && mode != 2) {
     // means of d, e1, e2 (FP32 round-off of the inverse transform leaves a
     // tiny mean that the preconditioner never corrects); the update removes them
     double ms[3] = {0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < I.nblk_c2r; b += PSD_NT)
-      for (int q = 0; q < 3; ++q) ms[q] += I.part_c2r[3 * b + q];
-    block_reduce<3, 0>(ms, scratch);
+    gather_parts<3, 0>(I.part_c2r, I.nblk_c2r, ms);
+    block_reduce<3, 0, PSD_FIN_NT>(ms, scratch);
     if (threadIdx.x == 0) {
       for (int q = 0; q < 3; ++q) st->mean[q] = ms[q] * I.inv_ntot;
       // sum (d - dbar)^2 = sum d^2 - N dbar^2
@@ -281,6 +279,7 @@ __device__ __forceinline__ RowArgs<T> row_args(const Inst& I, int fs, cx<T>* spe
   RowArgs<T> A;
   A.spec = spec;
   A.nspec = sizeof(T) == 8 ? I.nspec64 : I.nspec32;
+  A.nyq = sizeof(T) == 8 ? I.nyq64 : I.nyq32;
   A.ncp = sizeof(T) == 8 ? I.ncp64 : I.ncp32;
   A.rpf = I.ncell / I.n;
   A.nrows = A.rpf * nf;
@@ -316,26 +315,36 @@ __global__ __launch_bounds__(PSD_NT) void k_rows(const Inst* __restrict__ insts,
   }
 }
 
-// plain column pass: task.a = outer index, task.b = first column; NF fields
+// y-axis column pass (3D): lines along y of length N.  Plain block
+// (task.c = 0): columns kx = task.b .. (kx < N/2) of plane z = task.a, lines
+// at stride ncp.  Nyquist block (task.c = 1): the contiguous kx = N/2 lines of
+// planes task.a, task.a + 1, ... in the Nyquist plane.
 template <typename T, int NF, int DIR, int N>
 __global__ __launch_bounds__(PSD_NT) void k_cols(const Inst* __restrict__ insts,
-                                                 const Task2* __restrict__ tasks, int axis,
-                                                 int solver) {
+                                                 const Task2* __restrict__ tasks, int solver) {
   extern __shared__ double smem[];
   const Task2 t = tasks[blockIdx.x];
   const Inst& I = insts[t.inst];
   if (solver && I.st->done) return;
+  constexpr int W = col_width<T, N, NF>();
   cx<T>* buf = (cx<T>*)smem;
   const cx<T>* tw = (const cx<T>*)(sizeof(T) == 8 ? I.tw64 : I.tw32);
-  const long long n = N;
   const long long ncp = sizeof(T) == 8 ? I.ncp64 : I.ncp32;
   const long long fstride = sizeof(T) == 8 ? I.nspec64 : I.nspec32;
-  // axis 1: lines along y (stride ncp), columns kx, outer z (stride n*ncp)
-  // axis 2: lines along z (stride n*ncp), columns (ky,kx)
-  const long long inner = (axis == 1) ? ncp : n * ncp;
-  const long long lstride = (axis == 1) ? ncp : n * ncp;
-  cx<T>* base = (cx<T>*)I.spec + (axis == 1 ? (long long)t.a * n * ncp : 0);
-  col_pass<T, N, col_width<T, N, NF>(), NF, DIR>(base, inner, t.b, lstride, fstride, buf, tw);
+  const long long nyq = sizeof(T) == 8 ? I.nyq64 : I.nyq32;
+  ColSet cs;
+  if (t.c == 0) {
+    cs.cbase = (long long)t.a * N * ncp + t.b;
+    cs.cstride = 1;
+    cs.lstride = ncp;
+    cs.ncols = min(W, N / 2 - t.b);
+  } else {
+    cs.cbase = nyq + (long long)t.a * N;
+    cs.cstride = N;
+    cs.lstride = 1;
+    cs.ncols = min(W, N - t.a);
+  }
+  col_pass<T, N, W, NF, DIR>((cx<T>*)I.spec, cs, fstride, buf, tw);
 }
 
 // Spectral operators applied between the forward and inverse transform of
@@ -349,59 +358,54 @@ __global__ __launch_bounds__(PSD_NT) void k_cols(const Inst* __restrict__ insts,
 // K = S[kx] + S[ky] (+ S[kz]) is the symbol of -Delta_h (appendix).
 enum SpecOp { OP_PRECOND4 = 0, OP_PRECOND6 = 1, OP_POISSON = 2 };
 
+// Last-axis pass: lines of length N along the last axis.  Plain block
+// (task.c = 0): columns kx = task.b .. (kx < N/2) of row ky = task.a (3D;
+// 2D: task.a = 0), lines at stride ncp (2D) or N*ncp (3D).  Nyquist block
+// (task.c = 1), kx = N/2: 3D, rows ky = task.a, task.a + 1, ... of the
+// Nyquist plane (lines at stride N); 2D, the one contiguous Nyquist line.
 template <typename T, int N, int W, int OP>
 __device__ __forceinline__ void fused_col(const Inst& I, const Task2& t, cx<T>* buf, double (&acc)[2]) {
   constexpr int NFI = (OP == OP_PRECOND6) ? 2 : 1;
   constexpr int NFO = (OP == OP_PRECOND6) ? 3 : 1;
   constexpr int LS = fft_ls(N);
+  static_assert(PSD_NT % W == 0, "a thread keeps one column");
   const cx<T>* tw = (const cx<T>*)(sizeof(T) == 8 ? I.tw64 : I.tw32);
-  const long long n = I.n, nc = I.nc;
+  const int dim = I.dim;
   const long long ncp = sizeof(T) == 8 ? I.ncp64 : I.ncp32;
   const long long fstride = sizeof(T) == 8 ? I.nspec64 : I.nspec32;
-  const int dim = I.dim;
-  const long long inner = (dim == 2) ? ncp : n * ncp;
-  const long long lstride = inner;
   cx<T>* base = (cx<T>*)I.spec;
-  const long long col0 = t.b;
+  const bool nyq = t.c != 0;
+  ColSet cs;
+  if (!nyq) {
+    cs.cbase = (long long)t.a * ncp + t.b;
+    cs.cstride = 1;
+    cs.lstride = (dim == 2) ? ncp : (long long)N * ncp;
+    cs.ncols = min(W, N / 2 - t.b);
+  } else {
+    cs.cbase = (sizeof(T) == 8 ? I.nyq64 : I.nyq32) + t.a;
+    cs.cstride = 1;
+    cs.lstride = (dim == 2) ? 1 : N;
+    cs.ncols = (dim == 2) ? 1 : min(W, N - t.a);
+  }
   constexpr int NLMAX = (NFI > NFO ? NFI : NFO) * W;
   cx<T>* twl = buf + NLMAX * LS;
   stage_twiddles<T, N>(twl, tw);
-  col_load<T, N, W, NFI>(base, inner, col0, lstride, fstride, buf);
+  col_load<T, N, W, NFI>(base, cs, fstride, buf);
   __syncthreads();
   lds_fft<T, N, NFI * W, LS, -1>(buf, twl);
   const double s = I.s, se2 = I.se2, inv = I.inv_ntot;
   const double* S = I.S;
-  // column of this thread (fixed when W divides the block size)
-  int c_fix = -1, kx_fix = 0, ky_fix = 0;
-  double Kc_fix = 0.0;
-  if (PSD_NT % W == 0) {
-    c_fix = threadIdx.x % W;
-    const int col = (int)col0 + c_fix;
-    kx_fix = col % (int)ncp;
-    ky_fix = col / (int)ncp;
-    Kc_fix = S[kx_fix < nc ? kx_fix : 0] + (dim == 3 ? S[ky_fix < n ? ky_fix : 0] : 0.0);
-  }
+  // wave numbers of this thread's column: kx, and ky in 3D (2D: ky = line index)
+  const int c = threadIdx.x % W;
+  const bool live = c < cs.ncols;
+  const int kx = nyq ? N / 2 : t.b + c;
+  const int ky3 = nyq ? t.a + c : t.a;
+  const double wgt = (kx == 0 || 2 * kx == N) ? 1.0 : 2.0;
+  const double Kc = S[live ? kx : 0] + (dim == 3 ? S[live ? ky3 : 0] : 0.0);
   for (int e = threadIdx.x; e < W * N; e += PSD_NT) {
-    const int c = (PSD_NT % W == 0) ? c_fix : e % W, tt = e / W;
-    const int col = (int)col0 + c;
-    if (col >= inner) continue;
-    int kx, ky;
-    double K;
-    if (PSD_NT % W == 0) {
-      kx = kx_fix;
-      ky = (dim == 2) ? tt : ky_fix;
-      K = Kc_fix + S[tt];
-    } else {
-      kx = col % (int)ncp;
-      ky = (dim == 2) ? tt : col / (int)ncp;
-      K = S[kx < nc ? kx : 0] + S[ky] + (dim == 3 ? S[tt] : 0.0);
-    }
-    if (kx >= nc) {  // row padding: keep it zero, contribute nothing
-#pragma unroll
-      for (int f = 0; f < NFO; ++f) buf[(f * W + c) * LS + pidx(tt)] = mk(T(0), T(0));
-      continue;
-    }
-    const double wgt = (kx == 0 || 2 * kx == (int)n) ? 1.0 : 2.0;
+    if (!live) break;
+    const int tt = e / W;
+    const double K = Kc + S[tt];
     if (OP == OP_PRECOND4) {
       const cx<T> X = buf[c * LS + pidx(tt)];
       const double sig = 1.0 + s * K + se2 * K * K;
@@ -438,12 +442,7 @@ __device__ __forceinline__ void fused_col(const Inst& I, const Task2& t, cx<T>* 
   }
   __syncthreads();
   lds_fft<T, N, NFO * W, LS, 1>(buf, twl);
-  for (int e = threadIdx.x; e < NFO * W * N; e += PSD_NT) {
-    const int c = e % W;
-    const int ft = e / W;
-    const int tt = ft % N, f = ft / N;
-    if (col0 + c < inner) base[f * fstride + col0 + c + tt * lstride] = buf[(f * W + c) * LS + pidx(tt)];
-  }
+  col_store<T, N, W, NFO>(base, cs, fstride, buf);
 }
 
 template <typename T, int OP, int N>

@@ -284,8 +284,13 @@ static void build_fft_tasks(psd_handle* h, FftTasks& F, int nfi, int nfo, bool w
         for (int b = 0; b < h->batch; ++b) {
           const Inst& I = h->hI[b];
           if (I.n != n) continue;
-          for (int z = 0; z < I.n; ++z)
-            for (int c0 = 0; c0 < (sizeof(T) == 8 ? I.ncp64 : I.ncp32); c0 += W) {
+          for (int z0 = 0; z0 < n; z0 += W) {  // Nyquist y-lines of W planes
+            Task2 t{};
+            t.inst = b; t.a = z0; t.c = 1;
+            h->hT.push_back(t);
+          }
+          for (int z = 0; z < n; ++z)          // plain blocks: kx < n/2
+            for (int c0 = 0; c0 < n / 2; c0 += W) {
               Task2 t{};
               t.inst = b; t.a = z; t.b = c0;
               h->hT.push_back(t);
@@ -306,14 +311,19 @@ static void build_fft_tasks(psd_handle* h, FftTasks& F, int nfi, int nfo, bool w
     for (int b = 0; b < h->batch; ++b) {
       Inst& I = h->hI[b];
       if (I.n != n) continue;
-      const long long ncp = sizeof(T) == 8 ? I.ncp64 : I.ncp32;
-      const long long inner = h->dim == 2 ? ncp : (long long)I.n * ncp;
+      const int rows = h->dim == 2 ? 1 : n;   // ky rows of columns (3D)
       int slot = 0;
-      for (long long c0 = 0; c0 < inner; c0 += W) {
+      for (int ky0 = 0; ky0 < rows; ky0 += W) {  // Nyquist lines of W rows
         Task2 t{};
-        t.inst = b; t.a = 0; t.b = (int)c0; t.slot = slot++;
+        t.inst = b; t.a = ky0; t.c = 1; t.slot = slot++;
         h->hT.push_back(t);
       }
+      for (int ky = 0; ky < rows; ++ky)        // plain blocks: kx < n/2
+        for (int c0 = 0; c0 < n / 2; c0 += W) {
+          Task2 t{};
+          t.inst = b; t.a = ky; t.b = c0; t.slot = slot++;
+          h->hT.push_back(t);
+        }
       if (with_slots) I.nblk_sp = slot;
     }
     close_part(R, std::max(((size_t)nfm * W * fft_ls(n) + n) * cxs, (size_t)64 * 8));
@@ -411,7 +421,7 @@ static void launch_cols(const Range& R, const Inst* dI, const Task2* dT, int sv,
   for (const NPart& p : R.parts) {
     switch (p.n) {
 #define PSD_L(NN) \
-      case NN: k_cols<T, NF, DIR, NN><<<p.cnt, PSD_NT, p.lds, s>>>(dI, dT + p.off, 1, sv); break;
+      case NN: k_cols<T, NF, DIR, NN><<<p.cnt, PSD_NT, p.lds, s>>>(dI, dT + p.off, sv); break;
       PSD_FOR_EACH_N3(PSD_L)
 #undef PSD_L
       default: break;
@@ -487,7 +497,7 @@ static void run_residual(psd_handle* h, bool upd) {
     }
   }
   ProfScope ps(h, upd ? PSD_PASS_RES_FIN : -1);
-  k_res_finalize<<<h->batch, PSD_NT, 0, s>>>(h->dI, upd ? 1 : 0);
+  k_res_finalize<<<h->batch, PSD_FIN_NT, 0, s>>>(h->dI, upd ? 1 : 0);
 }
 
 template <typename TD>
@@ -509,7 +519,7 @@ static void run_ls(psd_handle* h, int mode) {
     }
   }
   ProfScope ps(h, PSD_PASS_LS_FIN);
-  k_ls_finalize<<<h->batch, PSD_NT, 0, s>>>(h->dI, mode);
+  k_ls_finalize<<<h->batch, PSD_FIN_NT, 0, s>>>(h->dI, mode);
 }
 
 // one PSD iteration (p = 4: fixed launch sequence, capturable)
@@ -809,11 +819,17 @@ extern "C" psd_status psd_create(const psd_problem* probs, int batch, const psd_
     std::memset(&I, 0, sizeof(Inst));
     I.dim = P.dim; I.n = P.n; I.nc = P.n / 2 + 1; I.order = P.order;
     I.ncell = (long long)P.n * P.n * (P.dim == 3 ? P.n : 1);
-    I.ncp32 = (I.nc + 15) / 16 * 16;   // 16 FP32 complex = 128 bytes
-    I.ncp64 = (I.nc + 7) / 8 * 8;      // 8 FP64 complex = 128 bytes
-    I.nspec32 = (long long)I.ncp32 * P.n * (P.dim == 3 ? P.n : 1);
-    I.nspec64 = (long long)I.ncp64 * P.n * (P.dim == 3 ? P.n : 1);
-    I.nspec = I.nspec64;
+    {
+      const long long rows = I.ncell / P.n;       // spectrum rows per field
+      I.ncp32 = (P.n / 2 + 15) / 16 * 16;         // 16 FP32 complex = 128 bytes
+      I.ncp64 = (P.n / 2 + 7) / 8 * 8;            // 8 FP64 complex = 128 bytes
+      I.nyq32 = (long long)I.ncp32 * rows;
+      I.nyq64 = (long long)I.ncp64 * rows;
+      I.nspec32 = (I.nyq32 + rows + 15) / 16 * 16;
+      I.nspec64 = (I.nyq64 + rows + 7) / 8 * 8;
+      // buffer size per field in units of FP64 complex (16 bytes)
+      I.nspec = std::max(I.nspec64, (I.nspec32 + 1) / 2);
+    }
     I.h = P.L / P.n; I.inv_h = P.n / P.L; I.p = P.p; I.s = P.s;
     I.se2 = P.s * P.eps * P.eps; I.lam = P.lambda;
     I.inv_ntot = 1.0 / (double)I.ncell;
