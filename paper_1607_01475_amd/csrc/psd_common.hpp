@@ -179,6 +179,49 @@ __device__ __forceinline__ void gather_parts(const double* __restrict__ part, in
   }
 }
 
+// Reduce K-wide block partials part[K*b + k], b < nblk, read as one flat
+// array: with K a power of two dividing 64, thread t only ever sees entry
+// k = t mod K, so every wave load is contiguous.  The first M entries are
+// maxima of non-negative values, the rest sums.  Lanes of equal k are
+// combined by a fixed butterfly, then waves in order; result in thread 0.
+template <int K, int M, int NT>
+__device__ __forceinline__ void flat_reduce(const double* __restrict__ part, int nblk,
+                                            double (&out)[K], double* scratch) {
+  static_assert((K & (K - 1)) == 0 && K <= PSD_WAVE && NT % PSD_WAVE == 0, "K | 64");
+  constexpr int NW = NT / PSD_WAVE;
+  constexpr int U = 8;
+  const int tid = threadIdx.x, lane = tid & (PSD_WAVE - 1), wid = tid / PSD_WAVE;
+  const bool is_max = (tid % K) < M;
+  const int total = K * nblk;
+  double a = 0.0;
+  for (int j0 = 0; j0 < total; j0 += U * NT) {
+    double v[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int j = j0 + q * NT + tid;
+      v[q] = j < total ? part[j] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) a = is_max ? fmax(a, v[q]) : a + v[q];
+  }
+#pragma unroll
+  for (int o = PSD_WAVE / 2; o >= K; o >>= 1) {
+    const double b = __shfl_xor(a, o, PSD_WAVE);
+    a = is_max ? fmax(a, b) : a + b;
+  }
+  if (lane < K) scratch[wid * K + lane] = a;
+  __syncthreads();
+  if (tid == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double r = scratch[k];
+      for (int w = 1; w < NW; ++w) r = (k < M) ? fmax(r, scratch[w * K + k]) : r + scratch[w * K + k];
+      out[k] = r;
+    }
+  }
+  __syncthreads();
+}
+
 // periodic index for offsets within one period (3D tiles: n >= 32 is
 // required so that every halo index lies in [-n, 2n))
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }

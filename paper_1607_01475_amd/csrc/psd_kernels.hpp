@@ -64,7 +64,7 @@ __global__ __launch_bounds__(PSD_NT) void k_res2d(const Inst* __restrict__ insts
 #ifndef PSD_RES3D_WAVES
 #define PSD_RES3D_WAVES 4
 #endif
-template <typename TD, typename TR, bool UPD>
+template <typename TD, typename TR, bool UPD, int PK>
 __global__ __launch_bounds__(PSD_NT) __attribute__((amdgpu_waves_per_eu(PSD_RES3D_WAVES))) void k_res3d(const Inst* __restrict__ insts,
                                                   const Task2* __restrict__ tasks) {
   extern __shared__ double smem[];
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(PSD_NT) __attribute__((amdgpu_waves_per_eu(PSD_RES3
   const Inst& I = insts[t.inst];
   if (I.st->done) return;
   double acc[2] = {0.0, 0.0};
-  res3d_tile<TD, TR, UPD>(I, t.a, t.b, t.c, smem, acc);
+  res3d_tile<TD, TR, UPD, false, PK>(I, t.a, t.b, t.c, smem, acc);
   block_reduce<2, 1>(acc, smem + R3_LDS);
   if (threadIdx.x == 0) {
     I.part_res[2 * t.slot] = acc[0];
@@ -88,8 +88,7 @@ __global__ __launch_bounds__(PSD_FIN_NT) void k_res_finalize(const Inst* __restr
   SolveState* st = I.st;
   if (st->done) return;
   double acc[2] = {0.0, 0.0};
-  gather_parts<2, 1>(I.part_res, I.nblk_res, acc);
-  block_reduce<2, 1, PSD_FIN_NT>(acc, scratch);
+  flat_reduce<2, 1, PSD_FIN_NT>(I.part_res, I.nblk_res, acc, scratch);
   if (threadIdx.x == 0) {
     const double rinf = acc[0];
     const double rl2 = sqrt(I.hd * acc[1]);
@@ -179,17 +178,16 @@ __global__ __launch_bounds__(PSD_FIN_NT) void k_ls_finalize(const Inst* __restri
   double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   {
     double a8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    gather_parts<8, 0>(I.part_ls, I.nblk_ls, a8);
+    flat_reduce<8, 0, PSD_FIN_NT>(I.part_ls, I.nblk_ls, a8, scratch);
 #pragma unroll
     for (int k = 0; k < 8; ++k) acc[k] = a8[k];
   }
   if (mode != 2) {
     double a2[2] = {0.0, 0.0};
-    gather_parts<2, 0>(I.part_sp, I.nblk_sp, a2);
+    flat_reduce<2, 0, PSD_FIN_NT>(I.part_sp, I.nblk_sp, a2, scratch);
     acc[8] = a2[0];
     acc[9] = a2[1];
   }
-  block_reduce<10, 0, PSD_FIN_NT>(acc, scratch);
   if (I.order == 6 && mode != 2) {
     // means of d, e1, e2 (FP32 round-off of the inverse transform leaves a
     // tiny mean that the preconditioner never corrects); the update removes them
@@ -573,7 +571,7 @@ __global__ __launch_bounds__(PSD_NT) void k_hess3d(const Inst* __restrict__ inst
   const Inst& I = insts[t.inst];
   if (I.st->done) return;
   double acc[2] = {0.0, 0.0};
-  res3d_tile<double, TR, false, true>(I, t.a, t.b, t.c, smem, acc);
+  res3d_tile<double, TR, false, true, 0>(I, t.a, t.b, t.c, smem, acc);
   block_reduce<2, 1>(acc, smem + R3H_LDS);
   if (threadIdx.x == 0) {
     I.part_res[2 * t.slot] = 0.0;

@@ -108,7 +108,7 @@ struct psd_handle_s {
   int gchunk = 0;
   bool adj_alloc = false;
   // tuning (autotuner or defaults)
-  int tune_zc_res = T3Z, tune_zc_ls = T3Z;
+  int tune_zc_res = T3Z_RES, tune_zc_ls = T3Z_LS;
   bool tune_xcd_res = false, tune_xcd_ls = false;
   size_t dT_cap = 0;
   std::string err;
@@ -492,8 +492,18 @@ static void run_residual(psd_handle* h, bool upd) {
         else k_res2d<TD, TR, 6, false><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
       }
     } else {
-      if (upd) k_res3d<TD, TR, true><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
-      else k_res3d<TD, TR, false><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
+      // exponent class of the flux (all instances share p)
+      const double p = h->hI[0].p;
+      if (p == 4.0) {
+        if (upd) k_res3d<TD, TR, true, 4><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
+        else k_res3d<TD, TR, false, 4><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
+      } else if (p == 2.0) {
+        if (upd) k_res3d<TD, TR, true, 2><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
+        else k_res3d<TD, TR, false, 2><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
+      } else {
+        if (upd) k_res3d<TD, TR, true, 0><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
+        else k_res3d<TD, TR, false, 0><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
+      }
     }
   }
   ProfScope ps(h, upd ? PSD_PASS_RES_FIN : -1);
@@ -672,7 +682,9 @@ static bool tune_cache_read(psd_handle* h, const std::string& key) {
     const size_t bar = l.find('|');
     if (bar == std::string::npos || l.substr(0, bar) != key) continue;
     int a, b, c, d;
-    if (std::sscanf(l.c_str() + bar + 1, "%d %d %d %d", &a, &b, &c, &d) == 4) {
+    // chunks below T3Z_MIN would need more partial slots than were allocated
+    if (std::sscanf(l.c_str() + bar + 1, "%d %d %d %d", &a, &b, &c, &d) == 4 && a >= T3Z_MIN &&
+        b >= T3Z_MIN) {
       h->tune_zc_res = a; h->tune_zc_ls = b; h->tune_xcd_res = c != 0; h->tune_xcd_ls = d != 0;
       found = true;
     }
@@ -724,16 +736,18 @@ static psd_status autotune_impl(psd_handle* h) {
       I.g = I.tmp;
     }
   }
-  std::vector<int> zcs = {8, 16, 32, 64};
-  if (h->dim == 2) zcs = {T3Z};
+  // z-chunk candidates (residual, line search): whole groups of six steps
+  std::vector<int> zres = {16, 28, 40, 64}, zls = {12, 24, 36, 60};
+  if (h->dim == 2) { zres = {T3Z_RES}; zls = {T3Z_LS}; }
   const int save_prof = h->opt.profile;
   h->opt.profile = 1;
   double best_res = 1e300, best_ls = 1e300;
-  int bz_res = T3Z, bz_ls = T3Z;
+  int bz_res = T3Z_RES, bz_ls = T3Z_LS;
   bool bx_res = false, bx_ls = false;
-  for (int zc : zcs) {
+  for (size_t zi = 0; zi < zres.size(); ++zi) {
     for (int xcd = 0; xcd < 2; ++xcd) {
-      h->tune_zc_res = h->tune_zc_ls = zc;
+      h->tune_zc_res = zres[zi];
+      h->tune_zc_ls = zls[zi];
       h->tune_xcd_res = h->tune_xcd_ls = xcd != 0;
       build_all_tasks(h, nsp_aux);
       psd_status st = upload_tasks(h);
@@ -750,8 +764,8 @@ static psd_status autotune_impl(psd_handle* h) {
       }
       HIPCHK(hipGetLastError());
       const double tr = h->pass_ms[PSD_PASS_RES], tl = h->pass_ms[PSD_PASS_LS];
-      if (tr < best_res) { best_res = tr; bz_res = zc; bx_res = xcd != 0; }
-      if (tl < best_ls) { best_ls = tl; bz_ls = zc; bx_ls = xcd != 0; }
+      if (tr < best_res) { best_res = tr; bz_res = zres[zi]; bx_res = xcd != 0; }
+      if (tl < best_ls) { best_ls = tl; bz_ls = zls[zi]; bx_ls = xcd != 0; }
     }
   }
   h->opt.profile = save_prof;
@@ -875,12 +889,13 @@ extern "C" psd_status psd_create(const psd_problem* probs, int batch, const psd_
   }
   // task tables: capacities from the finest z-chunk any tuning may pick
   std::vector<int> nsp_aux;
-  h->tune_zc_res = h->tune_zc_ls = 8;
+  h->tune_zc_res = h->tune_zc_ls = T3Z_MIN;
   build_all_tasks(h, nsp_aux);
   h->dT_cap = h->hT.size();
   std::vector<int> cap_res(batch), cap_ls(batch);
   for (int b = 0; b < batch; ++b) { cap_res[b] = h->hI[b].nblk_res; cap_ls[b] = h->hI[b].nblk_ls; }
-  h->tune_zc_res = h->tune_zc_ls = T3Z;
+  h->tune_zc_res = T3Z_RES;
+  h->tune_zc_ls = T3Z_LS;
   build_all_tasks(h, nsp_aux);
   // partial arrays and states
   if (dalloc(h, &h->dState, sizeof(SolveState) * batch)) return fail("out of device memory");

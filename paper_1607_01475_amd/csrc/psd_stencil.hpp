@@ -19,7 +19,11 @@ namespace psd {
 // tile shapes
 constexpr int T2X = 64, T2Y = 8;     // 2D: 512 cells, 2 per thread
 constexpr int T3X = 32, T3Y = 8;     // 3D: one (x,y) column per thread
-constexpr int T3Z = 16;              // 3D: default planes marched per block
+// 3D: planes marched per block.  The residual runs z-chunk + 2 steps, the
+// line search z-chunk steps, both in groups of six: chunks with 6 | steps
+// waste nothing.  Defaults and the autotuner's candidates follow that rule.
+constexpr int T3Z_RES = 28, T3Z_LS = 24;
+constexpr int T3Z_MIN = 12;          // smallest chunk any tuning may pick
 
 __device__ __forceinline__ double flux_r(double g2, double p, int p_is_4, int p_is_2) {
   if (p_is_4) return g2;
@@ -169,7 +173,7 @@ __device__ void res2d_tile(const Inst& I, int x0, int y0, double* lds, double (&
 }
 
 // ===========================================================================
-// 3D residual: a T3X x T3Y column tile marching T3Z planes in z.
+// 3D residual: a T3X x T3Y column tile marching a chunk of planes in z.
 // Each thread owns one (x, y) column: its values of v = u + alpha d and of
 // Delta_h v at the planes in flight stay in registers; LDS holds the xy-halo
 // of 3 v planes (halo 2), 2 planes of Delta_h v (halo 1) and one vertex plane
@@ -223,22 +227,6 @@ struct R3Prefetch {
   TD d_own, d_ring;
 };
 
-template <typename TD, bool UPD>
-__device__ __forceinline__ void r3_fetch(const double* __restrict__ u, const TD* __restrict__ d, int n,
-                                         int x0, int y0, int z, int ring_ey, int ring_ex,
-                                         R3Prefetch<TD>& pf) {
-  const long long zo = (long long)wrapi(z, n) * n * n;
-  const int tx = threadIdx.x % T3X, ty = threadIdx.x / T3X;
-  const long long go = zo + wrapi(x0 + tx, n) + (long long)n * wrapi(y0 + ty, n);
-  pf.u_own = u[go];
-  if (UPD) pf.d_own = d[go];
-  if (threadIdx.x < R3_VRING) {
-    const long long gr = zo + wrapi(x0 - 2 + ring_ex, n) + (long long)n * wrapi(y0 - 2 + ring_ey, n);
-    pf.u_ring = u[gr];
-    if (UPD) pf.d_ring = d[gr];
-  }
-}
-
 // Per-plane partial sums of the 2x2 cells (c00, c10, c01, c11) below or
 // above a vertex: the vertex gradient of Sec. 5.1 (3D form) between planes k
 // and k+1 is (ex_k + ex_k+1, ey_k + ey_k+1, sm_k+1 - sm_k) / (4h), so each
@@ -280,163 +268,250 @@ __device__ __forceinline__ void r3_flux_lin(const Inst& I, const VPart& lo, cons
   C = fz;
 }
 
-template <typename TD, typename TR, bool UPD, bool HESS = false>
-__device__ void res3d_tile(const Inst& I, int x0, int y0, int z0, double* lds, double (&acc)[2]) {
-  static_assert(!(HESS && UPD), "no update in Hessian mode");
-  static_assert(!HESS || sizeof(TD) == 8, "u* is FP64");
-  constexpr bool LOADD = UPD || HESS;
-  const int n = I.n;
-  const SolveState* st = I.st;
-  const int cur = st->iter & 1;
-  const double alpha = UPD ? st->alpha : 0.0;
-  const double* __restrict__ u = HESS ? I.adj_p : I.u[cur];
-  double* __restrict__ uo = I.u[cur ^ 1];
-  const TD* __restrict__ d = HESS ? (const TD*)I.adj_us : (const TD*)I.d;
-  double* sb = lds + R3_LDS;           // Hessian mode: 3 planes of u*
-  double* vb = lds;                    // 3 v planes
-  double* lb = vb + 3 * R3_VP;         // 2 Laplacian planes
-  double* fA = lb + 2 * R3_LP;         // one vertex plane: A, B, C
-  double* fB = fA + R3_FP;
-  double* fC = fB + R3_FP;
-  const double ih = I.inv_h, ih2 = ih * ih, qh = 0.25 * ih;
-  // (1/(4h))^p: the divergence's 1/(4h) times the flux's (1/(4h))^(p-1)
-  const double qhp = I.p_is_4 ? (qh * qh) * (qh * qh) : (I.p_is_2 ? qh * qh : pow(qh, I.p));
-  const double s = I.s, se2 = I.se2;
-  const int z1 = min(z0 + I.zchunk_res, n);
-  const int tid = threadIdx.x;
-  const int tx = tid % T3X, ty = tid / T3X;
-  const int vown = (ty + 2) * R3_VW + tx + 2;      // own cell in a v plane
-  const int lown = (ty + 1) * R3_LW + tx + 1;      // own cell in a Laplacian plane
-  const int fown = (ty + 1) * R3_FW + tx + 1;      // own vertex (i+1/2, j+1/2)
-  const int vring = tid < R3_VRING ? r3_vring_pos(tid) : 0;
-  const int ring_ey = vring / R3_VW, ring_ex = vring - ring_ey * R3_VW;
-  const int lring = tid < R3_LRING ? r3_lring_pos(tid) : 0;
-  const int fring = tid < R3_FRING ? r3_fring_pos(tid) : 0;
-  // low-corner cell of the ring vertex in a v plane
-  const int fring_c = (fring / R3_FW + 1) * R3_VW + fring % R3_FW + 1;
-  const int gx = x0 + tx, gy = y0 + ty;
-  const bool own = gx < n && gy < n;
+// flux factor |g|^{p-2} at compile-time exponent class PK (4: p = 4,
+// 2: p = 2, 0: any p >= 2 at run time)
+template <int PK>
+__device__ __forceinline__ double flux_rr(double g2, double p) {
+  if (PK == 4) return g2;
+  if (PK == 2) return 1.0;
+  return g2 > 0.0 ? pow(g2, 0.5 * (p - 2.0)) : 0.0;
+}
 
-  // own-column registers: v at planes j, j+1, j+2; Laplacian at j-1, j, j+1;
-  // Hessian mode: u* at planes j, j+1, j+2
-  double vc0 = 0.0, vc1 = 0.0, vc2 = 0.0, lm = 0.0, l0 = 0.0, lp = 0.0;
-  double sc1 = 0.0, sc2 = 0.0;
-  double P_old = 0.0, Q_old = 0.0;
-  // plane partials of the lower plane of the current vertex plane: own
-  // vertex and ring vertex, of v and (Hessian mode) u*
-  VPart po = {0.0, 0.0, 0.0}, pr = {0.0, 0.0, 0.0}, so = {0.0, 0.0, 0.0}, sr = {0.0, 0.0, 0.0};
-  double f_next = 0.0;                 // f at the own cell of the next output plane
-  const long long fcol = (long long)wrapi(gx, n) + (long long)n * wrapi(gy, n);
+// The plane march of a 3D residual block.  Step j (relative index
+// q = j - (z0 - 2)) stores plane j+2, forms the Laplacian and the vertex
+// partials of plane j+1, the fluxes of vertex plane j+1/2, and writes output
+// plane j.  Every buffer rotates with period 2 or 3, so six consecutive steps
+// are unrolled with compile-time buffer indices (no register copies, no
+// modulo arithmetic); a block runs whole groups of six steps, steps past the
+// chunk write nothing.
+template <typename TD, typename TR, bool UPD, bool HESS, int PK>
+struct Res3March {
+  static constexpr bool LOADD = UPD || HESS;
+  const Inst& I;
+  const double* __restrict__ u;
+  double* __restrict__ uo;
+  const TD* __restrict__ d;
+  double* vb;   // 3 v planes
+  double* lb;   // 2 Laplacian planes
+  double* fA;   // one vertex plane: A, B, C
+  double* fB;
+  double* fC;
+  double* sb;   // Hessian mode: 3 planes of u*
+  double alpha, ih2, qhp, s, se2, p;
+  long long nn;             // n*n
+  long long own_xy, ring_xy, fcol;
+  int n, z0, z1, tid;
+  int vown, lown, fown, vring, lring, fring, fring_c;
+  long long gout;           // output offset of the own cell in plane 0
+  bool own;
+  // rotating registers
+  double vc[3], sc[3], lap[3];
+  VPart po[2], pr[2], so[2], sr[2];
+  double Pq[2], Qq[2], fv[2];
   R3Prefetch<TD> pf;
-  // planes z0-2 and z0-1 go straight to LDS; plane z0 is prefetched
-  for (int q = -2; q <= -1; ++q) {
-    r3_fetch<TD, LOADD>(u, d, n, x0, y0, z0 + q, ring_ey, ring_ex, pf);
-    const int sl = ((z0 + q + 6) % 3) * R3_VP;
-    const double vo = UPD ? pf.u_own + alpha * (double)pf.d_own : pf.u_own;
-    vb[sl + vown] = vo;
-    if (tid < R3_VRING) vb[sl + vring] = UPD ? pf.u_ring + alpha * (double)pf.d_ring : pf.u_ring;
-    vc1 = vc2;
-    vc2 = vo;
-    if (HESS) {
-      sb[sl + vown] = (double)pf.d_own;
-      if (tid < R3_VRING) sb[sl + vring] = (double)pf.d_ring;
-      sc1 = sc2;
-      sc2 = (double)pf.d_own;
+  double acc0, acc1;
+
+  __device__ __forceinline__ Res3March(const Inst& I_, int x0, int y0, int z0_, double* lds)
+      : I(I_) {
+    const SolveState* st = I.st;
+    const int cur = st->iter & 1;
+    alpha = UPD ? st->alpha : 0.0;
+    u = HESS ? I.adj_p : I.u[cur];
+    uo = I.u[cur ^ 1];
+    d = HESS ? (const TD*)I.adj_us : (const TD*)I.d;
+    vb = lds;
+    lb = vb + 3 * R3_VP;
+    fA = lb + 2 * R3_LP;
+    fB = fA + R3_FP;
+    fC = fB + R3_FP;
+    sb = lds + R3_LDS;
+    n = I.n;
+    nn = (long long)n * n;
+    const double ih = I.inv_h, qh = 0.25 * ih;
+    ih2 = ih * ih;
+    // (1/(4h))^p: the divergence's 1/(4h) times the flux's (1/(4h))^(p-1)
+    qhp = PK == 4 ? (qh * qh) * (qh * qh) : (PK == 2 ? qh * qh : pow(qh, I.p));
+    s = I.s;
+    se2 = I.se2;
+    p = I.p;
+    z0 = z0_;
+    z1 = min(z0 + I.zchunk_res, n);
+    tid = threadIdx.x;
+    const int tx = tid % T3X, ty = tid / T3X;
+    vown = (ty + 2) * R3_VW + tx + 2;
+    lown = (ty + 1) * R3_LW + tx + 1;
+    fown = (ty + 1) * R3_FW + tx + 1;
+    vring = tid < R3_VRING ? r3_vring_pos(tid) : vown;
+    const int rey = vring / R3_VW, rex = vring - rey * R3_VW;
+    lring = tid < R3_LRING ? r3_lring_pos(tid) : lown;
+    fring = tid < R3_FRING ? r3_fring_pos(tid) : fown;
+    fring_c = (fring / R3_FW + 1) * R3_VW + fring % R3_FW + 1;
+    const int gx = x0 + tx, gy = y0 + ty;
+    own = gx < n && gy < n;
+    own_xy = wrapi(gx, n) + (long long)n * wrapi(gy, n);
+    ring_xy = wrapi(x0 - 2 + rex, n) + (long long)n * wrapi(y0 - 2 + rey, n);
+    fcol = own_xy;
+    gout = gx + (long long)n * gy;
+    acc0 = 0.0;
+    acc1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { vc[k] = 0.0; sc[k] = 0.0; lap[k] = 0.0; }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      po[k] = pr[k] = so[k] = sr[k] = VPart{0.0, 0.0, 0.0};
+      Pq[k] = Qq[k] = fv[k] = 0.0;
     }
   }
-  r3_fetch<TD, LOADD>(u, d, n, x0, y0, z0, ring_ey, ring_ex, pf);
 
-  for (int j = z0 - 2; j < z1; ++j) {
-    // store plane j+2 (prefetched), then prefetch plane j+3
-    double* vn = vb + ((j + 2 + 6) % 3) * R3_VP;
+  __device__ __forceinline__ void fetch(int z) {
+    const long long zo = (long long)wrapi(z, n) * nn;
+    pf.u_own = u[zo + own_xy];
+    if (LOADD) pf.d_own = d[zo + own_xy];
+    if (tid < R3_VRING) {
+      pf.u_ring = u[zo + ring_xy];
+      if (LOADD) pf.d_ring = d[zo + ring_xy];
+    }
+  }
+
+  // put the prefetched plane into v slot S (and u* slot S); returns own v
+  template <int S>
+  __device__ __forceinline__ double put(){
+    double* vn = vb + S * R3_VP;
     const double vo = UPD ? pf.u_own + alpha * (double)pf.d_own : pf.u_own;
     vn[vown] = vo;
     if (tid < R3_VRING) vn[vring] = UPD ? pf.u_ring + alpha * (double)pf.d_ring : pf.u_ring;
-    vc0 = vc1; vc1 = vc2; vc2 = vo;
     if (HESS) {
-      double* sn = sb + ((j + 2 + 6) % 3) * R3_VP;
+      double* sn = sb + S * R3_VP;
       sn[vown] = (double)pf.d_own;
       if (tid < R3_VRING) sn[vring] = (double)pf.d_ring;
-      sc1 = sc2; sc2 = (double)pf.d_own;
+      sc[S] = (double)pf.d_own;
     }
-    if (j + 1 < z1) r3_fetch<TD, LOADD>(u, d, n, x0, y0, j + 3, ring_ey, ring_ex, pf);
-    // the output of this step (plane j) needs f(j): load it one step ahead
-    const double f_cur = f_next;
-    if (!HESS && j + 1 >= z0 && j + 1 < z1) f_next = I.f[fcol + (long long)n * n * (j + 1)];
+    return vo;
+  }
+
+  __device__ __forceinline__ void flux(const VPart& lo, const VPart& hi, const VPart& slo,
+                                       const VPart& shi, double& A, double& B, double& C) const {
+    if (HESS) {
+      r3_flux_lin(I, lo, hi, slo, shi, A, B, C);
+    } else {
+      const double gx = lo.ex + hi.ex, gy = lo.ey + hi.ey, gz = hi.sm - lo.sm;
+      const double rr = flux_rr<PK>(gx * gx + gy * gy + gz * gz, p);
+      const double fx = rr * gx, fy = rr * gy;
+      A = fx + fy;
+      B = fx - fy;
+      C = rr * gz;
+    }
+  }
+
+  // planes z0-2, z0-1 into slots 0, 1; plane z0 prefetched
+  __device__ __forceinline__ void prologue() {
+    fetch(z0 - 2);
+    vc[0] = put<0>();
+    fetch(z0 - 1);
+    vc[1] = put<1>();
+    fetch(z0);
+  }
+
+  template <int Q>
+  __device__ __forceinline__ void step(int j) {
+    constexpr int S0 = Q % 3, S1 = (Q + 1) % 3, S2 = (Q + 2) % 3;   // planes j, j+1, j+2
+    constexpr int P0 = Q & 1, P1 = (Q + 1) & 1;                      // planes j, j+1
+    vc[S2] = put<S2>();
+    if (j + 1 < z1) fetch(j + 3);
+    if (!HESS && j + 1 >= z0 && j + 1 < z1) fv[P1] = I.f[fcol + nn * (j + 1)];
     __syncthreads();
-    const double* v0 = vb + ((j + 6) % 3) * R3_VP;       // plane j
-    const double* v1 = vb + ((j + 1 + 6) % 3) * R3_VP;   // plane j+1
-    const double* v2 = vn;                                // plane j+2
-    // own neighbours in plane j+1 (Laplacian and vertex partials)
+    const double* v0 = vb + S0 * R3_VP;
+    const double* v1 = vb + S1 * R3_VP;
+    const double* v2 = vb + S2 * R3_VP;
     const int c = vown;
     const double xm = v1[c - 1], xp = v1[c + 1], ym = v1[c - R3_VW], yp = v1[c + R3_VW];
     const double xyp = v1[c + R3_VW + 1];
-    // Laplacian of plane j+1: own cell (z neighbours from registers) and ring
-    double* ln = lb + ((j + 1 + 2) & 1) * R3_LP;
+    // Laplacian of plane j+1: own cell and ring
+    double* ln = lb + P1 * R3_LP;
     {
-      const double lap = (xm + xp + ym + yp + vc0 + vc2 - 6.0 * vc1) * ih2;
-      ln[lown] = lap;
-      lm = l0; l0 = lp; lp = lap;
+      const double lp = (xm + xp + ym + yp + vc[S0] + vc[S2] - 6.0 * vc[S1]) * ih2;
+      ln[lown] = lp;
+      lap[S1] = lp;
       if (tid < R3_LRING) {
         const int ly = lring / R3_LW, lx = lring - ly * R3_LW;
         const int cc = (ly + 1) * R3_VW + lx + 1;
         ln[lring] = (v1[cc - 1] + v1[cc + 1] + v1[cc - R3_VW] + v1[cc + R3_VW] + v0[cc] + v2[cc] - 6.0 * v1[cc]) * ih2;
       }
     }
-    // partials of plane j+1 for the own and the ring vertex
-    const VPart pn = vpart(vc1, xp, yp, xyp);
-    VPart prn = {0.0, 0.0, 0.0}, sn_own = {0.0, 0.0, 0.0}, srn = {0.0, 0.0, 0.0};
-    if (tid < R3_FRING)
-      prn = vpart(v1[fring_c], v1[fring_c + 1], v1[fring_c + R3_VW], v1[fring_c + R3_VW + 1]);
+    // partials of plane j+1 (own vertex; ring vertex on the ring threads)
+    po[P1] = vpart(vc[S1], xp, yp, xyp);
+    pr[P1] = vpart(v1[fring_c], v1[fring_c + 1], v1[fring_c + R3_VW], v1[fring_c + R3_VW + 1]);
     if (HESS) {
-      const double* s1 = sb + ((j + 1 + 6) % 3) * R3_VP;
-      sn_own = vpart(sc1, s1[c + 1], s1[c + R3_VW], s1[c + R3_VW + 1]);
-      if (tid < R3_FRING)
-        srn = vpart(s1[fring_c], s1[fring_c + 1], s1[fring_c + R3_VW], s1[fring_c + R3_VW + 1]);
+      const double* s1 = sb + S1 * R3_VP;
+      so[P1] = vpart(sc[S1], s1[c + 1], s1[c + R3_VW], s1[c + R3_VW + 1]);
+      sr[P1] = vpart(s1[fring_c], s1[fring_c + 1], s1[fring_c + R3_VW], s1[fring_c + R3_VW + 1]);
     }
-    // fluxes at vertex plane j+1/2 (cells j, j+1) and the partial divergence
+    const bool flx = j >= z0 - 1;
     double A_own = 0.0, C_own = 0.0;
-    if (j >= z0 - 1) {
+    if (flx) {
       double A, B, C;
-      if (HESS) r3_flux_lin(I, po, pn, so, sn_own, A, B, C);
-      else r3_flux(I, po, pn, A, B, C);
+      flux(po[P0], po[P1], so[P0], so[P1], A, B, C);
       fA[fown] = A; fB[fown] = B; fC[fown] = C;
       A_own = A; C_own = C;
       if (tid < R3_FRING) {
-        if (HESS) r3_flux_lin(I, pr, prn, sr, srn, A, B, C);
-        else r3_flux(I, pr, prn, A, B, C);
+        flux(pr[P0], pr[P1], sr[P0], sr[P1], A, B, C);
         fA[fring] = A; fB[fring] = B; fC[fring] = C;
       }
     }
-    po = pn; pr = prn;
-    if (HESS) { so = sn_own; sr = srn; }
     __syncthreads();
-    if (j >= z0 - 1) {
+    if (flx) {
       const int fx = fown - 1, fy = fown - R3_FW, fxy = fown - R3_FW - 1;
       const double P = A_own - fA[fxy] + fB[fy] - fB[fx];
-      const double Q = C_own + fC[fx] + fC[fy] + fC[fxy];
-      if (j >= z0 && own) {
-        // output plane j: v(j) = vc0, Laplacian planes j-1, j, j+1 = lm, l0, lp
-        const double div = qhp * (P + P_old + Q - Q_old);
-        const double* lc = lb + ((j + 2) & 1) * R3_LP;   // Laplacian plane j
-        const double l2 = (lc[lown - 1] + lc[lown + 1] + lc[lown - R3_LW] + lc[lown + R3_LW] + lm + lp - 6.0 * l0) * ih2;
-        const long long gi = gx + (long long)n * (gy + (long long)n * j);
+      const double Qz = C_own + fC[fx] + fC[fy] + fC[fxy];
+      if (j >= z0 && j < z1 && own) {
+        // output plane j: v(j) = vc[S0], Laplacian planes j-1, j, j+1
+        const double div = qhp * (P + Pq[P1] + Qz - Qq[P1]);
+        const double* lc = lb + P0 * R3_LP;   // Laplacian plane j
+        const double l2 = (lc[lown - 1] + lc[lown + 1] + lc[lown - R3_LW] + lc[lown + R3_LW] + lap[S2] +
+                           lap[S1] - 6.0 * lap[S0]) * ih2;
+        const long long gi = gout + nn * j;
+        const double v = vc[S0];
         if (HESS) {
-          const double hx = vc0 - s * div + se2 * l2;
+          const double hx = v - s * div + se2 * l2;
           I.adj_Hp[gi] = hx;
-          acc[1] += vc0 * hx;
+          acc1 += v * hx;
         } else {
-          const double r = f_cur - (vc0 - s * div + se2 * l2);
+          const double r = fv[P0] - (v - s * div + se2 * l2);
           ((TR*)I.r)[gi] = (TR)r;
-          if (UPD) uo[gi] = vc0;
-          acc[0] = fmax(acc[0], fabs(r));
-          acc[1] += r * r;
+          if (UPD) uo[gi] = v;
+          acc0 = fmax(acc0, fabs(r));
+          acc1 += r * r;
         }
       }
-      P_old = P;
-      Q_old = Q;
+      Pq[P0] = P;
+      Qq[P0] = Qz;
     }
   }
+
+  __device__ __forceinline__ void run() {
+    prologue();
+    const int T = z1 - z0 + 2;
+    for (int q = 0; q < T; q += 6) {
+      const int j = z0 - 2 + q;
+      step<0>(j);
+      step<1>(j + 1);
+      step<2>(j + 2);
+      step<3>(j + 3);
+      step<4>(j + 4);
+      step<5>(j + 5);
+    }
+  }
+};
+
+template <typename TD, typename TR, bool UPD, bool HESS, int PK>
+__device__ __forceinline__ void res3d_tile(const Inst& I, int x0, int y0, int z0, double* lds,
+                                           double (&acc)[2]) {
+  static_assert(!(HESS && UPD), "no update in Hessian mode");
+  static_assert(!HESS || sizeof(TD) == 8, "u* is FP64");
+  Res3March<TD, TR, UPD, HESS, PK> m(I, x0, y0, z0, lds);
+  m.run();
+  acc[0] = m.acc0;
+  acc[1] = m.acc1;
 }
 
 // ===========================================================================
@@ -521,115 +596,154 @@ struct L3Prefetch {
   TD d_own, d_ring;
 };
 
-template <typename TD>
-__device__ __forceinline__ void l3_fetch(const double* __restrict__ u, const TD* __restrict__ d, int n,
-                                         int x0, int y0, int z, int ring_ey, int ring_ex,
-                                         L3Prefetch<TD>& pf) {
-  const long long zo = (long long)wrapi(z, n) * n * n;
-  const int tx = threadIdx.x % T3X, ty = threadIdx.x / T3X;
-  const long long go = zo + wrapi(x0 + tx, n) + (long long)n * wrapi(y0 + ty, n);
-  pf.u_own = u[go];
-  pf.d_own = d[go];
-  if (threadIdx.x < L3_RING) {
-    const long long gr = zo + wrapi(x0 - 1 + ring_ex, n) + (long long)n * wrapi(y0 - 1 + ring_ey, n);
-    pf.u_ring = u[gr];
-    pf.d_ring = d[gr];
-  }
-}
-
-// Vertex gradients from per-plane partial sums of the 2x2 cells around a
-// vertex column: for a plane, Ex = (c10 - c00) + (c11 - c01),
-// Ey = (c01 - c00) + (c11 - c10), Sm = c00 + c10 + c01 + c11; the gradient at
-// the vertex between planes k and k+1 is (Ex_k + Ex_k+1, Ey_k + Ey_k+1,
-// Sm_k+1 - Sm_k) / (4h).  The 1/(4h) factor is applied once to the sums.
+// The plane march of a 3D line-search block.  Step k (relative q = k - z0)
+// stores plane k+1, forms the vertex partials of plane k+1 for u and d (the
+// vertex gradients of Sec. 5.1 between planes k and k+1 are sums of the two
+// planes' partials, kept scaled by 4h and rescaled once at the end) and the
+// Laplacian of d at plane k.  As in the residual, six steps are unrolled with
+// compile-time buffer indices; steps past the chunk add nothing.
 template <typename TD, int MODE>
-__device__ void ls3d_tile(const Inst& I, int x0, int y0, int z0, double* lds,
-                          double (&acc)[8]) {
-  const int n = I.n;
-  const SolveState* st = I.st;
-  const double* __restrict__ u = I.u[st->iter & 1];
-  const TD* __restrict__ d = (const TD*)I.d;
-  const double alpha = (MODE == 2) ? st->x : 0.0;
-  double* ub = lds;
-  double* db = lds + 3 * L3_P;
-  const double ih2 = I.inv_h * I.inv_h;
-  const int z1 = min(z0 + I.zchunk_ls, n);
-  const int tid = threadIdx.x;
-  const int tx = tid % T3X, ty = tid / T3X;
-  const bool own = x0 + tx < n && y0 + ty < n;
-  const int c = (ty + 1) * L3_W + tx + 1;           // own cell in a plane buffer
-  const int ring = tid < L3_RING ? r3_lring_pos(tid) : 0;   // same ring shape as a Laplacian plane
-  const int ring_ey = ring / L3_W, ring_ex = ring - ring_ey * L3_W;
-  double uc1 = 0.0, dm = 0.0, dc0 = 0.0, dc1 = 0.0;
-  // plane partials of u and d for the own vertex column (plane k), and the
-  // +x, +y neighbours of d in plane k (reused by the Laplacian of d)
-  double exu = 0.0, eyu = 0.0, smu = 0.0, exd = 0.0, eyd = 0.0, smd = 0.0;
-  double d10 = 0.0, d01 = 0.0;
-  double sacc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+struct Ls3March {
+  const Inst& I;
+  const double* __restrict__ u;
+  const TD* __restrict__ d;
+  double* ub;
+  double* db;
+  double alpha, ih2;
+  long long nn, own_xy, ring_xy;
+  int n, z0, z1, tid, c, ring;
+  bool own;
+  double dcol[3];                  // own d at planes (rel) r mod 3
+  VPart pu[2], pd[2];              // partials of u, d at planes r mod 2
+  double n10[2], n01[2];           // d at (x+1), (y+1) of the own cell, planes r mod 2
+  double sacc[8];
   L3Prefetch<TD> pf;
-  // plane z0-1 enters only through the own-column d (Laplacian along z)
-  dc0 = (double)d[(long long)wrapi(z0 - 1, n) * n * n + wrapi(x0 + tx, n) +
-                  (long long)n * wrapi(y0 + ty, n)];
-  {
-    l3_fetch<TD>(u, d, n, x0, y0, z0, ring_ey, ring_ex, pf);
-    const int sl = (z0 % 3) * L3_P;
-    ub[sl + c] = pf.u_own;
-    db[sl + c] = (double)pf.d_own;
-    if (tid < L3_RING) { ub[sl + ring] = pf.u_ring; db[sl + ring] = (double)pf.d_ring; }
-    uc1 = pf.u_own;
-    dc1 = (double)pf.d_own;
-  }
-  // now uc1 = u(z0), dc0 = d(z0-1), dc1 = d(z0); partials of plane z0
-  __syncthreads();
-  {
-    const int s0 = (z0 % 3) * L3_P;
-    const double u10 = ub[s0 + c + 1], u01 = ub[s0 + c + L3_W], u11 = ub[s0 + c + L3_W + 1];
-    exu = (u10 - uc1) + (u11 - u01); eyu = (u01 - uc1) + (u11 - u10); smu = uc1 + u10 + u01 + u11;
-    d10 = db[s0 + c + 1]; d01 = db[s0 + c + L3_W];
-    const double e11 = db[s0 + c + L3_W + 1];
-    exd = (d10 - dc1) + (e11 - d01); eyd = (d01 - dc1) + (e11 - d10); smd = dc1 + d10 + d01 + e11;
-  }
-  l3_fetch<TD>(u, d, n, x0, y0, z0 + 1, ring_ey, ring_ex, pf);
-  for (int k = z0; k < z1; ++k) {
-    const int sn = ((k + 1 + 3) % 3) * L3_P;
-    ub[sn + c] = pf.u_own;
-    db[sn + c] = (double)pf.d_own;
-    if (tid < L3_RING) { ub[sn + ring] = pf.u_ring; db[sn + ring] = (double)pf.d_ring; }
-    uc1 = pf.u_own;
-    dm = dc0; dc0 = dc1; dc1 = (double)pf.d_own;
-    if (k + 1 < z1) l3_fetch<TD>(u, d, n, x0, y0, k + 2, ring_ey, ring_ex, pf);
-    __syncthreads();
-    // partials of plane k+1
-    const double* u1 = ub + sn;
-    const double* d1 = db + sn;
-    const double u10 = u1[c + 1], u01 = u1[c + L3_W], u11 = u1[c + L3_W + 1];
-    const double exu1 = (u10 - uc1) + (u11 - u01), eyu1 = (u01 - uc1) + (u11 - u10);
-    const double smu1 = uc1 + u10 + u01 + u11;
-    const double n10 = d1[c + 1], n01 = d1[c + L3_W], n11 = d1[c + L3_W + 1];
-    const double exd1 = (n10 - dc1) + (n11 - n01), eyd1 = (n01 - dc1) + (n11 - n10);
-    const double smd1 = dc1 + n10 + n01 + n11;
-    if (own) {
-      const double ax = exu + exu1, ay = eyu + eyu1, az = smu1 - smu;
-      const double bx = exd + exd1, by = eyd + eyd1, bz = smd1 - smd;
-      ls_vertex<MODE>(I.p, alpha, ax, ay, az, bx, by, bz, sacc);
-      const double* d0 = db + ((k + 3) % 3) * L3_P;
-      const double ld = (d0[c - 1] + d10 + d0[c - L3_W] + d01 + dm + dc1 - 6.0 * dc0) * ih2;
-      if (MODE == 0) { sacc[4] += dc0 * dc0; sacc[5] += ld * ld; }
-      else { sacc[2] += dc0 * dc0; sacc[3] += ld * ld; }
+
+  __device__ __forceinline__ Ls3March(const Inst& I_, int x0, int y0, int z0_, double* lds) : I(I_) {
+    const SolveState* st = I.st;
+    u = I.u[st->iter & 1];
+    d = (const TD*)I.d;
+    alpha = (MODE == 2) ? st->x : 0.0;
+    ub = lds;
+    db = lds + 3 * L3_P;
+    ih2 = I.inv_h * I.inv_h;
+    n = I.n;
+    nn = (long long)n * n;
+    z0 = z0_;
+    z1 = min(z0 + I.zchunk_ls, n);
+    tid = threadIdx.x;
+    const int tx = tid % T3X, ty = tid / T3X;
+    own = x0 + tx < n && y0 + ty < n;
+    c = (ty + 1) * L3_W + tx + 1;
+    ring = tid < L3_RING ? r3_lring_pos(tid) : c;   // same ring shape as a Laplacian plane
+    const int rey = ring / L3_W, rex = ring - rey * L3_W;
+    own_xy = wrapi(x0 + tx, n) + (long long)n * wrapi(y0 + ty, n);
+    ring_xy = wrapi(x0 - 1 + rex, n) + (long long)n * wrapi(y0 - 1 + rey, n);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dcol[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      pu[k] = pd[k] = VPart{0.0, 0.0, 0.0};
+      n10[k] = n01[k] = 0.0;
     }
-    exu = exu1; eyu = eyu1; smu = smu1;
-    exd = exd1; eyd = eyd1; smd = smd1;
-    d10 = n10; d01 = n01;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sacc[k] = 0.0;
   }
+
+  __device__ __forceinline__ void fetch(int z) {
+    const long long zo = (long long)wrapi(z, n) * nn;
+    pf.u_own = u[zo + own_xy];
+    pf.d_own = d[zo + own_xy];
+    if (tid < L3_RING) {
+      pf.u_ring = u[zo + ring_xy];
+      pf.d_ring = d[zo + ring_xy];
+    }
+  }
+
+  template <int S>
+  __device__ __forceinline__ void put() {
+    ub[S * L3_P + c] = pf.u_own;
+    db[S * L3_P + c] = (double)pf.d_own;
+    if (tid < L3_RING) {
+      ub[S * L3_P + ring] = pf.u_ring;
+      db[S * L3_P + ring] = (double)pf.d_ring;
+    }
+    dcol[S] = (double)pf.d_own;
+  }
+
+  // partials of the plane in slot S into register slot R
+  template <int S, int R>
+  __device__ __forceinline__ void partials() {
+    const double* u1 = ub + S * L3_P;
+    const double* d1 = db + S * L3_P;
+    const double a10 = u1[c + 1], a01 = u1[c + L3_W], a11 = u1[c + L3_W + 1];
+    pu[R] = vpart(u1[c], a10, a01, a11);
+    const double b10 = d1[c + 1], b01 = d1[c + L3_W], b11 = d1[c + L3_W + 1];
+    pd[R] = vpart(dcol[S], b10, b01, b11);
+    n10[R] = b10;
+    n01[R] = b01;
+  }
+
+  // plane z0-1 enters only through the own d; plane z0 in slot 1
+  __device__ __forceinline__ void prologue() {
+    dcol[0] = (double)d[(long long)wrapi(z0 - 1, n) * nn + own_xy];
+    fetch(z0);
+    put<1>();
+    __syncthreads();
+    partials<1, 1>();
+    fetch(z0 + 1);
+  }
+
+  template <int Q>
+  __device__ __forceinline__ void step(int k) {
+    // relative plane index r = plane - z0 + 1: k-1 -> q, k -> q+1, k+1 -> q+2
+    constexpr int SM = Q % 3, SK = (Q + 1) % 3, SN = (Q + 2) % 3;
+    constexpr int RK = (Q + 1) & 1, RN = Q & 1;
+    put<SN>();
+    if (k + 1 < z1) fetch(k + 2);
+    __syncthreads();
+    partials<SN, RN>();
+    if (k < z1 && own) {
+      const double ax = pu[RK].ex + pu[RN].ex, ay = pu[RK].ey + pu[RN].ey, az = pu[RN].sm - pu[RK].sm;
+      const double bx = pd[RK].ex + pd[RN].ex, by = pd[RK].ey + pd[RN].ey, bz = pd[RN].sm - pd[RK].sm;
+      ls_vertex<MODE>(I.p, alpha, ax, ay, az, bx, by, bz, sacc);
+      const double* d0 = db + SK * L3_P;
+      const double dk = dcol[SK];
+      const double ld = (d0[c - 1] + n10[RK] + d0[c - L3_W] + n01[RK] + dcol[SM] + dcol[SN] - 6.0 * dk) * ih2;
+      if (MODE == 0) { sacc[4] += dk * dk; sacc[5] += ld * ld; }
+      else { sacc[2] += dk * dk; sacc[3] += ld * ld; }
+    }
+  }
+
+  __device__ __forceinline__ void run() {
+    prologue();
+    const int T = z1 - z0;
+    for (int q = 0; q < T; q += 6) {
+      const int k = z0 + q;
+      step<0>(k);
+      step<1>(k + 1);
+      step<2>(k + 2);
+      step<3>(k + 3);
+      step<4>(k + 4);
+      step<5>(k + 5);
+    }
+  }
+};
+
+template <typename TD, int MODE>
+__device__ __forceinline__ void ls3d_tile(const Inst& I, int x0, int y0, int z0, double* lds,
+                                          double (&acc)[8]) {
+  Ls3March<TD, MODE> m(I, x0, y0, z0, lds);
+  m.run();
   // vertex sums were taken with gradients scaled by 4h: undo once
   const double qh = 0.25 * I.inv_h;
   const double sc = (MODE == 0 || I.p_is_4) ? qh * qh * qh * qh : pow(qh, I.p);
   if (MODE == 0) {
-    for (int q = 0; q < 4; ++q) acc[q] += sc * sacc[q];
-    acc[4] += sacc[4]; acc[5] += sacc[5];
+    for (int q = 0; q < 4; ++q) acc[q] += sc * m.sacc[q];
+    acc[4] += m.sacc[4]; acc[5] += m.sacc[5];
   } else {
-    acc[0] += sc * sacc[0]; acc[1] += sc * sacc[1];
-    acc[2] += sacc[2]; acc[3] += sacc[3];
+    acc[0] += sc * m.sacc[0]; acc[1] += sc * m.sacc[1];
+    acc[2] += m.sacc[2]; acc[3] += m.sacc[3];
   }
 }
 

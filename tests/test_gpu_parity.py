@@ -233,7 +233,8 @@ def test_autotuned_tiling_gives_same_solution(psd):
     for tune in (False, True):
         with psd.Solver(P, tol=1e-10, max_iter=300, precision="mixed", autotune=tune) as S:
             t = S.tuning()
-            assert t[0] in (8, 16, 32, 64) and t[1] in (8, 16, 32, 64)
+            # residual / line-search z-chunks run whole groups of six plane steps
+            assert t[0] in (16, 28, 40, 64) and t[1] in (12, 24, 36, 60)
             u = torch.zeros_like(dev(f))
             st = S.solve([dev(f)], [u])[0]
             res.append((st.iters, host(u), t))
