@@ -77,6 +77,63 @@ def traffic_for(kernel: str, workload: str):
         return None
 
 
+# kernels of the passes of the mixed 256^3 p=4 form (rocprofv3 kernel names)
+PASS_KERNELS = {
+    "rows_r2c": "psd::k_rows<float, float, true, 256>",
+    "cols_fwd": "psd::k_cols<float, 1, -1, 256>",
+    "cols_fused": "psd::k_cols_fused<float, 0, 256>",
+    "cols_inv": "psd::k_cols<float, 1, 1, 256>",
+    "rows_c2r": "psd::k_rows<float, float, false, 256>",
+    "ls": "psd::k_ls3d<float, 0>",
+    "res": "psd::k_res3d<float, float, true, 4>",
+}
+COPY_BYTES = 512 * 1024 * 1024   # the --copy-calibration device copy
+
+
+def summarize_pmc(fetch_dir: str, write_dir: str, out: str, workload: str = "c3_256") -> dict:
+    """HBM bytes per launch of every pass from two rocprofv3 --pmc runs of
+    `bench.py --steps 1 --warmup 0 --no-cpu-baseline --forms mixed
+    --copy-calibration` (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).
+    Each counter is scaled by what it reads for the 512 MiB calibration copy;
+    the median over the last ten launches of a kernel (the ten iterations of
+    the final host-driven solve) is kept.  Writes `out` (JSON)."""
+    import csv
+    import statistics
+
+    def load(d, counter):
+        path = os.path.join(d, "pmc_counter_collection.csv")
+        per = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+            per.setdefault(name, []).append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+        return per
+
+    fetch, write = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    copy = "__amd_rocclr_copyBuffer"
+    fscale = COPY_BYTES / (1024.0 * max(v for _, v in fetch[copy]))
+    wscale = COPY_BYTES / (1024.0 * max(v for _, v in write[copy]))
+    rec = {"_calibration": {"copy_bytes": COPY_BYTES, "fetch_scale": round(fscale, 4),
+                            "write_scale": round(wscale, 4)}}
+    src = source_hash()
+    for pname, kname in PASS_KERNELS.items():
+        fv = [v for _, v in sorted(fetch.get(kname, []))[-10:]]
+        wv = [v for _, v in sorted(write.get(kname, []))[-10:]]
+        if not fv or not wv:
+            continue
+        fb = statistics.median(fv) * 1024.0 * fscale
+        wb = statistics.median(wv) * 1024.0 * wscale
+        alg = kernel_bytes(pname, 256, 3, True)
+        rec[f"{workload}:{pname}"] = {"kernel": kname, "fetch_bytes": round(fb), "write_bytes": round(wb),
+                                      "bytes_per_launch": round(fb + wb),
+                                      "algorithmic_bytes": alg, "ratio": round((fb + wb) / alg, 3),
+                                      "source_hash": src}
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return rec
+
+
 def run_form(psd, torch, P, f, precision, chunk, steps, warmup, tol=1e-10):
     # per-kernel HIP-event timing is available in the host-driven loop only
     S = psd.Solver(P, tol=tol, max_iter=500, precision=precision, graph_chunk=chunk,
@@ -140,7 +197,13 @@ def main():
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 512 MiB device copy (reference for HBM counters)")
+    ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
+                    help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) into HBM bytes per launch")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        rec = summarize_pmc(*args.summarize_pmc)
+        print(json.dumps(rec))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs on one GPU; multi-GPU runs are not part of "
                                    "this build (run with --gpus 1)"}))
