@@ -260,9 +260,12 @@ struct RowArgs {
   }
 };
 
-template <int N, typename T>
-constexpr int rows_lines() {  // complex lines per block for row passes
-  return (N * 2 * sizeof(T) * 2 <= 8192 * 2) ? 16 : (N >= 1024 ? 4 : 8);
+// Field and row of global row gr of a row pass (at most three fields of
+// rpf rows each; gr < 3 rpf): comparisons instead of a 64-bit division.
+__device__ __forceinline__ int row_field(long long gr, long long rpf, long long& row) {
+  const int fld = (gr >= rpf ? 1 : 0) + (gr >= 2 * rpf ? 1 : 0);
+  row = gr - fld * rpf;
+  return fld;
 }
 
 template <typename T, typename TIN, int N, int NL>
@@ -287,8 +290,8 @@ __device__ __forceinline__ void r2c_rows(const RowArgs<T>& A, long long row0, cx
     const long long gr = row0 + rr;
     if ((NV % PSD_NT == 0 || e < NV) && gr < A.nrows) {
       const int col = e * VEC - rr * N;
-      const int fld = (int)(gr / A.rpf);
-      const long long row = gr - (long long)fld * A.rpf;
+      long long row;
+      const int fld = row_field(gr, A.rpf, row);
       regs[it] = *(const V*)((const TIN*)A.in(fld) + row * N + col);
     } else {
 #pragma unroll
@@ -315,8 +318,8 @@ __device__ __forceinline__ void r2c_rows(const RowArgs<T>& A, long long row0, cx
     const cx<T> b = scale(mul_i<-1>(zk - zm), T(0.5));
     const long long gr = row0 + 2 * l;
     if (gr >= A.nrows) continue;
-    const int fld = (int)(gr / A.rpf);
-    const long long row = gr - (long long)fld * A.rpf;
+    long long row;
+    const int fld = row_field(gr, A.rpf, row);
     cx<T>* out = A.spec + fld * A.nspec;
     // rows row, row+1: columns kx < N/2 in the row array, kx = N/2 in the Nyquist plane
     const long long oa = (k < N / 2) ? row * A.ncp + k : A.nyq + row;
@@ -345,8 +348,8 @@ __device__ __forceinline__ void c2r_rows(const RowArgs<T>& A, long long row0, cx
     ra[it] = mk(T(0), T(0));
     rb[it] = mk(T(0), T(0));
     if ((NE % PSD_NT == 0 || e < NE) && gr < A.nrows) {
-      const int fld = (int)(gr / A.rpf);
-      const long long row = gr - (long long)fld * A.rpf;
+      long long row;
+      const int fld = row_field(gr, A.rpf, row);
       const cx<T>* in = A.spec + fld * A.nspec;
       const long long oa = (k < N / 2) ? row * A.ncp + k : A.nyq + row;
       const long long ob = (k < N / 2) ? oa + A.ncp : oa + 1;
@@ -374,8 +377,8 @@ __device__ __forceinline__ void c2r_rows(const RowArgs<T>& A, long long row0, cx
     const int rr = (e * VEC) / N, col = e * VEC - rr * N;
     const long long gr = row0 + rr;
     if (gr >= A.nrows) continue;
-    const int fld = (int)(gr / A.rpf);
-    const long long row = gr - (long long)fld * A.rpf;
+    long long row;
+    const int fld = row_field(gr, A.rpf, row);
     const T* src = (const T*)(buf + (rr >> 1) * LS + pidx(col)) + (rr & 1);
     V out;
     double part = 0.0;

@@ -399,6 +399,7 @@ __device__ __forceinline__ void fused_col(const Inst& I, const Task2& t, cx<T>* 
   const int kx = nyq ? N / 2 : t.b + c;
   const int ky3 = nyq ? t.a + c : t.a;
   const double wgt = (kx == 0 || 2 * kx == N) ? 1.0 : 2.0;
+  const double wgt_inv = wgt * inv;
   const double Kc = S[live ? kx : 0] + (dim == 3 ? S[live ? ky3 : 0] : 0.0);
   for (int e = threadIdx.x; e < W * N; e += PSD_NT) {
     if (!live) break;
@@ -406,10 +407,10 @@ __device__ __forceinline__ void fused_col(const Inst& I, const Task2& t, cx<T>* 
     const double K = Kc + S[tt];
     if (OP == OP_PRECOND4) {
       const cx<T> X = buf[c * LS + pidx(tt)];
-      const double sig = 1.0 + s * K + se2 * K * K;
+      const double rs = 1.0 / (1.0 + s * K + se2 * K * K);   // 1 / sigma
       const double x2 = (double)X.x * X.x + (double)X.y * X.y;
-      acc[0] += wgt * x2 / sig * inv;
-      buf[c * LS + pidx(tt)] = scale(X, (T)(inv / sig));
+      acc[0] += wgt_inv * x2 * rs;
+      buf[c * LS + pidx(tt)] = scale(X, (T)(inv * rs));
     } else if (OP == OP_POISSON) {
       const cx<T> X = buf[c * LS + pidx(tt)];
       if (K > 0.0) {

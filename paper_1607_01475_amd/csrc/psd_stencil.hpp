@@ -308,7 +308,7 @@ struct Res3March {
   double vc[3], sc[3], lap[3];
   VPart po[2], pr[2], so[2], sr[2];
   double Pq[2], Qq[2], fv[2];
-  R3Prefetch<TD> pf;
+  R3Prefetch<TD> pf[2];     // planes in flight: two steps ahead
   double acc0, acc1;
 
   __device__ __forceinline__ Res3March(const Inst& I_, int x0, int y0, int z0_, double* lds)
@@ -363,19 +363,21 @@ struct Res3March {
     }
   }
 
+  template <int B>
   __device__ __forceinline__ void fetch(int z) {
     const long long zo = (long long)wrapi(z, n) * nn;
-    pf.u_own = u[zo + own_xy];
-    if (LOADD) pf.d_own = d[zo + own_xy];
+    pf[B].u_own = u[zo + own_xy];
+    if (LOADD) pf[B].d_own = d[zo + own_xy];
     if (tid < R3_VRING) {
-      pf.u_ring = u[zo + ring_xy];
-      if (LOADD) pf.d_ring = d[zo + ring_xy];
+      pf[B].u_ring = u[zo + ring_xy];
+      if (LOADD) pf[B].d_ring = d[zo + ring_xy];
     }
   }
 
-  // put the prefetched plane into v slot S (and u* slot S); returns own v
-  template <int S>
-  __device__ __forceinline__ double put(){
+  // put the plane prefetched in buffer B into v slot S (and u* slot S); returns own v
+  template <int S, int B>
+  __device__ __forceinline__ double put() {
+    const R3Prefetch<TD>& pf = this->pf[B];
     double* vn = vb + S * R3_VP;
     const double vo = UPD ? pf.u_own + alpha * (double)pf.d_own : pf.u_own;
     vn[vown] = vo;
@@ -403,21 +405,24 @@ struct Res3March {
     }
   }
 
-  // planes z0-2, z0-1 into slots 0, 1; plane z0 prefetched
+  // planes z0-2, z0-1 into slots 0, 1; planes z0 (buffer 0) and z0+1
+  // (buffer 1) in flight
   __device__ __forceinline__ void prologue() {
-    fetch(z0 - 2);
-    vc[0] = put<0>();
-    fetch(z0 - 1);
-    vc[1] = put<1>();
-    fetch(z0);
+    fetch<0>(z0 - 2);
+    fetch<1>(z0 - 1);
+    vc[0] = put<0, 0>();
+    vc[1] = put<1, 1>();
+    fetch<0>(z0);
+    fetch<1>(z0 + 1);
   }
 
   template <int Q>
   __device__ __forceinline__ void step(int j) {
     constexpr int S0 = Q % 3, S1 = (Q + 1) % 3, S2 = (Q + 2) % 3;   // planes j, j+1, j+2
     constexpr int P0 = Q & 1, P1 = (Q + 1) & 1;                      // planes j, j+1
-    vc[S2] = put<S2>();
-    if (j + 1 < z1) fetch(j + 3);
+    // plane j+2 = z0 + q sits in buffer q mod 2; refill it with plane j+4
+    vc[S2] = put<S2, P0>();
+    if (j + 2 < z1) fetch<P0>(j + 4);
     if (!HESS && j + 1 >= z0 && j + 1 < z1) fv[P1] = I.f[fcol + nn * (j + 1)];
     __syncthreads();
     const double* v0 = vb + S0 * R3_VP;
@@ -617,7 +622,7 @@ struct Ls3March {
   VPart pu[2], pd[2];              // partials of u, d at planes r mod 2
   double n10[2], n01[2];           // d at (x+1), (y+1) of the own cell, planes r mod 2
   double sacc[8];
-  L3Prefetch<TD> pf;
+  L3Prefetch<TD> pf[1];            // plane in flight: one step ahead (more costs a wave per SIMD)
 
   __device__ __forceinline__ Ls3March(const Inst& I_, int x0, int y0, int z0_, double* lds) : I(I_) {
     const SolveState* st = I.st;
@@ -650,18 +655,20 @@ struct Ls3March {
     for (int k = 0; k < 8; ++k) sacc[k] = 0.0;
   }
 
+  template <int B>
   __device__ __forceinline__ void fetch(int z) {
     const long long zo = (long long)wrapi(z, n) * nn;
-    pf.u_own = u[zo + own_xy];
-    pf.d_own = d[zo + own_xy];
+    pf[B].u_own = u[zo + own_xy];
+    pf[B].d_own = d[zo + own_xy];
     if (tid < L3_RING) {
-      pf.u_ring = u[zo + ring_xy];
-      pf.d_ring = d[zo + ring_xy];
+      pf[B].u_ring = u[zo + ring_xy];
+      pf[B].d_ring = d[zo + ring_xy];
     }
   }
 
-  template <int S>
+  template <int S, int B>
   __device__ __forceinline__ void put() {
+    const L3Prefetch<TD>& pf = this->pf[B];
     ub[S * L3_P + c] = pf.u_own;
     db[S * L3_P + c] = (double)pf.d_own;
     if (tid < L3_RING) {
@@ -684,14 +691,15 @@ struct Ls3March {
     n01[R] = b01;
   }
 
-  // plane z0-1 enters only through the own d; plane z0 in slot 1
+  // plane z0-1 enters only through the own d; plane z0 in slot 1; plane
+  // z0+1 in flight
   __device__ __forceinline__ void prologue() {
     dcol[0] = (double)d[(long long)wrapi(z0 - 1, n) * nn + own_xy];
-    fetch(z0);
-    put<1>();
+    fetch<0>(z0);
+    put<1, 0>();
+    fetch<0>(z0 + 1);
     __syncthreads();
     partials<1, 1>();
-    fetch(z0 + 1);
   }
 
   template <int Q>
@@ -699,8 +707,8 @@ struct Ls3March {
     // relative plane index r = plane - z0 + 1: k-1 -> q, k -> q+1, k+1 -> q+2
     constexpr int SM = Q % 3, SK = (Q + 1) % 3, SN = (Q + 2) % 3;
     constexpr int RK = (Q + 1) & 1, RN = Q & 1;
-    put<SN>();
-    if (k + 1 < z1) fetch(k + 2);
+    put<SN, 0>();
+    if (k + 1 < z1) fetch<0>(k + 2);
     __syncthreads();
     partials<SN, RN>();
     if (k < z1 && own) {
