@@ -153,6 +153,35 @@ __device__ __forceinline__ void block_reduce(double (&v)[K], double* scratch) {
   __syncthreads();
 }
 
+// Global-memory view of a pointer read from a table.  Pointers taken from the
+// instance table are generic to the compiler, which then issues flat memory
+// instructions; those also count against the LDS wait counter, so every LDS
+// wait (and every barrier) would drain all loads in flight.  Casting to the
+// global address space gives global loads and stores instead.
+#define PSD_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ PSD_GLOBAL T* gmem(T* p) { return (PSD_GLOBAL T*)p; }
+template <typename T>
+__device__ __forceinline__ const PSD_GLOBAL T* gmem(const T* p) { return (const PSD_GLOBAL T*)p; }
+
+// Native vectors for global loads and stores of small aggregates (structs
+// cannot be copied to or from the global address space).
+template <typename T, int K>
+using gvec = T __attribute__((ext_vector_type(K)));
+
+template <typename T>
+__device__ __forceinline__ cx<T> gld(const cx<T>* p) {
+  const gvec<T, 2> v = *(const PSD_GLOBAL gvec<T, 2>*)gmem(p);
+  return mk(v.x, v.y);
+}
+template <typename T>
+__device__ __forceinline__ void gst(cx<T>* p, const cx<T>& a) {
+  gvec<T, 2> v;
+  v.x = a.x;
+  v.y = a.y;
+  *(PSD_GLOBAL gvec<T, 2>*)gmem(p) = v;
+}
+
 // Threads of the per-instance finalize kernels (one block per instance).
 constexpr int PSD_FIN_NT = 1024;
 
@@ -170,7 +199,7 @@ __device__ __forceinline__ void gather_parts(const double* __restrict__ part, in
     for (int j = 0; j < U; ++j) {
       const int b = b0 + j * PSD_FIN_NT + (int)threadIdx.x;
 #pragma unroll
-      for (int k = 0; k < K; ++k) v[j][k] = b < nblk ? part[K * b + k] : 0.0;
+      for (int k = 0; k < K; ++k) v[j][k] = b < nblk ? gmem(part)[K * b + k] : 0.0;
     }
 #pragma unroll
     for (int j = 0; j < U; ++j)
@@ -199,7 +228,7 @@ __device__ __forceinline__ void flat_reduce(const double* __restrict__ part, int
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       const int j = j0 + q * NT + tid;
-      v[q] = j < total ? part[j] : 0.0;
+      v[q] = j < total ? gmem(part)[j] : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < U; ++q) a = is_max ? fmax(a, v[q]) : a + v[q];

@@ -164,7 +164,7 @@ __device__ __forceinline__ int pidx(int t) { return t + (t >> 4); }
 // caller's next barrier publishes it.
 template <typename T, int N>
 __device__ __forceinline__ void stage_twiddles(cx<T>* dst, const cx<T>* __restrict__ tw) {
-  for (int i = threadIdx.x; i < N; i += PSD_NT) dst[i] = tw[i];
+  for (int i = threadIdx.x; i < N; i += PSD_NT) dst[i] = gld(tw + i);
 }
 
 template <int S, int NSTG, typename F>
@@ -292,7 +292,9 @@ __device__ __forceinline__ void r2c_rows(const RowArgs<T>& A, long long row0, cx
       const int col = e * VEC - rr * N;
       long long row;
       const int fld = row_field(gr, A.rpf, row);
-      regs[it] = *(const V*)((const TIN*)A.in(fld) + row * N + col);
+      const gvec<TIN, VEC> g = *(const PSD_GLOBAL gvec<TIN, VEC>*)(gmem((const TIN*)A.in(fld)) + row * N + col);
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) regs[it].x[q] = g[q];
     } else {
 #pragma unroll
       for (int q = 0; q < VEC; ++q) regs[it].x[q] = TIN(0);
@@ -324,8 +326,8 @@ __device__ __forceinline__ void r2c_rows(const RowArgs<T>& A, long long row0, cx
     // rows row, row+1: columns kx < N/2 in the row array, kx = N/2 in the Nyquist plane
     const long long oa = (k < N / 2) ? row * A.ncp + k : A.nyq + row;
     const long long ob = (k < N / 2) ? oa + A.ncp : oa + 1;
-    out[oa] = a;
-    out[ob] = b;
+    gst(out + oa, a);
+    gst(out + ob, b);
   }
 }
 
@@ -353,8 +355,8 @@ __device__ __forceinline__ void c2r_rows(const RowArgs<T>& A, long long row0, cx
       const cx<T>* in = A.spec + fld * A.nspec;
       const long long oa = (k < N / 2) ? row * A.ncp + k : A.nyq + row;
       const long long ob = (k < N / 2) ? oa + A.ncp : oa + 1;
-      ra[it] = in[oa];
-      rb[it] = in[ob];
+      ra[it] = gld(in + oa);
+      rb[it] = gld(in + ob);
     }
   }
 #pragma unroll
@@ -372,7 +374,6 @@ __device__ __forceinline__ void c2r_rows(const RowArgs<T>& A, long long row0, cx
   lds_fft<T, N, NL, LS, 1>(buf, twl);
   constexpr int VEC = 16 / (int)sizeof(TOUT);
   constexpr int NV = 2 * NL * N / VEC;
-  struct alignas(16) V { TOUT x[VEC]; };
   for (int e = threadIdx.x; e < NV; e += PSD_NT) {
     const int rr = (e * VEC) / N, col = e * VEC - rr * N;
     const long long gr = row0 + rr;
@@ -380,14 +381,14 @@ __device__ __forceinline__ void c2r_rows(const RowArgs<T>& A, long long row0, cx
     long long row;
     const int fld = row_field(gr, A.rpf, row);
     const T* src = (const T*)(buf + (rr >> 1) * LS + pidx(col)) + (rr & 1);
-    V out;
+    gvec<TOUT, VEC> out;
     double part = 0.0;
 #pragma unroll
     for (int q = 0; q < VEC; ++q) {
-      out.x[q] = (TOUT)src[2 * q];
-      part += (double)out.x[q];
+      out[q] = (TOUT)src[2 * q];
+      part += (double)out[q];
     }
-    *(V*)((TOUT*)A.out(fld) + row * N + col) = out;
+    *(PSD_GLOBAL gvec<TOUT, VEC>*)(gmem((TOUT*)A.out(fld)) + row * N + col) = out;
     fsum[0] += fld == 0 ? part : 0.0;
     fsum[1] += fld == 1 ? part : 0.0;
     fsum[2] += fld == 2 ? part : 0.0;
@@ -421,7 +422,7 @@ __device__ __forceinline__ void col_load(const cx<T>* base, const ColSet& cs, lo
     const int ft = e / W;
     const int t = ft % N, f = ft / N;
     regs[it] = mk(T(0), T(0));
-    if ((NE % PSD_NT == 0 || e < NE) && live) regs[it] = base[f * fstride + coff + t * cs.lstride];
+    if ((NE % PSD_NT == 0 || e < NE) && live) regs[it] = gld(base + f * fstride + coff + t * cs.lstride);
   }
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
@@ -446,7 +447,7 @@ __device__ __forceinline__ void col_store(cx<T>* base, const ColSet& cs, long lo
   for (int e = threadIdx.x; e < NF * W * N; e += PSD_NT) {
     const int ft = e / W;
     const int t = ft % N, f = ft / N;
-    base[f * fstride + coff + t * cs.lstride] = buf[(f * W + c) * LS + pidx(t)];
+    gst(base + f * fstride + coff + t * cs.lstride, buf[(f * W + c) * LS + pidx(t)]);
   }
 }
 

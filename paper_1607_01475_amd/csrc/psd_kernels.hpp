@@ -124,8 +124,12 @@ __global__ __launch_bounds__(PSD_NT) void k_ls2d(const Inst* __restrict__ insts,
     for (int k = 0; k < 8; ++k) I.part_ls[8 * t.slot + k] = acc[k];
 }
 
+// Register budget of the 3D line search: PSD_LS3D_WAVES waves per SIMD
+#ifndef PSD_LS3D_WAVES
+#define PSD_LS3D_WAVES 1
+#endif
 template <typename TD, int MODE>
-__global__ __launch_bounds__(PSD_NT) void k_ls3d(const Inst* __restrict__ insts,
+__global__ __launch_bounds__(PSD_NT) __attribute__((amdgpu_waves_per_eu(PSD_LS3D_WAVES))) void k_ls3d(const Inst* __restrict__ insts,
                                                  const Task2* __restrict__ tasks) {
   extern __shared__ double smem[];
   const Task2 t = tasks[blockIdx.x];
@@ -392,7 +396,7 @@ __device__ __forceinline__ void fused_col(const Inst& I, const Task2& t, cx<T>* 
   __syncthreads();
   lds_fft<T, N, NFI * W, LS, -1>(buf, twl);
   const double s = I.s, se2 = I.se2, inv = I.inv_ntot;
-  const double* S = I.S;
+  const PSD_GLOBAL double* S = gmem(I.S);
   // wave numbers of this thread's column: kx, and ky in 3D (2D: ky = line index)
   const int c = threadIdx.x % W;
   const bool live = c < cs.ncols;

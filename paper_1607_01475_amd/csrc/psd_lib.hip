@@ -363,8 +363,9 @@ static void build_tile_tasks(psd_handle* h) {
           }
       } else {
         const int z = std::min(zc, I.n);
+        const int ty = T3Y;   // tile height of the residual and line search
         for (int z0 = 0; z0 < I.n; z0 += z)
-          for (int y0 = 0; y0 < I.n; y0 += T3Y)
+          for (int y0 = 0; y0 < I.n; y0 += ty)
             for (int x0 = 0; x0 < I.n; x0 += T3X) {
               Task2 t{}; t.inst = b; t.a = x0; t.b = y0; t.c = z0; t.slot = slot++;
               h->hT.push_back(t);

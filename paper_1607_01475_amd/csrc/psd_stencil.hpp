@@ -610,8 +610,8 @@ struct L3Prefetch {
 template <typename TD, int MODE>
 struct Ls3March {
   const Inst& I;
-  const double* __restrict__ u;
-  const TD* __restrict__ d;
+  const PSD_GLOBAL double* u;
+  const PSD_GLOBAL TD* d;
   double* ub;
   double* db;
   double alpha, ih2;
@@ -626,8 +626,8 @@ struct Ls3March {
 
   __device__ __forceinline__ Ls3March(const Inst& I_, int x0, int y0, int z0_, double* lds) : I(I_) {
     const SolveState* st = I.st;
-    u = I.u[st->iter & 1];
-    d = (const TD*)I.d;
+    u = gmem((const double*)I.u[st->iter & 1]);
+    d = gmem((const TD*)I.d);
     alpha = (MODE == 2) ? st->x : 0.0;
     ub = lds;
     db = lds + 3 * L3_P;
@@ -643,7 +643,7 @@ struct Ls3March {
     ring = tid < L3_RING ? r3_lring_pos(tid) : c;   // same ring shape as a Laplacian plane
     const int rey = ring / L3_W, rex = ring - rey * L3_W;
     own_xy = wrapi(x0 + tx, n) + (long long)n * wrapi(y0 + ty, n);
-    ring_xy = wrapi(x0 - 1 + rex, n) + (long long)n * wrapi(y0 - 1 + rey, n);
+    ring_xy = tid < L3_RING ? wrapi(x0 - 1 + rex, n) + (long long)n * wrapi(y0 - 1 + rey, n) : own_xy;
 #pragma unroll
     for (int k = 0; k < 3; ++k) dcol[k] = 0.0;
 #pragma unroll
@@ -658,12 +658,12 @@ struct Ls3March {
   template <int B>
   __device__ __forceinline__ void fetch(int z) {
     const long long zo = (long long)wrapi(z, n) * nn;
+    // ring loads on every thread (non-ring threads re-read their own cell)
+    // and a fetch in every step: a fixed number of global loads per step
     pf[B].u_own = u[zo + own_xy];
     pf[B].d_own = d[zo + own_xy];
-    if (tid < L3_RING) {
-      pf[B].u_ring = u[zo + ring_xy];
-      pf[B].d_ring = d[zo + ring_xy];
-    }
+    pf[B].u_ring = u[zo + ring_xy];
+    pf[B].d_ring = d[zo + ring_xy];
   }
 
   template <int S, int B>
@@ -708,7 +708,7 @@ struct Ls3March {
     constexpr int SM = Q % 3, SK = (Q + 1) % 3, SN = (Q + 2) % 3;
     constexpr int RK = (Q + 1) & 1, RN = Q & 1;
     put<SN, 0>();
-    if (k + 1 < z1) fetch<0>(k + 2);
+    fetch<0>(k + 2);   // planes past the chunk are read and never used
     __syncthreads();
     partials<SN, RN>();
     if (k < z1 && own) {
