@@ -195,6 +195,7 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="fp64,mixed")
+    ap.add_argument("--chunk", type=int, default=4, help="PSD iterations per HIP graph replay")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 512 MiB device copy (reference for HBM counters)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
@@ -234,8 +235,8 @@ def main():
         log("bench: FP64 form (host-driven loop)")
         res["fp64"] = run_form(psd, torch, P, f, "fp64", 0, args.steps, args.warmup)
     if "mixed" in forms:
-        log("bench: mixed form (FP32 FFT, FP64 residual, HIP graph chunk 4)")
-        res["mixed"] = run_form(psd, torch, P, f, "mixed", 4, args.steps, args.warmup)
+        log(f"bench: mixed form (FP32 FFT, FP64 residual, HIP graph chunk {args.chunk})")
+        res["mixed"] = run_form(psd, torch, P, f, "mixed", args.chunk, args.steps, args.warmup)
         log("bench: mixed form, host-driven with per-kernel HIP events (roofline)")
         res["mixed_stream"] = run_form(psd, torch, P, f, "mixed", 0, args.steps, 0)
     head = res.get("mixed", res.get("fp64"))
@@ -295,7 +296,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"3D fourth-order PSD, p=4, {w.n}^3, [0,12.8]^3, s=0.01, eps=0.1, "
                                f"tol 1e-10, seeded Fourier field |k|<=12",
-                   "form": "mixed precision + HIP graph (chunk 4)" if head_mixed else "fp64",
+                   "form": f"mixed precision + HIP graph (chunk {args.chunk})" if head_mixed else "fp64",
                    "iters_per_solve": it_med},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -124,20 +124,16 @@ __global__ __launch_bounds__(PSD_NT) void k_ls2d(const Inst* __restrict__ insts,
     for (int k = 0; k < 8; ++k) I.part_ls[8 * t.slot + k] = acc[k];
 }
 
-// Register budget of the 3D line search: PSD_LS3D_WAVES waves per SIMD
-#ifndef PSD_LS3D_WAVES
-#define PSD_LS3D_WAVES 1
-#endif
-template <typename TD, int MODE>
-__global__ __launch_bounds__(PSD_NT) __attribute__((amdgpu_waves_per_eu(PSD_LS3D_WAVES))) void k_ls3d(const Inst* __restrict__ insts,
+template <typename TD, int MODE, int TX>
+__global__ __launch_bounds__(PSD_NT) void k_ls3d(const Inst* __restrict__ insts,
                                                  const Task2* __restrict__ tasks) {
   extern __shared__ double smem[];
   const Task2 t = tasks[blockIdx.x];
   const Inst& I = insts[t.inst];
   if (I.st->done || (MODE == 2 && I.st->ls_phase == 2)) return;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  ls3d_tile<TD, MODE>(I, t.a, t.b, t.c, smem, acc);
-  block_reduce<8, 0>(acc, smem + L3_LDS);
+  ls3d_tile<TD, MODE, TX>(I, t.a, t.b, t.c, smem, acc);
+  block_reduce<8, 0>(acc, smem + L3Shape<TX>::LDS);
   if (threadIdx.x == 0)
     for (int k = 0; k < 8; ++k) I.part_ls[8 * t.slot + k] = acc[k];
 }

@@ -109,6 +109,7 @@ struct psd_handle_s {
   bool adj_alloc = false;
   // tuning (autotuner or defaults)
   int tune_zc_res = T3Z_RES, tune_zc_ls = T3Z_LS;
+  int ls_tx = L3_TX_NARROW;   // 3D line-search tile width (wide when every n >= 64)
   bool tune_xcd_res = false, tune_xcd_ls = false;
   size_t dT_cap = 0;
   std::string err;
@@ -363,10 +364,10 @@ static void build_tile_tasks(psd_handle* h) {
           }
       } else {
         const int z = std::min(zc, I.n);
-        const int ty = T3Y;   // tile height of the residual and line search
+        const int tx = pass == 0 ? T3X : h->ls_tx, ty = pass == 0 ? T3Y : PSD_NT / h->ls_tx;   // tile shape
         for (int z0 = 0; z0 < I.n; z0 += z)
           for (int y0 = 0; y0 < I.n; y0 += ty)
-            for (int x0 = 0; x0 < I.n; x0 += T3X) {
+            for (int x0 = 0; x0 < I.n; x0 += tx) {
               Task2 t{}; t.inst = b; t.a = x0; t.b = y0; t.c = z0; t.slot = slot++;
               h->hT.push_back(t);
             }
@@ -379,7 +380,9 @@ static void build_tile_tasks(psd_handle* h) {
     if (h->dim == 2)
       R.lds = pass == 0 ? (R2_LDS + 16) * sizeof(double) : (L2_LDS + 32) * sizeof(double);
     else
-      R.lds = pass == 0 ? (R3_LDS + 16) * sizeof(double) : (L3_LDS + 32) * sizeof(double);
+      R.lds = pass == 0 ? (R3_LDS + 16) * sizeof(double)
+                        : ((h->ls_tx == L3_TX_WIDE ? L3Shape<L3_TX_WIDE>::LDS : L3Shape<L3_TX_NARROW>::LDS) + 32) *
+                              sizeof(double);
   }
 }
 
@@ -524,9 +527,15 @@ static void run_ls(psd_handle* h, int mode) {
       else if (mode == 1) k_ls2d<TD, 1><<<nb, PSD_NT, lds, s>>>(h->dI, t);
       else k_ls2d<TD, 2><<<nb, PSD_NT, lds, s>>>(h->dI, t);
     } else {
-      if (mode == 0) k_ls3d<TD, 0><<<nb, PSD_NT, lds, s>>>(h->dI, t);
-      else if (mode == 1) k_ls3d<TD, 1><<<nb, PSD_NT, lds, s>>>(h->dI, t);
-      else k_ls3d<TD, 2><<<nb, PSD_NT, lds, s>>>(h->dI, t);
+      if (h->ls_tx == L3_TX_WIDE) {
+        if (mode == 0) k_ls3d<TD, 0, L3_TX_WIDE><<<nb, PSD_NT, lds, s>>>(h->dI, t);
+        else if (mode == 1) k_ls3d<TD, 1, L3_TX_WIDE><<<nb, PSD_NT, lds, s>>>(h->dI, t);
+        else k_ls3d<TD, 2, L3_TX_WIDE><<<nb, PSD_NT, lds, s>>>(h->dI, t);
+      } else {
+        if (mode == 0) k_ls3d<TD, 0, L3_TX_NARROW><<<nb, PSD_NT, lds, s>>>(h->dI, t);
+        else if (mode == 1) k_ls3d<TD, 1, L3_TX_NARROW><<<nb, PSD_NT, lds, s>>>(h->dI, t);
+        else k_ls3d<TD, 2, L3_TX_NARROW><<<nb, PSD_NT, lds, s>>>(h->dI, t);
+      }
     }
   }
   ProfScope ps(h, PSD_PASS_LS_FIN);
@@ -592,13 +601,37 @@ static psd_status solve_loop(psd_handle* h) {
       HIPCHK(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
       h->gchunk = chunk;
     }
+    // Replays are queued back to back and the host checks the device flag
+    // only after each batch.  The batch size comes from the residual decay
+    // observed so far (PSD converges linearly, Sec. 2.3): enough chunks to
+    // reach tol at the measured rate.  Extra replays cost only early exits.
     const int max_launch = h->opt.max_iter / chunk + 2;
-    for (int it = 0; it < max_launch; ++it) {
-      HIPCHK(hipGraphLaunch(h->gexec, h->stream));
+    std::vector<double> r_prev(h->batch);
+    std::vector<int> k_prev(h->batch);
+    for (int b = 0; b < h->batch; ++b) { r_prev[b] = h->hState[b].rinf; k_prev[b] = h->hState[b].iter; }
+    int launched = 0, nrep = 1;
+    while (launched < max_launch) {
+      for (int k = 0; k < nrep && launched < max_launch; ++k, ++launched)
+        HIPCHK(hipGraphLaunch(h->gexec, h->stream));
       psd_status st = read_states(h);
       if (st != PSD_OK) return st;
-
       if (all_done(h)) break;
+      double k_rem = 0.0;
+      for (int b = 0; b < h->batch; ++b) {
+        const SolveState& S = h->hState[b];
+        if (S.done) continue;
+        const int dk = S.iter - k_prev[b];
+        double need = chunk;
+        if (dk > 0 && S.rinf > 0.0 && r_prev[b] > S.rinf) {
+          const double rate = std::pow(S.rinf / r_prev[b], 1.0 / dk);   // per iteration
+          need = std::log(h->hI[b].tol / S.rinf) / std::log(rate);
+        }
+        k_rem = std::max(k_rem, need);
+        r_prev[b] = S.rinf;
+        k_prev[b] = S.iter;
+      }
+      nrep = (int)std::ceil(std::min(k_rem, (double)h->opt.max_iter) / chunk);
+      nrep = std::max(1, std::min(nrep, 8));
     }
     return PSD_OK;
   }
@@ -811,6 +844,9 @@ extern "C" psd_status psd_create(const psd_problem* probs, int batch, const psd_
   h->dim = probs[0].dim;
   h->order = probs[0].order;
   h->p_is_4 = probs[0].p == 4.0;
+  h->ls_tx = L3_TX_WIDE;
+  for (int b = 0; b < batch; ++b)
+    if (probs[b].n < L3_TX_WIDE) h->ls_tx = L3_TX_NARROW;
   h->opt = *opt;
   h->mixed = opt->precision == PSD_MIXED;
   h->probs.assign(probs, probs + batch);

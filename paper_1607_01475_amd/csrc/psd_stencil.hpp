@@ -588,12 +588,30 @@ __device__ void ls2d_tile(const Inst& I, int x0, int y0, double* lds, double (&a
   }
 }
 
-// 3D line-search sums: the same column tiling; own-column u (planes k,
-// k+1) and d (planes k-1, k, k+1) in registers, xy-halo of 3 planes of u and
-// d in LDS (halo 1), loads of plane k+2 issued before plane k is reduced.
-constexpr int L3_W = T3X + 2, L3_H = T3Y + 2, L3_P = L3_W * L3_H;
-constexpr int L3_RING = L3_P - T3X * T3Y;   // 84
-constexpr int L3_LDS = 6 * L3_P;            // u: 3 planes, d: 3 planes
+// 3D line-search sums: a TX x (256/TX) column tile (one column per thread;
+// TX = 64 where every grid has n >= 64, else 32: wider tiles need fewer
+// single-element halo loads per plane); own-column u (planes k, k+1) and d
+// (planes k-1, k, k+1) in registers, xy-halo of 3 planes of u and d in LDS
+// (halo 1), loads of plane k+2 issued before plane k is reduced.
+template <int TX>
+struct L3Shape {
+  static constexpr int TY = PSD_NT / TX;
+  static constexpr int W = TX + 2, H = TY + 2, P = W * H;
+  static constexpr int RING = P - TX * TY;   // halo cells of a plane
+  static constexpr int LDS = 6 * P;          // u: 3 planes, d: 3 planes
+  static_assert(RING <= PSD_NT, "ring size");
+  // position in a plane buffer of halo cell number t (< RING)
+  static __device__ __forceinline__ int ring_pos(int t) {
+    if (t < 2 * W) {
+      const int r = t / W, lx = t - r * W;
+      return (r == 0 ? 0 : H - 1) * W + lx;
+    }
+    const int q = t - 2 * W;
+    const int ly = 1 + (q >> 1);
+    return ly * W + ((q & 1) ? W - 1 : 0);
+  }
+};
+constexpr int L3_TX_WIDE = 64, L3_TX_NARROW = 32;
 
 template <typename TD>
 struct L3Prefetch {
@@ -607,8 +625,10 @@ struct L3Prefetch {
 // planes' partials, kept scaled by 4h and rescaled once at the end) and the
 // Laplacian of d at plane k.  As in the residual, six steps are unrolled with
 // compile-time buffer indices; steps past the chunk add nothing.
-template <typename TD, int MODE>
+template <typename TD, int MODE, int TX>
 struct Ls3March {
+  using SH = L3Shape<TX>;
+  static constexpr int L3_W = SH::W, L3_P = SH::P, L3_RING = SH::RING;
   const Inst& I;
   const PSD_GLOBAL double* u;
   const PSD_GLOBAL TD* d;
@@ -637,10 +657,10 @@ struct Ls3March {
     z0 = z0_;
     z1 = min(z0 + I.zchunk_ls, n);
     tid = threadIdx.x;
-    const int tx = tid % T3X, ty = tid / T3X;
+    const int tx = tid % TX, ty = tid / TX;
     own = x0 + tx < n && y0 + ty < n;
     c = (ty + 1) * L3_W + tx + 1;
-    ring = tid < L3_RING ? r3_lring_pos(tid) : c;   // same ring shape as a Laplacian plane
+    ring = tid < L3_RING ? SH::ring_pos(tid) : c;
     const int rey = ring / L3_W, rex = ring - rey * L3_W;
     own_xy = wrapi(x0 + tx, n) + (long long)n * wrapi(y0 + ty, n);
     ring_xy = tid < L3_RING ? wrapi(x0 - 1 + rex, n) + (long long)n * wrapi(y0 - 1 + rey, n) : own_xy;
@@ -738,10 +758,10 @@ struct Ls3March {
   }
 };
 
-template <typename TD, int MODE>
+template <typename TD, int MODE, int TX>
 __device__ __forceinline__ void ls3d_tile(const Inst& I, int x0, int y0, int z0, double* lds,
                                           double (&acc)[8]) {
-  Ls3March<TD, MODE> m(I, x0, y0, z0, lds);
+  Ls3March<TD, MODE, TX> m(I, x0, y0, z0, lds);
   m.run();
   // vertex sums were taken with gradients scaled by 4h: undo once
   const double qh = 0.25 * I.inv_h;

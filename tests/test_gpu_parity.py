@@ -94,7 +94,9 @@ def test_residual_parity_order6(psd):
 # solve parity (FP64)
 # --------------------------------------------------------------------------
 SOLVES = [(2, 64, 4.0, 12.8, 0.01, 0.1), (2, 96, 4.0, 12.8, 0.01, 0.1), (2, 128, 3.0, 25.6, 0.005, 0.05),
-          (3, 32, 4.0, 12.8, 0.01, 0.1), (3, 48, 4.0, 12.8, 0.01, 0.1)]
+          (3, 32, 4.0, 12.8, 0.01, 0.1), (3, 48, 4.0, 12.8, 0.01, 0.1),
+          # wide (64-column) line-search tiles, one of them partial
+          (3, 96, 4.0, 12.8, 0.01, 0.1)]
 
 
 @pytest.mark.parametrize("dim,n,p,L,s,eps", SOLVES)
