@@ -165,6 +165,121 @@ def run_form(psd, torch, P, f, precision, chunk, steps, warmup, tol=1e-10):
     return dict(times=times, iters=iters, passes=agg, u=u.clone(), res_inf=st.res_inf, tuning=tuning)
 
 
+def timed(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ts, outs = [], []
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs.append(fn())
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return ts, outs
+
+
+def bench_c2(psd, torch, np, psd_inputs, args):
+    """2D fourth order, 1024^2, p = 4 and p = 3: time to 1e-10 of the FP64 and
+    the mixed form (HIP graph for p = 4; general p runs the host-driven root
+    rule)."""
+    out = {}
+    for p in (4.0, 3.0):
+        w = psd_inputs.config2(p)
+        f = torch.from_numpy(w.f).to("cuda")
+        P = psd.Problem(2, w.n, w.L, 4, w.p, w.s, w.eps)
+        for prec in ("fp64", "mixed"):
+            chunk = args.chunk if (prec == "mixed" and p == 4.0) else 0
+            with psd.Solver(P, tol=1e-10, max_iter=500, precision=prec, graph_chunk=chunk) as S:
+                u = torch.zeros_like(f)
+
+                def run():
+                    u.zero_()
+                    return S.solve([f], [u])[0]
+                ts, sts = timed(torch, run, args.steps, args.warmup)
+            st = sts[-1]
+            if st.status != 0:
+                raise RuntimeError(f"C2 p={p} {prec}: {st}")
+            key = f"p{p:g}_{prec}"
+            out[key] = {"time_to_1e-10_ms": round(1e3 * float(np.median(ts)), 3), "iters": st.iters,
+                        "iters_per_s": round(st.iters / float(np.median(ts)), 1)}
+    head = out["p4_mixed"]
+    return {"metric": "time-to-1e-10 residual & PSD iters/s, 2D 1024^2 fourth order (p=4, p=3)",
+            "value": head["iters_per_s"], "unit": "PSD iters/s", "ms_per_step": head["time_to_1e-10_ms"],
+            "higher_is_better": True, "dtype": "f64 (f32 FFT preconditioner)", "data": "synthetic",
+            "config": {"workload": "2D fourth-order PSD, 1024^2, [0,25.6]^2, s=0.005, eps=0.05, tol 1e-10, "
+                                   "seeded Fourier field |k|<=8 + 1e-3 white noise"},
+            "forms": out}
+
+
+def bench_c4(psd, torch, np, psd_inputs, args):
+    """64 sixth-order (u, w) instances of uneven sizes in one handle, mixed
+    precision, HIP graph: time until every instance reaches 1e-10."""
+    ws = psd_inputs.config4()
+    P = [psd.Problem(2, w.n, w.L, 6, w.p, w.s, w.eps, w.lam) for w in ws]
+    fs = [torch.from_numpy(w.f).to("cuda") for w in ws]
+    gs = [torch.from_numpy(w.g).to("cuda") for w in ws]
+    u0 = [float(w.g.mean()) for w in ws]
+    with psd.Solver(P, tol=1e-10, max_iter=500, precision="mixed", graph_chunk=args.chunk,
+                    autotune=True) as S:
+        us = [torch.empty_like(f) for f in fs]
+        wv = [torch.zeros_like(f) for f in fs]
+
+        def run():
+            for u, m in zip(us, u0):
+                u.fill_(m)
+            return S.solve(fs, us, g=gs, w=wv)
+        ts, outs = timed(torch, run, args.steps, args.warmup)
+    stats = outs[-1]
+    if any(st.status != 0 for st in stats):
+        raise RuntimeError("C4: an instance did not converge")
+    t = float(np.median(ts))
+    its = [st.iters for st in stats]
+    cells = sum(w.n * w.n for w in ws)
+    cell_its = sum(w.n * w.n * st.iters for w, st in zip(ws, stats))
+    return {"metric": "batched sixth-order PSD: instance-iterations/s, 64 instances of 128^2..512^2",
+            "value": round(sum(its) / t, 1), "unit": "instance PSD iters/s", "ms_per_step": round(1e3 * t, 3),
+            "higher_is_better": True, "dtype": "f64 (f32 FFT preconditioner)", "data": "synthetic",
+            "config": {"workload": "64 x 2D sixth-order (u,w) PSD, n from {128,192,256,384,512} by seed, "
+                                   "p=4, lambda=1, s=0.02, eps=0.1, tol 1e-10, mixed precision, HIP graph"},
+            "iters_min": min(its), "iters_max": max(its), "cells": cells,
+            "cell_iters_per_s": round(cell_its / t, 1)}
+
+
+def bench_c5(psd, torch, np, psd_inputs, args):
+    """Adjoint of 8 converged 128^3 solves: forward solve + Hessian-CG adjoint
+    for J = 0.5 ||u* - u_target||^2 (gradients w.r.t. f, s, eps)."""
+    ws = psd_inputs.config5()
+    w0 = ws[0]
+    P = [psd.Problem(3, w.n, w.L, 4, w.p, w.s, w.eps) for w in ws]
+    fs = [torch.from_numpy(w.f).to("cuda") for w in ws]
+    uts = [torch.from_numpy(w.u_target).to("cuda") for w in ws]
+    with psd.Solver(P, tol=1e-10, max_iter=500, precision="mixed", graph_chunk=args.chunk) as S:
+        us = [torch.zeros_like(f) for f in fs]
+
+        def fwd():
+            for u in us:
+                u.zero_()
+            return S.solve(fs, us)
+
+        def adj():
+            g = [u - ut for u, ut in zip(us, uts)]
+            return S.adjoint(us, g, rtol=1e-10, max_iter=500)
+        tf, sts = timed(torch, fwd, args.steps, args.warmup)
+        ta, adjs = timed(torch, adj, args.steps, args.warmup)
+    if any(st.status != 0 for st in sts[-1]):
+        raise RuntimeError("C5: a forward solve did not converge")
+    cg = adjs[-1][3]
+    t_f, t_a = float(np.median(tf)), float(np.median(ta))
+    return {"metric": "adjoint gradient (f, s, eps) of 8 converged 128^3 solves: time per gradient",
+            "value": round(1e3 * (t_f + t_a), 3), "unit": "ms", "ms_per_step": round(1e3 * (t_f + t_a), 3),
+            "higher_is_better": False, "dtype": "f64 (f32 FFT preconditioner)", "data": "synthetic",
+            "config": {"workload": f"8 x 3D fourth-order PSD, {w0.n}^3, p=4, s=0.01, eps=0.1, tol 1e-10; "
+                                   "loss 0.5||u*-u_target||^2; Hessian CG rtol 1e-10"},
+            "forward_ms": round(1e3 * t_f, 3), "adjoint_ms": round(1e3 * t_a, 3),
+            "forward_iters": [st.iters for st in sts[-1]], "cg_iters": cg}
+
+
 def cpu_baseline(f_np, n, L, p, s, eps):
     """Time one PSD iteration of the plain FP64 CPU oracle on the same
     256^3 workload: preconditioner application, line-search coefficients and
@@ -196,6 +311,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--chunk", type=int, default=4, help="PSD iterations per HIP graph replay")
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "c5"],
+                    help="c3: the 256^3 line (default); c2: 2D 1024^2; c4: 64-instance sixth-order "
+                         "batch; c5: adjoint of 8 x 128^3")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 512 MiB device copy (reference for HBM counters)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
@@ -218,6 +336,12 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
     psd.load_library()
+    if args.workload != "c3":
+        fn = {"c2": bench_c2, "c4": bench_c4, "c5": bench_c5}[args.workload]
+        out = fn(psd, torch, np, psd_inputs, args)
+        out.update({"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "vs_baseline": None})
+        print(json.dumps(out), flush=True)
+        return
     if args.copy_calibration:
         a = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
