@@ -64,7 +64,7 @@ __global__ __launch_bounds__(PSD_NT) void k_res2d(const Inst* __restrict__ insts
 #ifndef PSD_RES3D_WAVES
 #define PSD_RES3D_WAVES 4
 #endif
-template <typename TD, typename TR, bool UPD, int PK>
+template <typename TD, typename TR, bool UPD, int PK, int TX>
 __global__ __launch_bounds__(PSD_NT) __attribute__((amdgpu_waves_per_eu(PSD_RES3D_WAVES))) void k_res3d(const Inst* __restrict__ insts,
                                                   const Task2* __restrict__ tasks) {
   extern __shared__ double smem[];
@@ -72,8 +72,8 @@ __global__ __launch_bounds__(PSD_NT) __attribute__((amdgpu_waves_per_eu(PSD_RES3
   const Inst& I = insts[t.inst];
   if (I.st->done) return;
   double acc[2] = {0.0, 0.0};
-  res3d_tile<TD, TR, UPD, false, PK>(I, t.a, t.b, t.c, smem, acc);
-  block_reduce<2, 1>(acc, smem + R3_LDS);
+  res3d_tile<TD, TR, UPD, false, PK, TX>(I, t.a, t.b, t.c, smem, acc);
+  block_reduce<2, 1>(acc, smem + R3Shape<TX>::LDS);
   if (threadIdx.x == 0) {
     I.part_res[2 * t.slot] = acc[0];
     I.part_res[2 * t.slot + 1] = acc[1];
@@ -564,7 +564,7 @@ __global__ __launch_bounds__(PSD_NT) void k_hess2d(const Inst* __restrict__ inst
   }
 }
 
-template <typename TR>
+template <typename TR, int TX>
 __global__ __launch_bounds__(PSD_NT) void k_hess3d(const Inst* __restrict__ insts,
                                                    const Task2* __restrict__ tasks) {
   extern __shared__ double smem[];
@@ -572,8 +572,8 @@ __global__ __launch_bounds__(PSD_NT) void k_hess3d(const Inst* __restrict__ inst
   const Inst& I = insts[t.inst];
   if (I.st->done) return;
   double acc[2] = {0.0, 0.0};
-  res3d_tile<double, TR, false, true, 0>(I, t.a, t.b, t.c, smem, acc);
-  block_reduce<2, 1>(acc, smem + R3H_LDS);
+  res3d_tile<double, TR, false, true, 0, TX>(I, t.a, t.b, t.c, smem, acc);
+  block_reduce<2, 1>(acc, smem + R3Shape<TX>::HLDS);
   if (threadIdx.x == 0) {
     I.part_res[2 * t.slot] = 0.0;
     I.part_res[2 * t.slot + 1] = acc[1];

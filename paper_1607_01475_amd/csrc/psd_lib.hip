@@ -364,7 +364,8 @@ static void build_tile_tasks(psd_handle* h) {
           }
       } else {
         const int z = std::min(zc, I.n);
-        const int tx = pass == 0 ? T3X : h->ls_tx, ty = pass == 0 ? T3Y : PSD_NT / h->ls_tx;   // tile shape
+        const int tx = pass == 0 ? R3_TX : h->ls_tx;   // tile shape tx x (256 / tx)
+        const int ty = PSD_NT / tx;
         for (int z0 = 0; z0 < I.n; z0 += z)
           for (int y0 = 0; y0 < I.n; y0 += ty)
             for (int x0 = 0; x0 < I.n; x0 += tx) {
@@ -380,7 +381,7 @@ static void build_tile_tasks(psd_handle* h) {
     if (h->dim == 2)
       R.lds = pass == 0 ? (R2_LDS + 16) * sizeof(double) : (L2_LDS + 32) * sizeof(double);
     else
-      R.lds = pass == 0 ? (R3_LDS + 16) * sizeof(double)
+      R.lds = pass == 0 ? (R3Shape<R3_TX>::LDS + 16) * sizeof(double)
                         : ((h->ls_tx == L3_TX_WIDE ? L3Shape<L3_TX_WIDE>::LDS : L3Shape<L3_TX_NARROW>::LDS) + 32) *
                               sizeof(double);
   }
@@ -480,6 +481,20 @@ static void run_fft(psd_handle* h, const FftTasks& F, int op, bool solver) {
   }
 }
 
+template <typename TD, typename TR, int TX>
+static void launch_res3d(int pk, bool upd, int n, size_t lds, hipStream_t s, const Inst* dI, const Task2* t) {
+  if (pk == 4) {
+    if (upd) k_res3d<TD, TR, true, 4, TX><<<n, PSD_NT, lds, s>>>(dI, t);
+    else k_res3d<TD, TR, false, 4, TX><<<n, PSD_NT, lds, s>>>(dI, t);
+  } else if (pk == 2) {
+    if (upd) k_res3d<TD, TR, true, 2, TX><<<n, PSD_NT, lds, s>>>(dI, t);
+    else k_res3d<TD, TR, false, 2, TX><<<n, PSD_NT, lds, s>>>(dI, t);
+  } else {
+    if (upd) k_res3d<TD, TR, true, 0, TX><<<n, PSD_NT, lds, s>>>(dI, t);
+    else k_res3d<TD, TR, false, 0, TX><<<n, PSD_NT, lds, s>>>(dI, t);
+  }
+}
+
 template <typename TD, typename TR>
 static void run_residual(psd_handle* h, bool upd) {
   hipStream_t s = h->stream;
@@ -496,18 +511,10 @@ static void run_residual(psd_handle* h, bool upd) {
         else k_res2d<TD, TR, 6, false><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
       }
     } else {
-      // exponent class of the flux (all instances share p)
+      // exponent class of the flux (all instances share p) and tile width
       const double p = h->hI[0].p;
-      if (p == 4.0) {
-        if (upd) k_res3d<TD, TR, true, 4><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
-        else k_res3d<TD, TR, false, 4><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
-      } else if (p == 2.0) {
-        if (upd) k_res3d<TD, TR, true, 2><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
-        else k_res3d<TD, TR, false, 2><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
-      } else {
-        if (upd) k_res3d<TD, TR, true, 0><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
-        else k_res3d<TD, TR, false, 0><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
-      }
+      const int pk = p == 4.0 ? 4 : (p == 2.0 ? 2 : 0);
+      launch_res3d<TD, TR, R3_TX>(pk, upd, n, h->res.lds, s, h->dI, t);
     }
   }
   ProfScope ps(h, upd ? PSD_PASS_RES_FIN : -1);
@@ -1273,7 +1280,7 @@ static psd_status adjoint_impl(psd_handle* h, const double* const* u_star, const
   const Task2* tt = h->dT + h->res.off;
   for (int it = 0; it < max_iter; ++it) {
     if (h->dim == 2) k_hess2d<TD, TR><<<h->res.cnt, PSD_NT, (R2_LDS + 16) * sizeof(double), s>>>(h->dI, tt);
-    else k_hess3d<TR><<<h->res.cnt, PSD_NT, (R3H_LDS + 16) * sizeof(double), s>>>(h->dI, tt);
+    else k_hess3d<TR, R3_TX><<<h->res.cnt, PSD_NT, (R3Shape<R3_TX>::HLDS + 16) * sizeof(double), s>>>(h->dI, tt);
     fin(2);
     vec(1);
     fin(3);

@@ -18,7 +18,7 @@ namespace psd {
 
 // tile shapes
 constexpr int T2X = 64, T2Y = 8;     // 2D: 512 cells, 2 per thread
-constexpr int T3X = 32, T3Y = 8;     // 3D: one (x,y) column per thread
+// 3D tiles: one (x,y) column per thread; shapes in R3Shape / L3Shape
 // 3D: planes marched per block.  The residual runs z-chunk + 2 steps, the
 // line search z-chunk steps, both in groups of six: chunks with 6 | steps
 // waste nothing.  Defaults and the autotuner's candidates follow that rule.
@@ -183,48 +183,55 @@ __device__ void res2d_tile(const Inst& I, int x0, int y0, double* lds, double (&
 // vertices, and div = (P_below + P_above + Q_above - Q_below) / (4h).
 // The global loads of plane k+3 are issued before plane k is computed.
 // ===========================================================================
-constexpr int R3_VW = T3X + 4, R3_VH = T3Y + 4, R3_VP = R3_VW * R3_VH;
-constexpr int R3_LW = T3X + 2, R3_LH = T3Y + 2, R3_LP = R3_LW * R3_LH;
-constexpr int R3_FW = T3X + 1, R3_FH = T3Y + 1, R3_FP = R3_FW * R3_FH;
-constexpr int R3_VRING = R3_VP - T3X * T3Y;   // 176 halo cells of a v plane
-constexpr int R3_LRING = R3_LP - T3X * T3Y;   // 84 halo cells of a Laplacian plane
-constexpr int R3_FRING = R3_FP - T3X * T3Y;   // 41 halo vertices of a flux plane
-constexpr int R3_LDS = 3 * R3_VP + 2 * R3_LP + 3 * R3_FP;
-constexpr int R3H_LDS = R3_LDS + 3 * R3_VP;   // Hessian mode: 3 more planes (u*)
-static_assert(R3_VRING <= PSD_NT && R3_LRING <= PSD_NT && R3_FRING <= PSD_NT, "ring sizes");
-
-// position in the v plane buffer of halo cell number t (0 <= t < R3_VRING)
-__device__ __forceinline__ int r3_vring_pos(int t) {
-  if (t < 4 * R3_VW) {                          // rows 0, 1, VH-2, VH-1
-    const int r = t / R3_VW, ex = t - r * R3_VW;
-    const int ey = r < 2 ? r : r + (R3_VH - 4);
-    return ey * R3_VW + ex;
+// Tile shape of the 3D residual: TX x (256 / TX) columns.  TX = 32 (32 x 8);
+// 64 x 4 was measured slower at 256^3 (the wider halo rows cost more than the
+// fewer single-element halo loads save).
+template <int TX>
+struct R3Shape {
+  static constexpr int TY = PSD_NT / TX;
+  static constexpr int VW = TX + 4, VH = TY + 4, VP = VW * VH;   // v planes (halo 2)
+  static constexpr int LW = TX + 2, LH = TY + 2, LP = LW * LH;   // Laplacian planes (halo 1)
+  static constexpr int FW = TX + 1, FH = TY + 1, FP = FW * FH;   // vertex planes
+  static constexpr int VRING = VP - TX * TY;   // halo cells of a v plane
+  static constexpr int LRING = LP - TX * TY;   // halo cells of a Laplacian plane
+  static constexpr int FRING = FP - TX * TY;   // halo vertices of a flux plane
+  static constexpr int LDS = 3 * VP + 2 * LP + 3 * FP;
+  static constexpr int HLDS = LDS + 3 * VP;   // Hessian mode: 3 more planes (u*)
+  static_assert(VRING <= 2 * PSD_NT && LRING <= PSD_NT && FRING <= PSD_NT, "ring sizes");
+  // position in a v plane of halo cell number t (0 <= t < VRING)
+  static __device__ __forceinline__ int vring_pos(int t) {
+    if (t < 4 * VW) {                             // rows 0, 1, VH-2, VH-1
+      const int r = t / VW, ex = t - r * VW;
+      const int ey = r < 2 ? r : r + (VH - 4);
+      return ey * VW + ex;
+    }
+    const int q = t - 4 * VW;                     // columns 0, 1, VW-2, VW-1 of rows 2..VH-3
+    const int ey = 2 + (q >> 2), c = q & 3;
+    const int ex = c < 2 ? c : c + (VW - 4);
+    return ey * VW + ex;
   }
-  const int q = t - 4 * R3_VW;                  // columns 0, 1, VW-2, VW-1 of rows 2..VH-3
-  const int ey = 2 + (q >> 2), c = q & 3;
-  const int ex = c < 2 ? c : c + (R3_VW - 4);
-  return ey * R3_VW + ex;
-}
-// position in the Laplacian plane buffer of halo cell number t (< R3_LRING)
-__device__ __forceinline__ int r3_lring_pos(int t) {
-  if (t < 2 * R3_LW) {
-    const int r = t / R3_LW, lx = t - r * R3_LW;
-    return (r == 0 ? 0 : R3_LH - 1) * R3_LW + lx;
+  // position in a Laplacian plane of halo cell number t (< LRING)
+  static __device__ __forceinline__ int lring_pos(int t) {
+    if (t < 2 * LW) {
+      const int r = t / LW, lx = t - r * LW;
+      return (r == 0 ? 0 : LH - 1) * LW + lx;
+    }
+    const int q = t - 2 * LW;
+    const int ly = 1 + (q >> 1);
+    return ly * LW + ((q & 1) ? LW - 1 : 0);
   }
-  const int q = t - 2 * R3_LW;
-  const int ly = 1 + (q >> 1);
-  return ly * R3_LW + ((q & 1) ? R3_LW - 1 : 0);
-}
-// position in the flux plane buffer of halo vertex number t (< R3_FRING)
-__device__ __forceinline__ int r3_fring_pos(int t) {
-  if (t < R3_FW) return t;                      // row y0-1
-  return (t - R3_FW + 1) * R3_FW;               // column x0-1, rows 1..FH-1
-}
+  // position in a flux plane of halo vertex number t (< FRING)
+  static __device__ __forceinline__ int fring_pos(int t) {
+    if (t < FW) return t;                         // row y0-1
+    return (t - FW + 1) * FW;                     // column x0-1, rows 1..FH-1
+  }
+};
+constexpr int R3_TX = 32;
 
 template <typename TD>
 struct R3Prefetch {
-  double u_own, u_ring;
-  TD d_own, d_ring;
+  double u_own, u_ring, u_ring2;
+  TD d_own, d_ring, d_ring2;
 };
 
 // Per-plane partial sums of the 2x2 cells (c00, c10, c01, c11) below or
@@ -284,9 +291,14 @@ __device__ __forceinline__ double flux_rr(double g2, double p) {
 // are unrolled with compile-time buffer indices (no register copies, no
 // modulo arithmetic); a block runs whole groups of six steps, steps past the
 // chunk write nothing.
-template <typename TD, typename TR, bool UPD, bool HESS, int PK>
+template <typename TD, typename TR, bool UPD, bool HESS, int PK, int TX>
 struct Res3March {
   static constexpr bool LOADD = UPD || HESS;
+  using SH = R3Shape<TX>;
+  static constexpr int R3_VW = SH::VW, R3_VP = SH::VP, R3_LW = SH::LW, R3_LP = SH::LP;
+  static constexpr int R3_FW = SH::FW, R3_FP = SH::FP;
+  static constexpr int R3_VRING = SH::VRING, R3_LRING = SH::LRING, R3_FRING = SH::FRING;
+  static constexpr bool RING2 = SH::VRING > PSD_NT;   // second halo cell on the first threads
   const Inst& I;
   const double* __restrict__ u;
   double* __restrict__ uo;
@@ -301,7 +313,8 @@ struct Res3March {
   long long nn;             // n*n
   long long own_xy, ring_xy, fcol;
   int n, z0, z1, tid;
-  int vown, lown, fown, vring, lring, fring, fring_c;
+  int vown, lown, fown, vring, vring2, lring, fring, fring_c;
+  long long ring2_xy;
   long long gout;           // output offset of the own cell in plane 0
   bool own;
   // rotating registers
@@ -324,7 +337,7 @@ struct Res3March {
     fA = lb + 2 * R3_LP;
     fB = fA + R3_FP;
     fC = fB + R3_FP;
-    sb = lds + R3_LDS;
+    sb = lds + SH::LDS;
     n = I.n;
     nn = (long long)n * n;
     const double ih = I.inv_h, qh = 0.25 * ih;
@@ -337,19 +350,22 @@ struct Res3March {
     z0 = z0_;
     z1 = min(z0 + I.zchunk_res, n);
     tid = threadIdx.x;
-    const int tx = tid % T3X, ty = tid / T3X;
+    const int tx = tid % TX, ty = tid / TX;
     vown = (ty + 2) * R3_VW + tx + 2;
     lown = (ty + 1) * R3_LW + tx + 1;
     fown = (ty + 1) * R3_FW + tx + 1;
-    vring = tid < R3_VRING ? r3_vring_pos(tid) : vown;
+    vring = tid < R3_VRING ? SH::vring_pos(tid) : vown;
     const int rey = vring / R3_VW, rex = vring - rey * R3_VW;
-    lring = tid < R3_LRING ? r3_lring_pos(tid) : lown;
-    fring = tid < R3_FRING ? r3_fring_pos(tid) : fown;
+    vring2 = tid + PSD_NT < R3_VRING ? SH::vring_pos(tid + PSD_NT) : vown;
+    const int rey2 = vring2 / R3_VW, rex2 = vring2 - rey2 * R3_VW;
+    lring = tid < R3_LRING ? SH::lring_pos(tid) : lown;
+    fring = tid < R3_FRING ? SH::fring_pos(tid) : fown;
     fring_c = (fring / R3_FW + 1) * R3_VW + fring % R3_FW + 1;
     const int gx = x0 + tx, gy = y0 + ty;
     own = gx < n && gy < n;
     own_xy = wrapi(gx, n) + (long long)n * wrapi(gy, n);
     ring_xy = wrapi(x0 - 2 + rex, n) + (long long)n * wrapi(y0 - 2 + rey, n);
+    ring2_xy = wrapi(x0 - 2 + rex2, n) + (long long)n * wrapi(y0 - 2 + rey2, n);
     fcol = own_xy;
     gout = gx + (long long)n * gy;
     acc0 = 0.0;
@@ -372,6 +388,10 @@ struct Res3March {
       pf[B].u_ring = u[zo + ring_xy];
       if (LOADD) pf[B].d_ring = d[zo + ring_xy];
     }
+    if (RING2 && tid + PSD_NT < R3_VRING) {
+      pf[B].u_ring2 = u[zo + ring2_xy];
+      if (LOADD) pf[B].d_ring2 = d[zo + ring2_xy];
+    }
   }
 
   // put the plane prefetched in buffer B into v slot S (and u* slot S); returns own v
@@ -382,10 +402,13 @@ struct Res3March {
     const double vo = UPD ? pf.u_own + alpha * (double)pf.d_own : pf.u_own;
     vn[vown] = vo;
     if (tid < R3_VRING) vn[vring] = UPD ? pf.u_ring + alpha * (double)pf.d_ring : pf.u_ring;
+    if (RING2 && tid + PSD_NT < R3_VRING)
+      vn[vring2] = UPD ? pf.u_ring2 + alpha * (double)pf.d_ring2 : pf.u_ring2;
     if (HESS) {
       double* sn = sb + S * R3_VP;
       sn[vown] = (double)pf.d_own;
       if (tid < R3_VRING) sn[vring] = (double)pf.d_ring;
+      if (RING2 && tid + PSD_NT < R3_VRING) sn[vring2] = (double)pf.d_ring2;
       sc[S] = (double)pf.d_own;
     }
     return vo;
@@ -508,12 +531,12 @@ struct Res3March {
   }
 };
 
-template <typename TD, typename TR, bool UPD, bool HESS, int PK>
+template <typename TD, typename TR, bool UPD, bool HESS, int PK, int TX>
 __device__ __forceinline__ void res3d_tile(const Inst& I, int x0, int y0, int z0, double* lds,
                                            double (&acc)[2]) {
   static_assert(!(HESS && UPD), "no update in Hessian mode");
   static_assert(!HESS || sizeof(TD) == 8, "u* is FP64");
-  Res3March<TD, TR, UPD, HESS, PK> m(I, x0, y0, z0, lds);
+  Res3March<TD, TR, UPD, HESS, PK, TX> m(I, x0, y0, z0, lds);
   m.run();
   acc[0] = m.acc0;
   acc[1] = m.acc1;
