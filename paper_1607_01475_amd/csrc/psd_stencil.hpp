@@ -300,9 +300,12 @@ struct Res3March {
   static constexpr int R3_VRING = SH::VRING, R3_LRING = SH::LRING, R3_FRING = SH::FRING;
   static constexpr bool RING2 = SH::VRING > PSD_NT;   // second halo cell on the first threads
   const Inst& I;
-  const double* __restrict__ u;
-  double* __restrict__ uo;
-  const TD* __restrict__ d;
+  const PSD_GLOBAL double* u;
+  PSD_GLOBAL double* uo;
+  const PSD_GLOBAL TD* d;
+  const PSD_GLOBAL double* f;
+  PSD_GLOBAL TR* r;
+  PSD_GLOBAL double* hp;   // Hessian mode output
   double* vb;   // 3 v planes
   double* lb;   // 2 Laplacian planes
   double* fA;   // one vertex plane: A, B, C
@@ -329,9 +332,12 @@ struct Res3March {
     const SolveState* st = I.st;
     const int cur = st->iter & 1;
     alpha = UPD ? st->alpha : 0.0;
-    u = HESS ? I.adj_p : I.u[cur];
-    uo = I.u[cur ^ 1];
-    d = HESS ? (const TD*)I.adj_us : (const TD*)I.d;
+    u = gmem(HESS ? (const double*)I.adj_p : (const double*)I.u[cur]);
+    uo = gmem(I.u[cur ^ 1]);
+    d = gmem(HESS ? (const TD*)I.adj_us : (const TD*)I.d);
+    f = gmem(I.f);
+    r = gmem((TR*)I.r);
+    hp = gmem(I.adj_Hp);
     vb = lds;
     lb = vb + 3 * R3_VP;
     fA = lb + 2 * R3_LP;
@@ -446,7 +452,7 @@ struct Res3March {
     // plane j+2 = z0 + q sits in buffer q mod 2; refill it with plane j+4
     vc[S2] = put<S2, P0>();
     if (j + 2 < z1) fetch<P0>(j + 4);
-    if (!HESS && j + 1 >= z0 && j + 1 < z1) fv[P1] = I.f[fcol + nn * (j + 1)];
+    if (!HESS && j + 1 >= z0 && j + 1 < z1) fv[P1] = f[fcol + nn * (j + 1)];
     __syncthreads();
     const double* v0 = vb + S0 * R3_VP;
     const double* v1 = vb + S1 * R3_VP;
@@ -501,14 +507,14 @@ struct Res3March {
         const double v = vc[S0];
         if (HESS) {
           const double hx = v - s * div + se2 * l2;
-          I.adj_Hp[gi] = hx;
+          hp[gi] = hx;
           acc1 += v * hx;
         } else {
-          const double r = fv[P0] - (v - s * div + se2 * l2);
-          ((TR*)I.r)[gi] = (TR)r;
+          const double rr = fv[P0] - (v - s * div + se2 * l2);
+          r[gi] = (TR)rr;
           if (UPD) uo[gi] = v;
-          acc0 = fmax(acc0, fabs(r));
-          acc1 += r * r;
+          acc0 = fmax(acc0, fabs(rr));
+          acc1 += rr * rr;
         }
       }
       Pq[P0] = P;
