@@ -251,6 +251,55 @@ __device__ __forceinline__ void flat_reduce(const double* __restrict__ part, int
   __syncthreads();
 }
 
+// Two flat reductions (K1- and K2-wide sums of block partials) whose loads
+// are issued together, so that both cost one memory round trip.  Results in
+// thread 0.  scratch: (K1 + K2) * NT / 64 doubles.
+template <int K1, int K2, int NT>
+__device__ __forceinline__ void flat_reduce2(const double* __restrict__ p1, int n1,
+                                             const double* __restrict__ p2, int n2,
+                                             double (&o1)[K1], double (&o2)[K2], double* scratch) {
+  static_assert((K1 & (K1 - 1)) == 0 && (K2 & (K2 - 1)) == 0 && K1 <= PSD_WAVE && K2 <= PSD_WAVE, "K | 64");
+  constexpr int NW = NT / PSD_WAVE;
+  constexpr int U = 8;
+  const int tid = threadIdx.x, lane = tid & (PSD_WAVE - 1), wid = tid / PSD_WAVE;
+  const int t1 = K1 * n1, t2 = K2 * n2;
+  const int tmax = t1 > t2 ? t1 : t2;
+  double a = 0.0, b = 0.0;
+  for (int j0 = 0; j0 < tmax; j0 += U * NT) {
+    double v[U], w[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int j = j0 + q * NT + tid;
+      v[q] = j < t1 ? gmem(p1)[j] : 0.0;
+      w[q] = j < t2 ? gmem(p2)[j] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) { a += v[q]; b += w[q]; }
+  }
+#pragma unroll
+  for (int o = PSD_WAVE / 2; o >= K1; o >>= 1) a += __shfl_xor(a, o, PSD_WAVE);
+#pragma unroll
+  for (int o = PSD_WAVE / 2; o >= K2; o >>= 1) b += __shfl_xor(b, o, PSD_WAVE);
+  if (lane < K1) scratch[wid * K1 + lane] = a;
+  if (lane < K2) scratch[NW * K1 + wid * K2 + lane] = b;
+  __syncthreads();
+  if (tid == 0) {
+#pragma unroll
+    for (int k = 0; k < K1; ++k) {
+      double r = scratch[k];
+      for (int w2 = 1; w2 < NW; ++w2) r += scratch[w2 * K1 + k];
+      o1[k] = r;
+    }
+#pragma unroll
+    for (int k = 0; k < K2; ++k) {
+      double r = scratch[NW * K1 + k];
+      for (int w2 = 1; w2 < NW; ++w2) r += scratch[NW * K1 + w2 * K2 + k];
+      o2[k] = r;
+    }
+  }
+  __syncthreads();
+}
+
 // periodic index for offsets within one period (3D tiles: n >= 32 is
 // required so that every halo index lies in [-n, 2n))
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }

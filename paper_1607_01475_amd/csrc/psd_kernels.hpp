@@ -32,9 +32,12 @@ constexpr int row_lines() {
 // columns per block of a column pass: 128-byte segments where the LDS
 // footprint NF*W*fft_ls(N) complex plus N twiddles stays within 64 KB; a
 // power of two, so that a thread keeps one column
+#ifndef PSD_COL_BYTES
+#define PSD_COL_BYTES 128
+#endif
 template <typename T, int N, int NF>
 constexpr int col_width() {
-  int w = 128 / (int)sizeof(cx<T>);
+  int w = PSD_COL_BYTES / (int)sizeof(cx<T>);
   const int cap = (65536 - N * (int)sizeof(cx<T>)) / (NF * fft_ls(N) * (int)sizeof(cx<T>));
   while (w > cap && w > 1) w /= 2;
   return w;
@@ -86,9 +89,10 @@ __global__ __launch_bounds__(PSD_FIN_NT) void k_res_finalize(const Inst* __restr
   __shared__ double scratch[2 * PSD_FIN_NT / PSD_WAVE];
   const Inst& I = insts[blockIdx.x];
   SolveState* st = I.st;
-  if (st->done) return;
+  const int done = st->done;   // loaded together with the partials
   double acc[2] = {0.0, 0.0};
   flat_reduce<2, 1, PSD_FIN_NT>(I.part_res, I.nblk_res, acc, scratch);
+  if (done) return;
   if (threadIdx.x == 0) {
     const double rinf = acc[0];
     const double rl2 = sqrt(I.hd * acc[1]);
@@ -174,20 +178,20 @@ __global__ __launch_bounds__(PSD_FIN_NT) void k_ls_finalize(const Inst* __restri
   __shared__ double scratch[10 * PSD_FIN_NT / PSD_WAVE];
   const Inst& I = insts[blockIdx.x];
   SolveState* st = I.st;
-  if (st->done || (mode == 2 && st->ls_phase == 2)) return;
+  // state, line-search and spectral partials are loaded together
+  const bool skip = st->done || (mode == 2 && st->ls_phase == 2);
   double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   {
     double a8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    flat_reduce<8, 0, PSD_FIN_NT>(I.part_ls, I.nblk_ls, a8, scratch);
+    double a2[2] = {0.0, 0.0};
+    flat_reduce2<8, 2, PSD_FIN_NT>(I.part_ls, I.nblk_ls, I.part_sp, mode != 2 ? I.nblk_sp : 0, a8, a2,
+                                   scratch);
 #pragma unroll
     for (int k = 0; k < 8; ++k) acc[k] = a8[k];
-  }
-  if (mode != 2) {
-    double a2[2] = {0.0, 0.0};
-    flat_reduce<2, 0, PSD_FIN_NT>(I.part_sp, I.nblk_sp, a2, scratch);
     acc[8] = a2[0];
     acc[9] = a2[1];
   }
+  if (skip) return;
   if (I.order == 6 && mode != 2) {
     // means of d, e1, e2 (FP32 round-off of the inverse transform leaves a
     // tiny mean that the preconditioner never corrects); the update removes them
