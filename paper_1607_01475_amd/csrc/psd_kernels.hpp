@@ -297,23 +297,44 @@ __device__ __forceinline__ RowArgs<T> row_args(const Inst& I, int fs, cx<T>* spe
 // set, task.c = number of fields.  One kernel per row length N: every block
 // of a launch works on instances with n = N.
 template <typename T, typename TIO, bool FWD, int N>
-__global__ __launch_bounds__(PSD_NT) void k_rows(const Inst* __restrict__ insts,
-                                                 const Task2* __restrict__ tasks, int solver) {
-  extern __shared__ double smem[];
-  const Task2 t = tasks[blockIdx.x];
-  const Inst& I = insts[t.inst];
-  if (solver && I.st->done) return;
+__device__ __forceinline__ void rows_body(const Inst& I, const Task2& t, double* smem, int solver) {
   cx<T>* buf = (cx<T>*)smem;
   const cx<T>* tw = (const cx<T>*)(sizeof(T) == 8 ? I.tw64 : I.tw32);
   RowArgs<T> A = row_args<T>(I, t.b, (cx<T>*)I.spec, t.c);
   double fsum[3] = {0.0, 0.0, 0.0};
   if (FWD) r2c_rows<T, TIO, N, row_lines<T, N>()>(A, t.a, buf, tw);
   else c2r_rows<T, TIO, N, row_lines<T, N>()>(A, t.a, buf, tw, fsum);
-  if (!FWD && solver && I.order == 6) {
+  if (!FWD && solver && I.order == 6) {   // field sums of the solver's inverse transform
     __syncthreads();
     block_reduce<3, 0>(fsum, smem);
     if (threadIdx.x == 0)
       for (int q = 0; q < 3; ++q) I.part_c2r[3 * t.slot + q] = fsum[q];
+  }
+}
+
+template <typename T, typename TIO, bool FWD, int N>
+__global__ __launch_bounds__(PSD_NT) void k_rows(const Inst* __restrict__ insts,
+                                                 const Task2* __restrict__ tasks, int solver) {
+  extern __shared__ double smem[];
+  const Task2 t = tasks[blockIdx.x];
+  const Inst& I = insts[t.inst];
+  if (solver && I.st->done) return;
+  rows_body<T, TIO, FWD, N>(I, t, smem, solver);
+}
+
+// Batches of several grid sizes: one launch, the length chosen per block.
+template <typename T, typename TIO, bool FWD>
+__global__ __launch_bounds__(PSD_NT) void k_rows_any(const Inst* __restrict__ insts,
+                                                     const Task2* __restrict__ tasks, int solver) {
+  extern __shared__ double smem[];
+  const Task2 t = tasks[blockIdx.x];
+  const Inst& I = insts[t.inst];
+  if (solver && I.st->done) return;
+  switch (I.n) {
+#define PSD_C(NN) case NN: rows_body<T, TIO, FWD, NN>(I, t, smem, solver); break;
+    PSD_FOR_EACH_N(PSD_C)
+#undef PSD_C
+    default: break;
   }
 }
 
@@ -322,12 +343,7 @@ __global__ __launch_bounds__(PSD_NT) void k_rows(const Inst* __restrict__ insts,
 // at stride ncp.  Nyquist block (task.c = 1): the contiguous kx = N/2 lines of
 // planes task.a, task.a + 1, ... in the Nyquist plane.
 template <typename T, int NF, int DIR, int N>
-__global__ __launch_bounds__(PSD_NT) void k_cols(const Inst* __restrict__ insts,
-                                                 const Task2* __restrict__ tasks, int solver) {
-  extern __shared__ double smem[];
-  const Task2 t = tasks[blockIdx.x];
-  const Inst& I = insts[t.inst];
-  if (solver && I.st->done) return;
+__device__ __forceinline__ void cols_body(const Inst& I, const Task2& t, double* smem) {
   constexpr int W = col_width<T, N, NF>();
   cx<T>* buf = (cx<T>*)smem;
   const cx<T>* tw = (const cx<T>*)(sizeof(T) == 8 ? I.tw64 : I.tw32);
@@ -347,6 +363,31 @@ __global__ __launch_bounds__(PSD_NT) void k_cols(const Inst* __restrict__ insts,
     cs.ncols = min(W, N - t.a);
   }
   col_pass<T, N, W, NF, DIR>((cx<T>*)I.spec, cs, fstride, buf, tw);
+}
+
+template <typename T, int NF, int DIR, int N>
+__global__ __launch_bounds__(PSD_NT) void k_cols(const Inst* __restrict__ insts,
+                                                 const Task2* __restrict__ tasks, int solver) {
+  extern __shared__ double smem[];
+  const Task2 t = tasks[blockIdx.x];
+  const Inst& I = insts[t.inst];
+  if (solver && I.st->done) return;
+  cols_body<T, NF, DIR, N>(I, t, smem);
+}
+
+template <typename T, int NF, int DIR>
+__global__ __launch_bounds__(PSD_NT) void k_cols_any(const Inst* __restrict__ insts,
+                                                     const Task2* __restrict__ tasks, int solver) {
+  extern __shared__ double smem[];
+  const Task2 t = tasks[blockIdx.x];
+  const Inst& I = insts[t.inst];
+  if (solver && I.st->done) return;
+  switch (I.n) {
+#define PSD_C(NN) case NN: cols_body<T, NF, DIR, NN>(I, t, smem); break;
+    PSD_FOR_EACH_N3(PSD_C)
+#undef PSD_C
+    default: break;
+  }
 }
 
 // Spectral operators applied between the forward and inverse transform of
@@ -449,12 +490,7 @@ __device__ __forceinline__ void fused_col(const Inst& I, const Task2& t, cx<T>* 
 }
 
 template <typename T, int OP, int N>
-__global__ __launch_bounds__(PSD_NT) void k_cols_fused(const Inst* __restrict__ insts,
-                                                       const Task2* __restrict__ tasks, int solver) {
-  extern __shared__ double smem[];
-  const Task2 t = tasks[blockIdx.x];
-  const Inst& I = insts[t.inst];
-  if (solver && I.st->done) return;
+__device__ __forceinline__ void fused_body(const Inst& I, const Task2& t, double* smem) {
   cx<T>* buf = (cx<T>*)smem;
   double acc[2] = {0.0, 0.0};
   constexpr int NFM = (OP == OP_PRECOND6) ? 3 : 1;
@@ -465,6 +501,31 @@ __global__ __launch_bounds__(PSD_NT) void k_cols_fused(const Inst* __restrict__ 
   if (threadIdx.x == 0) {
     I.part_sp[2 * t.slot] = acc[0];
     I.part_sp[2 * t.slot + 1] = acc[1];
+  }
+}
+
+template <typename T, int OP, int N>
+__global__ __launch_bounds__(PSD_NT) void k_cols_fused(const Inst* __restrict__ insts,
+                                                       const Task2* __restrict__ tasks, int solver) {
+  extern __shared__ double smem[];
+  const Task2 t = tasks[blockIdx.x];
+  const Inst& I = insts[t.inst];
+  if (solver && I.st->done) return;
+  fused_body<T, OP, N>(I, t, smem);
+}
+
+template <typename T, int OP>
+__global__ __launch_bounds__(PSD_NT) void k_cols_fused_any(const Inst* __restrict__ insts,
+                                                           const Task2* __restrict__ tasks, int solver) {
+  extern __shared__ double smem[];
+  const Task2 t = tasks[blockIdx.x];
+  const Inst& I = insts[t.inst];
+  if (solver && I.st->done) return;
+  switch (I.n) {
+#define PSD_C(NN) case NN: fused_body<T, OP, NN>(I, t, smem); break;
+    PSD_FOR_EACH_N(PSD_C)
+#undef PSD_C
+    default: break;
   }
 }
 

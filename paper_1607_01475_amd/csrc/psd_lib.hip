@@ -407,9 +407,14 @@ static void build_all_tasks(psd_handle* h, std::vector<int>& nsp_aux) {
 // ---------------------------------------------------------------------------
 // launches
 // ---------------------------------------------------------------------------
-// one launch per transform length of the pass
+// One launch per pass: the kernel specialised to the transform length when
+// the batch has one grid size, else the kernel that switches per block.
 template <typename T, typename TIO, bool FWD>
 static void launch_rows(const Range& R, const Inst* dI, const Task2* dT, int sv, hipStream_t s) {
+  if (R.parts.size() > 1) {
+    k_rows_any<T, TIO, FWD><<<R.cnt, PSD_NT, R.lds, s>>>(dI, dT + R.off, sv);
+    return;
+  }
   for (const NPart& p : R.parts) {
     switch (p.n) {
 #define PSD_L(NN) \
@@ -423,6 +428,10 @@ static void launch_rows(const Range& R, const Inst* dI, const Task2* dT, int sv,
 
 template <typename T, int NF, int DIR>
 static void launch_cols(const Range& R, const Inst* dI, const Task2* dT, int sv, hipStream_t s) {
+  if (R.parts.size() > 1) {
+    k_cols_any<T, NF, DIR><<<R.cnt, PSD_NT, R.lds, s>>>(dI, dT + R.off, sv);
+    return;
+  }
   for (const NPart& p : R.parts) {
     switch (p.n) {
 #define PSD_L(NN) \
@@ -436,6 +445,10 @@ static void launch_cols(const Range& R, const Inst* dI, const Task2* dT, int sv,
 
 template <typename T, int OP>
 static void launch_fused(const Range& R, const Inst* dI, const Task2* dT, int sv, hipStream_t s) {
+  if (R.parts.size() > 1) {
+    k_cols_fused_any<T, OP><<<R.cnt, PSD_NT, R.lds, s>>>(dI, dT + R.off, sv);
+    return;
+  }
   for (const NPart& p : R.parts) {
     switch (p.n) {
 #define PSD_L(NN) \
