@@ -59,61 +59,100 @@ constexpr int R2_LDS = R2_VW * R2_VH + R2_LW * R2_LH + 2 * R2_FW * R2_FH + R2_LW
 
 // HESS: Hessian-vector product H xi = xi - s div(F_lin) + s eps^2 Delta_h^2 xi
 // with xi = I.adj_p and u* = I.adj_us (written to I.adj_Hp; acc[1] = sum xi H xi).
+// periodic 2D tile index: tiles plus halo may be wider than small grids
+__device__ __forceinline__ int wrap2(int i, int n, bool small) { return small ? posmod(i, n) : wrapi(i, n); }
+
 template <typename TD, typename TR, int ORDER, bool UPD, bool HESS = false>
 __device__ void res2d_tile(const Inst& I, int x0, int y0, double* lds, double (&acc)[2]) {
   const int n = I.n;
+  const bool small = n < T2X + 4;   // else every tile index lies in [-n, 2n)
   const SolveState* st = I.st;
   const int cur = st->iter & 1;
   const double alpha = UPD ? st->alpha : 0.0;
   // order 6: d, e1, e2 are mean-zero in exact arithmetic; remove the round-off mean
   const double dbar = (ORDER == 6) ? st->mean[0] : 0.0;
-  const double* __restrict__ u = HESS ? I.adj_p : I.u[cur];
-  const TD* __restrict__ d = (const TD*)I.d;
+  const PSD_GLOBAL double* u = gmem(HESS ? (const double*)I.adj_p : (const double*)I.u[cur]);
+  const PSD_GLOBAL TD* d = gmem((const TD*)I.d);
   double* v = lds;
   double* lap = v + R2_VW * R2_VH;
   double* Fx = lap + R2_LW * R2_LH;
   double* Fy = Fx + R2_FW * R2_FH;
   double* wl = Fy + R2_FW * R2_FH;
   const double ih = I.inv_h, ih2 = ih * ih;
+  const int tid = threadIdx.x;
 
-  for (int e = threadIdx.x; e < R2_VW * R2_VH; e += PSD_NT) {
-    const int ey = e / R2_VW, ex = e - ey * R2_VW;
-    const int gx = posmod(x0 - 2 + ex, n), gy = posmod(y0 - 2 + ey, n);
-    const long long gi = gx + (long long)n * gy;
-    double val = u[gi];
-    if (UPD) val += alpha * ((double)d[gi] - dbar);
-    v[e] = val;
+  // own cells (2 per thread): right-hand sides loaded with the tile
+  constexpr int NO = T2X * T2Y / PSD_NT;
+  double fo[NO], go[NO];
+#pragma unroll
+  for (int k = 0; k < NO; ++k) {
+    const int e = tid + k * PSD_NT, ty = e / T2X, tx = e - ty * T2X;
+    const long long gi = wrap2(x0 + tx, n, small) + (long long)n * wrap2(y0 + ty, n, small);
+    fo[k] = HESS ? 0.0 : gmem(I.f)[gi];
+    go[k] = (ORDER == 6 && !HESS) ? gmem(I.g)[gi] : 0.0;
+  }
+  // v = u + alpha d on the tile plus a 2-cell ring: all loads issued first
+  {
+    constexpr int NV = R2_VW * R2_VH, IT = (NV + PSD_NT - 1) / PSD_NT;
+    double uv[IT];
+    TD dv[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = tid + it * PSD_NT;
+      if (e < NV) {
+        const int ey = e / R2_VW, ex = e - ey * R2_VW;
+        const long long gi = wrap2(x0 - 2 + ex, n, small) + (long long)n * wrap2(y0 - 2 + ey, n, small);
+        uv[it] = u[gi];
+        if (UPD) dv[it] = d[gi];
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = tid + it * PSD_NT;
+      if (e < NV) v[e] = UPD ? uv[it] + alpha * ((double)dv[it] - dbar) : uv[it];
+    }
   }
   if (HESS) {  // u* on the tile plus a 1-cell ring (vertex gradients)
-    for (int e = threadIdx.x; e < R2_LW * R2_LH; e += PSD_NT) {
+    for (int e = tid; e < R2_LW * R2_LH; e += PSD_NT) {
       const int ey = e / R2_LW, ex = e - ey * R2_LW;
-      const int gx = posmod(x0 - 1 + ex, n), gy = posmod(y0 - 1 + ey, n);
-      wl[e] = I.adj_us[gx + (long long)n * gy];
+      const int gx = wrap2(x0 - 1 + ex, n, small), gy = wrap2(y0 - 1 + ey, n, small);
+      wl[e] = gmem(I.adj_us)[gx + (long long)n * gy];
     }
   }
   if (ORDER == 6 && !HESS) {
     const double e1bar = st->mean[1], e2bar = st->mean[2];
-    const double* __restrict__ w = I.w[cur];
-    const TD* __restrict__ e1 = (const TD*)I.e1;
-    const TD* __restrict__ e2 = (const TD*)I.e2;
-    for (int e = threadIdx.x; e < R2_LW * R2_LH; e += PSD_NT) {
-      const int ey = e / R2_LW, ex = e - ey * R2_LW;
-      const int gx = posmod(x0 - 1 + ex, n), gy = posmod(y0 - 1 + ey, n);
-      const long long gi = gx + (long long)n * gy;
-      double val = w[gi];
-      if (UPD) val += ((double)e1[gi] - e1bar) - alpha * ((double)e2[gi] - e2bar);
-      wl[e] = val;
+    const PSD_GLOBAL double* w = gmem((const double*)I.w[cur]);
+    const PSD_GLOBAL TD* e1 = gmem((const TD*)I.e1);
+    const PSD_GLOBAL TD* e2 = gmem((const TD*)I.e2);
+    constexpr int NW = R2_LW * R2_LH, IT = (NW + PSD_NT - 1) / PSD_NT;
+    double wv[IT];
+    TD e1v[IT], e2v[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = tid + it * PSD_NT;
+      if (e < NW) {
+        const int ey = e / R2_LW, ex = e - ey * R2_LW;
+        const long long gi = wrap2(x0 - 1 + ex, n, small) + (long long)n * wrap2(y0 - 1 + ey, n, small);
+        wv[it] = w[gi];
+        if (UPD) { e1v[it] = e1[gi]; e2v[it] = e2[gi]; }
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = tid + it * PSD_NT;
+      if (e < NW)
+        wl[e] = UPD ? wv[it] + (((double)e1v[it] - e1bar) - alpha * ((double)e2v[it] - e2bar)) : wv[it];
     }
   }
   __syncthreads();
   // Laplacian on the tile plus a 1-cell ring
-  for (int e = threadIdx.x; e < R2_LW * R2_LH; e += PSD_NT) {
+  for (int e = tid; e < R2_LW * R2_LH; e += PSD_NT) {
     const int ly = e / R2_LW, lx = e - ly * R2_LW;
     const int c = (ly + 1) * R2_VW + lx + 1;
     lap[e] = (v[c - 1] + v[c + 1] + v[c - R2_VW] + v[c + R2_VW] - 4.0 * v[c]) * ih2;
   }
   // fluxes at vertices (i+1/2, j+1/2), i in [x0-1, x0+TX), j in [y0-1, y0+TY)
-  for (int e = threadIdx.x; e < R2_FW * R2_FH; e += PSD_NT) {
+  for (int e = tid; e < R2_FW * R2_FH; e += PSD_NT) {
     const int fy = e / R2_FW, fx = e - fy * R2_FW;
     const int c = (fy + 1) * R2_VW + fx + 1;  // cell (i, j) of the vertex
     const double c00 = v[c], c10 = v[c + 1], c01 = v[c + R2_VW], c11 = v[c + R2_VW + 1];
@@ -136,8 +175,10 @@ __device__ void res2d_tile(const Inst& I, int x0, int y0, double* lds, double (&
   }
   __syncthreads();
   const double s = I.s, se2 = I.se2;
-  double* __restrict__ uo = I.u[cur ^ 1];
-  for (int e = threadIdx.x; e < T2X * T2Y; e += PSD_NT) {
+  PSD_GLOBAL double* uo = gmem(I.u[cur ^ 1]);
+#pragma unroll
+  for (int k = 0; k < NO; ++k) {
+    const int e = tid + k * PSD_NT;
     const int ty = e / T2X, tx = e - ty * T2X;
     const int gx = x0 + tx, gy = y0 + ty;
     if (gx >= n || gy >= n) continue;
@@ -150,22 +191,22 @@ __device__ void res2d_tile(const Inst& I, int x0, int y0, double* lds, double (&
     const double vc = v[(ty + 2) * R2_VW + tx + 2];
     if (HESS) {
       const double hx = vc - s * div + se2 * l2;
-      I.adj_Hp[gi] = hx;
+      gmem(I.adj_Hp)[gi] = hx;
       acc[1] += vc * hx;
     } else if (ORDER == 4) {
-      const double r = I.f[gi] - (vc - s * div + se2 * l2);
-      ((TR*)I.r)[gi] = (TR)r;
+      const double r = fo[k] - (vc - s * div + se2 * l2);
+      gmem((TR*)I.r)[gi] = (TR)r;
       if (UPD) uo[gi] = vc;
       acc[0] = fmax(acc[0], fabs(r));
       acc[1] += r * r;
     } else {
       const double wc = wl[lc];
       const double lw = (wl[lc - 1] + wl[lc + 1] + wl[lc - R2_LW] + wl[lc + R2_LW] - 4.0 * wc) * ih2;
-      const double r1 = I.g[gi] - vc + lw;
-      const double r2 = I.f[gi] - (s * I.lam * vc - s * div + se2 * l2 - wc);
-      ((TR*)I.r1)[gi] = (TR)r1;
-      ((TR*)I.r)[gi] = (TR)r2;
-      if (UPD) { uo[gi] = vc; I.w[cur ^ 1][gi] = wc; }
+      const double r1 = go[k] - vc + lw;
+      const double r2 = fo[k] - (s * I.lam * vc - s * div + se2 * l2 - wc);
+      gmem((TR*)I.r1)[gi] = (TR)r1;
+      gmem((TR*)I.r)[gi] = (TR)r2;
+      if (UPD) { uo[gi] = vc; gmem(I.w[cur ^ 1])[gi] = wc; }
       acc[0] = fmax(acc[0], fmax(fabs(r1), fabs(r2)));
       acc[1] += r1 * r1 + r2 * r2;
     }
@@ -587,18 +628,32 @@ constexpr int L2_LDS = 2 * L2_W * L2_H;
 template <typename TD, int MODE>
 __device__ void ls2d_tile(const Inst& I, int x0, int y0, double* lds, double (&acc)[8]) {
   const int n = I.n;
+  const bool small = n < T2X + 2;   // else every tile index lies in [-n, 2n)
   const SolveState* st = I.st;
-  const double* __restrict__ u = I.u[st->iter & 1];
-  const TD* __restrict__ d = (const TD*)I.d;
+  const PSD_GLOBAL double* u = gmem((const double*)I.u[st->iter & 1]);
+  const PSD_GLOBAL TD* d = gmem((const TD*)I.d);
   const double alpha = (MODE == 2) ? st->x : 0.0;
   double* ul = lds;
   double* dl = lds + L2_W * L2_H;
-  for (int e = threadIdx.x; e < L2_W * L2_H; e += PSD_NT) {
-    const int ey = e / L2_W, ex = e - ey * L2_W;
-    const int gx = posmod(x0 - 1 + ex, n), gy = posmod(y0 - 1 + ey, n);
-    const long long gi = gx + (long long)n * gy;
-    ul[e] = u[gi];
-    dl[e] = (double)d[gi];
+  {
+    constexpr int NV = L2_W * L2_H, IT = (NV + PSD_NT - 1) / PSD_NT;
+    double uv[IT];
+    TD dv[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = threadIdx.x + it * PSD_NT;
+      if (e < NV) {
+        const int ey = e / L2_W, ex = e - ey * L2_W;
+        const long long gi = wrap2(x0 - 1 + ex, n, small) + (long long)n * wrap2(y0 - 1 + ey, n, small);
+        uv[it] = u[gi];
+        dv[it] = d[gi];
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = threadIdx.x + it * PSD_NT;
+      if (e < NV) { ul[e] = uv[it]; dl[e] = (double)dv[it]; }
+    }
   }
   __syncthreads();
   const double hh = 0.5 * I.inv_h, ih2 = I.inv_h * I.inv_h;
