@@ -89,10 +89,12 @@ typedef struct {
     int history;
     int profile;   /* non-zero: time every kernel launch with HIP events on the
                       solver stream (see psd_pass_times) */
-    int autotune;  /* non-zero: at psd_create, time the stencil-kernel tilings
-                      (3D z-chunk 8/16/32/64, natural or XCD-grouped block order)
-                      on this handle's buffers and keep the fastest; results are
-                      cached in the file named by PSD_TUNE_CACHE when set */
+    int autotune;  /* non-zero: at psd_create, time the 3D stencil-kernel tilings
+                      (residual z-chunk 16/28/40/64, line-search z-chunk
+                      12/24/36/60, line-search tile 64x4 or 32x8, natural or
+                      XCD-grouped block order) on this handle's buffers and keep
+                      the fastest; results are cached in the file named by
+                      PSD_TUNE_CACHE when set */
 } psd_options;
 
 /* Per-instance result.  energy is E_h at the final iterate (Sec. 5.3 and

@@ -735,11 +735,13 @@ static bool tune_cache_read(psd_handle* h, const std::string& key) {
     std::string l(line);
     const size_t bar = l.find('|');
     if (bar == std::string::npos || l.substr(0, bar) != key) continue;
-    int a, b, c, d;
-    // chunks below T3Z_MIN would need more partial slots than were allocated
-    if (std::sscanf(l.c_str() + bar + 1, "%d %d %d %d", &a, &b, &c, &d) == 4 && a >= T3Z_MIN &&
-        b >= T3Z_MIN) {
+    int a, b, c, d, e;
+    // chunks below T3Z_MIN would need more partial slots than were allocated;
+    // a wide line-search tile needs every n >= 64
+    if (std::sscanf(l.c_str() + bar + 1, "%d %d %d %d %d", &a, &b, &c, &d, &e) == 5 && a >= T3Z_MIN &&
+        b >= T3Z_MIN && (e == L3_TX_NARROW || (e == L3_TX_WIDE && h->ls_tx == L3_TX_WIDE))) {
       h->tune_zc_res = a; h->tune_zc_ls = b; h->tune_xcd_res = c != 0; h->tune_xcd_ls = d != 0;
+      h->ls_tx = e;
       found = true;
     }
   }
@@ -752,8 +754,8 @@ static void tune_cache_write(psd_handle* h, const std::string& key) {
   if (!path) return;
   FILE* fp = std::fopen(path, "a");
   if (!fp) return;
-  std::fprintf(fp, "%s|%d %d %d %d\n", key.c_str(), h->tune_zc_res, h->tune_zc_ls, (int)h->tune_xcd_res,
-               (int)h->tune_xcd_ls);
+  std::fprintf(fp, "%s|%d %d %d %d %d\n", key.c_str(), h->tune_zc_res, h->tune_zc_ls, (int)h->tune_xcd_res,
+               (int)h->tune_xcd_ls, h->ls_tx);
   std::fclose(fp);
 }
 
@@ -798,8 +800,14 @@ static psd_status autotune_impl(psd_handle* h) {
   double best_res = 1e300, best_ls = 1e300;
   int bz_res = T3Z_RES, bz_ls = T3Z_LS;
   bool bx_res = false, bx_ls = false;
-  for (size_t zi = 0; zi < zres.size(); ++zi) {
+  // line-search tile widths: 64 only where every grid has n >= 64
+  std::vector<int> txs = {h->ls_tx};
+  if (h->dim == 3 && h->ls_tx == L3_TX_WIDE) txs.push_back(L3_TX_NARROW);
+  int btx_ls = h->ls_tx;
+  for (size_t zi = 0; zi < zres.size(); ++zi)
+  for (int tx : txs) {
     for (int xcd = 0; xcd < 2; ++xcd) {
+      h->ls_tx = tx;
       h->tune_zc_res = zres[zi];
       h->tune_zc_ls = zls[zi];
       h->tune_xcd_res = h->tune_xcd_ls = xcd != 0;
@@ -819,12 +827,13 @@ static psd_status autotune_impl(psd_handle* h) {
       HIPCHK(hipGetLastError());
       const double tr = h->pass_ms[PSD_PASS_RES], tl = h->pass_ms[PSD_PASS_LS];
       if (tr < best_res) { best_res = tr; bz_res = zres[zi]; bx_res = xcd != 0; }
-      if (tl < best_ls) { best_ls = tl; bz_ls = zls[zi]; bx_ls = xcd != 0; }
+      if (tl < best_ls) { best_ls = tl; bz_ls = zls[zi]; bx_ls = xcd != 0; btx_ls = tx; }
     }
   }
   h->opt.profile = save_prof;
   h->tune_zc_res = bz_res; h->tune_zc_ls = bz_ls;
   h->tune_xcd_res = bx_res; h->tune_xcd_ls = bx_ls;
+  h->ls_tx = btx_ls;
   h->hI = saved;
   build_all_tasks(h, nsp_aux);
   for (int k = 0; k < PSD_NPASS; ++k) { h->pass_ms[k] = 0.0; h->pass_n[k] = 0; }
@@ -944,13 +953,23 @@ extern "C" psd_status psd_create(const psd_problem* probs, int batch, const psd_
       I.hist_cap = opt->max_iter;
     }
   }
-  // task tables: capacities from the finest z-chunk any tuning may pick
+  // task tables: capacities from the finest z-chunk and every line-search
+  // tile width any tuning may pick
   std::vector<int> nsp_aux;
-  h->tune_zc_res = h->tune_zc_ls = T3Z_MIN;
-  build_all_tasks(h, nsp_aux);
-  h->dT_cap = h->hT.size();
-  std::vector<int> cap_res(batch), cap_ls(batch);
-  for (int b = 0; b < batch; ++b) { cap_res[b] = h->hI[b].nblk_res; cap_ls[b] = h->hI[b].nblk_ls; }
+  std::vector<int> cap_res(batch, 0), cap_ls(batch, 0);
+  const int ls_tx0 = h->ls_tx;
+  h->dT_cap = 0;
+  for (int tx : {L3_TX_NARROW, ls_tx0}) {
+    h->ls_tx = tx;
+    h->tune_zc_res = h->tune_zc_ls = T3Z_MIN;
+    build_all_tasks(h, nsp_aux);
+    h->dT_cap = std::max(h->dT_cap, h->hT.size());
+    for (int b = 0; b < batch; ++b) {
+      cap_res[b] = std::max(cap_res[b], h->hI[b].nblk_res);
+      cap_ls[b] = std::max(cap_ls[b], h->hI[b].nblk_ls);
+    }
+  }
+  h->ls_tx = ls_tx0;
   h->tune_zc_res = T3Z_RES;
   h->tune_zc_ls = T3Z_LS;
   build_all_tasks(h, nsp_aux);
