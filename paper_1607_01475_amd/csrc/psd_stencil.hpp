@@ -214,7 +214,7 @@ __device__ void res2d_tile(const Inst& I, int x0, int y0, double* lds, double (&
 }
 
 // ===========================================================================
-// 3D residual: a T3X x T3Y column tile marching a chunk of planes in z.
+// 3D residual: a 32 x 8 column tile marching a chunk of planes in z.
 // Each thread owns one (x, y) column: its values of v = u + alpha d and of
 // Delta_h v at the planes in flight stay in registers; LDS holds the xy-halo
 // of 3 v planes (halo 2), 2 planes of Delta_h v (halo 1) and one vertex plane
@@ -222,7 +222,8 @@ __device__ void res2d_tile(const Inst& I, int x0, int y0, double* lds, double (&
 // thread forms the partial divergence of its cell for that vertex plane:
 //   P = A(i,j) - A(i-1,j-1) + B(i,j-1) - B(i-1,j),  Q = sum of C over the 4
 // vertices, and div = (P_below + P_above + Q_above - Q_below) / (4h).
-// The global loads of plane k+3 are issued before plane k is computed.
+// The global loads of planes j+3 and j+4 are in flight while plane j is
+// computed.
 // ===========================================================================
 // Tile shape of the 3D residual: TX x (256 / TX) columns.  TX = 32 (32 x 8);
 // 64 x 4 was measured slower at 256^3 (the wider halo rows cost more than the
@@ -238,7 +239,7 @@ struct R3Shape {
   static constexpr int FRING = FP - TX * TY;   // halo vertices of a flux plane
   static constexpr int LDS = 3 * VP + 2 * LP + 3 * FP;
   static constexpr int HLDS = LDS + 3 * VP;   // Hessian mode: 3 more planes (u*)
-  static_assert(VRING <= 2 * PSD_NT && LRING <= PSD_NT && FRING <= PSD_NT, "ring sizes");
+  static_assert(VRING <= PSD_NT && LRING <= PSD_NT && FRING <= PSD_NT, "ring sizes");
   // position in a v plane of halo cell number t (0 <= t < VRING)
   static __device__ __forceinline__ int vring_pos(int t) {
     if (t < 4 * VW) {                             // rows 0, 1, VH-2, VH-1
@@ -271,8 +272,8 @@ constexpr int R3_TX = 32;
 
 template <typename TD>
 struct R3Prefetch {
-  double u_own, u_ring, u_ring2;
-  TD d_own, d_ring, d_ring2;
+  double u_own, u_ring;
+  TD d_own, d_ring;
 };
 
 // Per-plane partial sums of the 2x2 cells (c00, c10, c01, c11) below or
@@ -339,7 +340,6 @@ struct Res3March {
   static constexpr int R3_VW = SH::VW, R3_VP = SH::VP, R3_LW = SH::LW, R3_LP = SH::LP;
   static constexpr int R3_FW = SH::FW, R3_FP = SH::FP;
   static constexpr int R3_VRING = SH::VRING, R3_LRING = SH::LRING, R3_FRING = SH::FRING;
-  static constexpr bool RING2 = SH::VRING > PSD_NT;   // second halo cell on the first threads
   const Inst& I;
   const PSD_GLOBAL double* u;
   PSD_GLOBAL double* uo;
@@ -357,8 +357,7 @@ struct Res3March {
   long long nn;             // n*n
   long long own_xy, ring_xy, fcol;
   int n, z0, z1, tid;
-  int vown, lown, fown, vring, vring2, lring, fring, fring_c;
-  long long ring2_xy;
+  int vown, lown, fown, vring, lring, fring, fring_c;
   long long gout;           // output offset of the own cell in plane 0
   bool own;
   // rotating registers
@@ -403,8 +402,6 @@ struct Res3March {
     fown = (ty + 1) * R3_FW + tx + 1;
     vring = tid < R3_VRING ? SH::vring_pos(tid) : vown;
     const int rey = vring / R3_VW, rex = vring - rey * R3_VW;
-    vring2 = tid + PSD_NT < R3_VRING ? SH::vring_pos(tid + PSD_NT) : vown;
-    const int rey2 = vring2 / R3_VW, rex2 = vring2 - rey2 * R3_VW;
     lring = tid < R3_LRING ? SH::lring_pos(tid) : lown;
     fring = tid < R3_FRING ? SH::fring_pos(tid) : fown;
     fring_c = (fring / R3_FW + 1) * R3_VW + fring % R3_FW + 1;
@@ -412,7 +409,6 @@ struct Res3March {
     own = gx < n && gy < n;
     own_xy = wrapi(gx, n) + (long long)n * wrapi(gy, n);
     ring_xy = wrapi(x0 - 2 + rex, n) + (long long)n * wrapi(y0 - 2 + rey, n);
-    ring2_xy = wrapi(x0 - 2 + rex2, n) + (long long)n * wrapi(y0 - 2 + rey2, n);
     fcol = own_xy;
     gout = gx + (long long)n * gy;
     acc0 = 0.0;
@@ -435,10 +431,6 @@ struct Res3March {
       pf[B].u_ring = u[zo + ring_xy];
       if (LOADD) pf[B].d_ring = d[zo + ring_xy];
     }
-    if (RING2 && tid + PSD_NT < R3_VRING) {
-      pf[B].u_ring2 = u[zo + ring2_xy];
-      if (LOADD) pf[B].d_ring2 = d[zo + ring2_xy];
-    }
   }
 
   // put the plane prefetched in buffer B into v slot S (and u* slot S); returns own v
@@ -449,13 +441,10 @@ struct Res3March {
     const double vo = UPD ? pf.u_own + alpha * (double)pf.d_own : pf.u_own;
     vn[vown] = vo;
     if (tid < R3_VRING) vn[vring] = UPD ? pf.u_ring + alpha * (double)pf.d_ring : pf.u_ring;
-    if (RING2 && tid + PSD_NT < R3_VRING)
-      vn[vring2] = UPD ? pf.u_ring2 + alpha * (double)pf.d_ring2 : pf.u_ring2;
     if (HESS) {
       double* sn = sb + S * R3_VP;
       sn[vown] = (double)pf.d_own;
       if (tid < R3_VRING) sn[vring] = (double)pf.d_ring;
-      if (RING2 && tid + PSD_NT < R3_VRING) sn[vring2] = (double)pf.d_ring2;
       sc[S] = (double)pf.d_own;
     }
     return vo;
@@ -726,7 +715,7 @@ struct Ls3March {
   VPart pu[2], pd[2];              // partials of u, d at planes r mod 2
   double n10[2], n01[2];           // d at (x+1), (y+1) of the own cell, planes r mod 2
   double sacc[8];
-  L3Prefetch<TD> pf[1];            // plane in flight: one step ahead (more costs a wave per SIMD)
+  L3Prefetch<TD> pf[1];            // plane in flight: one step ahead (two measured no faster)
 
   __device__ __forceinline__ Ls3March(const Inst& I_, int x0, int y0, int z0_, double* lds) : I(I_) {
     const SolveState* st = I.st;
