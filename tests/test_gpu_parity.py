@@ -227,6 +227,27 @@ def test_batched_instances_match_single(psd):
         assert rel(host(u), ref["u"]) <= 1e-9
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_3d_sizes_match_oracle(psd, precision):
+    """3D instances of different n in one handle: every FFT pass runs as one
+    launch over both sizes (per-block length switch); narrow line-search tiles."""
+    sizes = [32, 48]
+    probs = [psd.Problem(3, n, 12.8, 4, 4.0, 0.01, 0.1) for n in sizes]
+    fs = [psd_inputs.small_field(3, n, 12.8, 90 + i, K=5) for i, n in enumerate(sizes)]
+    log(f"case batched 3D sizes {sizes} {precision}")
+    with psd.Solver(probs, tol=1e-10, max_iter=300, precision=precision, graph_chunk=4) as S:
+        us = [torch.zeros_like(dev(f)) for f in fs]
+        stats = S.solve([dev(f) for f in fs], us)
+    for f, n, u, st in zip(fs, sizes, us, stats):
+        O = oracle.Problem(3, n, 12.8, p=4.0, s=0.01, eps=0.1)
+        assert st.status == 0 and st.res_inf <= 1e-10
+        ref = O.solve(f, tol=1e-10, max_iter=300)
+        if precision == "fp64":
+            assert abs(st.iters - ref["iters"]) <= 1
+        assert rel(host(u), ref["u"]) <= (1e-11 if precision == "fp64" and st.iters == ref["iters"] else 1e-9)
+        assert np.abs(O.residual(f, host(u))).max() <= 1.5e-10
+
+
 def test_autotuned_tiling_gives_same_solution(psd):
     n, L = 64, 12.8
     f = psd_inputs.small_field(3, n, L, 101, K=6)
