@@ -22,7 +22,7 @@ constexpr int T2X = 64, T2Y = 8;     // 2D: 512 cells, 2 per thread
 // 3D: planes marched per block.  The residual runs z-chunk + 2 steps, the
 // line search z-chunk steps, both in groups of six: chunks with 6 | steps
 // waste nothing.  Defaults and the autotuner's candidates follow that rule.
-constexpr int T3Z_RES = 28, T3Z_LS = 24;
+constexpr int T3Z_RES = 64, T3Z_LS = 60;   // one full wave of resident blocks at 256^3
 constexpr int T3Z_MIN = 12;          // smallest chunk any tuning may pick
 
 __device__ __forceinline__ double flux_r(double g2, double p, int p_is_4, int p_is_2) {
