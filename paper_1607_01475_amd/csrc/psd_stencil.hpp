@@ -24,6 +24,10 @@ constexpr int T2X = 64, T2Y = 8;     // 2D: 512 cells, 2 per thread
 // waste nothing.  Defaults and the autotuner's candidates follow that rule.
 constexpr int T3Z_RES = 64, T3Z_LS = 60;   // one full wave of resident blocks at 256^3
 constexpr int T3Z_MIN = 12;          // smallest chunk any tuning may pick
+// planes whose line-search loads are in flight ahead of the current step
+#ifndef PSD_LS_PREFETCH
+#define PSD_LS_PREFETCH 1
+#endif
 
 __device__ __forceinline__ double flux_r(double g2, double p, int p_is_4, int p_is_2) {
   if (p_is_4) return g2;
@@ -715,7 +719,8 @@ struct Ls3March {
   VPart pu[2], pd[2];              // partials of u, d at planes r mod 2
   double n10[2], n01[2];           // d at (x+1), (y+1) of the own cell, planes r mod 2
   double sacc[8];
-  L3Prefetch<TD> pf[1];            // plane in flight: one step ahead (two measured no faster)
+  static constexpr int PD = PSD_LS_PREFETCH;   // planes in flight ahead of the step
+  L3Prefetch<TD> pf[PD];
 
   __device__ __forceinline__ Ls3March(const Inst& I_, int x0, int y0, int z0_, double* lds) : I(I_) {
     const SolveState* st = I.st;
@@ -790,7 +795,8 @@ struct Ls3March {
     dcol[0] = (double)d[(long long)wrapi(z0 - 1, n) * nn + own_xy];
     fetch<0>(z0);
     put<1, 0>();
-    fetch<0>(z0 + 1);
+    fetch<0>(z0 + 1);                          // plane z0+m in buffer (m-1) mod PD
+    if constexpr (PD == 2) fetch<1>(z0 + 2);
     __syncthreads();
     partials<1, 1>();
   }
@@ -800,8 +806,9 @@ struct Ls3March {
     // relative plane index r = plane - z0 + 1: k-1 -> q, k -> q+1, k+1 -> q+2
     constexpr int SM = Q % 3, SK = (Q + 1) % 3, SN = (Q + 2) % 3;
     constexpr int RK = (Q + 1) & 1, RN = Q & 1;
-    put<SN, 0>();
-    fetch<0>(k + 2);   // planes past the chunk are read and never used
+    constexpr int B = (PD == 2) ? (Q & 1) : 0;   // buffer of plane k+1
+    put<SN, B>();
+    fetch<B>(k + 1 + PD);   // planes past the chunk are read and never used
     __syncthreads();
     partials<SN, RN>();
     if (k < z1 && own) {
