@@ -24,6 +24,10 @@ constexpr int T2X = 64, T2Y = 8;     // 2D: 512 cells, 2 per thread
 // waste nothing.  Defaults and the autotuner's candidates follow that rule.
 constexpr int T3Z_RES = 64, T3Z_LS = 60;   // one full wave of resident blocks at 256^3
 constexpr int T3Z_MIN = 12;          // smallest chunk any tuning may pick
+// line-search halo loads on every thread (1) or on the halo threads only (0)
+#ifndef PSD_LS_RING_ALL
+#define PSD_LS_RING_ALL 0
+#endif
 // planes whose line-search loads are in flight ahead of the current step
 #ifndef PSD_LS_PREFETCH
 #define PSD_LS_PREFETCH 1
@@ -756,12 +760,18 @@ struct Ls3March {
   template <int B>
   __device__ __forceinline__ void fetch(int z) {
     const long long zo = (long long)wrapi(z, n) * nn;
-    // ring loads on every thread (non-ring threads re-read their own cell)
-    // and a fetch in every step: a fixed number of global loads per step
     pf[B].u_own = u[zo + own_xy];
     pf[B].d_own = d[zo + own_xy];
+#if PSD_LS_RING_ALL
+    // ring loads on every thread (non-ring threads re-read their own cell)
     pf[B].u_ring = u[zo + ring_xy];
     pf[B].d_ring = d[zo + ring_xy];
+#else
+    if (tid < L3_RING) {
+      pf[B].u_ring = u[zo + ring_xy];
+      pf[B].d_ring = d[zo + ring_xy];
+    }
+#endif
   }
 
   template <int S, int B>
