@@ -77,15 +77,16 @@ def traffic_for(kernel: str, workload: str):
         return None
 
 
-# kernels of the passes of the mixed 256^3 p=4 form (rocprofv3 kernel names)
+# kernels of the passes of the mixed 256^3 p=4 form (prefixes of rocprofv3
+# kernel names; the line-search tile width is a trailing template argument)
 PASS_KERNELS = {
     "rows_r2c": "psd::k_rows<float, float, true, 256>",
     "cols_fwd": "psd::k_cols<float, 1, -1, 256>",
     "cols_fused": "psd::k_cols_fused<float, 0, 256>",
     "cols_inv": "psd::k_cols<float, 1, 1, 256>",
     "rows_c2r": "psd::k_rows<float, float, false, 256>",
-    "ls": "psd::k_ls3d<float, 0>",
-    "res": "psd::k_res3d<float, float, true, 4>",
+    "ls": "psd::k_ls3d<float, 0, ",
+    "res": "psd::k_res3d<float, float, true, 4, ",
 }
 COPY_BYTES = 512 * 1024 * 1024   # the --copy-calibration device copy
 
@@ -117,15 +118,23 @@ def summarize_pmc(fetch_dir: str, write_dir: str, out: str, workload: str = "c3_
     rec = {"_calibration": {"copy_bytes": COPY_BYTES, "fetch_scale": round(fscale, 4),
                             "write_scale": round(wscale, 4)}}
     src = source_hash()
+    def launches(per, prefix):
+        out = []
+        for name, vals in per.items():
+            if name.startswith(prefix):
+                out += vals
+        return sorted(out)
+
     for pname, kname in PASS_KERNELS.items():
-        fv = [v for _, v in sorted(fetch.get(kname, []))[-10:]]
-        wv = [v for _, v in sorted(write.get(kname, []))[-10:]]
+        fv = [v for _, v in launches(fetch, kname)[-10:]]
+        wv = [v for _, v in launches(write, kname)[-10:]]
         if not fv or not wv:
             continue
         fb = statistics.median(fv) * 1024.0 * fscale
         wb = statistics.median(wv) * 1024.0 * wscale
         alg = kernel_bytes(pname, 256, 3, True)
-        rec[f"{workload}:{pname}"] = {"kernel": kname, "fetch_bytes": round(fb), "write_bytes": round(wb),
+        kfull = sorted(n for n in fetch if n.startswith(kname))
+        rec[f"{workload}:{pname}"] = {"kernel": ", ".join(kfull), "fetch_bytes": round(fb), "write_bytes": round(wb),
                                       "bytes_per_launch": round(fb + wb),
                                       "algorithmic_bytes": alg, "ratio": round((fb + wb) / alg, 3),
                                       "source_hash": src}

@@ -104,7 +104,7 @@ struct Inst {
   int nblk_c2r;
   int zchunk_res;      // 3D: z-planes marched per residual block (tuned)
   int zchunk_ls;       // 3D: z-planes marched per line-search block (tuned)
-  int pad1;
+  int nblk_vec;        // blocks of the adjoint's vector kernels (and their partials)
 };
 
 // A block's unit of work: instance and up to three integer coordinates.

@@ -703,7 +703,9 @@ __global__ __launch_bounds__(PSD_NT) void k_cg_fin(const Inst* __restrict__ inst
   double acc[2] = {0.0, 0.0};
   if (mode == 1 || mode == 4)
     for (int b = threadIdx.x; b < I.nblk_sp; b += PSD_NT) acc[0] += I.part_sp[2 * b];
-  const int nb = (mode == 2 || nblk_vec < 0) ? I.nblk_res : nblk_vec;
+  // mode 2 reduces the Hessian pass (one partial per residual tile), the
+  // others the vector kernels (nblk_vec partials, or the count given)
+  const int nb = mode == 2 ? I.nblk_res : (nblk_vec < 0 ? I.nblk_vec : nblk_vec);
   if (mode != 1)
     for (int b = threadIdx.x; b < nb; b += PSD_NT) acc[1] += I.part_res[2 * b + 1];
   block_reduce<2, 0>(acc, scratch);

@@ -978,7 +978,9 @@ extern "C" psd_status psd_create(const psd_problem* probs, int batch, const psd_
   for (int b = 0; b < batch; ++b) {
     Inst& I = h->hI[b];
     const int nsp_max = std::max(I.nblk_sp, nsp_aux[b]);
-    const int nres = std::max(cap_res[b], 1024);   // vector kernels use up to nblk_res blocks
+    // adjoint vector kernels: a block per 2048 cells, 64 .. 1024 blocks
+    I.nblk_vec = (int)std::min<long long>(1024, std::max<long long>(64, I.ncell / 2048));
+    const int nres = std::max(cap_res[b], I.nblk_vec);
     if (dalloc(h, &I.part_res, (size_t)nres * 2 * 8) || dalloc(h, &I.part_ls, (size_t)cap_ls[b] * 8 * 8) ||
         dalloc(h, &I.part_sp, (size_t)nsp_max * 2 * 8) || dalloc(h, &I.part_c2r, (size_t)I.nblk_c2r * 3 * 8))
       return fail("out of device memory");
@@ -1295,13 +1297,10 @@ static psd_status adjoint_impl(psd_handle* h, const double* const* u_star, const
   const double rtol2 = rtol * rtol;
   auto vec = [&](int op) {
     for (int b = 0; b < B; ++b)
-      k_cg_vec<TD, TR><<<h->hI[b].nblk_res, PSD_NT, 0, s>>>(h->dI, b, op);
+      k_cg_vec<TD, TR><<<h->hI[b].nblk_vec, PSD_NT, 0, s>>>(h->dI, b, op);
   };
-  // nblk_vec = nblk_res (vector kernels use one block per residual tile count)
-  const int nbv = 0;  // per-instance block count read from Inst in k_cg_fin
-  (void)nbv;
   auto fin = [&](int mode) {
-    // vector partial counts equal nblk_res for every instance
+    // vector partials: nblk_vec per instance (read from the instance table)
     k_cg_fin<<<B, PSD_NT, 0, s>>>(h->dI, mode, -1, rtol2);
   };
   vec(0);

@@ -48,7 +48,7 @@ def _write_counters(path, rows):
 
 def test_summarize_pmc_scales_by_the_copy(tmp_path):
     copy = "__amd_rocclr_copyBuffer"
-    res = bench.PASS_KERNELS["res"]
+    res = bench.PASS_KERNELS["res"] + "32>"
     mib = bench.COPY_BYTES / 1024.0  # KiB of the calibration copy
     # the copy reads report half their bytes, writes all of them
     fetch = [(1, copy, "FETCH_SIZE", mib / 2), (2, copy, "FETCH_SIZE", 3.0)]
