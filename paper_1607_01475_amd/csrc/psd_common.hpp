@@ -159,6 +159,17 @@ __device__ __forceinline__ void block_reduce(double (&v)[K], double* scratch) {
 // wait (and every barrier) would drain all loads in flight.  Casting to the
 // global address space gives global loads and stores instead.
 #define PSD_GLOBAL __attribute__((address_space(1)))
+
+// 1/x for finite x >= 1: the hardware reciprocal estimate refined by two
+// Newton-Raphson steps r <- r + r (1 - x r), each of which squares the
+// relative error
+__device__ __forceinline__ double rcp_pos(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
 template <typename T>
 __device__ __forceinline__ PSD_GLOBAL T* gmem(T* p) { return (PSD_GLOBAL T*)p; }
 template <typename T>

@@ -452,12 +452,73 @@ __device__ __forceinline__ void col_store(cx<T>* base, const ColSet& cs, long lo
 }
 
 // ---------------------------------------------------------------------------
+// 256-point column transforms with the values in registers (four-step FFT,
+// 256 = 16 x 16).  Thread (g, c) = (tid / 16, tid % 16) of a 16-column block
+// holds the values g + 16 j (j < 16) of column c in x[j]; one transform is a
+// 16-point DFT over j, the twiddles exp(DIR 2 pi i g k / 256), a transpose
+// through LDS and a 16-point DFT over g, after which x[k] holds output index
+// g + 16 k.  So loads and stores of a pass use the same addresses whatever
+// the direction, and a forward/inverse pair needs no reordering.  buf: the
+// transpose buffer, 16 rows of F256_RS complex ([row][g][c]: 64-lane
+// accesses of 512 contiguous bytes on the write side).  The call starts
+// with LDS writes: every thread must be past its reads of buf.
+// ---------------------------------------------------------------------------
+constexpr int F256_RS = 256;
+
+template <int DIR, typename T>
+__device__ __forceinline__ void four_step256(cx<T>* x, int g, int c, cx<T>* buf, const cx<T>* twl) {
+  dft16<DIR>(x);
+#pragma unroll
+  for (int k = 1; k < 16; ++k) {
+    cx<T> w = twl[g * k];
+    if (DIR > 0) w.y = -w.y;
+    x[k] = x[k] * w;
+  }
+#pragma unroll
+  for (int k = 0; k < 16; ++k) buf[k * F256_RS + g * 16 + c] = x[k];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 16; ++j) x[j] = buf[g * F256_RS + j * 16 + c];
+  dft16<DIR>(x);
+}
+
+// values g + 16 j of column c (zeros for a column past ncols)
+template <typename T>
+__device__ __forceinline__ void col256_load(const cx<T>* base, const ColSet& cs, int c, int g, bool live,
+                                            cx<T>* x) {
+  const cx<T>* col = base + cs.cbase + c * cs.cstride + g * cs.lstride;
+  const long long step = 16 * cs.lstride;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) x[j] = live ? gld(col + j * step) : mk(T(0), T(0));
+}
+
+template <typename T>
+__device__ __forceinline__ void col256_store(cx<T>* base, const ColSet& cs, int c, int g, const cx<T>* x) {
+  cx<T>* col = base + cs.cbase + c * cs.cstride + g * cs.lstride;
+  const long long step = 16 * cs.lstride;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) gst(col + j * step, x[j]);
+}
+
+// ---------------------------------------------------------------------------
 // Column pass: the block's columns (ColSet) of length N, NF fields.  Loads,
 // transforms (DIR), stores.
 // ---------------------------------------------------------------------------
 template <typename T, int N, int W, int NF, int DIR>
 __device__ __forceinline__ void col_pass(cx<T>* base, const ColSet& cs, long long fstride, cx<T>* buf,
                                          const cx<T>* tw) {
+  if constexpr (N == 256 && W == 16 && NF == 1 && PSD_NT == 256) {
+    const int c = threadIdx.x % W, g = threadIdx.x / W;
+    const bool live = c < cs.ncols;
+    cx<T> x[16];
+    col256_load(base, cs, c, g, live, x);
+    cx<T>* twl = buf + 16 * F256_RS;
+    stage_twiddles<T, N>(twl, tw);
+    __syncthreads();
+    four_step256<DIR>(x, g, c, buf, twl);
+    if (live) col256_store(base, cs, c, g, x);
+    return;
+  }
   constexpr int LS = fft_ls(N);
   cx<T>* twl = buf + NF * W * LS;
   stage_twiddles<T, N>(twl, tw);

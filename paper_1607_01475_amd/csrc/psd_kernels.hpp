@@ -30,15 +30,17 @@ constexpr int row_lines() {
   return p;
 }
 // columns per block of a column pass: 128-byte segments where the LDS
-// footprint NF*W*fft_ls(N) complex plus N twiddles stays within 64 KB; a
-// power of two, so that a thread keeps one column
+// footprint NF*W*fft_ls(N) complex plus N twiddles and N doubles of the
+// symbol (fused pass) stays within 64 KB; a power of two, so that a thread
+// keeps one column
 #ifndef PSD_COL_BYTES
 #define PSD_COL_BYTES 128
 #endif
 template <typename T, int N, int NF>
 constexpr int col_width() {
   int w = PSD_COL_BYTES / (int)sizeof(cx<T>);
-  const int cap = (65536 - N * (int)sizeof(cx<T>)) / (NF * fft_ls(N) * (int)sizeof(cx<T>));
+  // 64 KB per block: W columns per field, twiddles, and (fused pass) the symbol
+  const int cap = (65536 - N * (int)sizeof(cx<T>) - N * 8) / (NF * fft_ls(N) * (int)sizeof(cx<T>));
   while (w > cap && w > 1) w /= 2;
   return w;
 }
@@ -406,20 +408,12 @@ enum SpecOp { OP_PRECOND4 = 0, OP_PRECOND6 = 1, OP_POISSON = 2 };
 // 2D: task.a = 0), lines at stride ncp (2D) or N*ncp (3D).  Nyquist block
 // (task.c = 1), kx = N/2: 3D, rows ky = task.a, task.a + 1, ... of the
 // Nyquist plane (lines at stride N); 2D, the one contiguous Nyquist line.
-template <typename T, int N, int W, int OP>
-__device__ __forceinline__ void fused_col(const Inst& I, const Task2& t, cx<T>* buf, double (&acc)[2]) {
-  constexpr int NFI = (OP == OP_PRECOND6) ? 2 : 1;
-  constexpr int NFO = (OP == OP_PRECOND6) ? 3 : 1;
-  constexpr int LS = fft_ls(N);
-  static_assert(PSD_NT % W == 0, "a thread keeps one column");
-  const cx<T>* tw = (const cx<T>*)(sizeof(T) == 8 ? I.tw64 : I.tw32);
+template <typename T, int N, int W>
+__device__ __forceinline__ ColSet fused_cols(const Inst& I, const Task2& t) {
   const int dim = I.dim;
   const long long ncp = sizeof(T) == 8 ? I.ncp64 : I.ncp32;
-  const long long fstride = sizeof(T) == 8 ? I.nspec64 : I.nspec32;
-  cx<T>* base = (cx<T>*)I.spec;
-  const bool nyq = t.c != 0;
   ColSet cs;
-  if (!nyq) {
+  if (t.c == 0) {
     cs.cbase = (long long)t.a * ncp + t.b;
     cs.cstride = 1;
     cs.lstride = (dim == 2) ? ncp : (long long)N * ncp;
@@ -430,14 +424,49 @@ __device__ __forceinline__ void fused_col(const Inst& I, const Task2& t, cx<T>* 
     cs.lstride = (dim == 2) ? 1 : N;
     cs.ncols = (dim == 2) ? 1 : min(W, N - t.a);
   }
+  return cs;
+}
+
+// One-field operators on one spectral value X at symbol K (wgt_inv = w/Ntot).
+template <typename T, int OP>
+__device__ __forceinline__ cx<T> spec_one(cx<T> X, double K, double s, double se2, double inv,
+                                          double wgt_inv, double& acc0) {
+  static_assert(OP == OP_PRECOND4 || OP == OP_POISSON, "one-field operators");
+  const double x2 = (double)X.x * X.x + (double)X.y * X.y;
+  if (OP == OP_PRECOND4) {
+    const double rs = rcp_pos(1.0 + s * K + se2 * K * K);   // 1 / sigma
+    acc0 += wgt_inv * x2 * rs;
+    return scale(X, (T)(inv * rs));
+  } else {
+    if (!(K > 0.0)) return mk(T(0), T(0));
+    acc0 += wgt_inv * x2 / K;
+    return scale(X, (T)(inv / K));
+  }
+}
+
+template <typename T, int N, int W, int OP>
+__device__ __forceinline__ void fused_col(const Inst& I, const Task2& t, cx<T>* buf, double (&acc)[2]) {
+  constexpr int NFI = (OP == OP_PRECOND6) ? 2 : 1;
+  constexpr int NFO = (OP == OP_PRECOND6) ? 3 : 1;
+  constexpr int LS = fft_ls(N);
+  static_assert(PSD_NT % W == 0, "a thread keeps one column");
+  const cx<T>* tw = (const cx<T>*)(sizeof(T) == 8 ? I.tw64 : I.tw32);
+  const int dim = I.dim;
+  const long long fstride = sizeof(T) == 8 ? I.nspec64 : I.nspec32;
+  cx<T>* base = (cx<T>*)I.spec;
+  const bool nyq = t.c != 0;
+  const ColSet cs = fused_cols<T, N, W>(I, t);
   constexpr int NLMAX = (NFI > NFO ? NFI : NFO) * W;
   cx<T>* twl = buf + NLMAX * LS;
   stage_twiddles<T, N>(twl, tw);
+  // the symbol S(k) of the last axis, staged with the twiddles
+  double* Sl = (double*)(twl + N);
+  const PSD_GLOBAL double* S = gmem(I.S);
+  for (int e = threadIdx.x; e < N; e += PSD_NT) Sl[e] = S[e];
   col_load<T, N, W, NFI>(base, cs, fstride, buf);
   __syncthreads();
   lds_fft<T, N, NFI * W, LS, -1>(buf, twl);
   const double s = I.s, se2 = I.se2, inv = I.inv_ntot;
-  const PSD_GLOBAL double* S = gmem(I.S);
   // wave numbers of this thread's column: kx, and ky in 3D (2D: ky = line index)
   const int c = threadIdx.x % W;
   const bool live = c < cs.ncols;
@@ -445,34 +474,25 @@ __device__ __forceinline__ void fused_col(const Inst& I, const Task2& t, cx<T>* 
   const int ky3 = nyq ? t.a + c : t.a;
   const double wgt = (kx == 0 || 2 * kx == N) ? 1.0 : 2.0;
   const double wgt_inv = wgt * inv;
-  const double Kc = S[live ? kx : 0] + (dim == 3 ? S[live ? ky3 : 0] : 0.0);
-  for (int e = threadIdx.x; e < W * N; e += PSD_NT) {
-    if (!live) break;
-    const int tt = e / W;
-    const double K = Kc + S[tt];
-    if (OP == OP_PRECOND4) {
-      const cx<T> X = buf[c * LS + pidx(tt)];
-      const double rs = 1.0 / (1.0 + s * K + se2 * K * K);   // 1 / sigma
-      const double x2 = (double)X.x * X.x + (double)X.y * X.y;
-      acc[0] += wgt_inv * x2 * rs;
-      buf[c * LS + pidx(tt)] = scale(X, (T)(inv * rs));
-    } else if (OP == OP_POISSON) {
-      const cx<T> X = buf[c * LS + pidx(tt)];
-      if (K > 0.0) {
-        const double x2 = (double)X.x * X.x + (double)X.y * X.y;
-        acc[0] += wgt * x2 / K * inv;
-        buf[c * LS + pidx(tt)] = scale(X, (T)(inv / K));
-      } else {
-        buf[c * LS + pidx(tt)] = mk(T(0), T(0));
-      }
+  const double Kc = Sl[live ? kx : 0] + (dim == 3 ? Sl[live ? ky3 : 0] : 0.0);
+  // a thread's elements lie in its column c, rows threadIdx.x / W + i * (PSD_NT / W)
+  constexpr int RPT = (W * N + PSD_NT - 1) / PSD_NT;
+#pragma unroll 4
+  for (int i = 0; i < (live ? RPT : 0); ++i) {
+    const int tt = threadIdx.x / W + i * (PSD_NT / W);
+    if (W * N % PSD_NT != 0 && tt >= N) break;
+    const double K = Kc + Sl[tt];
+    if constexpr (OP != OP_PRECOND6) {
+      buf[c * LS + pidx(tt)] = spec_one<T, OP>(buf[c * LS + pidx(tt)], K, s, se2, inv, wgt_inv, acc[0]);
     } else {
       const cx<T> X2 = buf[c * LS + pidx(tt)], X1 = buf[(W + c) * LS + pidx(tt)];
       if (K > 0.0) {
         const double iK = 1.0 / K;
         const double sig = s * I.lam + s * K + se2 * K * K + iK;
+        const double isig = 1.0 / sig;
         const double px = (double)X2.x + iK * X1.x, py = (double)X2.y + iK * X1.y;
-        const double dx = px / sig, dy = py / sig;
-        acc[0] += wgt * (px * px + py * py) / sig * inv;
+        const double dx = px * isig, dy = py * isig;
+        acc[0] += wgt * (px * px + py * py) * isig * inv;
         acc[1] += wgt * (dx * dx + dy * dy) * iK * inv;
         buf[c * LS + pidx(tt)] = mk((T)(dx * inv), (T)(dy * inv));
         buf[(W + c) * LS + pidx(tt)] = mk((T)(X1.x * iK * inv), (T)(X1.y * iK * inv));
@@ -489,12 +509,53 @@ __device__ __forceinline__ void fused_col(const Inst& I, const Task2& t, cx<T>* 
   col_store<T, N, W, NFO>(base, cs, fstride, buf);
 }
 
+// Last-axis pass for N = 256 and one field of 16 columns, values in
+// registers (four_step256); the operator is applied where the thread holds
+// frequencies g + 16 k.  LDS: transpose buffer | twiddles | symbol.
+template <typename T, int OP>
+__device__ __forceinline__ void fused_col256(const Inst& I, const Task2& t, cx<T>* buf, double (&acc)[2]) {
+  constexpr int N = 256, W = 16;
+  const cx<T>* tw = (const cx<T>*)(sizeof(T) == 8 ? I.tw64 : I.tw32);
+  cx<T>* base = (cx<T>*)I.spec;
+  const ColSet cs = fused_cols<T, N, W>(I, t);
+  const int c = threadIdx.x % W, g = threadIdx.x / W;
+  const bool live = c < cs.ncols;
+  cx<T> x[16];
+  col256_load(base, cs, c, g, live, x);
+  cx<T>* twl = buf + 16 * F256_RS;
+  double* Sl = (double*)(twl + N);
+  stage_twiddles<T, N>(twl, tw);
+  const PSD_GLOBAL double* S = gmem(I.S);
+  Sl[threadIdx.x] = S[threadIdx.x];
+  __syncthreads();
+  four_step256<-1>(x, g, c, buf, twl);   // x[k] = frequency g + 16 k
+  {
+    const double s = I.s, se2 = I.se2, inv = I.inv_ntot;
+    const bool nyq = t.c != 0;
+    const int kx = nyq ? N / 2 : t.b + c;
+    const int ky3 = nyq ? t.a + c : t.a;
+    const double wgt = (kx == 0 || 2 * kx == N) ? 1.0 : 2.0;
+    const double wgt_inv = wgt * inv;
+    const double Kc = Sl[live ? kx : 0] + (I.dim == 3 ? Sl[live ? ky3 : 0] : 0.0);
+    double a0 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) x[k] = spec_one<T, OP>(x[k], Kc + Sl[g + 16 * k], s, se2, inv, wgt_inv, a0);
+    if (live) acc[0] += a0;
+  }
+  __syncthreads();   // every thread has read the forward transpose
+  four_step256<1>(x, g, c, buf, twl);    // x[r] = element g + 16 r
+  if (live) col256_store(base, cs, c, g, x);
+}
+
 template <typename T, int OP, int N>
 __device__ __forceinline__ void fused_body(const Inst& I, const Task2& t, double* smem) {
   cx<T>* buf = (cx<T>*)smem;
   double acc[2] = {0.0, 0.0};
   constexpr int NFM = (OP == OP_PRECOND6) ? 3 : 1;
-  fused_col<T, N, col_width<T, N, NFM>(), OP>(I, t, buf, acc);
+  if constexpr (N == 256 && NFM == 1 && col_width<T, N, NFM>() == 16 && PSD_NT == 256)
+    fused_col256<T, OP>(I, t, buf, acc);
+  else
+    fused_col<T, N, col_width<T, N, NFM>(), OP>(I, t, buf, acc);
   // the FFT buffers are dead after this barrier: reuse them for the reduction
   __syncthreads();
   block_reduce<2, 0>(acc, smem);

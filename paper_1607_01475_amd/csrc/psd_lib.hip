@@ -327,7 +327,7 @@ static void build_fft_tasks(psd_handle* h, FftTasks& F, int nfi, int nfo, bool w
         }
       if (with_slots) I.nblk_sp = slot;
     }
-    close_part(R, std::max(((size_t)nfm * W * fft_ls(n) + n) * cxs, (size_t)64 * 8));
+    close_part(R, std::max(((size_t)nfm * W * fft_ls(n) + n) * cxs + n * sizeof(double), (size_t)64 * 8));
   }
   R.cnt = (int)h->hT.size() - R.off;
 }
