@@ -91,10 +91,11 @@ typedef struct {
                       solver stream (see psd_pass_times) */
     int autotune;  /* non-zero: at psd_create, time the 3D stencil-kernel tilings
                       (residual z-chunk 16/28/40/64, line-search z-chunk
-                      12/24/36/60, line-search tile 64x4 or 32x8, natural or
-                      XCD-grouped block order) on this handle's buffers and keep
-                      the fastest; results are cached in the file named by
-                      PSD_TUNE_CACHE when set */
+                      12/24/36/60, plus per kernel the chunk at which all its
+                      blocks are resident at once; line-search tile 64x4 or
+                      32x8; natural or XCD-grouped block order) on this
+                      handle's buffers and keep the fastest; results are
+                      cached in the file named by PSD_TUNE_CACHE when set */
 } psd_options;
 
 /* Per-instance result.  energy is E_h at the final iterate (Sec. 5.3 and

@@ -795,6 +795,41 @@ static psd_status autotune_impl(psd_handle* h) {
   // z-chunk candidates (residual, line search): whole groups of six steps
   std::vector<int> zres = {16, 28, 40, 64}, zls = {12, 24, 36, 60};
   if (h->dim == 2) { zres = {T3Z_RES}; zls = {T3Z_LS}; }
+  else {
+    // plus the chunk at which the whole grid is one round of resident blocks
+    // (column tiles x chunks = CUs x blocks per CU), rounded up to whole groups
+    // of six steps: no block waits for a slot and no slot idles at the end
+    int ncu = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) ncu = prop.multiProcessorCount;
+    int occ_res = 0, occ_ls = 0;
+    const size_t lds_ls = ((h->ls_tx == L3_TX_WIDE ? L3Shape<L3_TX_WIDE>::LDS : L3Shape<L3_TX_NARROW>::LDS) + 32) *
+                          sizeof(double);
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_res, k_res3d<TD, TR, true, 4, R3_TX>, PSD_NT,
+                                                        (R3Shape<R3_TX>::LDS + 16) * sizeof(double)));
+    if (h->ls_tx == L3_TX_WIDE)
+      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_ls, k_ls3d<TD, 0, L3_TX_WIDE>, PSD_NT, lds_ls));
+    else
+      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_ls, k_ls3d<TD, 0, L3_TX_NARROW>, PSD_NT, lds_ls));
+    auto balanced = [&](int tx, int occ, int extra_steps) {
+      const int ty = PSD_NT / tx;
+      long long tiles = 0;
+      int nmax = 0;
+      for (int b = 0; b < h->batch; ++b) {
+        const int n = h->hI[b].n;
+        tiles += (long long)((n + tx - 1) / tx) * ((n + ty - 1) / ty);
+        nmax = std::max(nmax, n);
+      }
+      const long long k = std::max(1LL, (long long)ncu * std::max(occ, 1) / std::max(tiles, 1LL));
+      int z = std::max((int)((nmax + k - 1) / k), T3Z_MIN);
+      while ((z + extra_steps) % 6) ++z;
+      return z;
+    };
+    const int zr = balanced(R3_TX, occ_res, 2), zl = balanced(h->ls_tx, occ_ls, 0);
+    bool seen = false;
+    for (size_t i = 0; i < zres.size(); ++i) seen = seen || (zres[i] == zr && zls[i] == zl);
+    if (!seen) { zres.push_back(zr); zls.push_back(zl); }
+  }
   const int save_prof = h->opt.profile;
   h->opt.profile = 1;
   double best_res = 1e300, best_ls = 1e300;

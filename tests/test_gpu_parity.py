@@ -257,7 +257,8 @@ def test_autotuned_tiling_gives_same_solution(psd):
         with psd.Solver(P, tol=1e-10, max_iter=300, precision="mixed", autotune=tune) as S:
             t = S.tuning()
             # residual / line-search z-chunks run whole groups of six plane steps
-            assert t[0] in (16, 28, 40, 64) and t[1] in (12, 24, 36, 60)
+            # (the residual's chunk + 2, the line search's chunk)
+            assert t[0] >= 12 and (t[0] + 2) % 6 == 0 and t[1] >= 12 and t[1] % 6 == 0
             u = torch.zeros_like(dev(f))
             st = S.solve([dev(f)], [u])[0]
             res.append((st.iters, host(u), t))
