@@ -82,6 +82,12 @@ def test_config3_256(psd):
         S.solve([dev(w.f)], [u])
     ref = O.solve(w.f, tol=0.0, max_iter=1)
     assert rel(host(u), ref["u"]) <= 1e-12
+    # the same iteration in mixed precision (FP32 residual and spectrum; the
+    # 256-point y and z passes run the register four-step transform)
+    with psd.Solver(P, tol=0.0, max_iter=1, precision="mixed") as S:
+        u = torch.zeros_like(dev(w.f))
+        S.solve([dev(w.f)], [u])
+    assert rel(host(u), ref["u"]) <= 2e-6
 
 
 def test_config4_batch64(psd):

@@ -227,6 +227,35 @@ def test_batched_instances_match_single(psd):
         assert rel(host(u), ref["u"]) <= 1e-9
 
 
+@pytest.mark.parametrize("mode", ["one_iteration", "solve"])
+def test_256_point_register_transforms_2d(psd, mode):
+    """FP32 256-point lines take the register four-step transform (the last
+    axis of a 2D 256^2 grid, with its one-column Nyquist block): one mixed
+    iteration from zero against the oracle's to FP32 accuracy, and a full
+    mixed solve against the oracle's solution."""
+    n, L = 256, 25.6
+    # the noise puts energy in every mode, the Nyquist column included
+    f = psd_inputs.small_field(2, n, L, 41, K=8, noise=0.05)
+    O = oracle.Problem(2, n, L, p=4.0, s=0.01, eps=0.1)
+    P = psd.Problem(2, n, L, 4, 4.0, 0.01, 0.1)
+    log(f"case 2D n={n} mixed {mode}")
+    if mode == "one_iteration":
+        with psd.Solver(P, tol=0.0, max_iter=1, precision="mixed") as S:
+            u = torch.zeros_like(dev(f))
+            S.solve([dev(f)], [u])
+        ref = O.solve(f, tol=0.0, max_iter=1)
+        # FP32 residual and spectrum: the step is exact to about 1e-7 relative
+        assert rel(host(u), ref["u"]) <= 2e-6
+    else:
+        with psd.Solver(P, tol=1e-10, max_iter=300, precision="mixed", graph_chunk=4) as S:
+            u = torch.zeros_like(dev(f))
+            st = S.solve([dev(f)], [u])[0]
+        assert st.status == 0 and st.res_inf <= 1e-10
+        ref = O.solve(f, tol=1e-10, max_iter=300)
+        assert rel(host(u), ref["u"]) <= 1e-9
+        assert np.abs(O.residual(f, host(u))).max() <= 1.5e-10
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_batched_3d_sizes_match_oracle(psd, precision):
     """3D instances of different n in one handle: every FFT pass runs as one
