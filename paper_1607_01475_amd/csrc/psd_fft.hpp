@@ -452,21 +452,32 @@ __device__ __forceinline__ void col_store(cx<T>* base, const ColSet& cs, long lo
 }
 
 // ---------------------------------------------------------------------------
-// 256-point column transforms with the values in registers (four-step FFT,
-// 256 = 16 x 16).  Thread (g, c) = (tid / 16, tid % 16) of a 16-column block
-// holds the values g + 16 j (j < 16) of column c in x[j]; one transform is a
-// 16-point DFT over j, the twiddles exp(DIR 2 pi i g k / 256), a transpose
-// through LDS and a 16-point DFT over g, after which x[k] holds output index
-// g + 16 k.  So loads and stores of a pass use the same addresses whatever
-// the direction, and a forward/inverse pair needs no reordering.  buf: the
-// transpose buffer, 16 rows of F256_RS complex ([row][g][c]: 64-lane
-// accesses of 512 contiguous bytes on the write side).  The call starts
-// with LDS writes: every thread must be past its reads of buf.
+// Column transforms with the values in registers (four-step FFT) for FP32
+// lines of N = 16 N1 points, N1 = 8 or 16: W = 256 / N1 adjacent columns per
+// block (W x 8 contiguous bytes per line element; W <= N/2, so a block row of
+// the half spectrum fills it) and N1 threads per column.  Thread (g, c) =
+// (tid / W, tid % W) holds the points g + N1 j (j < 16) of column c in x[j].
+// A transform is a 16-point DFT over j, the twiddles exp(DIR 2 pi i g k / N),
+// a transpose through LDS and, for each row k = g + N1 m (m < 16 / N1) the
+// thread takes, an N1-point DFT across the column's threads; afterwards x[j]
+// again holds output index g + N1 j.  So loads and stores of a pass use the
+// same addresses whatever the direction, and a forward/inverse pair needs no
+// reordering.  buf: the transpose buffer, 16 rows of FS_RS = N1 W = 256
+// complex ([row][g][c]: 64-lane writes of 512 contiguous bytes).  The call
+// starts with LDS writes: every thread must be past its reads of buf.
 // ---------------------------------------------------------------------------
-constexpr int F256_RS = 256;
+template <typename T, int N>
+constexpr bool col_four_step() {
+  return std::is_same<T, float>::value && PSD_NT == 256 && (N == 128 || N == 256);
+}
+template <int N>
+constexpr int four_step_width() { return PSD_NT / (N / 16); }
+constexpr int FS_RS = 256;
 
-template <int DIR, typename T>
-__device__ __forceinline__ void four_step256(cx<T>* x, int g, int c, cx<T>* buf, const cx<T>* twl) {
+template <int N, int DIR, typename T>
+__device__ __forceinline__ void four_step(cx<T>* x, int g, int c, cx<T>* buf, const cx<T>* twl) {
+  constexpr int N1 = N / 16, W = PSD_NT / N1, M = 16 / N1;
+  static_assert(N1 * W == FS_RS, "transpose buffer rows");
   dft16<DIR>(x);
 #pragma unroll
   for (int k = 1; k < 16; ++k) {
@@ -475,27 +486,33 @@ __device__ __forceinline__ void four_step256(cx<T>* x, int g, int c, cx<T>* buf,
     x[k] = x[k] * w;
   }
 #pragma unroll
-  for (int k = 0; k < 16; ++k) buf[k * F256_RS + g * 16 + c] = x[k];
+  for (int k = 0; k < 16; ++k) buf[k * FS_RS + g * W + c] = x[k];
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < 16; ++j) x[j] = buf[g * F256_RS + j * 16 + c];
-  dft16<DIR>(x);
+  for (int m = 0; m < M; ++m) {
+    cx<T> v[N1];
+#pragma unroll
+    for (int t1 = 0; t1 < N1; ++t1) v[t1] = buf[(g + N1 * m) * FS_RS + t1 * W + c];
+    dftR<N1, DIR>(v);
+#pragma unroll
+    for (int q = 0; q < N1; ++q) x[m + M * q] = v[q];
+  }
 }
 
-// values g + 16 j of column c (zeros for a column past ncols)
-template <typename T>
-__device__ __forceinline__ void col256_load(const cx<T>* base, const ColSet& cs, int c, int g, bool live,
+// points g + N1 j of column c (zeros for a column past ncols)
+template <int N, typename T>
+__device__ __forceinline__ void col_fs_load(const cx<T>* base, const ColSet& cs, int c, int g, bool live,
                                             cx<T>* x) {
   const cx<T>* col = base + cs.cbase + c * cs.cstride + g * cs.lstride;
-  const long long step = 16 * cs.lstride;
+  const long long step = (N / 16) * cs.lstride;
 #pragma unroll
   for (int j = 0; j < 16; ++j) x[j] = live ? gld(col + j * step) : mk(T(0), T(0));
 }
 
-template <typename T>
-__device__ __forceinline__ void col256_store(cx<T>* base, const ColSet& cs, int c, int g, const cx<T>* x) {
+template <int N, typename T>
+__device__ __forceinline__ void col_fs_store(cx<T>* base, const ColSet& cs, int c, int g, const cx<T>* x) {
   cx<T>* col = base + cs.cbase + c * cs.cstride + g * cs.lstride;
-  const long long step = 16 * cs.lstride;
+  const long long step = (N / 16) * cs.lstride;
 #pragma unroll
   for (int j = 0; j < 16; ++j) gst(col + j * step, x[j]);
 }
@@ -507,16 +524,16 @@ __device__ __forceinline__ void col256_store(cx<T>* base, const ColSet& cs, int 
 template <typename T, int N, int W, int NF, int DIR>
 __device__ __forceinline__ void col_pass(cx<T>* base, const ColSet& cs, long long fstride, cx<T>* buf,
                                          const cx<T>* tw) {
-  if constexpr (N == 256 && W == 16 && NF == 1 && PSD_NT == 256) {
+  if constexpr (col_four_step<T, N>() && W == four_step_width<N>() && NF == 1) {
     const int c = threadIdx.x % W, g = threadIdx.x / W;
     const bool live = c < cs.ncols;
     cx<T> x[16];
-    col256_load(base, cs, c, g, live, x);
-    cx<T>* twl = buf + 16 * F256_RS;
+    col_fs_load<N>(base, cs, c, g, live, x);
+    cx<T>* twl = buf + 16 * FS_RS;
     stage_twiddles<T, N>(twl, tw);
     __syncthreads();
-    four_step256<DIR>(x, g, c, buf, twl);
-    if (live) col256_store(base, cs, c, g, x);
+    four_step<N, DIR>(x, g, c, buf, twl);
+    if (live) col_fs_store<N>(base, cs, c, g, x);
     return;
   }
   constexpr int LS = fft_ls(N);

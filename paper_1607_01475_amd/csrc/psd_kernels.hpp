@@ -38,6 +38,7 @@ constexpr int row_lines() {
 #endif
 template <typename T, int N, int NF>
 constexpr int col_width() {
+  if (NF == 1 && col_four_step<T, N>()) return four_step_width<N>();
   int w = PSD_COL_BYTES / (int)sizeof(cx<T>);
   // 64 KB per block: W columns per field, twiddles, and (fused pass) the symbol
   const int cap = (65536 - N * (int)sizeof(cx<T>) - N * 8) / (NF * fft_ls(N) * (int)sizeof(cx<T>));
@@ -509,26 +510,26 @@ __device__ __forceinline__ void fused_col(const Inst& I, const Task2& t, cx<T>* 
   col_store<T, N, W, NFO>(base, cs, fstride, buf);
 }
 
-// Last-axis pass for N = 256 and one field of 16 columns, values in
-// registers (four_step256); the operator is applied where the thread holds
-// frequencies g + 16 k.  LDS: transpose buffer | twiddles | symbol.
-template <typename T, int OP>
-__device__ __forceinline__ void fused_col256(const Inst& I, const Task2& t, cx<T>* buf, double (&acc)[2]) {
-  constexpr int N = 256, W = 16;
+// Last-axis pass for one field with the values in registers (four_step):
+// the operator is applied where the thread holds frequencies g + N1 k.
+// LDS: transpose buffer | twiddles | symbol.
+template <typename T, int N, int OP>
+__device__ __forceinline__ void fused_col_fs(const Inst& I, const Task2& t, cx<T>* buf, double (&acc)[2]) {
+  constexpr int W = four_step_width<N>(), N1 = N / 16;
   const cx<T>* tw = (const cx<T>*)(sizeof(T) == 8 ? I.tw64 : I.tw32);
   cx<T>* base = (cx<T>*)I.spec;
   const ColSet cs = fused_cols<T, N, W>(I, t);
   const int c = threadIdx.x % W, g = threadIdx.x / W;
   const bool live = c < cs.ncols;
   cx<T> x[16];
-  col256_load(base, cs, c, g, live, x);
-  cx<T>* twl = buf + 16 * F256_RS;
+  col_fs_load<N>(base, cs, c, g, live, x);
+  cx<T>* twl = buf + 16 * FS_RS;
   double* Sl = (double*)(twl + N);
   stage_twiddles<T, N>(twl, tw);
   const PSD_GLOBAL double* S = gmem(I.S);
-  Sl[threadIdx.x] = S[threadIdx.x];
+  if (threadIdx.x < N) Sl[threadIdx.x] = S[threadIdx.x];
   __syncthreads();
-  four_step256<-1>(x, g, c, buf, twl);   // x[k] = frequency g + 16 k
+  four_step<N, -1>(x, g, c, buf, twl);   // x[k] = frequency g + N1 k
   {
     const double s = I.s, se2 = I.se2, inv = I.inv_ntot;
     const bool nyq = t.c != 0;
@@ -539,12 +540,12 @@ __device__ __forceinline__ void fused_col256(const Inst& I, const Task2& t, cx<T
     const double Kc = Sl[live ? kx : 0] + (I.dim == 3 ? Sl[live ? ky3 : 0] : 0.0);
     double a0 = 0.0;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) x[k] = spec_one<T, OP>(x[k], Kc + Sl[g + 16 * k], s, se2, inv, wgt_inv, a0);
+    for (int k = 0; k < 16; ++k) x[k] = spec_one<T, OP>(x[k], Kc + Sl[g + N1 * k], s, se2, inv, wgt_inv, a0);
     if (live) acc[0] += a0;
   }
   __syncthreads();   // every thread has read the forward transpose
-  four_step256<1>(x, g, c, buf, twl);    // x[r] = element g + 16 r
-  if (live) col256_store(base, cs, c, g, x);
+  four_step<N, 1>(x, g, c, buf, twl);    // x[r] = point g + N1 r
+  if (live) col_fs_store<N>(base, cs, c, g, x);
 }
 
 template <typename T, int OP, int N>
@@ -552,8 +553,8 @@ __device__ __forceinline__ void fused_body(const Inst& I, const Task2& t, double
   cx<T>* buf = (cx<T>*)smem;
   double acc[2] = {0.0, 0.0};
   constexpr int NFM = (OP == OP_PRECOND6) ? 3 : 1;
-  if constexpr (N == 256 && NFM == 1 && col_width<T, N, NFM>() == 16 && PSD_NT == 256)
-    fused_col256<T, OP>(I, t, buf, acc);
+  if constexpr (NFM == 1 && col_four_step<T, N>() && col_width<T, N, NFM>() == four_step_width<N>())
+    fused_col_fs<T, N, OP>(I, t, buf, acc);
   else
     fused_col<T, N, col_width<T, N, NFM>(), OP>(I, t, buf, acc);
   // the FFT buffers are dead after this barrier: reuse them for the reduction

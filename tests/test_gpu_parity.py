@@ -227,18 +227,20 @@ def test_batched_instances_match_single(psd):
         assert rel(host(u), ref["u"]) <= 1e-9
 
 
-@pytest.mark.parametrize("mode", ["one_iteration", "solve"])
-def test_256_point_register_transforms_2d(psd, mode):
-    """FP32 256-point lines take the register four-step transform (the last
-    axis of a 2D 256^2 grid, with its one-column Nyquist block): one mixed
-    iteration from zero against the oracle's to FP32 accuracy, and a full
-    mixed solve against the oracle's solution."""
-    n, L = 256, 25.6
-    # the noise puts energy in every mode, the Nyquist column included
-    f = psd_inputs.small_field(2, n, L, 41, K=8, noise=0.05)
-    O = oracle.Problem(2, n, L, p=4.0, s=0.01, eps=0.1)
-    P = psd.Problem(2, n, L, 4, 4.0, 0.01, 0.1)
-    log(f"case 2D n={n} mixed {mode}")
+@pytest.mark.parametrize("dim,n,mode", [(2, 256, "one_iteration"), (2, 256, "solve"),
+                                        (2, 128, "one_iteration"), (2, 128, "solve"),
+                                        (3, 128, "one_iteration")])
+def test_register_transforms_mixed(psd, dim, n, mode):
+    """FP32 lines of 128 and 256 points take the register four-step transform
+    (y passes and the fused last axis; 2D grids include the one-column Nyquist
+    block): one mixed iteration from zero against the oracle's to FP32
+    accuracy, and a full mixed solve against the oracle's solution."""
+    L = 0.1 * n
+    # the noise puts energy in every mode, the Nyquist lines included
+    f = psd_inputs.small_field(dim, n, L, 41, K=8, noise=0.05)
+    O = oracle.Problem(dim, n, L, p=4.0, s=0.01, eps=0.1)
+    P = psd.Problem(dim, n, L, 4, 4.0, 0.01, 0.1)
+    log(f"case {dim}D n={n} mixed {mode}")
     if mode == "one_iteration":
         with psd.Solver(P, tol=0.0, max_iter=1, precision="mixed") as S:
             u = torch.zeros_like(dev(f))
