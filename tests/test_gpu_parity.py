@@ -259,6 +259,37 @@ def test_register_transforms_mixed(psd, dim, n, mode):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_degenerate_inputs(psd, precision):
+    """Degenerate cases: f = 0 from u0 = 0 (the residual is zero at the
+    start: no iteration), a restart from a converged answer (no iteration,
+    the answer untouched), and the smallest grid (2D 16^2) against the oracle."""
+    n, L = 16, 3.2
+    P = psd.Problem(2, n, L, 4, 4.0, 0.01, 0.1)
+    log(f"case degenerate {precision}")
+    with psd.Solver(P, tol=1e-10, max_iter=50, precision=precision) as S:
+        z = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        u = torch.zeros_like(z)
+        st = S.solve([z], [u])[0]
+        assert st.status == 0 and st.iters == 0 and st.res_inf == 0.0
+        assert not bool(u.abs().max() > 0)
+    f = psd_inputs.small_field(2, n, L, 71, K=4, noise=0.05)
+    O = oracle.Problem(2, n, L, p=4.0, s=0.01, eps=0.1)
+    ref = O.solve(f, tol=1e-10, max_iter=300)
+    with psd.Solver(P, tol=1e-10, max_iter=300, precision=precision) as S:
+        u = torch.zeros_like(dev(f))
+        st = S.solve([dev(f)], [u])[0]
+        assert st.status == 0 and st.res_inf <= 1e-10
+        if precision == "fp64":
+            assert abs(st.iters - ref["iters"]) <= 1
+        assert rel(host(u), ref["u"]) <= (1e-11 if precision == "fp64" and st.iters == ref["iters"] else 1e-9)
+        # restart from the converged answer
+        u_conv = host(u).copy()
+        st2 = S.solve([dev(f)], [u])[0]
+        assert st2.status == 0 and st2.iters == 0
+        assert np.array_equal(host(u), u_conv)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_batched_3d_sizes_match_oracle(psd, precision):
     """3D instances of different n in one handle: every FFT pass runs as one
     launch over both sizes (per-block length switch); narrow line-search tiles."""
