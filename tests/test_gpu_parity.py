@@ -96,7 +96,9 @@ def test_residual_parity_order6(psd):
 SOLVES = [(2, 64, 4.0, 12.8, 0.01, 0.1), (2, 96, 4.0, 12.8, 0.01, 0.1), (2, 128, 3.0, 25.6, 0.005, 0.05),
           (3, 32, 4.0, 12.8, 0.01, 0.1), (3, 48, 4.0, 12.8, 0.01, 0.1),
           # wide (64-column) line-search tiles, one of them partial
-          (3, 96, 4.0, 12.8, 0.01, 0.1)]
+          (3, 96, 4.0, 12.8, 0.01, 0.1),
+          # 3D general p: line search by (q, q') evaluations and the host root rule
+          (3, 32, 3.0, 12.8, 0.01, 0.1)]
 
 
 @pytest.mark.parametrize("dim,n,p,L,s,eps", SOLVES)
@@ -173,13 +175,13 @@ def test_solve_parity_order6(psd, n):
 # --------------------------------------------------------------------------
 # mixed precision, graphs, batching
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("dim,n", [(2, 128), (3, 48)])
-def test_mixed_precision_reaches_fp64_answer(psd, dim, n):
+@pytest.mark.parametrize("dim,n,p", [(2, 128, 4.0), (3, 48, 4.0), (3, 32, 3.0)])
+def test_mixed_precision_reaches_fp64_answer(psd, dim, n, p):
     L = 12.8
     f = psd_inputs.small_field(dim, n, L, 51, K=6)
-    O = oracle.Problem(dim, n, L, p=4.0, s=0.01, eps=0.1)
+    O = oracle.Problem(dim, n, L, p=p, s=0.01, eps=0.1)
     ref = O.solve(f, tol=1e-12, max_iter=300)
-    P = psd.Problem(dim, n, L, 4, 4.0, 0.01, 0.1)
+    P = psd.Problem(dim, n, L, 4, p, 0.01, 0.1)
     with psd.Solver(P, tol=1e-10, max_iter=300, precision="mixed") as S:
         u = torch.zeros_like(dev(f))
         st = S.solve([dev(f)], [u])[0]
