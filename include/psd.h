@@ -92,8 +92,8 @@ typedef struct {
     int autotune;  /* non-zero: at psd_create, time the 3D stencil-kernel tilings
                       (residual z-chunk 16/28/40/64, line-search z-chunk
                       12/24/36/60, plus per kernel the chunk at which all its
-                      blocks are resident at once; line-search tile 64x4 or
-                      32x8; natural or XCD-grouped block order) on this
+                      blocks are resident at once; line-search tile 64x8 or
+                      32x16; natural or XCD-grouped block order) on this
                       handle's buffers and keep the fastest; results are
                       cached in the file named by PSD_TUNE_CACHE when set */
 } psd_options;

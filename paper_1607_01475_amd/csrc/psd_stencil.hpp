@@ -24,14 +24,6 @@ constexpr int T2X = 64, T2Y = 8;     // 2D: 512 cells, 2 per thread
 // waste nothing.  Defaults and the autotuner's candidates follow that rule.
 constexpr int T3Z_RES = 64, T3Z_LS = 60;   // one full wave of resident blocks at 256^3
 constexpr int T3Z_MIN = 12;          // smallest chunk any tuning may pick
-// line-search halo loads on every thread (1) or on the halo threads only (0)
-#ifndef PSD_LS_RING_ALL
-#define PSD_LS_RING_ALL 0
-#endif
-// planes whose line-search loads are in flight ahead of the current step
-#ifndef PSD_LS_PREFETCH
-#define PSD_LS_PREFETCH 1
-#endif
 
 __device__ __forceinline__ double flux_r(double g2, double p, int p_is_4, int p_is_2) {
   if (p_is_4) return g2;
@@ -669,16 +661,18 @@ __device__ void ls2d_tile(const Inst& I, int x0, int y0, double* lds, double (&a
   }
 }
 
-// 3D line-search sums: a TX x (256/TX) column tile (one column per thread;
-// TX = 64 where every grid has n >= 64, else 32: wider tiles need fewer
-// single-element halo loads per plane); own-column u (planes k, k+1) and d
-// (planes k-1, k, k+1) in registers, xy-halo of 3 planes of u and d in LDS
-// (halo 1), loads of plane k+2 issued before plane k is reduced.
+// 3D line-search sums: a TX x (2 * 256/TX) column tile, two cell columns
+// per thread (TX = 64 where every grid has n >= 64, else 32: wider tiles
+// need fewer single-element halo loads per plane); own-column u and d in
+// registers, xy-halo of 3 planes of u and d in LDS (halo 1), loads of plane
+// k+2 issued before plane k is reduced.
+constexpr int L3_CY = 2;   // cells per thread along y
 template <int TX>
 struct L3Shape {
-  static constexpr int TY = PSD_NT / TX;
-  static constexpr int W = TX + 2, H = TY + 2, P = W * H;
-  static constexpr int RING = P - TX * TY;   // halo cells of a plane
+  static constexpr int TY = PSD_NT / TX;        // thread rows
+  static constexpr int CH = L3_CY * TY;         // cell rows of a tile
+  static constexpr int W = TX + 2, H = CH + 2, P = W * H;
+  static constexpr int RING = P - TX * CH;   // halo cells of a plane
   static constexpr int LDS = 6 * P;          // u: 3 planes, d: 3 planes
   static_assert(RING <= PSD_NT, "ring size");
   // position in a plane buffer of halo cell number t (< RING)
@@ -694,21 +688,20 @@ struct L3Shape {
 };
 constexpr int L3_TX_WIDE = 64, L3_TX_NARROW = 32;
 
+// Thread (tx, ty) owns cells (tx, 2ty) and (tx, 2ty + 1) of the tile, so
+// the lower vertex row and the Laplacian's y-neighbours come from its own
+// registers: 11 LDS reads per two cells and plane instead of 18 with one
+// cell per thread, and one barrier per two cells.
 template <typename TD>
 struct L3Prefetch {
-  double u_own, u_ring;
-  TD d_own, d_ring;
+  double u0, u1, u_ring;
+  TD d0, d1, d_ring;
 };
 
-// The plane march of a 3D line-search block.  Step k (relative q = k - z0)
-// stores plane k+1, forms the vertex partials of plane k+1 for u and d (the
-// vertex gradients of Sec. 5.1 between planes k and k+1 are sums of the two
-// planes' partials, kept scaled by 4h and rescaled once at the end) and the
-// Laplacian of d at plane k.  As in the residual, six steps are unrolled with
-// compile-time buffer indices; steps past the chunk add nothing.
 template <typename TD, int MODE, int TX>
 struct Ls3March {
   using SH = L3Shape<TX>;
+  static_assert(SH::CH == 2 * SH::TY, "two cells per thread");
   static constexpr int L3_W = SH::W, L3_P = SH::P, L3_RING = SH::RING;
   const Inst& I;
   const PSD_GLOBAL double* u;
@@ -716,15 +709,14 @@ struct Ls3March {
   double* ub;
   double* db;
   double alpha, ih2;
-  long long nn, own_xy, ring_xy;
-  int n, z0, z1, tid, c, ring;
-  bool own;
-  double dcol[3];                  // own d at planes (rel) r mod 3
-  VPart pu[2], pd[2];              // partials of u, d at planes r mod 2
-  double n10[2], n01[2];           // d at (x+1), (y+1) of the own cell, planes r mod 2
+  long long nn, own0, own1, ring_xy;
+  int n, z0, z1, tid, c0, c1, ring;
+  bool ok0, ok1;
+  double ucol[3][2], dcol[3][2];   // own u, d of cells 0, 1 at planes (rel) r mod 3
+  VPart pu[2][2], pd[2][2];        // partials of the vertices of cells 0, 1, planes r mod 2
+  double n10[2][2], n01[2];        // d at x+1 of cells 0, 1 and at y+1 of cell 1, planes r mod 2
   double sacc[8];
-  static constexpr int PD = PSD_LS_PREFETCH;   // planes in flight ahead of the step
-  L3Prefetch<TD> pf[PD];
+  L3Prefetch<TD> pf;
 
   __device__ __forceinline__ Ls3March(const Inst& I_, int x0, int y0, int z0_, double* lds) : I(I_) {
     const SolveState* st = I.st;
@@ -740,50 +732,55 @@ struct Ls3March {
     z1 = min(z0 + I.zchunk_ls, n);
     tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
-    own = x0 + tx < n && y0 + ty < n;
-    c = (ty + 1) * L3_W + tx + 1;
-    ring = tid < L3_RING ? SH::ring_pos(tid) : c;
+    const int gx = x0 + tx, gy = y0 + 2 * ty;
+    ok0 = gx < n && gy < n;
+    ok1 = gx < n && gy + 1 < n;
+    c0 = (2 * ty + 1) * L3_W + tx + 1;
+    c1 = c0 + L3_W;
+    ring = tid < L3_RING ? SH::ring_pos(tid) : c0;
     const int rey = ring / L3_W, rex = ring - rey * L3_W;
-    own_xy = wrapi(x0 + tx, n) + (long long)n * wrapi(y0 + ty, n);
-    ring_xy = tid < L3_RING ? wrapi(x0 - 1 + rex, n) + (long long)n * wrapi(y0 - 1 + rey, n) : own_xy;
+    own0 = wrapi(gx, n) + (long long)n * wrapi(gy, n);
+    own1 = wrapi(gx, n) + (long long)n * wrapi(gy + 1, n);
+    ring_xy = tid < L3_RING ? wrapi(x0 - 1 + rex, n) + (long long)n * wrapi(y0 - 1 + rey, n) : own0;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) dcol[k] = 0.0;
+    for (int k = 0; k < 3; ++k) ucol[k][0] = ucol[k][1] = dcol[k][0] = dcol[k][1] = 0.0;
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      pu[k] = pd[k] = VPart{0.0, 0.0, 0.0};
-      n10[k] = n01[k] = 0.0;
+      pu[k][0] = pu[k][1] = pd[k][0] = pd[k][1] = VPart{0.0, 0.0, 0.0};
+      n10[k][0] = n10[k][1] = n01[k] = 0.0;
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) sacc[k] = 0.0;
   }
 
-  template <int B>
   __device__ __forceinline__ void fetch(int z) {
     const long long zo = (long long)wrapi(z, n) * nn;
-    pf[B].u_own = u[zo + own_xy];
-    pf[B].d_own = d[zo + own_xy];
-#if PSD_LS_RING_ALL
-    // ring loads on every thread (non-ring threads re-read their own cell)
-    pf[B].u_ring = u[zo + ring_xy];
-    pf[B].d_ring = d[zo + ring_xy];
-#else
+    pf.u0 = u[zo + own0];
+    pf.u1 = u[zo + own1];
+    pf.d0 = d[zo + own0];
+    pf.d1 = d[zo + own1];
     if (tid < L3_RING) {
-      pf[B].u_ring = u[zo + ring_xy];
-      pf[B].d_ring = d[zo + ring_xy];
+      pf.u_ring = u[zo + ring_xy];
+      pf.d_ring = d[zo + ring_xy];
     }
-#endif
   }
 
-  template <int S, int B>
+  template <int S>
   __device__ __forceinline__ void put() {
-    const L3Prefetch<TD>& pf = this->pf[B];
-    ub[S * L3_P + c] = pf.u_own;
-    db[S * L3_P + c] = (double)pf.d_own;
+    double* us = ub + S * L3_P;
+    double* ds = db + S * L3_P;
+    us[c0] = pf.u0;
+    us[c1] = pf.u1;
+    ds[c0] = (double)pf.d0;
+    ds[c1] = (double)pf.d1;
     if (tid < L3_RING) {
-      ub[S * L3_P + ring] = pf.u_ring;
-      db[S * L3_P + ring] = (double)pf.d_ring;
+      us[ring] = pf.u_ring;
+      ds[ring] = (double)pf.d_ring;
     }
-    dcol[S] = (double)pf.d_own;
+    ucol[S][0] = pf.u0;
+    ucol[S][1] = pf.u1;
+    dcol[S][0] = (double)pf.d0;
+    dcol[S][1] = (double)pf.d1;
   }
 
   // partials of the plane in slot S into register slot R
@@ -791,22 +788,37 @@ struct Ls3March {
   __device__ __forceinline__ void partials() {
     const double* u1 = ub + S * L3_P;
     const double* d1 = db + S * L3_P;
-    const double a10 = u1[c + 1], a01 = u1[c + L3_W], a11 = u1[c + L3_W + 1];
-    pu[R] = vpart(u1[c], a10, a01, a11);
-    const double b10 = d1[c + 1], b01 = d1[c + L3_W], b11 = d1[c + L3_W + 1];
-    pd[R] = vpart(dcol[S], b10, b01, b11);
-    n10[R] = b10;
-    n01[R] = b01;
+    const double ua = u1[c0 + 1], ub1 = u1[c1 + 1], uc = u1[c1 + L3_W], ud = u1[c1 + L3_W + 1];
+    pu[R][0] = vpart(ucol[S][0], ua, ucol[S][1], ub1);
+    pu[R][1] = vpart(ucol[S][1], ub1, uc, ud);
+    const double da = d1[c0 + 1], db1 = d1[c1 + 1], dc = d1[c1 + L3_W], dd = d1[c1 + L3_W + 1];
+    pd[R][0] = vpart(dcol[S][0], da, dcol[S][1], db1);
+    pd[R][1] = vpart(dcol[S][1], db1, dc, dd);
+    n10[R][0] = da;
+    n10[R][1] = db1;
+    n01[R] = dc;
+  }
+
+  __device__ __forceinline__ void vertex(const VPart& a0, const VPart& a1, const VPart& b0, const VPart& b1) {
+    const double ax = a0.ex + a1.ex, ay = a0.ey + a1.ey, az = a1.sm - a0.sm;
+    const double bx = b0.ex + b1.ex, by = b0.ey + b1.ey, bz = b1.sm - b0.sm;
+    ls_vertex<MODE>(I.p, alpha, ax, ay, az, bx, by, bz, sacc);
+  }
+
+  __device__ __forceinline__ void cell(double dk, double ld) {
+    if (MODE == 0) { sacc[4] += dk * dk; sacc[5] += ld * ld; }
+    else { sacc[2] += dk * dk; sacc[3] += ld * ld; }
   }
 
   // plane z0-1 enters only through the own d; plane z0 in slot 1; plane
   // z0+1 in flight
   __device__ __forceinline__ void prologue() {
-    dcol[0] = (double)d[(long long)wrapi(z0 - 1, n) * nn + own_xy];
-    fetch<0>(z0);
-    put<1, 0>();
-    fetch<0>(z0 + 1);                          // plane z0+m in buffer (m-1) mod PD
-    if constexpr (PD == 2) fetch<1>(z0 + 2);
+    const long long zm = (long long)wrapi(z0 - 1, n) * nn;
+    dcol[0][0] = (double)d[zm + own0];
+    dcol[0][1] = (double)d[zm + own1];
+    fetch(z0);
+    put<1>();
+    fetch(z0 + 1);
     __syncthreads();
     partials<1, 1>();
   }
@@ -816,20 +828,24 @@ struct Ls3March {
     // relative plane index r = plane - z0 + 1: k-1 -> q, k -> q+1, k+1 -> q+2
     constexpr int SM = Q % 3, SK = (Q + 1) % 3, SN = (Q + 2) % 3;
     constexpr int RK = (Q + 1) & 1, RN = Q & 1;
-    constexpr int B = (PD == 2) ? (Q & 1) : 0;   // buffer of plane k+1
-    put<SN, B>();
-    fetch<B>(k + 1 + PD);   // planes past the chunk are read and never used
+    put<SN>();
+    fetch(k + 2);   // planes past the chunk are read and never used
     __syncthreads();
     partials<SN, RN>();
-    if (k < z1 && own) {
-      const double ax = pu[RK].ex + pu[RN].ex, ay = pu[RK].ey + pu[RN].ey, az = pu[RN].sm - pu[RK].sm;
-      const double bx = pd[RK].ex + pd[RN].ex, by = pd[RK].ey + pd[RN].ey, bz = pd[RN].sm - pd[RK].sm;
-      ls_vertex<MODE>(I.p, alpha, ax, ay, az, bx, by, bz, sacc);
+    if (k < z1) {
       const double* d0 = db + SK * L3_P;
-      const double dk = dcol[SK];
-      const double ld = (d0[c - 1] + n10[RK] + d0[c - L3_W] + n01[RK] + dcol[SM] + dcol[SN] - 6.0 * dk) * ih2;
-      if (MODE == 0) { sacc[4] += dk * dk; sacc[5] += ld * ld; }
-      else { sacc[2] += dk * dk; sacc[3] += ld * ld; }
+      if (ok0) {
+        vertex(pu[RK][0], pu[RN][0], pd[RK][0], pd[RN][0]);
+        const double dk = dcol[SK][0];
+        cell(dk, (d0[c0 - 1] + n10[RK][0] + d0[c0 - L3_W] + dcol[SK][1] + dcol[SM][0] + dcol[SN][0] -
+                  6.0 * dk) * ih2);
+      }
+      if (ok1) {
+        vertex(pu[RK][1], pu[RN][1], pd[RK][1], pd[RN][1]);
+        const double dk = dcol[SK][1];
+        cell(dk, (d0[c1 - 1] + n10[RK][1] + dcol[SK][0] + n01[RK] + dcol[SM][1] + dcol[SN][1] -
+                  6.0 * dk) * ih2);
+      }
     }
   }
 
