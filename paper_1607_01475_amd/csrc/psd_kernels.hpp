@@ -65,13 +65,13 @@ __global__ __launch_bounds__(PSD_NT) void k_res2d(const Inst* __restrict__ insts
   }
 }
 
-// Register budget of the 3D residual: PSD_RES3D_WAVES waves per SIMD (4: at
-// most 128 VGPRs; the LDS tile allows six blocks per CU)
-#ifndef PSD_RES3D_WAVES
-#define PSD_RES3D_WAVES 4
-#endif
+// Register budget of the 3D residual: two cells per thread need up to 232
+// VGPRs (general p), so 2 waves per SIMD; at 3 waves the p = 4 mixed kernel
+// fits but measured slower (125 against 117 us at 256^3) and the general-p
+// and FP64 ones spill.
+constexpr int RES3D_WAVES = 2;
 template <typename TD, typename TR, bool UPD, int PK, int TX>
-__global__ __launch_bounds__(PSD_NT) __attribute__((amdgpu_waves_per_eu(PSD_RES3D_WAVES))) void k_res3d(const Inst* __restrict__ insts,
+__global__ __launch_bounds__(PSD_NT) __attribute__((amdgpu_waves_per_eu(RES3D_WAVES))) void k_res3d(const Inst* __restrict__ insts,
                                                   const Task2* __restrict__ tasks) {
   extern __shared__ double smem[];
   const Task2 t = tasks[blockIdx.x];

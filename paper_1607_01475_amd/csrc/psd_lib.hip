@@ -365,7 +365,7 @@ static void build_tile_tasks(psd_handle* h) {
       } else {
         const int z = std::min(zc, I.n);
         const int tx = pass == 0 ? R3_TX : h->ls_tx;   // tile shape tx x ty
-        const int ty = pass == 0 ? PSD_NT / tx : L3_CY * PSD_NT / tx;
+        const int ty = (pass == 0 ? R3_CY : L3_CY) * PSD_NT / tx;
         for (int z0 = 0; z0 < I.n; z0 += z)
           for (int y0 = 0; y0 < I.n; y0 += ty)
             for (int x0 = 0; x0 < I.n; x0 += tx) {
@@ -824,7 +824,7 @@ static psd_status autotune_impl(psd_handle* h) {
       while ((z + extra_steps) % 6) ++z;
       return z;
     };
-    const int zr = balanced(R3_TX, PSD_NT / R3_TX, occ_res, 2);
+    const int zr = balanced(R3_TX, R3_CY * PSD_NT / R3_TX, occ_res, 2);
     const int zl = balanced(h->ls_tx, L3_CY * PSD_NT / h->ls_tx, occ_ls, 0);
     bool seen = false;
     for (size_t i = 0; i < zres.size(); ++i) seen = seen || (zres[i] == zr && zls[i] == zl);

@@ -18,7 +18,7 @@ namespace psd {
 
 // tile shapes
 constexpr int T2X = 64, T2Y = 8;     // 2D: 512 cells, 2 per thread
-// 3D tiles: one (x,y) column per thread; shapes in R3Shape / L3Shape
+// 3D tiles: two (x,y) cell columns per thread; shapes in R3Shape / L3Shape
 // 3D: planes marched per block.  The residual runs z-chunk + 2 steps, the
 // line search z-chunk steps, both in groups of six: chunks with 6 | steps
 // waste nothing.  Defaults and the autotuner's candidates follow that rule.
@@ -214,8 +214,8 @@ __device__ void res2d_tile(const Inst& I, int x0, int y0, double* lds, double (&
 }
 
 // ===========================================================================
-// 3D residual: a 32 x 8 column tile marching a chunk of planes in z.
-// Each thread owns one (x, y) column: its values of v = u + alpha d and of
+// 3D residual: a 32 x 16 column tile marching a chunk of planes in z.
+// Each thread owns two (x, y) columns: their values of v = u + alpha d and of
 // Delta_h v at the planes in flight stay in registers; LDS holds the xy-halo
 // of 3 v planes (halo 2), 2 planes of Delta_h v (halo 1) and one vertex plane
 // of fluxes stored as A = Fx + Fy, B = Fx - Fy, C = Fz, from which each
@@ -225,18 +225,21 @@ __device__ void res2d_tile(const Inst& I, int x0, int y0, double* lds, double (&
 // The global loads of planes j+3 and j+4 are in flight while plane j is
 // computed.
 // ===========================================================================
-// Tile shape of the 3D residual: TX x (256 / TX) columns.  TX = 32 (32 x 8);
-// 64 x 4 was measured slower at 256^3 (the wider halo rows cost more than the
-// fewer single-element halo loads save).
+// Tile shape of the 3D residual: TX x (2 * 256 / TX) cell columns, two per
+// thread along y.  TX = 32 (32 x 16); 64-wide tiles were measured slower at
+// 256^3 (the wider halo rows cost more than the fewer single-element halo
+// loads save).
+constexpr int R3_CY = 2;   // cells per thread along y
 template <int TX>
 struct R3Shape {
-  static constexpr int TY = PSD_NT / TX;
-  static constexpr int VW = TX + 4, VH = TY + 4, VP = VW * VH;   // v planes (halo 2)
-  static constexpr int LW = TX + 2, LH = TY + 2, LP = LW * LH;   // Laplacian planes (halo 1)
-  static constexpr int FW = TX + 1, FH = TY + 1, FP = FW * FH;   // vertex planes
-  static constexpr int VRING = VP - TX * TY;   // halo cells of a v plane
-  static constexpr int LRING = LP - TX * TY;   // halo cells of a Laplacian plane
-  static constexpr int FRING = FP - TX * TY;   // halo vertices of a flux plane
+  static constexpr int TY = PSD_NT / TX;        // thread rows
+  static constexpr int CH = R3_CY * TY;         // cell rows of a tile
+  static constexpr int VW = TX + 4, VH = CH + 4, VP = VW * VH;   // v planes (halo 2)
+  static constexpr int LW = TX + 2, LH = CH + 2, LP = LW * LH;   // Laplacian planes (halo 1)
+  static constexpr int FW = TX + 1, FH = CH + 1, FP = FW * FH;   // vertex planes
+  static constexpr int VRING = VP - TX * CH;   // halo cells of a v plane
+  static constexpr int LRING = LP - TX * CH;   // halo cells of a Laplacian plane
+  static constexpr int FRING = FP - TX * CH;   // halo vertices of a flux plane
   static constexpr int LDS = 3 * VP + 2 * LP + 3 * FP;
   static constexpr int HLDS = LDS + 3 * VP;   // Hessian mode: 3 more planes (u*)
   static_assert(VRING <= PSD_NT && LRING <= PSD_NT && FRING <= PSD_NT, "ring sizes");
@@ -269,12 +272,6 @@ struct R3Shape {
   }
 };
 constexpr int R3_TX = 32;
-
-template <typename TD>
-struct R3Prefetch {
-  double u_own, u_ring;
-  TD d_own, d_ring;
-};
 
 // Per-plane partial sums of the 2x2 cells (c00, c10, c01, c11) below or
 // above a vertex: the vertex gradient of Sec. 5.1 (3D form) between planes k
@@ -332,39 +329,46 @@ __device__ __forceinline__ double flux_rr(double g2, double p) {
 // plane j.  Every buffer rotates with period 2 or 3, so six consecutive steps
 // are unrolled with compile-time buffer indices (no register copies, no
 // modulo arithmetic); a block runs whole groups of six steps, steps past the
-// chunk write nothing.
+// chunk write nothing.  Thread (tx, ty) owns cells (tx, 2ty) and (tx, 2ty + 1):
+// the y-neighbours inside the pair, the lower vertex of the upper cell and
+// its flux come from registers (7 LDS reads for both cells' Laplacians and
+// partials, 9 for their divergences, 6 for their Delta_h^2, against 10, 12
+// and 8 with one cell per thread).
+template <typename TD>
+struct R3Prefetch {
+  double u0, u1, u_ring;
+  TD d0, d1, d_ring;
+};
+
 template <typename TD, typename TR, bool UPD, bool HESS, int PK, int TX>
 struct Res3March {
   static constexpr bool LOADD = UPD || HESS;
   using SH = R3Shape<TX>;
-  static constexpr int R3_VW = SH::VW, R3_VP = SH::VP, R3_LW = SH::LW, R3_LP = SH::LP;
-  static constexpr int R3_FW = SH::FW, R3_FP = SH::FP;
-  static constexpr int R3_VRING = SH::VRING, R3_LRING = SH::LRING, R3_FRING = SH::FRING;
+  static_assert(SH::CH == 2 * SH::TY, "two cells per thread");
+  static constexpr int VW = SH::VW, VP = SH::VP, LW = SH::LW, LP = SH::LP, FW = SH::FW, FP = SH::FP;
+  static constexpr int VRING = SH::VRING, LRING = SH::LRING, FRING = SH::FRING;
   const Inst& I;
   const PSD_GLOBAL double* u;
   PSD_GLOBAL double* uo;
   const PSD_GLOBAL TD* d;
   const PSD_GLOBAL double* f;
   PSD_GLOBAL TR* r;
-  PSD_GLOBAL double* hp;   // Hessian mode output
-  double* vb;   // 3 v planes
-  double* lb;   // 2 Laplacian planes
-  double* fA;   // one vertex plane: A, B, C
+  PSD_GLOBAL double* hp;
+  double* vb;
+  double* lb;
+  double* fA;
   double* fB;
   double* fC;
-  double* sb;   // Hessian mode: 3 planes of u*
+  double* sb;
   double alpha, ih2, qhp, s, se2, p;
-  long long nn;             // n*n
-  long long own_xy, ring_xy, fcol;
+  long long nn, own0, own1, ring_xy, gout0;
   int n, z0, z1, tid;
-  int vown, lown, fown, vring, lring, fring, fring_c;
-  long long gout;           // output offset of the own cell in plane 0
-  bool own;
-  // rotating registers
-  double vc[3], sc[3], lap[3];
-  VPart po[2], pr[2], so[2], sr[2];
-  double Pq[2], Qq[2], fv[2];
-  R3Prefetch<TD> pf[2];     // planes in flight: two steps ahead
+  int c0, c1, l0, l1, f0, f1, vring, lring, lring_c, fring, fring_c;
+  bool ok0, ok1;
+  double vc[3][2], sc[3][2], lap[3][2];
+  VPart po[2][2], pr[2], so[2][2], sr[2];
+  double Pq[2], Qq[2], fv[2];   // per cell: divergence terms of the vertex plane below, f
+  R3Prefetch<TD> pf[2];
   double acc0, acc1;
 
   __device__ __forceinline__ Res3March(const Inst& I_, int x0, int y0, int z0_, double* lds)
@@ -379,16 +383,15 @@ struct Res3March {
     r = gmem((TR*)I.r);
     hp = gmem(I.adj_Hp);
     vb = lds;
-    lb = vb + 3 * R3_VP;
-    fA = lb + 2 * R3_LP;
-    fB = fA + R3_FP;
-    fC = fB + R3_FP;
+    lb = vb + 3 * VP;
+    fA = lb + 2 * LP;
+    fB = fA + FP;
+    fC = fB + FP;
     sb = lds + SH::LDS;
     n = I.n;
     nn = (long long)n * n;
     const double ih = I.inv_h, qh = 0.25 * ih;
     ih2 = ih * ih;
-    // (1/(4h))^p: the divergence's 1/(4h) times the flux's (1/(4h))^(p-1)
     qhp = PK == 4 ? (qh * qh) * (qh * qh) : (PK == 2 ? qh * qh : pow(qh, I.p));
     s = I.s;
     se2 = I.se2;
@@ -397,27 +400,36 @@ struct Res3March {
     z1 = min(z0 + I.zchunk_res, n);
     tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
-    vown = (ty + 2) * R3_VW + tx + 2;
-    lown = (ty + 1) * R3_LW + tx + 1;
-    fown = (ty + 1) * R3_FW + tx + 1;
-    vring = tid < R3_VRING ? SH::vring_pos(tid) : vown;
-    const int rey = vring / R3_VW, rex = vring - rey * R3_VW;
-    lring = tid < R3_LRING ? SH::lring_pos(tid) : lown;
-    fring = tid < R3_FRING ? SH::fring_pos(tid) : fown;
-    fring_c = (fring / R3_FW + 1) * R3_VW + fring % R3_FW + 1;
-    const int gx = x0 + tx, gy = y0 + ty;
-    own = gx < n && gy < n;
-    own_xy = wrapi(gx, n) + (long long)n * wrapi(gy, n);
+    c0 = (2 * ty + 2) * VW + tx + 2;
+    c1 = c0 + VW;
+    l0 = (2 * ty + 1) * LW + tx + 1;
+    l1 = l0 + LW;
+    f0 = (2 * ty + 1) * FW + tx + 1;
+    f1 = f0 + FW;
+    vring = tid < VRING ? SH::vring_pos(tid) : c0;
+    const int rey = vring / VW, rex = vring - rey * VW;
+    lring = tid < LRING ? SH::lring_pos(tid) : l0;
+    lring_c = (lring / LW + 1) * VW + lring % LW + 1;
+    fring = tid < FRING ? SH::fring_pos(tid) : f0;
+    fring_c = (fring / FW + 1) * VW + fring % FW + 1;
+    const int gx = x0 + tx, gy = y0 + 2 * ty;
+    ok0 = gx < n && gy < n;
+    ok1 = gx < n && gy + 1 < n;
+    own0 = wrapi(gx, n) + (long long)n * wrapi(gy, n);
+    own1 = wrapi(gx, n) + (long long)n * wrapi(gy + 1, n);
     ring_xy = wrapi(x0 - 2 + rex, n) + (long long)n * wrapi(y0 - 2 + rey, n);
-    fcol = own_xy;
-    gout = gx + (long long)n * gy;
+    gout0 = gx + (long long)n * gy;
     acc0 = 0.0;
     acc1 = 0.0;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) { vc[k] = 0.0; sc[k] = 0.0; lap[k] = 0.0; }
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) vc[k][e] = sc[k][e] = lap[k][e] = 0.0;
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      po[k] = pr[k] = so[k] = sr[k] = VPart{0.0, 0.0, 0.0};
+      pr[k] = sr[k] = VPart{0.0, 0.0, 0.0};
+#pragma unroll
+      for (int e = 0; e < 2; ++e) po[k][e] = so[k][e] = VPart{0.0, 0.0, 0.0};
       Pq[k] = Qq[k] = fv[k] = 0.0;
     }
   }
@@ -425,29 +437,38 @@ struct Res3March {
   template <int B>
   __device__ __forceinline__ void fetch(int z) {
     const long long zo = (long long)wrapi(z, n) * nn;
-    pf[B].u_own = u[zo + own_xy];
-    if (LOADD) pf[B].d_own = d[zo + own_xy];
-    if (tid < R3_VRING) {
+    pf[B].u0 = u[zo + own0];
+    pf[B].u1 = u[zo + own1];
+    if (LOADD) {
+      pf[B].d0 = d[zo + own0];
+      pf[B].d1 = d[zo + own1];
+    }
+    if (tid < VRING) {
       pf[B].u_ring = u[zo + ring_xy];
       if (LOADD) pf[B].d_ring = d[zo + ring_xy];
     }
   }
 
-  // put the plane prefetched in buffer B into v slot S (and u* slot S); returns own v
+  // the plane prefetched in buffer B into v slot S (and u* slot S)
   template <int S, int B>
-  __device__ __forceinline__ double put() {
-    const R3Prefetch<TD>& pf = this->pf[B];
-    double* vn = vb + S * R3_VP;
-    const double vo = UPD ? pf.u_own + alpha * (double)pf.d_own : pf.u_own;
-    vn[vown] = vo;
-    if (tid < R3_VRING) vn[vring] = UPD ? pf.u_ring + alpha * (double)pf.d_ring : pf.u_ring;
+  __device__ __forceinline__ void put() {
+    const R3Prefetch<TD>& q = pf[B];
+    double* vn = vb + S * VP;
+    const double v0 = UPD ? q.u0 + alpha * (double)q.d0 : q.u0;
+    const double v1 = UPD ? q.u1 + alpha * (double)q.d1 : q.u1;
+    vn[c0] = v0;
+    vn[c1] = v1;
+    if (tid < VRING) vn[vring] = UPD ? q.u_ring + alpha * (double)q.d_ring : q.u_ring;
+    vc[S][0] = v0;
+    vc[S][1] = v1;
     if (HESS) {
-      double* sn = sb + S * R3_VP;
-      sn[vown] = (double)pf.d_own;
-      if (tid < R3_VRING) sn[vring] = (double)pf.d_ring;
-      sc[S] = (double)pf.d_own;
+      double* sn = sb + S * VP;
+      sn[c0] = (double)q.d0;
+      sn[c1] = (double)q.d1;
+      if (tid < VRING) sn[vring] = (double)q.d_ring;
+      sc[S][0] = (double)q.d0;
+      sc[S][1] = (double)q.d1;
     }
-    return vo;
   }
 
   __device__ __forceinline__ void flux(const VPart& lo, const VPart& hi, const VPart& slo,
@@ -464,91 +485,113 @@ struct Res3March {
     }
   }
 
-  // planes z0-2, z0-1 into slots 0, 1; planes z0 (buffer 0) and z0+1
-  // (buffer 1) in flight
   __device__ __forceinline__ void prologue() {
     fetch<0>(z0 - 2);
     fetch<1>(z0 - 1);
-    vc[0] = put<0, 0>();
-    vc[1] = put<1, 1>();
+    put<0, 0>();
+    put<1, 1>();
     fetch<0>(z0);
     fetch<1>(z0 + 1);
+  }
+
+  // output value of one cell (residual, or Hessian-vector product)
+  __device__ __forceinline__ void emit(long long gi, double v, double div, double l2, double fval) {
+    if (HESS) {
+      const double hx = v - s * div + se2 * l2;
+      hp[gi] = hx;
+      acc1 += v * hx;
+    } else {
+      const double rr = fval - (v - s * div + se2 * l2);
+      r[gi] = (TR)rr;
+      if (UPD) uo[gi] = v;
+      acc0 = fmax(acc0, fabs(rr));
+      acc1 += rr * rr;
+    }
   }
 
   template <int Q>
   __device__ __forceinline__ void step(int j) {
     constexpr int S0 = Q % 3, S1 = (Q + 1) % 3, S2 = (Q + 2) % 3;   // planes j, j+1, j+2
     constexpr int P0 = Q & 1, P1 = (Q + 1) & 1;                      // planes j, j+1
-    // plane j+2 = z0 + q sits in buffer q mod 2; refill it with plane j+4
-    vc[S2] = put<S2, P0>();
+    put<S2, P0>();
     if (j + 2 < z1) fetch<P0>(j + 4);
-    if (!HESS && j + 1 >= z0 && j + 1 < z1) fv[P1] = f[fcol + nn * (j + 1)];
+    // f of output plane j: issued here, used after the second barrier
+    if (!HESS && j >= z0 && j < z1) {
+      fv[0] = f[own0 + nn * j];
+      fv[1] = f[own1 + nn * j];
+    }
     __syncthreads();
-    const double* v0 = vb + S0 * R3_VP;
-    const double* v1 = vb + S1 * R3_VP;
-    const double* v2 = vb + S2 * R3_VP;
-    const int c = vown;
-    const double xm = v1[c - 1], xp = v1[c + 1], ym = v1[c - R3_VW], yp = v1[c + R3_VW];
-    const double xyp = v1[c + R3_VW + 1];
-    // Laplacian of plane j+1: own cell and ring
-    double* ln = lb + P1 * R3_LP;
+    const double* v0 = vb + S0 * VP;
+    const double* v1 = vb + S1 * VP;
+    const double* v2 = vb + S2 * VP;
+    // plane j+1 around the pair: x-neighbours of both cells, y- of the lower,
+    // y+ and xy+ of the upper
+    const double xm0 = v1[c0 - 1], xp0 = v1[c0 + 1], ym0 = v1[c0 - VW];
+    const double xm1 = v1[c1 - 1], xp1 = v1[c1 + 1], yp1 = v1[c1 + VW], xyp1 = v1[c1 + VW + 1];
+    double* ln = lb + P1 * LP;
     {
-      const double lp = (xm + xp + ym + yp + vc[S0] + vc[S2] - 6.0 * vc[S1]) * ih2;
-      ln[lown] = lp;
-      lap[S1] = lp;
-      if (tid < R3_LRING) {
-        const int ly = lring / R3_LW, lx = lring - ly * R3_LW;
-        const int cc = (ly + 1) * R3_VW + lx + 1;
-        ln[lring] = (v1[cc - 1] + v1[cc + 1] + v1[cc - R3_VW] + v1[cc + R3_VW] + v0[cc] + v2[cc] - 6.0 * v1[cc]) * ih2;
+      const double lp0 = (xm0 + xp0 + ym0 + vc[S1][1] + vc[S0][0] + vc[S2][0] - 6.0 * vc[S1][0]) * ih2;
+      const double lp1 = (xm1 + xp1 + vc[S1][0] + yp1 + vc[S0][1] + vc[S2][1] - 6.0 * vc[S1][1]) * ih2;
+      ln[l0] = lp0;
+      ln[l1] = lp1;
+      lap[S1][0] = lp0;
+      lap[S1][1] = lp1;
+      if (tid < LRING) {
+        const int cc = lring_c;
+        ln[lring] = (v1[cc - 1] + v1[cc + 1] + v1[cc - VW] + v1[cc + VW] + v0[cc] + v2[cc] - 6.0 * v1[cc]) * ih2;
       }
     }
-    // partials of plane j+1 (own vertex; ring vertex on the ring threads)
-    po[P1] = vpart(vc[S1], xp, yp, xyp);
-    pr[P1] = vpart(v1[fring_c], v1[fring_c + 1], v1[fring_c + R3_VW], v1[fring_c + R3_VW + 1]);
+    // partials of plane j+1: the pair's two vertices and the ring vertex
+    po[P1][0] = vpart(vc[S1][0], xp0, vc[S1][1], xp1);
+    po[P1][1] = vpart(vc[S1][1], xp1, yp1, xyp1);
+    pr[P1] = vpart(v1[fring_c], v1[fring_c + 1], v1[fring_c + VW], v1[fring_c + VW + 1]);
     if (HESS) {
-      const double* s1 = sb + S1 * R3_VP;
-      so[P1] = vpart(sc[S1], s1[c + 1], s1[c + R3_VW], s1[c + R3_VW + 1]);
-      sr[P1] = vpart(s1[fring_c], s1[fring_c + 1], s1[fring_c + R3_VW], s1[fring_c + R3_VW + 1]);
+      const double* s1 = sb + S1 * VP;
+      const double sxp0 = s1[c0 + 1], sxp1 = s1[c1 + 1];
+      so[P1][0] = vpart(sc[S1][0], sxp0, sc[S1][1], sxp1);
+      so[P1][1] = vpart(sc[S1][1], sxp1, s1[c1 + VW], s1[c1 + VW + 1]);
+      sr[P1] = vpart(s1[fring_c], s1[fring_c + 1], s1[fring_c + VW], s1[fring_c + VW + 1]);
     }
     const bool flx = j >= z0 - 1;
-    double A_own = 0.0, C_own = 0.0;
+    double A0 = 0.0, B0 = 0.0, C0 = 0.0, A1 = 0.0, C1 = 0.0;
     if (flx) {
       double A, B, C;
-      flux(po[P0], po[P1], so[P0], so[P1], A, B, C);
-      fA[fown] = A; fB[fown] = B; fC[fown] = C;
-      A_own = A; C_own = C;
-      if (tid < R3_FRING) {
+      flux(po[P0][0], po[P1][0], so[P0][0], so[P1][0], A, B, C);
+      fA[f0] = A; fB[f0] = B; fC[f0] = C;
+      A0 = A; B0 = B; C0 = C;
+      flux(po[P0][1], po[P1][1], so[P0][1], so[P1][1], A, B, C);
+      fA[f1] = A; fB[f1] = B; fC[f1] = C;
+      A1 = A; C1 = C;
+      if (tid < FRING) {
         flux(pr[P0], pr[P1], sr[P0], sr[P1], A, B, C);
         fA[fring] = A; fB[fring] = B; fC[fring] = C;
       }
     }
     __syncthreads();
     if (flx) {
-      const int fx = fown - 1, fy = fown - R3_FW, fxy = fown - R3_FW - 1;
-      const double P = A_own - fA[fxy] + fB[fy] - fB[fx];
-      const double Qz = C_own + fC[fx] + fC[fy] + fC[fxy];
-      if (j >= z0 && j < z1 && own) {
-        // output plane j: v(j) = vc[S0], Laplacian planes j-1, j, j+1
-        const double div = qhp * (P + Pq[P1] + Qz - Qq[P1]);
-        const double* lc = lb + P0 * R3_LP;   // Laplacian plane j
-        const double l2 = (lc[lown - 1] + lc[lown + 1] + lc[lown - R3_LW] + lc[lown + R3_LW] + lap[S2] +
-                           lap[S1] - 6.0 * lap[S0]) * ih2;
-        const long long gi = gout + nn * j;
-        const double v = vc[S0];
-        if (HESS) {
-          const double hx = v - s * div + se2 * l2;
-          hp[gi] = hx;
-          acc1 += v * hx;
-        } else {
-          const double rr = fv[P0] - (v - s * div + se2 * l2);
-          r[gi] = (TR)rr;
-          if (UPD) uo[gi] = v;
-          acc0 = fmax(acc0, fabs(rr));
-          acc1 += rr * rr;
+      // lower cell: vertices f0 (own), f0-1, f0-FW, f0-FW-1; upper cell: f1
+      // (own), f1-1, f0 (own), f0-1
+      const double fBx0 = fB[f0 - 1], fCx0 = fC[f0 - 1];
+      const double P_0 = A0 - fA[f0 - FW - 1] + fB[f0 - FW] - fBx0;
+      const double Q_0 = C0 + fCx0 + fC[f0 - FW] + fC[f0 - FW - 1];
+      const double P_1 = A1 - fA[f0 - 1] + B0 - fB[f1 - 1];
+      const double Q_1 = C1 + fC[f1 - 1] + C0 + fCx0;
+      if (j >= z0 && j < z1) {
+        const double* lc = lb + P0 * LP;   // Laplacian plane j
+        const long long gi = gout0 + nn * j;
+        if (ok0) {
+          const double l2 = (lc[l0 - 1] + lc[l0 + 1] + lc[l0 - LW] + lap[S0][1] + lap[S2][0] + lap[S1][0] -
+                             6.0 * lap[S0][0]) * ih2;
+          emit(gi, vc[S0][0], qhp * (P_0 + Pq[0] + Q_0 - Qq[0]), l2, fv[0]);
+        }
+        if (ok1) {
+          const double l2 = (lc[l1 - 1] + lc[l1 + 1] + lap[S0][0] + lc[l1 + LW] + lap[S2][1] + lap[S1][1] -
+                             6.0 * lap[S0][1]) * ih2;
+          emit(gi + n, vc[S0][1], qhp * (P_1 + Pq[1] + Q_1 - Qq[1]), l2, fv[1]);
         }
       }
-      Pq[P0] = P;
-      Qq[P0] = Qz;
+      Pq[0] = P_0; Qq[0] = Q_0;
+      Pq[1] = P_1; Qq[1] = Q_1;
     }
   }
 
