@@ -18,6 +18,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -53,11 +54,20 @@ def kernel_bytes(pass_name: str, n: int, dim: int, mixed: bool) -> float:
     return float(table.get(pass_name, 0.0))
 
 
-def source_hash() -> str:
+KERNEL_SOURCES = ("psd_common.hpp", "psd_fft.hpp", "psd_stencil.hpp", "psd_kernels.hpp", "psd_lib.hip")
+
+
+def source_hash(csrc: str | None = None) -> str:
+    """Hash of the kernel sources with comments, trailing blanks and empty
+    lines removed: an edit to comments keeps committed counter files valid,
+    any change to the code invalidates them."""
+    csrc = csrc or os.path.join(ROOT, "paper_1607_01475_amd", "csrc")
     h = hashlib.sha256()
-    for rel in ("psd_common.hpp", "psd_fft.hpp", "psd_stencil.hpp", "psd_kernels.hpp", "psd_lib.hip"):
-        with open(os.path.join(ROOT, "paper_1607_01475_amd", "csrc", rel), "rb") as fh:
-            h.update(fh.read())
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(csrc, rel), encoding="utf-8") as fh:
+            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        lines = (re.sub(r"//.*", "", ln).rstrip() for ln in text.splitlines())
+        h.update("\n".join(ln for ln in lines if ln).encode())
     return h.hexdigest()[:16]
 
 

@@ -354,17 +354,20 @@ struct Res3March {
   const PSD_GLOBAL double* f;
   PSD_GLOBAL TR* r;
   PSD_GLOBAL double* hp;
-  double* vb;
-  double* lb;
-  double* fA;
+  double* vb;   // 3 v planes
+  double* lb;   // 2 Laplacian planes
+  double* fA;   // one vertex plane: A, B, C
   double* fB;
   double* fC;
-  double* sb;
+  double* sb;   // Hessian mode: 3 planes of u*
   double alpha, ih2, qhp, s, se2, p;
-  long long nn, own0, own1, ring_xy, gout0;
+  long long nn, own0, own1, ring_xy, gout0;   // (x, y) offsets of the pair, halo cell, output
   int n, z0, z1, tid;
+  // LDS positions of the pair (cell 1 = cell 0 + one row) and of this
+  // thread's halo cell, halo Laplacian cell and halo vertex
   int c0, c1, l0, l1, f0, f1, vring, lring, lring_c, fring, fring_c;
-  bool ok0, ok1;
+  bool ok0, ok1;   // the pair's cells lie inside the grid
+  // rotating registers: [plane slot][cell]
   double vc[3][2], sc[3][2], lap[3][2];
   VPart po[2][2], pr[2], so[2][2], sr[2];
   double Pq[2], Qq[2], fv[2];   // per cell: divergence terms of the vertex plane below, f

@@ -70,3 +70,18 @@ def test_summarize_pmc_scales_by_the_copy(tmp_path):
     assert r["bytes_per_launch"] == 2500 * 1024
     assert r["source_hash"] == bench.source_hash()
     assert json.load(open(out)) == rec
+
+
+def test_source_hash_ignores_comments_only(tmp_path):
+    src = os.path.join(ROOT, "paper_1607_01475_amd", "csrc")
+    for rel in bench.KERNEL_SOURCES:
+        with open(os.path.join(src, rel)) as fh:
+            (tmp_path / rel).write_text(fh.read())
+    h0 = bench.source_hash(str(tmp_path))
+    assert h0 == bench.source_hash()
+    k = tmp_path / "psd_kernels.hpp"
+    text = k.read_text()
+    k.write_text("// a new comment line\n" + text.replace("\n", "  // trailing note\n", 1) + "\n/* block */\n")
+    assert bench.source_hash(str(tmp_path)) == h0
+    k.write_text(text.replace("PSD_COL_BYTES 128", "PSD_COL_BYTES 64"))
+    assert bench.source_hash(str(tmp_path)) != h0
