@@ -22,7 +22,9 @@ constexpr int T2X = 64, T2Y = 8;     // 2D: 512 cells, 2 per thread
 // 3D: planes marched per block.  The residual runs z-chunk + 2 steps, the
 // line search z-chunk steps, both in groups of six: chunks with 6 | steps
 // waste nothing.  Defaults and the autotuner's candidates follow that rule.
-constexpr int T3Z_RES = 64, T3Z_LS = 60;   // one full wave of resident blocks at 256^3
+// Defaults: at 256^3 the residual's 128 tiles x 4 chunks fill its 2 blocks
+// per CU, the line search's 128 tiles x 8 chunks its 4 blocks per CU.
+constexpr int T3Z_RES = 64, T3Z_LS = 36;
 constexpr int T3Z_MIN = 12;          // smallest chunk any tuning may pick
 
 __device__ __forceinline__ double flux_r(double g2, double p, int p_is_4, int p_is_2) {
