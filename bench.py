@@ -153,6 +153,87 @@ def summarize_pmc(fetch_dir: str, write_dir: str, out: str, workload: str = "c3_
     return rec
 
 
+# Two counter passes over the shipped stencil kernels (each within one pass of
+# the SQ block's 8 counters; GRBM_GUI_ACTIVE counts GPU cycles).
+SQ_PASSES = {
+    "A": ["SQ_WAVES", "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS",
+          "SQ_ACTIVE_INST_VMEM", "SQ_WAIT_INST_ANY", "SQ_LDS_BANK_CONFLICT", "GRBM_GUI_ACTIVE"],
+    "B": ["SQ_WAVES", "SQ_WAIT_ANY", "SQ_ACTIVE_INST_ANY", "SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM",
+          "SQ_WAIT_INST_LDS", "SQ_LDS_IDX_ACTIVE", "GRBM_GUI_ACTIVE"],
+}
+SQ_KERNELS = "k_res3d|k_ls3d"
+
+
+def sq_command(tag: str) -> str:
+    return (f"PSD_TUNE_CACHE=gpurun_out/tune.txt rocprofv3 --pmc {' '.join(SQ_PASSES[tag])} "
+            f"--kernel-include-regex '{SQ_KERNELS}' --output-format csv -d gpurun_out/sq{tag} -o pmc "
+            "-- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --forms mixed")
+
+
+def summarize_sq(dir_a: str, dir_b: str, out: str) -> dict:
+    """Markdown summary of the two SQ counter passes (SQ_PASSES) of the
+    residual and line-search kernels: per kernel, the median over its last
+    ten launches (the final host-driven solve) of every counter, and the
+    per-wave fractions of time spent issuing VALU / LDS / VMEM instructions
+    and waiting (counter / SQ_WAVE_CYCLES), LDS bank-conflict cycles per LDS
+    active cycle, and LDS / VALU instructions per wave."""
+    import csv
+    import glob
+    import statistics
+
+    def load(d):
+        per = {}
+        for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(path)):
+                name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+                rec = per.setdefault(name, {})
+                rec.setdefault(r["Counter_Name"], []).append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+                rec["_vgpr"] = r.get("VGPR_Count") or r.get("Arch_VGPR_Count")
+                rec["_lds"] = r.get("LDS_Block_Size") or r.get("Lds_Size")
+        return per
+
+    def med(rec, c):
+        v = sorted(rec.get(c, []))[-10:]
+        return statistics.median(x for _, x in v) if v else float("nan")
+
+    A, B = load(dir_a), load(dir_b)
+    lines = ["# SQ counters of the 3D stencil kernels (256^3, p = 4, mixed form)", "",
+             f"Kernel sources: comment-insensitive hash `{source_hash()}` (bench.source_hash).", "",
+             "Commands (counter passes, then this summary):", "", "```"]
+    lines += [sq_command("A"), sq_command("B"),
+              f"python bench.py --summarize-sq gpurun_out/sqA gpurun_out/sqB {out}", "```", "",
+              "Medians over the last ten launches of each kernel (the ten iterations of the final",
+              "host-driven solve).  Fractions are per wave: counter / SQ_WAVE_CYCLES.", ""]
+    res = {}
+    for name in sorted(set(A) | set(B)):
+        a, b = A.get(name, {}), B.get(name, {})
+        wc = med(a, "SQ_WAVE_CYCLES")
+        row = {c: med(a, c) for c in SQ_PASSES["A"]}
+        row.update({c: med(b, c) for c in SQ_PASSES["B"] if c not in row})
+        waves = row["SQ_WAVES"]
+        der = {
+            "valu_issue_frac": row["SQ_ACTIVE_INST_VALU"] / wc,
+            "lds_issue_frac": row["SQ_ACTIVE_INST_LDS"] / wc,
+            "vmem_issue_frac": row["SQ_ACTIVE_INST_VMEM"] / wc,
+            "wait_inst_any_frac": row["SQ_WAIT_INST_ANY"] / wc,
+            "wait_any_frac": row["SQ_WAIT_ANY"] / wc,
+            "lds_bank_conflict_per_lds_active": row["SQ_LDS_BANK_CONFLICT"] / max(row["SQ_ACTIVE_INST_LDS"], 1.0),
+            "valu_insts_per_wave": row["SQ_INSTS_VALU"] / waves,
+            "lds_insts_per_wave": row["SQ_INSTS_LDS"] / waves,
+            "vmem_insts_per_wave": row["SQ_INSTS_VMEM"] / waves,
+        }
+        res[name] = {"counters": row, "derived": der, "vgpr": a.get("_vgpr"), "lds_bytes": a.get("_lds")}
+        lines += [f"## `{name}`", "", f"VGPRs {a.get('_vgpr')}, LDS bytes {a.get('_lds')}", "",
+                  "| counter | median |", "|---|---:|"]
+        lines += [f"| {c} | {v:.4g} |" for c, v in row.items()]
+        lines += ["", "| derived | value |", "|---|---:|"]
+        lines += [f"| {c} | {v:.4g} |" for c, v in der.items()]
+        lines += [""]
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return res
+
+
 def run_form(psd, torch, P, f, precision, chunk, steps, warmup, tol=1e-10):
     # per-kernel HIP-event timing is available in the host-driven loop only
     S = psd.Solver(P, tol=tol, max_iter=500, precision=precision, graph_chunk=chunk,
@@ -335,12 +416,18 @@ def main():
                          "batch; c5: adjoint of 8 x 128^3")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 512 MiB device copy (reference for HBM counters)")
+    ap.add_argument("--summarize-sq", nargs=3, metavar=("DIR_A", "DIR_B", "OUT_MD"),
+                    help="turn the two SQ counter passes (SQ_PASSES) into a markdown summary")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
                     help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) into HBM bytes per launch")
     args = ap.parse_args()
     if args.summarize_pmc:
         rec = summarize_pmc(*args.summarize_pmc)
         print(json.dumps(rec))
+        return
+    if args.summarize_sq:
+        rec = summarize_sq(*args.summarize_sq)
+        print(json.dumps({k: v["derived"] for k, v in rec.items()}))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs on one GPU; multi-GPU runs are not part of "
@@ -417,7 +504,7 @@ def main():
         extra[f"{k}_time_to_1e-10_ms"] = round(1e3 * float(np.median(r["times"])), 3)
         extra[f"{k}_iters"] = int(np.median(r["iters"]))
         extra[f"{k}_iters_per_s"] = round(float(np.sum(r["iters"]) / np.sum(r["times"])), 2)
-        extra[f"{k}_tiling"] = dict(zip(("zchunk_res", "zchunk_ls", "xcd_res", "xcd_ls"), r["tuning"]))
+        extra[f"{k}_tiling"] = dict(zip(("zchunk_res", "zchunk_ls", "xcd_res", "xcd_ls", "ls_tile_x"), r["tuning"]))
 
     cpu = None
     if not args.no_cpu_baseline:

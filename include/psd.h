@@ -191,9 +191,11 @@ enum {
 psd_status psd_pass_times(psd_handle* h, double* ms, int* launches);
 
 /* Tiling chosen for the stencil kernels (after autotuning or defaults):
- * out[0..3] = z-chunk of the residual, z-chunk of the line search,
- * XCD-grouped order of the residual (0/1), of the line search (0/1). */
-psd_status psd_tuning(const psd_handle* h, int* out4);
+ * out[0..4] = z-chunk of the residual, z-chunk of the line search,
+ * XCD-grouped order of the residual (0/1), of the line search (0/1),
+ * 3D line-search tile width (32 or 64 cells).  out5 is host memory of five
+ * ints.  The z-chunks and tile width matter in 3D only. */
+psd_status psd_tuning(const psd_handle* h, int* out5);
 
 /* Destroy the handle and free its workspace. */
 psd_status psd_destroy(psd_handle* h);

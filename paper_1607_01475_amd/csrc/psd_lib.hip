@@ -1044,10 +1044,11 @@ extern "C" psd_status psd_create(const psd_problem* probs, int batch, const psd_
   return PSD_OK;
 }
 
-extern "C" psd_status psd_tuning(const psd_handle* h, int* out4) {
-  if (!h || !out4) return PSD_ERR_ARG;
-  out4[0] = h->tune_zc_res; out4[1] = h->tune_zc_ls;
-  out4[2] = h->tune_xcd_res ? 1 : 0; out4[3] = h->tune_xcd_ls ? 1 : 0;
+extern "C" psd_status psd_tuning(const psd_handle* h, int* out5) {
+  if (!h || !out5) return PSD_ERR_ARG;
+  out5[0] = h->tune_zc_res; out5[1] = h->tune_zc_ls;
+  out5[2] = h->tune_xcd_res ? 1 : 0; out5[3] = h->tune_xcd_ls ? 1 : 0;
+  out5[4] = h->ls_tx;
   return PSD_OK;
 }
 

@@ -245,8 +245,9 @@ class Solver:
         return np.array(buf[: 4 * cnt.value]).reshape(cnt.value, 4)
 
     def tuning(self):
-        """(z-chunk residual, z-chunk line search, XCD order residual, XCD order line search)."""
-        out = (ctypes.c_int * 4)()
+        """(z-chunk residual, z-chunk line search, XCD order residual, XCD order line search,
+        3D line-search tile width)."""
+        out = (ctypes.c_int * 5)()
         self._check(self._lib.psd_tuning(self._h, out))
         return tuple(out)
 

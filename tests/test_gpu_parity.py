@@ -9,6 +9,7 @@ import pytest
 
 import oracle
 import psd_inputs
+from parity_bounds import check_alphas, rounding_scale
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -117,16 +118,10 @@ def test_solve_parity_fp64(psd, dim, n, p, L, s, eps):
     ug = host(u)
     if st.iters == ref["iters"]:
         assert rel(ug, ref["u"]) <= 1e-11
-    # step sizes agree (same iterate sequence up to rounding).  The residual
-    # carries ~1e-16 * |N_h terms| of absolute rounding, so the relative
-    # noise of alpha_k grows like that over ||r_k||: tight while the residual
-    # is large, loose near the tolerance.
-    k = min(len(hist), len(ref["hist"]))
-    a_g, a_o = hist[:k, 0], ref["hist"][:k, 0]
-    r_prev = np.concatenate([[np.inf], ref["hist"][:k - 1, 1]])
-    big = r_prev > 1e-5
-    assert np.abs(a_g - a_o)[big].max() <= 1e-10 * np.abs(a_o).max()
-    assert np.abs(a_g - a_o).max() <= 1e-5 * np.abs(a_o).max()
+    # step sizes agree (same iterate sequence up to rounding): per-update
+    # bound from the residual's rounding scale (parity_bounds)
+    check_alphas(hist[:, 0], ref["hist"][:, 0], ref["hist"][:, 1], np.abs(f).max(),
+                 rounding_scale(O, ref["u"]), log)
     # matched iteration count
     kk = max(ref["iters"] - 2, 1)
     with psd.Solver(P, tol=0.0, max_iter=kk) as S:
@@ -152,24 +147,82 @@ def test_solve_parity_config1(psd):
         assert rel(host(u), ref["u"]) <= 1e-11
 
 
-@pytest.mark.parametrize("n", [64, 96])
-def test_solve_parity_order6(psd, n):
-    L = 12.8
-    f = psd_inputs.small_field(2, n, L, 41, K=6)
-    g = psd_inputs.small_field(2, n, L, 42, K=6)
-    O = oracle.Problem(2, n, L, order=6, p=4.0, s=0.02, eps=0.1, lam=1.0)
-    ref = O.solve(f, g=g, tol=1e-10, max_iter=300)
-    P = psd.Problem(2, n, L, 6, 4.0, 0.02, 0.1, 1.0)
-    with psd.Solver(P, tol=1e-10, max_iter=300) as S:
+def order6_inputs(n, L, seed, gbar=0.0, fbar=0.0):
+    """Seeded sixth-order right-hand sides; gbar, fbar shift the means (the
+    mean handling of Sec. 4 and Sec. 5.4 runs only when they are non-zero)."""
+    f = psd_inputs.small_field(2, n, L, seed, K=6) + fbar
+    g = psd_inputs.small_field(2, n, L, seed + 1, K=6) + gbar
+    return f, g
+
+
+# n = 192 takes the radix-3 transform; n = 96 has non-zero means of f and g
+@pytest.mark.parametrize("n,gbar,fbar", [(64, 0.0, 0.0), (96, 0.3, -0.2), (192, 0.0, 0.0)])
+def test_solve_parity_order6(psd, n, gbar, fbar):
+    L, s, eps, lam = 12.8, 0.02, 0.1, 1.0
+    f, g = order6_inputs(n, L, 41, gbar, fbar)
+    O = oracle.Problem(2, n, L, order=6, p=4.0, s=s, eps=eps, lam=lam)
+    ref = O.solve(f, g=g, tol=1e-10, max_iter=300, history=True)
+    P = psd.Problem(2, n, L, 6, 4.0, s, eps, lam)
+    with psd.Solver(P, tol=1e-10, max_iter=300, history=True) as S:
         u = torch.full_like(dev(f), float(g.mean()))
         w = torch.zeros_like(u)
         st = S.solve([dev(f)], [u], g=[dev(g)], w=[w])[0]
-    log(f"order6 n={n}: gpu iters {st.iters} oracle iters {ref['iters']}")
+        hist = S.history(0)
+    log(f"order6 n={n} gbar={gbar} fbar={fbar}: gpu iters {st.iters} oracle iters {ref['iters']}")
+    # the GPU stops on max(|r1|, |r2|) of the mixed system, the oracle on the
+    # reduced residual rho: equal in exact arithmetic (carried w consistent)
     assert st.status == 0 and abs(st.iters - ref["iters"]) <= 1
-    assert rel(host(u), ref["u"]) <= 1e-9
-    assert rel(host(w), ref["w"]) <= 1e-9
     r1, r2 = O.mixed_residuals(f, g, host(u), host(w))
     assert np.abs(r1).max() <= 2e-10 and np.abs(r2).max() <= 2e-10
+    check_alphas(hist[:, 0], ref["hist"][:, 0], ref["hist"][:, 1],
+                 np.abs(O.residual(f, np.full_like(f, g.mean()), g)).max(),
+                 rounding_scale(O, ref["u"], ref["w"]), log)
+    # matched iteration count: u and the carried w against the oracle's u and
+    # w = T_h[g - u] + s lam gbar - fbar (Sec. 4)
+    kk = ref["iters"]
+    with psd.Solver(P, tol=0.0, max_iter=kk) as S:
+        u = torch.full_like(dev(f), float(g.mean()))
+        w = torch.zeros_like(u)
+        st = S.solve([dev(f)], [u], g=[dev(g)], w=[w])[0]
+    ref_k = O.solve(f, g=g, tol=0.0, max_iter=kk)
+    assert st.iters == kk and st.status == 1
+    ug, wg = host(u), host(w)
+    log(f"  matched k={kk}: u {rel(ug, ref_k['u']):.2e} w {rel(wg, ref_k['w']):.2e}")
+    assert rel(ug, ref_k["u"]) <= 1e-11
+    assert rel(wg, ref_k["w"]) <= 1e-11
+    # conservation (Sec. 4): mean(u) = gbar, mean(w) = s lam gbar - fbar
+    assert abs(ug.mean() - g.mean()) <= 1e-13 * (1 + abs(g.mean()))
+    assert abs(wg.mean() - (s * lam * g.mean() - f.mean())) <= 1e-12 * (1 + np.abs(wg).max())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_order6_nonzero_means(psd, precision):
+    """Sixth-order instances of three sizes with different non-zero means of f
+    and g in one handle (graph-captured): each against its own oracle solve,
+    with the conservation of Sec. 4."""
+    sizes, L, s, eps, lam = [64, 96, 192], 12.8, 0.02, 0.1, 1.0
+    means = [(0.25, -0.4), (-0.3, 0.15), (0.1, 0.5)]
+    data = [order6_inputs(n, L, 140 + 2 * i, gb, fb) for i, (n, (gb, fb)) in enumerate(zip(sizes, means))]
+    probs = [psd.Problem(2, n, L, 6, 4.0, s, eps, lam) for n in sizes]
+    log(f"case batched order 6 with means, {precision}")
+    with psd.Solver(probs, tol=1e-10, max_iter=300, precision=precision, graph_chunk=4) as S:
+        us = [torch.full_like(dev(f), float(g.mean())) for f, g in data]
+        ws = [torch.zeros_like(u) for u in us]
+        stats = S.solve([dev(f) for f, _ in data], us, g=[dev(g) for _, g in data], w=ws)
+    for (f, g), n, u, w, st in zip(data, sizes, us, ws, stats):
+        O = oracle.Problem(2, n, L, order=6, p=4.0, s=s, eps=eps, lam=lam)
+        ref = O.solve(f, g=g, tol=1e-10, max_iter=300)
+        ug, wg = host(u), host(w)
+        assert st.status == 0 and st.res_inf <= 1e-10
+        r1, r2 = O.mixed_residuals(f, g, ug, wg)
+        assert np.abs(r1).max() <= 2e-10 and np.abs(r2).max() <= 2e-10
+        same_k = precision == "fp64" and st.iters == ref["iters"]
+        if precision == "fp64":
+            assert abs(st.iters - ref["iters"]) <= 1
+        assert rel(ug, ref["u"]) <= (1e-11 if same_k else 1e-9)
+        assert rel(wg, ref["w"]) <= (1e-11 if same_k else 1e-9)
+        assert abs(ug.mean() - g.mean()) <= 1e-13 * (1 + abs(g.mean()))
+        assert abs(wg.mean() - (s * lam * g.mean() - f.mean())) <= 1e-12 * (1 + np.abs(wg).max())
 
 
 # --------------------------------------------------------------------------

@@ -167,6 +167,33 @@ def test_energy_closed_form_one_mode():
         assert abs(P.energy(np.zeros_like(u), u) - E) < 1e-12 * E
 
 
+def test_energy6_closed_form_one_mode():
+    # Sixth-order discrete energy (Sec. 5.4) at nu = u - gbar on x-only data:
+    #   u = gbar + A cos(th i + phi), g = gbar + B cos(th i + psi),
+    #   f = fbar + F cos(th i + om).
+    # z = nu - g + gbar is one mode of squared amplitude C^2 = A^2 + B^2 - 2AB cos(phi - psi),
+    # and T_h z = z / kappa, so
+    #   E/h^d = n^d C^2/(4 kappa) + lam s/2 n^d (A^2/2 + gbar^2) - n^d A F cos(phi - om)/2
+    #           + s/4 n^(d-1) (2A sin(th/2)/h)^4 3n/8 + s eps^2/2 kappa^2 n^d A^2/2.
+    # Every term is non-zero, the gbar^2 term included, and f's mean drops out.
+    A, B, F, gbar, fbar = 0.7, 0.4, 0.9, 0.35, -0.6
+    phi, psi, om = 0.4, 1.3, -0.8
+    for dim, n, k in [(2, 16, 3), (3, 8, 1)]:
+        P = Problem(dim, n, 2.0, order=6, p=4.0, s=0.3, eps=0.2, lam=0.7)
+        i = np.arange(n, dtype=np.float64)
+        th = 2 * math.pi * k / n
+        row = lambda amp, ph, c: np.broadcast_to(c + amp * np.cos(th * i + ph), P.shape).copy()
+        u, g, f = row(A, phi, gbar), row(B, psi, gbar), row(F, om, fbar)
+        kap = 4 / P.h ** 2 * math.sin(th / 2) ** 2
+        C2 = A * A + B * B - 2 * A * B * math.cos(phi - psi)
+        Nd = n ** dim
+        G4 = n ** (dim - 1) * (2 * A * math.sin(th / 2) / P.h) ** 4 * 3 * n / 8
+        E = P.hd * (Nd * C2 / (4 * kap) + P.lam * P.s / 2 * Nd * (A * A / 2 + gbar * gbar)
+                    - Nd * A * F * math.cos(phi - om) / 2 + P.s / 4 * G4
+                    + P.s * P.eps ** 2 / 2 * kap ** 2 * Nd * A * A / 2)
+        assert abs(P.energy(f, u, g) - E) < 1e-12 * abs(E)
+
+
 def test_plap_closed_form_one_mode():
     # 1D-varying data: plap(u)_i = (G_{i+1/2}^3 - G_{i-1/2}^3)/h with
     # G_{i+1/2} = (u_{i+1} - u_i)/h exactly (Sec. 5.1 with constant y).
