@@ -198,7 +198,7 @@ def summarize_sq(dir_a: str, dir_b: str, out: str) -> dict:
 
     A, B = load(dir_a), load(dir_b)
     lines = ["# SQ counters of the 3D stencil kernels (256^3, p = 4, mixed form)", "",
-             f"Kernel sources: comment-insensitive hash `{source_hash()}` (bench.source_hash).", "",
+             f"Kernel sources: comment-insensitive hash `{recorded_hash(dir_a + '/x')}` (bench.source_hash).", "",
              "Commands (counter passes, then this summary):", "", "```"]
     lines += [sq_command("A"), sq_command("B"),
               f"python bench.py --summarize-sq gpurun_out/sqA gpurun_out/sqB {out}", "```", "",
@@ -223,7 +223,8 @@ def summarize_sq(dir_a: str, dir_b: str, out: str) -> dict:
             "vmem_insts_per_wave": row["SQ_INSTS_VMEM"] / waves,
         }
         res[name] = {"counters": row, "derived": der, "vgpr": a.get("_vgpr"), "lds_bytes": a.get("_lds")}
-        lines += [f"## `{name}`", "", f"VGPRs {a.get('_vgpr')}, LDS bytes {a.get('_lds')}", "",
+        lines += [f"## `{name}`", "", f"rocprofv3 reports VGPR_Count {a.get('_vgpr')}, LDS_Block_Size {a.get('_lds')} "
+                  "(static LDS only; these kernels size their LDS at launch)", "",
                   "| counter | median |", "|---|---:|"]
         lines += [f"| {c} | {v:.4g} |" for c, v in row.items()]
         lines += ["", "| derived | value |", "|---|---:|"]
@@ -234,10 +235,43 @@ def summarize_sq(dir_a: str, dir_b: str, out: str) -> dict:
     return res
 
 
-def run_form(psd, torch, P, f, precision, chunk, steps, warmup, tol=1e-10):
-    # per-kernel HIP-event timing is available in the host-driven loop only
+def recorded_hash(path: str) -> str:
+    """Kernel-source hash recorded beside profiler output (source_hash.txt,
+    written on the GPU machine when the profile was taken, in the output folder
+    or one of its parents), else the current tree's."""
+    d = os.path.dirname(os.path.abspath(path))
+    for _ in range(3):
+        f = os.path.join(d, "source_hash.txt")
+        if os.path.exists(f):
+            return open(f).read().strip() + " (recorded when the profile was taken)"
+        d = os.path.dirname(d)
+    return source_hash() + " (current tree)"
+
+
+def summarize_trace(stats_csv: str, out: str, title: str, command: str, top: int = 25) -> list:
+    """Markdown table of a rocprofv3 --kernel-trace --stats kernel_stats.csv
+    (calls, average and total duration, share of GPU time), top kernels first."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# {title}", "", f"Kernel sources: comment-insensitive hash `{recorded_hash(stats_csv)}` (bench.source_hash).",
+             "", "Commands (kernel trace, then this summary):", "", "```", command,
+             f"python bench.py --summarize-trace {stats_csv} {out} '{title}' \"{command}\"", "```", "",
+             "| kernel | calls | avg us | total ms | % |", "|---|---:|---:|---:|---:|"]
+    for r in rows[:top]:
+        name = r["Name"].replace("void ", "").split("(")[0]
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['Percentage']):.1f} |")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return rows
+
+
+def run_form(psd, torch, P, f, precision, chunk, steps, warmup, tol=1e-10, profile=False):
+    # per-kernel HIP-event timing (profile) exists in the host-driven loop only;
+    # timed forms run without it
     S = psd.Solver(P, tol=tol, max_iter=500, precision=precision, graph_chunk=chunk,
-                   profile=(chunk == 0), autotune=True)
+                   profile=profile and chunk == 0, autotune=True)
     tuning = S.tuning()
     fd = f
     u = torch.zeros_like(fd)
@@ -402,6 +436,24 @@ def cpu_baseline(f_np, n, L, p, s, eps):
                        f"residual) of the single-threaded C oracle at {n}^3, {dt:.1f} s")
 
 
+def oracle_check(u, w, iters):
+    """The mixed GPU answer measured by the oracle: its FP64 residual over the
+    whole 256^3 grid, and its distance to the oracle's own converged iterate at
+    the 1025 sampled cells of tests/golden/fullsize_c3.json (written by the
+    oracle alone), with both iteration counts."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    O = oracle.Problem(3, w.n, w.L, p=w.p, s=w.s, eps=w.eps)
+    r = O.residual(w.f, u)
+    with open(os.path.join(ROOT, "tests", "golden", "fullsize_c3.json")) as fh:
+        G = json.load(fh)
+    idx = np.asarray(G["sample_idx"])
+    err = float(np.abs(u.ravel()[idx] - np.asarray(G["u_final"]["samples"])).max() / G["u_final"]["absmax"])
+    return {"oracle_residual_inf": float(np.abs(r).max()), "rel_err_vs_oracle_sampled": err,
+            "gpu_iters": int(iters), "oracle_iters": int(G["iters"])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -416,6 +468,8 @@ def main():
                          "batch; c5: adjoint of 8 x 128^3")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 512 MiB device copy (reference for HBM counters)")
+    ap.add_argument("--summarize-trace", nargs=4, metavar=("STATS_CSV", "OUT_MD", "TITLE", "COMMAND"),
+                    help="turn a rocprofv3 --stats kernel_stats.csv into a markdown summary")
     ap.add_argument("--summarize-sq", nargs=3, metavar=("DIR_A", "DIR_B", "OUT_MD"),
                     help="turn the two SQ counter passes (SQ_PASSES) into a markdown summary")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
@@ -424,6 +478,9 @@ def main():
     if args.summarize_pmc:
         rec = summarize_pmc(*args.summarize_pmc)
         print(json.dumps(rec))
+        return
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
         return
     if args.summarize_sq:
         rec = summarize_sq(*args.summarize_sq)
@@ -461,17 +518,23 @@ def main():
 
     res = {}
     forms = args.forms.split(",")
+    # the timed forms run without per-kernel events; the per-pass times come
+    # from a separate host-driven run with events (not part of any timing)
     if "fp64" in forms:
-        log("bench: FP64 form (host-driven loop)")
+        log("bench: FP64 form, host-driven loop")
         res["fp64"] = run_form(psd, torch, P, f, "fp64", 0, args.steps, args.warmup)
+        log(f"bench: FP64 form, HIP graph chunk {args.chunk}")
+        res["fp64_graph"] = run_form(psd, torch, P, f, "fp64", args.chunk, args.steps, args.warmup)
     if "mixed" in forms:
         log(f"bench: mixed form (FP32 FFT, FP64 residual, HIP graph chunk {args.chunk})")
         res["mixed"] = run_form(psd, torch, P, f, "mixed", args.chunk, args.steps, args.warmup)
-        log("bench: mixed form, host-driven with per-kernel HIP events (roofline)")
-        res["mixed_stream"] = run_form(psd, torch, P, f, "mixed", 0, args.steps, 0)
+        log("bench: mixed form, host-driven loop with per-kernel HIP events (per-pass times)")
+        res["mixed_events"] = run_form(psd, torch, P, f, "mixed", 0, args.steps, 0, profile=True)
     head = res.get("mixed", res.get("fp64"))
     head_mixed = "mixed" in res
-    prof = res.get("mixed_stream", res.get("fp64"))
+    if "mixed_events" not in res:
+        res["fp64_events"] = run_form(psd, torch, P, f, "fp64", 0, args.steps, 0, profile=True)
+    prof = res.get("mixed_events", res.get("fp64_events"))
     t_med = float(np.median(head["times"]))
     it_med = float(np.median(head["iters"]))
     total_t = float(np.sum(head["times"]))
@@ -499,8 +562,13 @@ def main():
     if "fp64" in res and "mixed" in res:
         ua, ub = res["fp64"]["u"], res["mixed"]["u"]
         extra["mixed_vs_fp64_rel_err"] = float((ub - ua).abs().max() / ua.abs().max())
+        # plain FP64 GPU form (host loop) against mixed + graph, and the
+        # precision alone (both graph-captured)
         extra["speedup_time_to_tol"] = float(np.median(res["fp64"]["times"]) / t_med)
+        extra["speedup_precision_only"] = float(np.median(res["fp64_graph"]["times"]) / t_med)
     for k, r in res.items():
+        if k.endswith("_events"):
+            extra[f"{k}_note"] = "host-driven loop with two HIP events per kernel: per-pass times only"
         extra[f"{k}_time_to_1e-10_ms"] = round(1e3 * float(np.median(r["times"])), 3)
         extra[f"{k}_iters"] = int(np.median(r["iters"]))
         extra[f"{k}_iters_per_s"] = round(float(np.sum(r["iters"]) / np.sum(r["times"])), 2)
@@ -510,6 +578,9 @@ def main():
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline (one iteration at full size)")
         cpu = cpu_baseline(w.f, w.n, w.L, w.p, w.s, w.eps)
+        if head_mixed and w.n == 256:
+            log("bench: oracle check of the mixed answer (FP64 residual, fixture samples)")
+            cpu["check"] = oracle_check(res["mixed"]["u"].cpu().numpy(), w, res["mixed"]["iters"][-1])
 
     out = {
         "metric": "time-to-1e-10 residual & PSD iters/s, 256³ p=4: mixed/batched vs FP64 GPU",

@@ -98,6 +98,7 @@ struct psd_handle_s {
   FftTasks fft_solver;   // solver precision, NF of the order
   FftTasks fft_aux;      // FP64, one field (Poisson / energy / residual helpers)
   SolveState* dState = nullptr;
+  SolveState* dAuxState = nullptr;  // states of auxiliary evaluations (keep dState intact)
   SolveState* hState = nullptr;  // pinned
   double* hPart = nullptr;       // pinned scratch for auxiliary partials
   size_t hPartCap = 0;
@@ -121,6 +122,12 @@ struct psd_handle_s {
   int prof_iter_slot = -1;          // iteration index within a graph chunk (-1: none)
   double pass_ms[PSD_NPASS] = {0};
   int pass_n[PSD_NPASS] = {0};
+  // arena mode (no-allocation entry point): device workspace carved from
+  // `arena`, host staging in arena_hstate / arena_hpart
+  char* arena = nullptr;
+  size_t arena_cap = 0, arena_used = 0;
+  SolveState* arena_hstate = nullptr;
+  double* arena_hpart = nullptr;
 };
 
 // ---------------------------------------------------------------------------
@@ -140,8 +147,18 @@ static psd_status set_err(psd_handle* h, psd_status st, const std::string& msg) 
   return st;
 }
 
+// Device workspace: hipMalloc, or 256-byte aligned pieces of the handle's
+// arena (the no-allocation entry point) when one is attached.
 template <typename P>
 static hipError_t dalloc(psd_handle* h, P** ptr, size_t bytes) {
+  if (h->arena) {
+    const size_t off = (h->arena_used + 255) & ~(size_t)255;
+    const size_t sz = bytes ? bytes : 16;
+    if (off + sz > h->arena_cap) return hipErrorOutOfMemory;
+    *ptr = (P*)(h->arena + off);
+    h->arena_used = off + sz;
+    return hipSuccess;
+  }
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, bytes ? bytes : 16);
   if (e == hipSuccess) {
@@ -570,8 +587,10 @@ static void run_iteration_p4(psd_handle* h) {
   run_residual<TD, TR>(h, true);
 }
 
+// Copy the states the instance table currently points at (the solver's, or
+// the auxiliary ones) to the host.
 static psd_status read_states(psd_handle* h) {
-  HIPCHK(hipMemcpyAsync(h->hState, h->dState, sizeof(SolveState) * h->batch, hipMemcpyDeviceToHost,
+  HIPCHK(hipMemcpyAsync(h->hState, h->hI[0].st, sizeof(SolveState) * h->batch, hipMemcpyDeviceToHost,
                         h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   return PSD_OK;
@@ -883,27 +902,37 @@ static psd_status autotune_impl(psd_handle* h) {
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
-extern "C" psd_status psd_create(const psd_problem* probs, int batch, const psd_options* opt,
-                                 void* hip_stream, psd_handle** out) {
-  g_create_error.clear();
-  if (!out) return set_err(nullptr, PSD_ERR_ARG, "out is NULL");
-  *out = nullptr;
-  if (!probs || batch <= 0 || !opt) return set_err(nullptr, PSD_ERR_ARG, "probs/opt NULL or batch <= 0");
+// Validate a problem batch and options (host only).
+static psd_status check_create_args(const psd_problem* probs, int batch, const psd_options* opt,
+                                    std::string& msg_out) {
+  if (!probs || batch <= 0 || !opt) { msg_out = "probs/opt NULL or batch <= 0"; return PSD_ERR_ARG; }
   char msg[128];
   for (int b = 0; b < batch; ++b) {
     psd_status st = psd_check_problem(&probs[b], msg, sizeof msg);
-    if (st != PSD_OK) return set_err(nullptr, st, "instance " + std::to_string(b) + ": " + msg);
-    if (probs[b].dim != probs[0].dim || probs[b].order != probs[0].order || probs[b].p != probs[0].p)
-      return set_err(nullptr, PSD_ERR_ARG, "all instances must share dim, order and p");
+    if (st != PSD_OK) { msg_out = "instance " + std::to_string(b) + ": " + msg; return st; }
+    if (probs[b].dim != probs[0].dim || probs[b].order != probs[0].order || probs[b].p != probs[0].p) {
+      msg_out = "all instances must share dim, order and p";
+      return PSD_ERR_ARG;
+    }
   }
   if (!(opt->tol >= 0.0) || opt->max_iter < 0 || (opt->precision != PSD_FP64 && opt->precision != PSD_MIXED) ||
-      opt->graph_chunk < 0)
-    return set_err(nullptr, PSD_ERR_ARG, "bad options");
-  int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
-    return set_err(nullptr, PSD_ERR_HIP, "no HIP device");
+      opt->graph_chunk < 0) {
+    msg_out = "bad options";
+    return PSD_ERR_ARG;
+  }
+  return PSD_OK;
+}
 
-  psd_handle* h = new psd_handle();
+__global__ void k_fill_zero(double* __restrict__ p, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+// Workspace, tables and task lists of a handle whose batch, options and
+// stream are set.  Device memory comes from dalloc (hipMalloc, or the handle's
+// arena when one is attached); host staging of the solver state is pinned
+// memory, or the arena's host buffers.  On failure h->err holds the reason.
+static psd_status setup_handle(psd_handle* h, const psd_problem* probs, int batch, const psd_options* opt) {
   h->batch = batch;
   h->dim = probs[0].dim;
   h->order = probs[0].order;
@@ -914,16 +943,24 @@ extern "C" psd_status psd_create(const psd_problem* probs, int batch, const psd_
   h->opt = *opt;
   h->mixed = opt->precision == PSD_MIXED;
   h->probs.assign(probs, probs + batch);
-  (void)hipGetDevice(&h->device);
-  if (hip_stream) h->stream = (hipStream_t)hip_stream;
-  else {
-    if (hipStreamCreate(&h->stream) != hipSuccess) { delete h; return set_err(nullptr, PSD_ERR_HIP, "stream"); }
-    h->own_stream = true;
-  }
   auto fail = [&](const std::string& m) {
-    g_create_error = m;
-    psd_destroy(h);
+    h->err = m;
     return PSD_ERR_HIP;
+  };
+  // out of workspace: a HIP error with hipMalloc; with the static array a
+  // problem too large for it, an argument error
+  auto oom = [&]() {
+    if (!h->arena) return fail("out of device memory");
+    h->err = "the problem needs more workspace than the static scratch array of " +
+             std::to_string(h->arena_cap >> 20) + " MiB";
+    return PSD_ERR_ARG;
+  };
+  auto zero = [&](void* p, size_t bytes) {
+    if (h->arena) {   // stream-ordered fill (the arena keeps the last call's contents)
+      k_fill_zero<<<256, PSD_NT, 0, h->stream>>>((double*)p, (long long)(bytes / 8));
+      return hipGetLastError();
+    }
+    return hipMemset(p, 0, bytes);
   };
 
   const size_t tds = h->mixed ? sizeof(float) : sizeof(double);
@@ -959,14 +996,14 @@ extern "C" psd_status psd_create(const psd_problem* probs, int batch, const psd_
         dalloc(h, (char**)&I.spec, (size_t)I.nspec * nspec_fields * 16) ||
         dalloc(h, (double**)&I.S, (size_t)P.n * 8) || dalloc(h, (char**)&I.tw32, (size_t)P.n * 8) ||
         dalloc(h, (char**)&I.tw64, (size_t)P.n * 16))
-      return fail("out of device memory");
+      return oom();
     if (P.order == 6) {
       if (dalloc(h, &I.w[0], N * 8) || dalloc(h, &I.w[1], N * 8) || dalloc(h, (char**)&I.e1, N * tds) ||
           dalloc(h, (char**)&I.e2, N * tds) || dalloc(h, (char**)&I.r1, N * tds))
-        return fail("out of device memory");
+        return oom();
     }
-    if (hipMemset(I.spec, 0, (size_t)I.nspec * nspec_fields * 16) != hipSuccess)
-      return fail("memset of the spectrum buffer failed");
+    if (zero(I.spec, (size_t)I.nspec * nspec_fields * 16) != hipSuccess)
+      return fail("clearing the spectrum buffer failed");
     // symbol table of -Delta_h along one axis and twiddles (host, long double)
     std::vector<double> S(P.n);
     std::vector<float> t32(2 * (size_t)P.n);
@@ -984,7 +1021,7 @@ extern "C" psd_status psd_create(const psd_problem* probs, int batch, const psd_
         hipMemcpy((void*)I.tw64, t64.data(), t64.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
       return fail("copy of tables failed");
     if (opt->history && opt->max_iter > 0) {
-      if (dalloc(h, &I.hist, (size_t)opt->max_iter * 4 * 8)) return fail("out of device memory");
+      if (dalloc(h, &I.hist, (size_t)opt->max_iter * 4 * 8)) return oom();
       I.hist_cap = opt->max_iter;
     }
   }
@@ -1007,9 +1044,11 @@ extern "C" psd_status psd_create(const psd_problem* probs, int batch, const psd_
   h->ls_tx = ls_tx0;
   h->tune_zc_res = T3Z_RES;
   h->tune_zc_ls = T3Z_LS;
+  h->tune_xcd_res = h->tune_xcd_ls = false;
   build_all_tasks(h, nsp_aux);
   // partial arrays and states
-  if (dalloc(h, &h->dState, sizeof(SolveState) * batch)) return fail("out of device memory");
+  if (dalloc(h, &h->dState, sizeof(SolveState) * batch) || dalloc(h, &h->dAuxState, sizeof(SolveState) * batch))
+    return oom();
   for (int b = 0; b < batch; ++b) {
     Inst& I = h->hI[b];
     const int nsp_max = std::max(I.nblk_sp, nsp_aux[b]);
@@ -1018,22 +1057,55 @@ extern "C" psd_status psd_create(const psd_problem* probs, int batch, const psd_
     const int nres = std::max(cap_res[b], I.nblk_vec);
     if (dalloc(h, &I.part_res, (size_t)nres * 2 * 8) || dalloc(h, &I.part_ls, (size_t)cap_ls[b] * 8 * 8) ||
         dalloc(h, &I.part_sp, (size_t)nsp_max * 2 * 8) || dalloc(h, &I.part_c2r, (size_t)I.nblk_c2r * 3 * 8))
-      return fail("out of device memory");
+      return oom();
     I.st = h->dState + b;
   }
   if (dalloc(h, &h->dI, sizeof(Inst) * batch) || dalloc(h, &h->dT, sizeof(Task2) * h->dT_cap) ||
       dalloc(h, &h->dAuxPart, sizeof(double) * 5 * 1024))
-    return fail("out of device memory");
-  if (hipHostMalloc((void**)&h->hState, sizeof(SolveState) * batch, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&h->hPart, sizeof(double) * 5 * 1024, hipHostMallocDefault) != hipSuccess)
+    return oom();
+  if (h->arena) {
+    // host staging provided with the arena (no pinned allocation)
+    h->hState = h->arena_hstate;
+    h->hPart = h->arena_hpart;
+  } else if (hipHostMalloc((void**)&h->hState, sizeof(SolveState) * batch, hipHostMallocDefault) != hipSuccess ||
+             hipHostMalloc((void**)&h->hPart, sizeof(double) * 5 * 1024, hipHostMallocDefault) != hipSuccess) {
     return fail("pinned allocation failed");
+  }
   std::memset(h->hState, 0, sizeof(SolveState) * batch);
   if (hipMemcpy(h->dT, h->hT.data(), sizeof(Task2) * h->hT.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(h->dI, h->hI.data(), sizeof(Inst) * batch, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemset(h->dState, 0, sizeof(SolveState) * batch) != hipSuccess)
+      zero(h->dState, sizeof(SolveState) * batch) != hipSuccess)
     return fail("upload of tables failed");
+  return PSD_OK;
+}
+
+extern "C" psd_status psd_create(const psd_problem* probs, int batch, const psd_options* opt,
+                                 void* hip_stream, psd_handle** out) {
+  g_create_error.clear();
+  if (!out) return set_err(nullptr, PSD_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  std::string msg;
+  psd_status cst = check_create_args(probs, batch, opt, msg);
+  if (cst != PSD_OK) return set_err(nullptr, cst, msg);
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+    return set_err(nullptr, PSD_ERR_HIP, "no HIP device");
+
+  psd_handle* h = new psd_handle();
+  (void)hipGetDevice(&h->device);
+  if (hip_stream) h->stream = (hipStream_t)hip_stream;
+  else {
+    if (hipStreamCreate(&h->stream) != hipSuccess) { delete h; return set_err(nullptr, PSD_ERR_HIP, "stream"); }
+    h->own_stream = true;
+  }
+  psd_status st = setup_handle(h, probs, batch, opt);
+  if (st != PSD_OK) {
+    std::string m = h->err;
+    psd_destroy(h);
+    return set_err(nullptr, st, m);
+  }
   if (opt->autotune) {
-    psd_status st = h->mixed ? autotune_impl<float, float>(h) : autotune_impl<double, double>(h);
+    st = h->mixed ? autotune_impl<float, float>(h) : autotune_impl<double, double>(h);
     if (st != PSD_OK) {
       std::string m = "autotune: " + h->err;
       psd_destroy(h);
@@ -1155,6 +1227,26 @@ extern "C" psd_status psd_solve(psd_handle* h, const double* const* f, const dou
   return solve_impl<double, double, double>(h, f, g, u, w, stats);
 }
 
+// Auxiliary single-instance evaluations (residual, energy, Poisson solves,
+// adjoint) run on a separate state array: the state of the last solve
+// (iteration count, residual norms, history length) survives them.  Every
+// instance but `inst` (all when inst < 0) is marked finished, so their
+// blocks return at once.
+static psd_status aux_enter(psd_handle* h, int inst) {
+  for (int b = 0; b < h->batch; ++b) h->hI[b].st = h->dAuxState + b;
+  psd_status st = upload_inst(h);
+  if (st != PSD_OK) return st;
+  k_reset_state<<<(h->batch + 63) / 64, 64, 0, h->stream>>>(h->dI, h->batch);
+  if (inst >= 0) k_mark_done<<<(h->batch + 63) / 64, 64, 0, h->stream>>>(h->dI, h->batch, inst);
+  HIPCHK(hipGetLastError());
+  return PSD_OK;
+}
+
+static psd_status aux_leave(psd_handle* h) {
+  for (int b = 0; b < h->batch; ++b) h->hI[b].st = h->dState + b;
+  return upload_inst(h);
+}
+
 // Evaluate the residual kernel once for instance `inst` at caller buffers,
 // writing FP64 r (and r1 for order 6) without an update.
 static psd_status aux_residual(psd_handle* h, int inst, const double* f, const double* g, const double* u,
@@ -1166,17 +1258,15 @@ static psd_status aux_residual(psd_handle* h, int inst, const double* f, const d
   I.g = g;
   I.r = r2out;
   if (h->order == 6) { I.w[0] = const_cast<double*>(wv); I.r1 = r1out; }
-  // other instances: mark done so their tiles return at once
-  psd_status st = upload_inst(h);
-  if (st != PSD_OK) { h->hI[inst] = saved; return st; }
-  k_reset_state<<<(h->batch + 63) / 64, 64, 0, h->stream>>>(h->dI, h->batch);
-  k_mark_done<<<(h->batch + 63) / 64, 64, 0, h->stream>>>(h->dI, h->batch, inst);
-  run_residual<double, double>(h, false);
-  HIPCHK(hipGetLastError());
-  st = read_states(h);
-  if (res_inf) *res_inf = h->hState[inst].rinf;
+  psd_status st = aux_enter(h, inst);   // other instances marked done
+  if (st == PSD_OK) {
+    run_residual<double, double>(h, false);
+    st = hipGetLastError() == hipSuccess ? read_states(h) : PSD_ERR_HIP;
+    if (st == PSD_OK && res_inf) *res_inf = h->hState[inst].rinf;
+  }
+  saved.st = h->dState + inst;
   h->hI[inst] = saved;
-  psd_status st2 = upload_inst(h);
+  psd_status st2 = aux_leave(h);
   HIPCHK(hipStreamSynchronize(h->stream));
   return st != PSD_OK ? st : st2;
 }
@@ -1194,11 +1284,12 @@ extern "C" psd_status psd_residual(psd_handle* h, int inst, const double* f, con
   }
   // order 6: w = T_h(g - u); r2 = f - (s lam u - s div + s eps^2 Delta^2 u - w); rho = r2 - mean(r2)
   k_axpby<<<1024, PSD_NT, 0, h->stream>>>(I.tmp, g, u, 1.0, -1.0, 0.0, I.ncell);
-  // mark other instances done for the auxiliary transform
-  k_reset_state<<<(h->batch + 63) / 64, 64, 0, h->stream>>>(h->dI, h->batch);
-  k_mark_done<<<(h->batch + 63) / 64, 64, 0, h->stream>>>(h->dI, h->batch, inst);
-  psd_status st = aux_poisson(h, inst, nullptr);
+  // the auxiliary transform runs on instance inst only
+  psd_status st = aux_enter(h, inst);
+  if (st == PSD_OK) st = aux_poisson(h, inst, nullptr);
+  psd_status st2 = aux_leave(h);
   if (st != PSD_OK) return st;
+  if (st2 != PSD_OK) return st2;
   double* rr = r ? r : (double*)I.d;  // FP64 scratch of ncell doubles needed
   double* wtmp = I.u[1];
   HIPCHK(hipMemcpyAsync(wtmp, I.tmp, I.ncell * 8, hipMemcpyDeviceToDevice, h->stream));
@@ -1206,7 +1297,6 @@ extern "C" psd_status psd_residual(psd_handle* h, int inst, const double* f, con
     // no caller buffer: use tmp for r2 (w copied to u[1] above)
     rr = I.tmp;
   }
-  std::vector<double> dummy;
   double* r1 = I.w[1];
   st = aux_residual(h, inst, f, g, u, wtmp, rr, r1, nullptr);
   if (st != PSD_OK) return st;
@@ -1266,11 +1356,12 @@ extern "C" psd_status psd_energy(psd_handle* h, int inst, const double* f, const
   if (st != PSD_OK) return st;
   const double gbar = sg[0] / I.ncell;
   k_axpby<<<1024, PSD_NT, 0, h->stream>>>(I.tmp, u, g, 1.0, -1.0, 0.0, I.ncell);
-  k_reset_state<<<(h->batch + 63) / 64, 64, 0, h->stream>>>(h->dI, h->batch);
-  k_mark_done<<<(h->batch + 63) / 64, 64, 0, h->stream>>>(h->dI, h->batch, inst);
   double zTz = 0.0;
-  st = aux_poisson(h, inst, &zTz);
+  st = aux_enter(h, inst);
+  if (st == PSD_OK) st = aux_poisson(h, inst, &zTz);
+  psd_status st2 = aux_leave(h);
   if (st != PSD_OK) return st;
+  if (st2 != PSD_OK) return st2;
   *E = I.hd * (0.5 * zTz + 0.5 * I.lam * s * a[3] - (a[4] - gbar * sf[0]) + s / p * a[1] + 0.5 * se2 * a[2]);
   return PSD_OK;
 }
@@ -1314,13 +1405,16 @@ static psd_status adjoint_impl(psd_handle* h, const double* const* u_star, const
   for (int b = 0; b < B; ++b) {
     Inst& I = h->hI[b];
     if (!h->adj_alloc) {
-      if (dalloc(h, &I.adj_r, I.ncell * 8) || dalloc(h, &I.adj_p, I.ncell * 8) || dalloc(h, &I.adj_Hp, I.ncell * 8))
+      if (dalloc(h, &I.adj_r, I.ncell * 8) || dalloc(h, &I.adj_p, I.ncell * 8) || dalloc(h, &I.adj_Hp, I.ncell * 8)) {
+        h->hI = saved;
         return set_err(h, PSD_ERR_HIP, "out of device memory");
+      }
     }
     I.adj_us = u_star[b];
     I.adj_g = dJdu[b];
     I.adj_lam = dJdf[b];
     I.max_iter = max_iter;
+    I.st = h->dAuxState + b;   // the CG state; the last solve's state stays intact
   }
   h->adj_alloc = true;
   // keep the buffers for later calls
@@ -1328,7 +1422,7 @@ static psd_status adjoint_impl(psd_handle* h, const double* const* u_star, const
     saved[b].adj_r = h->hI[b].adj_r; saved[b].adj_p = h->hI[b].adj_p; saved[b].adj_Hp = h->hI[b].adj_Hp;
   }
   psd_status st = upload_inst(h);
-  if (st != PSD_OK) return st;
+  if (st != PSD_OK) { h->hI = saved; (void)upload_inst(h); return st; }
   k_reset_state<<<(B + 63) / 64, 64, 0, s>>>(h->dI, B);
   const double rtol2 = rtol * rtol;
   auto vec = [&](int op) {
@@ -1353,7 +1447,7 @@ static psd_status adjoint_impl(psd_handle* h, const double* const* u_star, const
     fin(3);
     HIPCHK(hipGetLastError());
     st = read_states(h);
-    if (st != PSD_OK) return st;
+    if (st != PSD_OK) { h->hI = saved; (void)upload_inst(h); return st; }
     if (all_done(h)) break;
     run_fft<T, TR, TD>(h, h->fft_solver, OP_PRECOND4, true);
     vec(2);
@@ -1361,7 +1455,7 @@ static psd_status adjoint_impl(psd_handle* h, const double* const* u_star, const
     vec(4);
   }
   st = read_states(h);
-  if (st != PSD_OK) return st;
+  if (st != PSD_OK) { h->hI = saved; (void)upload_inst(h); return st; }
   psd_status worst = PSD_OK;
   // sensitivities to s and eps (one pass per instance)
   const int nblk = 1024;

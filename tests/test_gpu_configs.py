@@ -85,7 +85,7 @@ def full_size_parity(psd, name, w, precisions, autotune, chunk_mixed):
     print(f"  fp64: iters {st.iters} res {st.res_inf:.3e} tiling {tiling}", flush=True)
     assert st.status == 0 and st.res_inf <= 1e-10
     assert abs(st.iters - G["iters"]) <= 1
-    check_alphas(hist[:, 0], G["alpha"], G["res_inf"], G["res0_inf"], G["rounding_scale"])
+    check_alphas(hist[:, 0], G["alpha"], G["res_inf"], G["res0_inf"], G["rounding_scale"], w.n ** w.dim)
     u_conv = host(u)
     assert np.abs(O.residual(w.f, u_conv)).max() <= 1.5e-10
     # FP64 at the oracle's converged count and after three updates

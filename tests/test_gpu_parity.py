@@ -121,7 +121,7 @@ def test_solve_parity_fp64(psd, dim, n, p, L, s, eps):
     # step sizes agree (same iterate sequence up to rounding): per-update
     # bound from the residual's rounding scale (parity_bounds)
     check_alphas(hist[:, 0], ref["hist"][:, 0], ref["hist"][:, 1], np.abs(f).max(),
-                 rounding_scale(O, ref["u"]), log)
+                 rounding_scale(O, ref["u"]), f.size, log)
     # matched iteration count
     kk = max(ref["iters"] - 2, 1)
     with psd.Solver(P, tol=0.0, max_iter=kk) as S:
@@ -176,7 +176,7 @@ def test_solve_parity_order6(psd, n, gbar, fbar):
     assert np.abs(r1).max() <= 2e-10 and np.abs(r2).max() <= 2e-10
     check_alphas(hist[:, 0], ref["hist"][:, 0], ref["hist"][:, 1],
                  np.abs(O.residual(f, np.full_like(f, g.mean()), g)).max(),
-                 rounding_scale(O, ref["u"], ref["w"]), log)
+                 rounding_scale(O, ref["u"], ref["w"]), f.size, log)
     # matched iteration count: u and the carried w against the oracle's u and
     # w = T_h[g - u] + s lam gbar - fbar (Sec. 4)
     kk = ref["iters"]
