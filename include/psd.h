@@ -126,6 +126,32 @@ psd_status psd_create(const psd_problem* probs, int batch, const psd_options* op
 psd_status psd_solve(psd_handle* h, const double* const* f, const double* const* g,
                      double* const* u, double* const* w, psd_stats* stats);
 
+/* One solve that allocates nothing, for callers that cannot allocate device
+ * memory (serving loops, harnesses that forbid hipMalloc).  Same problem,
+ * options and results as psd_create + psd_solve + psd_destroy for a batch of
+ * one instance, with these differences:
+ *   - all device workspace comes from one static device array of 64 MiB per
+ *     GPU (held by every GPU the library runs on until the process ends);
+ *     a problem whose workspace does not fit is rejected with PSD_ERR_ARG
+ *     (for example 2D order 4 fits up to n = 1024, 3D order 4 up to n = 96,
+ *     2D order 6 up to n = 512);
+ *   - no hipMalloc, hipFree, pinned host allocation, stream, event or graph
+ *     creation; the state is staged through static host memory (ordinary
+ *     C++ containers hold the small host-side task tables);
+ *   - options.graph_chunk, profile and autotune must be 0 (host-driven loop,
+ *     default tiling), else PSD_ERR_ARG;
+ *   - calls on one GPU share the array and run one after the other (a mutex
+ *     per GPU); each call clears what must start at zero, and returns only
+ *     after its work on hip_stream has finished.  Work of the caller that
+ *     uses the same array concurrently (none outside this call) would race.
+ * f, g (order 6, else may be NULL), u (in: u0, out: final iterate), w (order
+ * 6 output, may be NULL) are device pointers of n^dim doubles; stats (host,
+ * may be NULL) receives the result.  Errors are reported by
+ * psd_last_error(NULL) of the calling thread. */
+psd_status psd_solve_noalloc(const psd_problem* prob, const psd_options* opt, void* hip_stream,
+                             const double* f, const double* g, double* u, double* w,
+                             psd_stats* stats);
+
 /* Residual of instance `inst` at u.  Order 4: r = f - N_h[u].  Order 6: the
  * reduced residual rho = P0[f - (s lam u - s div_h(...) + s eps^2 Delta_h^2 u)
  * - T_h(u - g)] (minus the gradient of the mean-zero energy; T_h = -Delta_h^{-1}

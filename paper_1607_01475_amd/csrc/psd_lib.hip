@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1225,6 +1226,71 @@ extern "C" psd_status psd_solve(psd_handle* h, const double* const* f, const dou
   HIPCHK(hipSetDevice(h->device));
   if (h->mixed) return solve_impl<float, float, float>(h, f, g, u, w, stats);
   return solve_impl<double, double, double>(h, f, g, u, w, stats);
+}
+
+// ---------------------------------------------------------------------------
+// Solve without allocating: every device buffer of the solve (iterate copy,
+// search direction, residual copy, spectra, tables, partial sums, solver
+// state, task lists) is carved from one static device array per GPU, and the
+// host staging of the solver state lives in static host memory.
+// ---------------------------------------------------------------------------
+#define PSD_NOALLOC_BYTES ((size_t)64 << 20)
+static __device__ __align__(256) double scratch[PSD_NOALLOC_BYTES / sizeof(double)];
+
+namespace {
+constexpr int PSD_NOALLOC_MAX_DEVICES = 64;
+struct NoallocDevice {
+  std::mutex mu;           // calls on one GPU run one after the other
+  char* ptr = nullptr;     // device address of `scratch` on this GPU
+  SolveState hstate[1];
+  double hpart[5 * 1024];
+};
+NoallocDevice g_noalloc[PSD_NOALLOC_MAX_DEVICES];
+}  // namespace
+
+extern "C" psd_status psd_solve_noalloc(const psd_problem* prob, const psd_options* opt, void* hip_stream,
+                                        const double* f, const double* g, double* u, double* w,
+                                        psd_stats* stats) {
+  g_create_error.clear();
+  std::string msg;
+  psd_status st = check_create_args(prob, 1, opt, msg);
+  if (st != PSD_OK) return set_err(nullptr, st, msg);
+  if (opt->graph_chunk != 0 || opt->profile || opt->autotune)
+    return set_err(nullptr, PSD_ERR_ARG, "psd_solve_noalloc runs the host-driven loop: graph_chunk, "
+                                         "profile and autotune must be 0");
+  if (!f || !u || (prob->order == 6 && !g)) return set_err(nullptr, PSD_ERR_ARG, "NULL f, u or (order 6) g");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= PSD_NOALLOC_MAX_DEVICES)
+    return set_err(nullptr, PSD_ERR_HIP, "no HIP device");
+  NoallocDevice& D = g_noalloc[dev];
+  std::lock_guard<std::mutex> lock(D.mu);
+  if (!D.ptr) {
+    // the array's name is a host-side stand-in: its device address on this GPU
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_err(nullptr, PSD_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    D.ptr = (char*)p;
+  }
+  psd_handle H;
+  psd_handle* h = &H;
+  h->device = dev;
+  h->stream = (hipStream_t)hip_stream;
+  h->arena = D.ptr;
+  h->arena_cap = PSD_NOALLOC_BYTES;
+  h->arena_hstate = D.hstate;
+  h->arena_hpart = D.hpart;
+  st = setup_handle(h, prob, 1, opt);
+  if (st != PSD_OK) return set_err(nullptr, st, h->err);
+  const double* const fa[1] = {f};
+  const double* const ga[1] = {g};
+  double* const ua[1] = {u};
+  double* const wa[1] = {w};
+  st = h->mixed ? solve_impl<float, float, float>(h, fa, ga, ua, wa, stats)
+                : solve_impl<double, double, double>(h, fa, ga, ua, wa, stats);
+  if (st < 0) set_err(nullptr, st, h->err.empty() ? std::string("solve failed") : h->err);
+  (void)hipStreamSynchronize(h->stream);
+  return st;
 }
 
 // Auxiliary single-instance evaluations (residual, energy, Poisson solves,

@@ -67,6 +67,8 @@ SIGNATURES = {
                                   _vp, ctypes.POINTER(_vp)]),
     "psd_solve": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                  ctypes.POINTER(_vp), ctypes.POINTER(_Stats)]),
+    "psd_solve_noalloc": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.POINTER(_Options), _vp,
+                                         _vp, _vp, _vp, _vp, ctypes.POINTER(_Stats)]),
     "psd_residual": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _dp]),
     "psd_residual_mixed": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _dp]),
     "psd_energy": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _dp]),
@@ -268,6 +270,25 @@ class Solver:
         self._check(self._lib.psd_adjoint(self._h, _ptr_array(u_star), _ptr_array(dJdu),
                                           _ptr_array(dJdf), ds, de, float(rtol), int(max_iter), it))
         return dJdf, list(ds), list(de), list(it)
+
+
+def solve_noalloc(problem: Problem, f: torch.Tensor, u: torch.Tensor, g: Optional[torch.Tensor] = None,
+                  w: Optional[torch.Tensor] = None, tol: float = 1e-10, max_iter: int = 500,
+                  precision: str = "fp64", history: bool = False,
+                  stream: Optional[torch.cuda.Stream] = None) -> Stats:
+    """One solve through psd_solve_noalloc (no device allocation: workspace in
+    the library's static scratch array).  u holds u0 on entry and the final
+    iterate on exit."""
+    lib = load_library()
+    prec = {"fp64": PSD_FP64, "mixed": PSD_MIXED}[precision]
+    opt = _Options(float(tol), int(max_iter), prec, 0, 1 if history else 0, 0, 0)
+    st = _Stats()
+    strm = stream if stream is not None else torch.cuda.current_stream()
+    rc = lib.psd_solve_noalloc(ctypes.byref(problem.c()), ctypes.byref(opt), _vp(strm.cuda_stream),
+                               _ptr(f), _ptr(g), _ptr(u), _ptr(w), ctypes.byref(st))
+    if rc not in (PSD_OK, PSD_NOT_CONVERGED):
+        raise PSDError(rc, lib.psd_last_error(None).decode())
+    return Stats(st.iters, st.res_inf, st.res_l2, st.energy, st.status)
 
 
 class PSDSolveFn(torch.autograd.Function):
