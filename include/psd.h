@@ -192,8 +192,9 @@ psd_status psd_adjoint(psd_handle* h, const double* const* u_star, const double*
 
 /* Per-update history of instance `inst` from the last psd_solve (options
  * history != 0): out[4*k + {0,1,2,3}] = alpha, ||r||_inf, ||r||_2, energy
- * decrease (order 4, p = 4; else 0).  Copies min(cap, iters) records to host
- * memory and returns their number in *count. */
+ * decrease (p = 4 and p = 6, the integral of the polynomial q of Sec. 6.1;
+ * else 0).  Copies min(cap, iters) records to host memory and returns their
+ * number in *count. */
 psd_status psd_history(psd_handle* h, int inst, double* out, int cap, int* count);
 
 /* Kernel passes of one PSD iteration, in launch order (psd_pass_times). */

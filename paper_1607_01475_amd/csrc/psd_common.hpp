@@ -49,7 +49,8 @@ __device__ __forceinline__ cx<T> mul_i(cx<T> a) {
 struct SolveState {
   double alpha;        // current line-search step
   double rinf, rl2;    // max-norm and l2 (h^dim weighted) of the last residual
-  double c[4];         // cubic coefficients (p = 4) or q(0), q'(0) (general p)
+  double c[6];         // polynomial coefficients of q (p = 4: cubic, p = 6: quintic)
+                       // or q(0), q'(0) (general p)
   double lin;          // general p: linear part of q'
   double nl0;          // general p: nonlinear vertex sum at alpha = 0
   double lo, hi, x, qx, dqx;  // root-rule state (general p)
@@ -72,7 +73,7 @@ struct Inst {
   long long nspec32, nspec64;  // spectrum field strides (complex elements)
   long long nyq32, nyq64;      // offset of the Nyquist plane in a field = ncp * n^(dim-1)
   double h, inv_h, p, s, se2, lam, inv_ntot, tol, hd;
-  int max_iter, p_is_4, p_is_2, pad0;
+  int max_iter, p_is_4, p_is_2, p_is_6;
   double* u[2];        // ping-pong iterate
   double* w[2];        // order 6 carried w (ping-pong)
   const double* f;

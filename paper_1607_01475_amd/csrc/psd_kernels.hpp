@@ -145,15 +145,27 @@ __global__ __launch_bounds__(PSD_NT) void k_ls3d(const Inst* __restrict__ insts,
     for (int k = 0; k < 8; ++k) I.part_ls[8 * t.slot + k] = acc[k];
 }
 
-// Root of the strictly increasing cubic q(x) = c0 + c1 x + c2 x^2 + c3 x^3
-// (Sec. 6.1).  Rule: x = -c0/c1, double until q > 0, then Newton from that
-// point with bisection whenever a step leaves the bracket; stop when
-// |q| <= 1e-16 (|c0| + c1 x) or |dx| <= 1e-15 x.
-__device__ double cubic_root(const double* c) {
+// q(x) = c0 + c1 x + ... + cD x^D and q'(x) by Horner's rule
+template <int D>
+__device__ __forceinline__ void poly_eval(const double* c, double x, double& q, double& dq) {
+  q = c[D];
+  dq = 0.0;
+#pragma unroll
+  for (int k = D - 1; k >= 0; --k) {
+    dq = dq * x + q;
+    q = q * x + c[k];
+  }
+}
+
+// Root of the strictly increasing polynomial q of degree D: the cubic (p = 4)
+// or quintic (p = 6) of Sec. 6.1.  Rule: x = -c0/c1, double until q > 0, then
+// Newton from that point with bisection whenever a step leaves the bracket;
+// stop when |q| <= 1e-16 (|c0| + c1 x) or |dx| <= 1e-15 x.
+template <int D>
+__device__ double poly_root(const double* c) {
   double lo = 0.0, hi = INFINITY, x = -c[0] / c[1], q = 0.0, dq = 0.0;
   for (int it = 0; it < 200; ++it) {
-    q = c[0] + x * (c[1] + x * (c[2] + x * c[3]));
-    dq = c[1] + x * (2.0 * c[2] + 3.0 * c[3] * x);
+    poly_eval<D>(c, x, q, dq);
     if (q > 0.0) { hi = x; break; }
     if (q == 0.0) return x;
     lo = x;
@@ -165,8 +177,7 @@ __device__ double cubic_root(const double* c) {
     if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
     if (fabs(xn - x) <= 1e-15 * x) { x = xn; break; }
     x = xn;
-    q = c[0] + x * (c[1] + x * (c[2] + x * c[3]));
-    dq = c[1] + x * (2.0 * c[2] + 3.0 * c[3] * x);
+    poly_eval<D>(c, x, q, dq);
     if (q > 0.0) hi = x;
     else if (q < 0.0) lo = x;
     else break;
@@ -175,8 +186,9 @@ __device__ double cubic_root(const double* c) {
 }
 
 // Reduce line-search and spectral partials; mode 0: cubic (p = 4) -> alpha;
-// mode 1: general p, first pass at alpha = 0 -> start the root rule;
-// mode 2: general p, one root-rule step after an evaluation at st->x.
+// mode 3: quintic (p = 6) -> alpha; mode 1: general p, first pass at
+// alpha = 0 -> start the root rule; mode 2: general p, one root-rule step
+// after an evaluation at st->x.
 __global__ __launch_bounds__(PSD_FIN_NT) void k_ls_finalize(const Inst* __restrict__ insts, int mode) {
   __shared__ double scratch[10 * PSD_FIN_NT / PSD_WAVE];
   const Inst& I = insts[blockIdx.x];
@@ -205,7 +217,7 @@ __global__ __launch_bounds__(PSD_FIN_NT) void k_ls_finalize(const Inst* __restri
       for (int q = 0; q < 3; ++q) st->mean[q] = ms[q] * I.inv_ntot;
       // sum (d - dbar)^2 = sum d^2 - N dbar^2
       const double corr = (double)I.ncell * st->mean[0] * st->mean[0];
-      if (mode == 0) acc[4] -= corr; else acc[2] -= corr;
+      if (mode == 0) acc[4] -= corr; else if (mode == 3) acc[5] -= corr; else acc[2] -= corr;
     }
   }
   if (threadIdx.x != 0) return;
@@ -219,13 +231,37 @@ __global__ __launch_bounds__(PSD_FIN_NT) void k_ls_finalize(const Inst* __restri
     c[2] = 3.0 * s * S4;
     c[3] = s * S5;
     for (int k = 0; k < 4; ++k) st->c[k] = c[k];
+    st->c[4] = st->c[5] = 0.0;
     if (!(c[0] < 0.0) || !(c[1] > 0.0)) {
       st->status = -5; st->done = 1; st->alpha = 0.0;
       return;
     }
-    const double a = cubic_root(c);
+    const double a = poly_root<3>(c);
     st->alpha = a;
     st->dE = I.hd * a * (c[0] + a * (c[1] / 2.0 + a * (c[2] / 3.0 + a * c[3] / 4.0)));
+    st->ls_phase = 2;
+    return;
+  }
+  if (mode == 3) {
+    // p = 6: q(x) = c0 + c1 x + ... + c5 x^5 with c0 = -(r, d),
+    // c1 = P2 + s t1 + s eps^2 P4 (order 6: s lam P2 + (T_h d, d) in place of P2),
+    // c_k = s t_k (k >= 2)
+    const double P2 = acc[5], P4 = acc[6];
+    const double lin = (I.order == 4) ? P2 : s * I.lam * P2 + acc[9];
+    double c[6];
+    c[0] = -acc[8];
+    c[1] = lin + s * acc[0] + se2 * P4;
+    for (int k = 2; k <= 5; ++k) c[k] = s * acc[k - 1];
+    for (int k = 0; k < 6; ++k) st->c[k] = c[k];
+    if (!(c[0] < 0.0) || !(c[1] > 0.0)) {
+      st->status = -5; st->done = 1; st->alpha = 0.0;
+      return;
+    }
+    const double a = poly_root<5>(c);
+    st->alpha = a;
+    double e = 0.0;   // integral of q from 0 to a
+    for (int k = 5; k >= 0; --k) e = e * a + c[k] / (double)(k + 1);
+    st->dE = I.hd * a * e;
     st->ls_phase = 2;
     return;
   }
@@ -637,7 +673,7 @@ __global__ __launch_bounds__(PSD_NT) void k_energy_parts(const Inst* __restrict_
       const double gz = q * ((c001 - uc) + (c101 - c100) + (c011 - c010) + (c111 - c110));
       g2 = gx * gx + gy * gy + gz * gz;
     }
-    acc[1] += (I.p_is_4) ? g2 * g2 : pow(g2, 0.5 * I.p);
+    acc[1] += I.p_is_4 ? g2 * g2 : (I.p_is_6 ? g2 * g2 * g2 : pow(g2, 0.5 * I.p));
   }
   block_reduce<5, 0>(acc, scratch);
   if (threadIdx.x == 0)

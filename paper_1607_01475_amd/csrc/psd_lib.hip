@@ -85,6 +85,8 @@ struct psd_handle_s {
   int batch = 0;
   int dim = 2, order = 4;
   bool p_is_4 = true;
+  bool p_is_6 = false;
+  bool poly_ls = true;   // p = 4 or 6: one line-search pass (polynomial q)
   psd_options opt{};
   bool mixed = false;
   hipStream_t stream = nullptr;
@@ -520,6 +522,9 @@ static void launch_res3d(int pk, bool upd, int n, size_t lds, hipStream_t s, con
   } else if (pk == 2) {
     if (upd) k_res3d<TD, TR, true, 2, TX><<<n, PSD_NT, lds, s>>>(dI, t);
     else k_res3d<TD, TR, false, 2, TX><<<n, PSD_NT, lds, s>>>(dI, t);
+  } else if (pk == 6) {
+    if (upd) k_res3d<TD, TR, true, 6, TX><<<n, PSD_NT, lds, s>>>(dI, t);
+    else k_res3d<TD, TR, false, 6, TX><<<n, PSD_NT, lds, s>>>(dI, t);
   } else {
     if (upd) k_res3d<TD, TR, true, 0, TX><<<n, PSD_NT, lds, s>>>(dI, t);
     else k_res3d<TD, TR, false, 0, TX><<<n, PSD_NT, lds, s>>>(dI, t);
@@ -544,7 +549,7 @@ static void run_residual(psd_handle* h, bool upd) {
     } else {
       // exponent class of the flux (all instances share p) and tile width
       const double p = h->hI[0].p;
-      const int pk = p == 4.0 ? 4 : (p == 2.0 ? 2 : 0);
+      const int pk = p == 4.0 ? 4 : (p == 2.0 ? 2 : (p == 6.0 ? 6 : 0));
       launch_res3d<TD, TR, R3_TX>(pk, upd, n, h->res.lds, s, h->dI, t);
     }
   }
@@ -563,15 +568,18 @@ static void run_ls(psd_handle* h, int mode) {
     if (h->dim == 2) {
       if (mode == 0) k_ls2d<TD, 0><<<nb, PSD_NT, lds, s>>>(h->dI, t);
       else if (mode == 1) k_ls2d<TD, 1><<<nb, PSD_NT, lds, s>>>(h->dI, t);
+      else if (mode == 3) k_ls2d<TD, 3><<<nb, PSD_NT, lds, s>>>(h->dI, t);
       else k_ls2d<TD, 2><<<nb, PSD_NT, lds, s>>>(h->dI, t);
     } else {
       if (h->ls_tx == L3_TX_WIDE) {
         if (mode == 0) k_ls3d<TD, 0, L3_TX_WIDE><<<nb, PSD_NT, lds, s>>>(h->dI, t);
         else if (mode == 1) k_ls3d<TD, 1, L3_TX_WIDE><<<nb, PSD_NT, lds, s>>>(h->dI, t);
+        else if (mode == 3) k_ls3d<TD, 3, L3_TX_WIDE><<<nb, PSD_NT, lds, s>>>(h->dI, t);
         else k_ls3d<TD, 2, L3_TX_WIDE><<<nb, PSD_NT, lds, s>>>(h->dI, t);
       } else {
         if (mode == 0) k_ls3d<TD, 0, L3_TX_NARROW><<<nb, PSD_NT, lds, s>>>(h->dI, t);
         else if (mode == 1) k_ls3d<TD, 1, L3_TX_NARROW><<<nb, PSD_NT, lds, s>>>(h->dI, t);
+        else if (mode == 3) k_ls3d<TD, 3, L3_TX_NARROW><<<nb, PSD_NT, lds, s>>>(h->dI, t);
         else k_ls3d<TD, 2, L3_TX_NARROW><<<nb, PSD_NT, lds, s>>>(h->dI, t);
       }
     }
@@ -580,11 +588,12 @@ static void run_ls(psd_handle* h, int mode) {
   k_ls_finalize<<<h->batch, PSD_FIN_NT, 0, s>>>(h->dI, mode);
 }
 
-// one PSD iteration (p = 4: fixed launch sequence, capturable)
+// one PSD iteration with a polynomial q (p = 4 cubic, p = 6 quintic; Sec.
+// 6.1): a fixed launch sequence, capturable in a graph
 template <typename T, typename TD, typename TR>
-static void run_iteration_p4(psd_handle* h) {
+static void run_iteration_poly(psd_handle* h) {
   run_fft<T, TR, TD>(h, h->fft_solver, h->order == 4 ? OP_PRECOND4 : OP_PRECOND6, true);
-  run_ls<TD>(h, 0);
+  run_ls<TD>(h, h->p_is_6 ? 3 : 0);
   run_residual<TD, TR>(h, true);
 }
 
@@ -625,7 +634,7 @@ static psd_status run_iteration_general(psd_handle* h) {
 template <typename T, typename TD, typename TR>
 static psd_status solve_loop(psd_handle* h) {
   const int chunk = h->opt.graph_chunk;
-  if (chunk > 0 && h->p_is_4) {
+  if (chunk > 0 && h->poly_ls) {
     if (!h->gexec || h->gchunk != chunk) {
       if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
       if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
@@ -634,7 +643,7 @@ static psd_status solve_loop(psd_handle* h) {
       HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
       for (int k = 0; k < chunk; ++k) {
         h->prof_iter_slot = k;
-        run_iteration_p4<T, TD, TR>(h);
+        run_iteration_poly<T, TD, TR>(h);
       }
       h->prof_iter_slot = -1;
       HIPCHK(hipStreamEndCapture(h->stream, &h->graph));
@@ -676,7 +685,7 @@ static psd_status solve_loop(psd_handle* h) {
     return PSD_OK;
   }
   for (int it = 0; it <= h->opt.max_iter; ++it) {
-    if (h->p_is_4) run_iteration_p4<T, TD, TR>(h);
+    if (h->poly_ls) run_iteration_poly<T, TD, TR>(h);
     else {
       psd_status st = run_iteration_general<T, TD, TR>(h);
       if (st != PSD_OK) return st;
@@ -938,6 +947,8 @@ static psd_status setup_handle(psd_handle* h, const psd_problem* probs, int batc
   h->dim = probs[0].dim;
   h->order = probs[0].order;
   h->p_is_4 = probs[0].p == 4.0;
+  h->p_is_6 = probs[0].p == 6.0;
+  h->poly_ls = h->p_is_4 || h->p_is_6;
   h->ls_tx = L3_TX_WIDE;
   for (int b = 0; b < batch; ++b)
     if (probs[b].n < L3_TX_WIDE) h->ls_tx = L3_TX_NARROW;
@@ -989,7 +1000,7 @@ static psd_status setup_handle(psd_handle* h, const psd_problem* probs, int batc
     I.tol = opt->tol;
     I.hd = std::pow(I.h, P.dim);
     I.max_iter = opt->max_iter;
-    I.p_is_4 = P.p == 4.0; I.p_is_2 = P.p == 2.0;
+    I.p_is_4 = P.p == 4.0; I.p_is_2 = P.p == 2.0; I.p_is_6 = P.p == 6.0;
     const size_t N = (size_t)I.ncell;
     const int nspec_fields = P.order == 6 ? 3 : 1;
     if (dalloc(h, &I.u[1], N * 8) || dalloc(h, &I.tmp, N * 8) ||

@@ -30,6 +30,7 @@ constexpr int T3Z_MIN = 12;          // smallest chunk any tuning may pick
 __device__ __forceinline__ double flux_r(double g2, double p, int p_is_4, int p_is_2) {
   if (p_is_4) return g2;
   if (p_is_2) return 1.0;
+  if (p == 6.0) return g2 * g2;
   return g2 > 0.0 ? pow(g2, 0.5 * (p - 2.0)) : 0.0;
 }
 
@@ -42,6 +43,7 @@ __device__ __forceinline__ void flux_lin(const Inst& I, double ax, double ay, do
   double r2, r4;
   if (I.p_is_4) { r2 = a2; r4 = 2.0; }
   else if (I.p_is_2) { r2 = 1.0; r4 = 0.0; }
+  else if (I.p_is_6) { r2 = a2 * a2; r4 = 4.0 * a2; }
   else if (a2 == 0.0) { r2 = 0.0; r4 = 0.0; }
   else { r2 = pow(a2, 0.5 * (I.p - 2.0)); r4 = (I.p - 2.0) * r2 / a2; }
   fx = r2 * bx + r4 * ab * ax;
@@ -322,6 +324,7 @@ template <int PK>
 __device__ __forceinline__ double flux_rr(double g2, double p) {
   if (PK == 4) return g2;
   if (PK == 2) return 1.0;
+  if (PK == 6) return g2 * g2;
   return g2 > 0.0 ? pow(g2, 0.5 * (p - 2.0)) : 0.0;
 }
 
@@ -397,7 +400,8 @@ struct Res3March {
     nn = (long long)n * n;
     const double ih = I.inv_h, qh = 0.25 * ih;
     ih2 = ih * ih;
-    qhp = PK == 4 ? (qh * qh) * (qh * qh) : (PK == 2 ? qh * qh : pow(qh, I.p));
+    qhp = PK == 4 ? (qh * qh) * (qh * qh)
+        : (PK == 2 ? qh * qh : (PK == 6 ? (qh * qh) * (qh * qh) * (qh * qh) : pow(qh, I.p)));
     s = I.s;
     se2 = I.se2;
     p = I.p;
@@ -632,8 +636,10 @@ __device__ __forceinline__ void res3d_tile(const Inst& I, int x0, int y0, int z0
 // a = grad u, b = grad d; P2 = sum d^2, P4 = sum (Delta_h d)^2 over cells.
 // MODE 1/2 (general p at alpha = 0 / alpha = st->x): NL = sum |g|^{p-2} g.b and
 // dNL = sum |g|^{p-2}|b|^2 + (p-2)|g|^{p-4}(g.b)^2, g = a + alpha b, plus
-// P2, P4.  Layout of the 8 partials: MODE 0: S2 S3 S4 S5 P2 P4 0 0;
-// MODE 1: NL dNL P2 P4 0 0 0 0.
+// P2, P4.  MODE 3 (p = 6 quintic): the five vertex sums t_1 .. t_5 of
+// |a + x b|^4 (a + x b).b (Sec. 6.1), plus P2, P4.  Layout of the 8 partials:
+// MODE 0: S2 S3 S4 S5 P2 P4 0 0;  MODE 1/2: NL dNL P2 P4 0 0 0 0;
+// MODE 3: t1 t2 t3 t4 t5 P2 P4 0.
 // ===========================================================================
 template <int MODE>
 __device__ __forceinline__ void ls_vertex(double p, double alpha, double ax, double ay,
@@ -646,6 +652,17 @@ __device__ __forceinline__ void ls_vertex(double p, double alpha, double ax, dou
     acc[1] += ab * ab;
     acc[2] += ab * b2;
     acc[3] += b2 * b2;
+  } else if (MODE == 3) {
+    // p = 6: |a + x b|^4 (a + x b).b = sum_k t_k x^k with A = |a|^2, B = a.b,
+    // C = |b|^2; t_0 = A^2 B enters q(0) = -(r, d) and is not summed here
+    const double A = ax * ax + ay * ay + az * az, C = bx * bx + by * by + bz * bz;
+    const double B = ax * bx + ay * by + az * bz;
+    const double B2 = B * B, AC = A * C;
+    acc[0] += A * (AC + 4.0 * B2);           // t_1 = A^2 C + 4 A B^2
+    acc[1] += B * (6.0 * AC + 4.0 * B2);     // t_2 = 6 A B C + 4 B^3
+    acc[2] += C * (8.0 * B2 + 2.0 * AC);     // t_3 = 8 B^2 C + 2 A C^2
+    acc[3] += 5.0 * B * C * C;               // t_4 = 5 B C^2
+    acc[4] += C * C * C;                     // t_5 = C^3
   } else {
     const double gx = ax + alpha * bx, gy = ay + alpha * by, gz = az + alpha * bz;
     const double g2 = gx * gx + gy * gy + gz * gz, b2 = bx * bx + by * by + bz * bz;
@@ -705,6 +722,7 @@ __device__ void ls2d_tile(const Inst& I, int x0, int y0, double* lds, double (&a
     ls_vertex<MODE>(I.p, alpha, ax, ay, 0.0, bx, by, 0.0, acc);
     const double ld = (dl[c - 1] + dl[c + 1] + dl[c - L2_W] + dl[c + L2_W] - 4.0 * b00) * ih2;
     if (MODE == 0) { acc[4] += b00 * b00; acc[5] += ld * ld; }
+    else if (MODE == 3) { acc[5] += b00 * b00; acc[6] += ld * ld; }
     else { acc[2] += b00 * b00; acc[3] += ld * ld; }
   }
 }
@@ -855,6 +873,7 @@ struct Ls3March {
 
   __device__ __forceinline__ void cell(double dk, double ld) {
     if (MODE == 0) { sacc[4] += dk * dk; sacc[5] += ld * ld; }
+    else if (MODE == 3) { sacc[5] += dk * dk; sacc[6] += ld * ld; }
     else { sacc[2] += dk * dk; sacc[3] += ld * ld; }
   }
 
@@ -918,11 +937,15 @@ __device__ __forceinline__ void ls3d_tile(const Inst& I, int x0, int y0, int z0,
   Ls3March<TD, MODE, TX> m(I, x0, y0, z0, lds);
   m.run();
   // vertex sums were taken with gradients scaled by 4h: undo once
-  const double qh = 0.25 * I.inv_h;
-  const double sc = (MODE == 0 || I.p_is_4) ? qh * qh * qh * qh : pow(qh, I.p);
+  const double qh = 0.25 * I.inv_h, qh2 = qh * qh;
+  const double sc = (MODE == 0 || I.p_is_4) ? qh2 * qh2
+                  : ((MODE == 3 || I.p_is_6) ? qh2 * qh2 * qh2 : pow(qh, I.p));
   if (MODE == 0) {
     for (int q = 0; q < 4; ++q) acc[q] += sc * m.sacc[q];
     acc[4] += m.sacc[4]; acc[5] += m.sacc[5];
+  } else if (MODE == 3) {
+    for (int q = 0; q < 5; ++q) acc[q] += sc * m.sacc[q];
+    acc[5] += m.sacc[5]; acc[6] += m.sacc[6];
   } else {
     acc[0] += sc * m.sacc[0]; acc[1] += sc * m.sacc[1];
     acc[2] += m.sacc[2]; acc[3] += m.sacc[3];

@@ -99,7 +99,10 @@ SOLVES = [(2, 64, 4.0, 12.8, 0.01, 0.1), (2, 96, 4.0, 12.8, 0.01, 0.1), (2, 128,
           # wide (64-column) line-search tiles, one of them partial
           (3, 96, 4.0, 12.8, 0.01, 0.1),
           # 3D general p: line search by (q, q') evaluations and the host root rule
-          (3, 32, 3.0, 12.8, 0.01, 0.1)]
+          (3, 32, 3.0, 12.8, 0.01, 0.1),
+          # p = 6: quintic q (Sec. 6.1), one line-search pass; the oracle finds
+          # the same root by (q, q') grid evaluations
+          (2, 64, 6.0, 12.8, 0.01, 0.1), (2, 96, 6.0, 3.2, 0.001, 0.1), (3, 32, 6.0, 12.8, 0.01, 0.1)]
 
 
 @pytest.mark.parametrize("dim,n,p,L,s,eps", SOLVES)
@@ -122,6 +125,15 @@ def test_solve_parity_fp64(psd, dim, n, p, L, s, eps):
     # bound from the residual's rounding scale (parity_bounds)
     check_alphas(hist[:, 0], ref["hist"][:, 0], ref["hist"][:, 1], np.abs(f).max(),
                  rounding_scale(O, ref["u"]), f.size, log)
+    if p in (4.0, 6.0):
+        # the energy decrease integrated from the GPU's polynomial q against
+        # the oracle's energies before and after each update (Sec. 2.2, 6.1)
+        k = min(len(hist), len(ref["hist"]))
+        E = np.concatenate([[O.energy(f, np.zeros_like(f))], ref["hist"][:k, 3]])
+        dE_ref = np.diff(E)
+        err = np.abs(hist[:k, 3] - dE_ref)
+        log(f"  dE: worst |diff| {err.max():.2e} (|E0| {abs(E[0]):.2e})")
+        assert (err <= 1e-12 * abs(E[0]) + 1e-9 * np.abs(dE_ref)).all()
     # matched iteration count
     kk = max(ref["iters"] - 2, 1)
     with psd.Solver(P, tol=0.0, max_iter=kk) as S:
@@ -132,6 +144,26 @@ def test_solve_parity_fp64(psd, dim, n, p, L, s, eps):
     assert rel(host(u), ref_k["u"]) <= 1e-11
     # the converged GPU iterate solves the oracle's discrete equation
     assert np.abs(O.residual(f, ug)).max() <= 1.5e-10
+
+
+def test_p6_wide_tiles_matched_count(psd):
+    """p = 6 in 3D at n = 64 (64-wide line-search tiles): six FP64 updates and
+    their step sizes against six oracle updates (the oracle's general-p root
+    rule at 64^3 takes minutes to convergence, so the count is fixed)."""
+    n, L, s, eps, k = 64, 12.8, 0.01, 0.1, 6
+    f = psd_inputs.small_field(3, n, L, 31, K=6)
+    O = oracle.Problem(3, n, L, p=6.0, s=s, eps=eps)
+    ref = O.solve(f, tol=0.0, max_iter=k, history=True)
+    P = psd.Problem(3, n, L, 4, 6.0, s, eps)
+    with psd.Solver(P, tol=0.0, max_iter=k, history=True) as S:
+        u = torch.zeros_like(dev(f))
+        st = S.solve([dev(f)], [u])[0]
+        hist = S.history(0)
+    log(f"case p6 3D n={n}: {st.iters} updates, rel {rel(host(u), ref['u']):.2e}")
+    assert st.iters == k
+    assert rel(host(u), ref["u"]) <= 1e-11
+    check_alphas(hist[:, 0], ref["hist"][:, 0], ref["hist"][:, 1], np.abs(f).max(),
+                 rounding_scale(O, ref["u"]), f.size, log)
 
 
 def test_solve_parity_config1(psd):
@@ -228,7 +260,7 @@ def test_batched_order6_nonzero_means(psd, precision):
 # --------------------------------------------------------------------------
 # mixed precision, graphs, batching
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("dim,n,p", [(2, 128, 4.0), (3, 48, 4.0), (3, 32, 3.0)])
+@pytest.mark.parametrize("dim,n,p", [(2, 128, 4.0), (3, 48, 4.0), (3, 32, 3.0), (2, 128, 6.0), (3, 48, 6.0)])
 def test_mixed_precision_reaches_fp64_answer(psd, dim, n, p):
     L = 12.8
     f = psd_inputs.small_field(dim, n, L, 51, K=6)
@@ -245,11 +277,11 @@ def test_mixed_precision_reaches_fp64_answer(psd, dim, n, p):
     assert rel(host(u), ref["u"]) <= 1e-9
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_graph_mode_matches_stream_mode(psd, precision):
+@pytest.mark.parametrize("precision,p", [("fp64", 4.0), ("mixed", 4.0), ("mixed", 6.0)])
+def test_graph_mode_matches_stream_mode(psd, precision, p):
     n, L = 48, 12.8
     f = psd_inputs.small_field(3, n, L, 61, K=6)
-    P = psd.Problem(3, n, L, 4, 4.0, 0.01, 0.1)
+    P = psd.Problem(3, n, L, 4, p, 0.01, 0.1)
     out = []
     for chunk in (0, 4):
         with psd.Solver(P, tol=1e-10, max_iter=300, precision=precision, graph_chunk=chunk) as S:
