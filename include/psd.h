@@ -190,6 +190,36 @@ psd_status psd_adjoint(psd_handle* h, const double* const* u_star, const double*
                        double* const* dJdf, double* dJds, double* dJdeps, double rtol,
                        int max_iter, int* cg_iters);
 
+/* Convex-splitting time stepping: nsteps time levels, each one PSD solve
+ * warm-started from the previous level (the handle's options: tol, max_iter,
+ * precision, graph_chunk).  The time step is the problem's s.
+ *   PSD_SCHEME_THINFILM (order-4 handle; Sec. 6.1, thin film with slope
+ *     selection): N_h[u^{n+1}] = u^n - s Delta_h^v u^n, Delta_h^v the skew
+ *     Laplacian of Sec. 5.1 (vertex gradient, then vertex-to-centre divergence);
+ *   PSD_SCHEME_SPFC (order-6 handle with lambda = gamma0; Sec. 6.2, square
+ *     phase field crystal): the sixth-order system with g = u^n and
+ *     f = -s gamma1 Delta_h u^n (5-point Laplacian; the factor s, absent
+ *     from the printed scheme, makes the step consistent with the H^-1
+ *     gradient flow and energy stable); w[b] (may be NULL) receives
+ *     w^{n+1} of the last step.
+ * u[b] (device) holds u^0 on entry and u^nsteps on exit.  stats[batch] (host)
+ * receives per instance the steps completed, the summed and the largest
+ * PSD iteration counts, the residual of the last solve and the worst status;
+ * step_iters (host, may be NULL) receives nsteps * batch iteration counts,
+ * step-major.  Stops at the first step whose solve fails (status < 0);
+ * a solve that hits max_iter is reported (PSD_NOT_CONVERGED) and stepping
+ * continues.  gamma1 is used by the SPFC scheme only (>= 0). */
+enum { PSD_SCHEME_THINFILM = 0, PSD_SCHEME_SPFC = 1 };
+typedef struct {
+    int steps;
+    int psd_iters;
+    int max_iters;
+    double res_inf;
+    int status;
+} psd_step_stats;
+psd_status psd_timestep(psd_handle* h, int scheme, double gamma1, double* const* u, double* const* w,
+                        int nsteps, psd_step_stats* stats, int* step_iters);
+
 /* Per-update history of instance `inst` from the last psd_solve (options
  * history != 0): out[4*k + {0,1,2,3}] = alpha, ||r||_inf, ||r||_2, energy
  * decrease (p = 4 and p = 6, the integral of the polynomial q of Sec. 6.1;

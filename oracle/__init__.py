@@ -319,3 +319,74 @@ def cholesky_solve(A: np.ndarray, b: np.ndarray) -> np.ndarray:
     if st != 0:
         raise RuntimeError("matrix not SPD")
     return x
+
+
+# ---------------------------------------------------------------------------
+# Convex-splitting time stepping (Sec. 6.1 thin film, Sec. 6.2 SPFC): each
+# step is one PSD solve, warm-started from the previous time level.
+# ---------------------------------------------------------------------------
+def skew_lap(P: "Problem", v) -> np.ndarray:
+    """Delta_h^v v = d.(D v): the vertex gradient of Sec. 5.1 followed by the
+    vertex-to-centre divergence (the 'skew' Laplacian of the thin-film
+    scheme)."""
+    return P.vdiv(P.vgrad(v))
+
+
+def thinfilm_steps(P: "Problem", u0, nsteps: int, tol: float = 1e-10, max_iter: int = 500):
+    """Thin-film convex-splitting scheme (Sec. 6.1): N_h[u^{n+1}] = u^n - s Delta_h^v u^n
+    with N_h of the fourth-order problem (time step s, exponent p, eps), PSD
+    started from u^n.  Returns (u^N, list of PSD iteration counts per step)."""
+    assert P.order == 4
+    u = _arr(u0).copy()
+    iters = []
+    for _ in range(nsteps):
+        f = u - P.s * skew_lap(P, u)
+        out = P.solve(f, u0=u, tol=tol, max_iter=max_iter)
+        u = out["u"]
+        iters.append(out["iters"])
+    return u, iters
+
+
+def spfc_steps(P: "Problem", u0, gamma1: float, nsteps: int, tol: float = 1e-10,
+               max_iter: int = 500):
+    """Square phase field crystal scheme (Sec. 6.2): the sixth-order mixed
+    system with lambda = gamma0, g = u^n and f = -s gamma1 Delta_h u^n (time
+    step s), PSD started from u^n.  The factor s on the explicit term is the
+    one that makes the step consistent with the H^-1 gradient flow of the SPFC
+    energy (the scheme is printed without it).  Returns (u^N, w^N, iteration
+    counts)."""
+    assert P.order == 6
+    u = _arr(u0).copy()
+    iters = []
+    w = None
+    for _ in range(nsteps):
+        g = u.copy()
+        f = -P.s * gamma1 * P.lap(u)
+        out = P.solve(f, u0=u, g=g, tol=tol, max_iter=max_iter)
+        u, w = out["u"], out["w"]
+        iters.append(out["iters"])
+    return u, w, iters
+
+
+def interp_coarse_to_fine(uc: np.ndarray) -> np.ndarray:
+    """Bilinear (2D) / trilinear (3D) interpolation from a periodic
+    cell-centred grid to the grid of half the spacing: fine cell 2i lies a
+    quarter of a coarse cell below coarse centre i, fine cell 2i+1 a quarter
+    above, so per axis the weights are 3/4 on the nearer and 1/4 on the
+    farther coarse centre."""
+    out = np.asarray(uc, dtype=np.float64)
+    for ax in range(out.ndim):
+        lo = np.roll(out, 1, axis=ax)    # coarse centre i-1
+        hi = np.roll(out, -1, axis=ax)   # coarse centre i+1
+        even = 0.75 * out + 0.25 * lo
+        odd = 0.75 * out + 0.25 * hi
+        shape = list(out.shape)
+        shape[ax] *= 2
+        res = np.empty(shape)
+        idx = [slice(None)] * out.ndim
+        idx[ax] = slice(0, None, 2)
+        res[tuple(idx)] = even
+        idx[ax] = slice(1, None, 2)
+        res[tuple(idx)] = odd
+        out = res
+    return out

@@ -840,6 +840,45 @@ __device__ __forceinline__ double at3(const double* u, int n, int dim, int i, in
   return u[i + (long long)n * (j + (long long)n * k)];
 }
 
+// div_h(R grad_h u) at cell (i, j, k) from the 4 (2D) or 8 (3D) vertices
+// around it, with R = |grad_h u|^{p-2} (linear = false) or R = 1 (linear =
+// true: the skew Laplacian Delta_h^v of Sec. 5.1); direct global reads.
+__device__ __forceinline__ double div_flux_at(const Inst& I, const double* u, int i, int j, int k,
+                                              bool linear) {
+  const int n = I.n, dim = I.dim;
+  const double ih = I.inv_h;
+  double div = 0.0;
+  const int nz = dim == 3 ? 2 : 1;
+  for (int cz = 0; cz < nz; ++cz)
+    for (int cy = 0; cy < 2; ++cy)
+      for (int cx = 0; cx < 2; ++cx) {
+        // vertex (i - 1 + cx + 1/2, j - 1 + cy + 1/2, k - 1 + cz + 1/2): lower cell corner
+        const int vi = i - 1 + cx, vj = j - 1 + cy, vk = dim == 3 ? k - 1 + cz : 0;
+        double gx, gy, gz = 0.0;
+        if (dim == 2) {
+          const double c00 = at3(u, n, 2, vi, vj, 0), c10 = at3(u, n, 2, vi + 1, vj, 0);
+          const double c01 = at3(u, n, 2, vi, vj + 1, 0), c11 = at3(u, n, 2, vi + 1, vj + 1, 0);
+          gx = 0.5 * ih * ((c10 - c00) + (c11 - c01));
+          gy = 0.5 * ih * ((c01 - c00) + (c11 - c10));
+        } else {
+          const double c000 = at3(u, n, 3, vi, vj, vk), c100 = at3(u, n, 3, vi + 1, vj, vk);
+          const double c010 = at3(u, n, 3, vi, vj + 1, vk), c110 = at3(u, n, 3, vi + 1, vj + 1, vk);
+          const double c001 = at3(u, n, 3, vi, vj, vk + 1), c101 = at3(u, n, 3, vi + 1, vj, vk + 1);
+          const double c011 = at3(u, n, 3, vi, vj + 1, vk + 1), c111 = at3(u, n, 3, vi + 1, vj + 1, vk + 1);
+          const double q = 0.25 * ih;
+          gx = q * ((c100 - c000) + (c110 - c010) + (c101 - c001) + (c111 - c011));
+          gy = q * ((c010 - c000) + (c110 - c100) + (c011 - c001) + (c111 - c101));
+          gz = q * ((c001 - c000) + (c101 - c100) + (c011 - c010) + (c111 - c110));
+        }
+        const double rr = linear ? 1.0 : flux_r(gx * gx + gy * gy + gz * gz, I.p, I.p_is_4, I.p_is_2);
+        // divergence weights: +-1/(2h) (2D) or +-1/(4h) (3D) per component
+        const double w = dim == 2 ? 0.5 * ih : 0.25 * ih;
+        div += w * ((cx ? 1.0 : -1.0) * rr * gx + (cy ? 1.0 : -1.0) * rr * gy +
+                    (dim == 3 ? (cz ? 1.0 : -1.0) * rr * gz : 0.0));
+      }
+  return div;
+}
+
 __global__ __launch_bounds__(PSD_NT) void k_param_sens(const Inst* __restrict__ insts, int inst,
                                                        double* __restrict__ part) {
   __shared__ double scratch[2 * PSD_NT / PSD_WAVE];
@@ -859,36 +898,7 @@ __global__ __launch_bounds__(PSD_NT) void k_param_sens(const Inst* __restrict__ 
     double l2 = lap(i + 1, j, k) + lap(i - 1, j, k) + lap(i, j + 1, k) + lap(i, j - 1, k) - 4.0 * lap(i, j, k);
     if (dim == 3) l2 += lap(i, j, k + 1) + lap(i, j, k - 1) - 2.0 * lap(i, j, k);
     l2 *= ih2;
-    // p-Laplacian: fluxes at the 4 (2D) or 8 (3D) vertices around the cell
-    double div = 0.0;
-    const int nz = dim == 3 ? 2 : 1;
-    for (int cz = 0; cz < nz; ++cz)
-      for (int cy = 0; cy < 2; ++cy)
-        for (int cx = 0; cx < 2; ++cx) {
-          // vertex (i - 1 + cx + 1/2, j - 1 + cy + 1/2, k - 1 + cz + 1/2): lower cell corner
-          const int vi = i - 1 + cx, vj = j - 1 + cy, vk = dim == 3 ? k - 1 + cz : 0;
-          double gx, gy, gz = 0.0;
-          if (dim == 2) {
-            const double c00 = at3(u, n, 2, vi, vj, 0), c10 = at3(u, n, 2, vi + 1, vj, 0);
-            const double c01 = at3(u, n, 2, vi, vj + 1, 0), c11 = at3(u, n, 2, vi + 1, vj + 1, 0);
-            gx = 0.5 * ih * ((c10 - c00) + (c11 - c01));
-            gy = 0.5 * ih * ((c01 - c00) + (c11 - c10));
-          } else {
-            const double c000 = at3(u, n, 3, vi, vj, vk), c100 = at3(u, n, 3, vi + 1, vj, vk);
-            const double c010 = at3(u, n, 3, vi, vj + 1, vk), c110 = at3(u, n, 3, vi + 1, vj + 1, vk);
-            const double c001 = at3(u, n, 3, vi, vj, vk + 1), c101 = at3(u, n, 3, vi + 1, vj, vk + 1);
-            const double c011 = at3(u, n, 3, vi, vj + 1, vk + 1), c111 = at3(u, n, 3, vi + 1, vj + 1, vk + 1);
-            const double q = 0.25 * ih;
-            gx = q * ((c100 - c000) + (c110 - c010) + (c101 - c001) + (c111 - c011));
-            gy = q * ((c010 - c000) + (c110 - c100) + (c011 - c001) + (c111 - c101));
-            gz = q * ((c001 - c000) + (c101 - c100) + (c011 - c010) + (c111 - c110));
-          }
-          const double rr = flux_r(gx * gx + gy * gy + gz * gz, I.p, I.p_is_4, I.p_is_2);
-          // divergence weights: +-1/(2h) (2D) or +-1/(4h) (3D) per component
-          const double w = dim == 2 ? 0.5 * ih : 0.25 * ih;
-          div += w * ((cx ? 1.0 : -1.0) * rr * gx + (cy ? 1.0 : -1.0) * rr * gy +
-                      (dim == 3 ? (cz ? 1.0 : -1.0) * rr * gz : 0.0));
-        }
+    const double div = div_flux_at(I, u, i, j, k, false);
     const double lam = I.adj_lam[c];
     const double e2 = I.se2 / I.s;
     acc[0] += lam * (-div + e2 * l2);
@@ -896,6 +906,32 @@ __global__ __launch_bounds__(PSD_NT) void k_param_sens(const Inst* __restrict__ 
   }
   block_reduce<2, 0>(acc, scratch);
   if (threadIdx.x == 0) { part[2 * blockIdx.x] = acc[0]; part[2 * blockIdx.x + 1] = acc[1]; }
+}
+
+// Right-hand sides of the convex-splitting time steps from the current time
+// level u (one thread per cell):
+//   scheme 0, thin film (Sec. 6.1):  f = u - s Delta_h^v u   (skew Laplacian)
+//   scheme 1, SPFC (Sec. 6.2):       g = u,  f = -s gamma1 Delta_h u   (5-point;
+//                                    s makes the step consistent with the H^-1 flow)
+__global__ __launch_bounds__(PSD_NT) void k_ts_rhs(const Inst* __restrict__ insts, int inst, int scheme,
+                                                   double gamma1, const double* __restrict__ u,
+                                                   double* __restrict__ f, double* __restrict__ g) {
+  const Inst& I = insts[inst];
+  const int n = I.n, dim = I.dim;
+  const double ih2 = I.inv_h * I.inv_h;
+  for (long long c = blockIdx.x * (long long)PSD_NT + threadIdx.x; c < I.ncell; c += (long long)gridDim.x * PSD_NT) {
+    const int i = (int)(c % n), j = (int)((c / n) % n), k = dim == 3 ? (int)(c / ((long long)n * n)) : 0;
+    const double uc = u[c];
+    if (scheme == 0) {
+      f[c] = uc - I.s * div_flux_at(I, u, i, j, k, true);
+    } else {
+      double lap = at3(u, n, dim, i + 1, j, k) + at3(u, n, dim, i - 1, j, k) + at3(u, n, dim, i, j + 1, k) +
+                   at3(u, n, dim, i, j - 1, k) - 4.0 * uc;
+      if (dim == 3) lap += at3(u, n, dim, i, j, k + 1) + at3(u, n, dim, i, j, k - 1) - 2.0 * uc;
+      f[c] = -I.s * gamma1 * lap * ih2;
+      g[c] = uc;
+    }
+  }
 }
 
 // mark every instance except `keep` as finished (auxiliary single-instance calls)

@@ -111,6 +111,7 @@ struct psd_handle_s {
   hipGraph_t graph = nullptr;
   int gchunk = 0;
   bool adj_alloc = false;
+  std::vector<double*> ts_f, ts_g;   // right-hand sides of the time steps (psd_timestep)
   // tuning (autotuner or defaults)
   int tune_zc_res = T3Z_RES, tune_zc_ls = T3Z_LS;
   int ls_tx = L3_TX_NARROW;   // 3D line-search tile width (wide when every n >= 64)
@@ -1302,6 +1303,74 @@ extern "C" psd_status psd_solve_noalloc(const psd_problem* prob, const psd_optio
   if (st < 0) set_err(nullptr, st, h->err.empty() ? std::string("solve failed") : h->err);
   (void)hipStreamSynchronize(h->stream);
   return st;
+}
+
+// ---------------------------------------------------------------------------
+// Convex-splitting time stepping: one warm-started PSD solve per time level
+// (Sec. 6.1 thin film, Sec. 6.2 SPFC).  The right-hand sides are formed on
+// the device from the current level; the solve is psd_solve's.
+// ---------------------------------------------------------------------------
+template <typename T, typename TD, typename TR>
+static psd_status timestep_impl(psd_handle* h, int scheme, double gamma1, double* const* u, double* const* w,
+                                int nsteps, psd_step_stats* stats, int* step_iters) {
+  const int B = h->batch;
+  if (h->ts_f.empty()) {
+    h->ts_f.assign(B, nullptr);
+    h->ts_g.assign(B, nullptr);
+    for (int b = 0; b < B; ++b) {
+      const size_t bytes = (size_t)h->hI[b].ncell * 8;
+      if (dalloc(h, &h->ts_f[b], bytes) || dalloc(h, &h->ts_g[b], bytes)) {
+        h->ts_f.clear();
+        h->ts_g.clear();
+        return set_err(h, PSD_ERR_HIP, "out of device memory");
+      }
+    }
+  }
+  for (int b = 0; b < B; ++b) {
+    stats[b].steps = 0; stats[b].psd_iters = 0; stats[b].max_iters = 0;
+    stats[b].res_inf = 0.0; stats[b].status = PSD_OK;
+  }
+  std::vector<psd_stats> st1(B);
+  const double* const* fa = h->ts_f.data();
+  const double* const* ga = scheme == PSD_SCHEME_SPFC ? (const double* const*)h->ts_g.data() : nullptr;
+  psd_status worst = PSD_OK;
+  for (int step = 0; step < nsteps; ++step) {
+    for (int b = 0; b < B; ++b)
+      k_ts_rhs<<<1024, PSD_NT, 0, h->stream>>>(h->dI, b, scheme, gamma1, u[b], h->ts_f[b], h->ts_g[b]);
+    HIPCHK(hipGetLastError());
+    psd_status st = solve_impl<T, TD, TR>(h, fa, ga, u, w, st1.data());
+    for (int b = 0; b < B; ++b) {
+      psd_step_stats& S = stats[b];
+      if (st1[b].status >= 0) S.steps += 1;
+      S.psd_iters += st1[b].iters;
+      S.max_iters = std::max(S.max_iters, st1[b].iters);
+      S.res_inf = st1[b].res_inf;
+      if (st1[b].status < 0 || (st1[b].status > 0 && S.status == PSD_OK)) S.status = st1[b].status;
+      if (step_iters) step_iters[(size_t)step * B + b] = st1[b].iters;
+    }
+    if (st < 0) return st;
+    if (st > 0) worst = st;
+  }
+  return worst;
+}
+
+extern "C" psd_status psd_timestep(psd_handle* h, int scheme, double gamma1, double* const* u, double* const* w,
+                                   int nsteps, psd_step_stats* stats, int* step_iters) {
+  if (!h) return PSD_ERR_ARG;
+  if (!u || !stats || nsteps < 0) return set_err(h, PSD_ERR_ARG, "u and stats must be given, nsteps >= 0");
+  for (int b = 0; b < h->batch; ++b)
+    if (!u[b]) return set_err(h, PSD_ERR_ARG, "NULL u[b]");
+  if (scheme == PSD_SCHEME_THINFILM) {
+    if (h->order != 4) return set_err(h, PSD_ERR_ARG, "the thin-film scheme needs an order-4 problem");
+  } else if (scheme == PSD_SCHEME_SPFC) {
+    if (h->order != 6) return set_err(h, PSD_ERR_ARG, "the SPFC scheme needs an order-6 problem");
+    if (!(gamma1 >= 0.0) || !std::isfinite(gamma1)) return set_err(h, PSD_ERR_RANGE, "gamma1 must be >= 0");
+  } else {
+    return set_err(h, PSD_ERR_ARG, "unknown scheme");
+  }
+  HIPCHK(hipSetDevice(h->device));
+  if (h->mixed) return timestep_impl<float, float, float>(h, scheme, gamma1, u, w, nsteps, stats, step_iters);
+  return timestep_impl<double, double, double>(h, scheme, gamma1, u, w, nsteps, stats, step_iters);
 }
 
 // Auxiliary single-instance evaluations (residual, energy, Poisson solves,

@@ -51,6 +51,16 @@ class _Options(ctypes.Structure):
                 ("autotune", ctypes.c_int)]
 
 
+class _StepStats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int), ("psd_iters", ctypes.c_int), ("max_iters", ctypes.c_int),
+                ("res_inf", ctypes.c_double), ("status", ctypes.c_int)]
+
+
+PSD_SCHEME_THINFILM = 0
+PSD_SCHEME_SPFC = 1
+SCHEMES = {"thinfilm": PSD_SCHEME_THINFILM, "spfc": PSD_SCHEME_SPFC}
+
+
 class _Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("res_inf", ctypes.c_double),
                 ("res_l2", ctypes.c_double), ("energy", ctypes.c_double),
@@ -76,6 +86,9 @@ SIGNATURES = {
     "psd_adjoint": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                    _dp, _dp, ctypes.c_double, ctypes.c_int,
                                    ctypes.POINTER(ctypes.c_int)]),
+    "psd_timestep": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.POINTER(_vp),
+                                    ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_StepStats),
+                                    ctypes.POINTER(ctypes.c_int)]),
     "psd_history": (ctypes.c_int, [_vp, ctypes.c_int, _dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "psd_pass_times": (ctypes.c_int, [_vp, _dp, ctypes.POINTER(ctypes.c_int)]),
     "psd_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
@@ -214,6 +227,27 @@ class Solver:
         if raise_on_error:
             self._check(st, allow=(PSD_OK, PSD_NOT_CONVERGED))
         return [Stats(s.iters, s.res_inf, s.res_l2, s.energy, s.status) for s in stats]
+
+    def timestep(self, u: Sequence[torch.Tensor], nsteps: int, scheme: str = "thinfilm",
+                 gamma1: float = 0.0, w: Optional[Sequence[torch.Tensor]] = None,
+                 per_step: bool = False, raise_on_error: bool = True):
+        """Convex-splitting time stepping (psd_timestep): u[b] holds u^0 on
+        entry and u^nsteps on exit.  Returns per-instance dicts (steps,
+        psd_iters, max_iters, res_inf, status) and, with per_step, the
+        (nsteps, batch) array of PSD iteration counts."""
+        import numpy as np
+        B = self.batch
+        stats = (_StepStats * B)()
+        its = (ctypes.c_int * max(1, nsteps * B))() if per_step else None
+        st = self._lib.psd_timestep(self._h, SCHEMES[scheme], float(gamma1), _ptr_array(u),
+                                    _ptr_array(w) if w is not None else None, int(nsteps), stats, its)
+        if raise_on_error:
+            self._check(st, allow=(PSD_OK, PSD_NOT_CONVERGED))
+        out = [dict(steps=x.steps, psd_iters=x.psd_iters, max_iters=x.max_iters, res_inf=x.res_inf,
+                    status=x.status) for x in stats]
+        if per_step:
+            return out, np.array(its[: nsteps * B], dtype=np.int64).reshape(nsteps, B)
+        return out
 
     def residual(self, inst: int, f, u, g=None, r=None):
         rinf = ctypes.c_double()

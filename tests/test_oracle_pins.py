@@ -537,3 +537,99 @@ def test_adjoint_matches_finite_differences():
     assert abs(fd_s - adj["dJds"]) < 1e-6 * abs(fd_s)
     fd_e = (J(P.replace(eps=P.eps + tau * P.eps), f)[0] - J(P.replace(eps=P.eps - tau * P.eps), f)[0]) / (2 * tau * P.eps)
     assert abs(fd_e - adj["dJdeps"]) < 1e-6 * abs(fd_e)
+
+
+# --------------------------------------------------------------------------
+# convex-splitting time stepping (Sec. 6.1 thin film, Sec. 6.2 SPFC)
+# --------------------------------------------------------------------------
+def _init_thinfilm(n, L=3.2):
+    # the periodic initial data of the Sec. 6.1 convergence test, at cell centres
+    x = (np.arange(n) + 0.5) * L / n
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    return (0.1 * np.sin(2 * np.pi * X / L) ** 2 * np.sin(4 * np.pi * (Y - 1.4) / L)
+            - 0.1 * np.cos(2 * np.pi * (X - 2.0) / L) * np.sin(2 * np.pi * Y / L))
+
+
+def test_thinfilm_step_p2_closed_form():
+    # p = 2: N_h = I - s Delta_h^v + s eps^2 Delta_h^2 and f = u^n - s Delta_h^v u^n are
+    # diagonal in Fourier space: u^ <- (1 + s kv) u^ / (1 + s kv + s eps^2 k^2) per step
+    n, L, nsteps = 32, 3.2, 5
+    P = Problem(2, n, L, p=2.0, s=(L / n) ** 2 / 10 * 20, eps=0.1)
+    u0 = _init_thinfilm(n, L) + 0.02 * psd_inputs.white_noise((n, n), 5)
+    u, its = oracle.thinfilm_steps(P, u0, nsteps, tol=1e-13)
+    kappa, kv = _kgrid(P)
+    U = np.fft.fftn(u0) * ((1 + P.s * kv) / (1 + P.s * kv + P.s * P.eps ** 2 * kappa ** 2)) ** nsteps
+    exact = np.fft.ifftn(U).real
+    assert np.abs(u - exact).max() < 1e-12 * np.abs(exact).max()
+    assert all(k > 0 for k in its)
+
+
+def test_spfc_step_p2_closed_form():
+    # p = 2 version of the SPFC step: (s g0 + s kv + s eps^2 k^2) u^ - w^ = s g1 k u^n^,
+    # u^ + k w^ = u^n^  =>  u^ = u^n^ (s g1 k + 1/k) / (s g0 + s kv + s eps^2 k^2 + 1/k),
+    # k != 0; the mean is kept
+    n, L, nsteps, g0, g1 = 32, 20.0, 4, 0.5, 2.0
+    P = Problem(2, n, L, order=6, p=2.0, s=0.05, eps=1.0, lam=g0)
+    u0 = 0.05 * (2 * np.random.default_rng(11).random((n, n)) - 1) + 0.1
+    u, w, its = oracle.spfc_steps(P, u0, g1, nsteps, tol=1e-13)
+    kappa, kv = _kgrid(P)
+    U = np.fft.fftn(u0)
+    nz = kappa > 0
+    fac = np.ones_like(kappa)
+    fac[nz] = (P.s * g1 * kappa[nz] + 1 / kappa[nz]) / (P.s * g0 + P.s * kv[nz] + P.s * P.eps ** 2 * kappa[nz] ** 2
+                                                  + 1 / kappa[nz])
+    exact = np.fft.ifftn(U * fac ** nsteps).real
+    assert np.abs(u - exact).max() < 1e-11 * np.abs(exact).max()
+
+
+def _thinfilm_energy(P, u):
+    # F_h = 1/p ||grad u||_p^p - 1/2 ||grad u||^2 + eps^2/2 ||Delta_h u||^2 with the vertex
+    # gradient (its concave part is the one the scheme treats explicitly)
+    G2 = (P.vgrad(u) ** 2).sum(axis=0)
+    return P.hd * ((G2 ** (P.p / 2)).sum() / P.p - 0.5 * G2.sum() + 0.5 * P.eps ** 2 * (P.lap(u) ** 2).sum())
+
+
+@pytest.mark.parametrize("p,sfac", [(4.0, 0.1), (4.0, 10.0), (6.0, 1.0)])
+def test_thinfilm_energy_decreases(p, sfac):
+    # convex splitting (Sec. 6.1): the discrete energy decreases at every step, for any s
+    n, L = 32, 3.2
+    P = Problem(2, n, L, p=p, s=sfac * (L / n) ** 2, eps=0.1)
+    u = _init_thinfilm(n, L)
+    E = [_thinfilm_energy(P, u)]
+    for _ in range(20):
+        u, _ = oracle.thinfilm_steps(P, u, 1, tol=1e-12)
+        E.append(_thinfilm_energy(P, u))
+    E = np.array(E)
+    assert (np.diff(E) <= 1e-13 * np.abs(E).max()).all()
+    assert E[-1] < E[0]
+
+
+def test_spfc_energy_decreases():
+    # SPFC energy (Sec. 6.2) with the 5-point gradient in the concave term the scheme
+    # treats explicitly: g0/2 ||u||^2 - g1/2 ||D u||^2 + eps^2/2 ||Delta_h u||^2 + 1/4 ||grad u||_4^4
+    n, L, g0, g1 = 32, 25.0, 0.5, 2.0
+    P = Problem(2, n, L, order=6, p=4.0, s=0.05, eps=1.0, lam=g0)
+    u = 0.05 * (2 * np.random.default_rng(12).random((n, n)) - 1)
+
+    def energy(v):
+        G2 = (P.vgrad(v) ** 2).sum(axis=0)
+        return P.hd * (0.5 * g0 * (v * v).sum() + 0.5 * g1 * (v * P.lap(v)).sum()
+                       + 0.5 * P.eps ** 2 * (P.lap(v) ** 2).sum() + 0.25 * (G2 * G2).sum())
+    E = [energy(u)]
+    for _ in range(15):
+        u, _, _ = oracle.spfc_steps(P, u, g1, 1, tol=1e-12)
+        E.append(energy(u))
+    E = np.array(E)
+    assert (np.diff(E) <= 1e-13 * np.abs(E).max()).all()
+    assert E[-1] < E[0]
+
+
+def test_interp_coarse_to_fine_exact_for_linear_in_cell_index():
+    # bilinear interpolation reproduces functions linear along each axis away from the
+    # periodic seam, and constants everywhere
+    c = np.full((8, 8), 3.5)
+    assert np.allclose(oracle.interp_coarse_to_fine(c), 3.5, atol=0, rtol=0)
+    xc = (np.arange(8) + 0.5) * 2.0          # coarse centres, h_c = 2
+    xf = (np.arange(16) + 0.5) * 1.0         # fine centres
+    fine = oracle.interp_coarse_to_fine(np.tile(xc, (8, 1)))
+    assert np.abs(fine[:, 1:-1] - xf[None, 1:-1]).max() < 1e-14
