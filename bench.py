@@ -314,16 +314,16 @@ def timed(torch, fn, steps, warmup):
 
 
 def bench_c2(psd, torch, np, psd_inputs, args):
-    """2D fourth order, 1024^2, p = 4 and p = 3: time to 1e-10 of the FP64 and
-    the mixed form (HIP graph for p = 4; general p runs the host-driven root
-    rule)."""
+    """2D fourth order, 1024^2, p = 4 and p = 3: time to 1e-10 of the FP64
+    form (host-driven loop) and the mixed form (HIP graph; general p captures a
+    fixed number of root-search passes per iteration)."""
     out = {}
     for p in (4.0, 3.0):
         w = psd_inputs.config2(p)
         f = torch.from_numpy(w.f).to("cuda")
         P = psd.Problem(2, w.n, w.L, 4, w.p, w.s, w.eps)
         for prec in ("fp64", "mixed"):
-            chunk = args.chunk if (prec == "mixed" and p == 4.0) else 0
+            chunk = args.chunk if prec == "mixed" else 0
             with psd.Solver(P, tol=1e-10, max_iter=500, precision=prec, graph_chunk=chunk) as S:
                 u = torch.zeros_like(f)
 

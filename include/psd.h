@@ -78,6 +78,8 @@ enum { PSD_FP64 = 0, PSD_MIXED = 1 };
  *   graph_chunk 0: host-driven loop, the host reads the convergence flag
  *               after every iteration.  k > 0: k iterations are captured once
  *               in a HIP graph and replayed until the device flag says done
+ *               (general p: each captured iteration runs up to 6 evaluation
+ *               passes of the root search; see psd_stats.ls_truncated)
  *   history     non-zero: record per-update (alpha, ||r||_inf, ||r||_2, dE)
  *   profile     non-zero: per-pass kernel timing of psd_solve (psd_pass_times)
  *   autotune    non-zero: pick stencil tilings by timing at creation */
@@ -100,11 +102,15 @@ typedef struct {
 
 /* Per-instance result.  energy is E_h at the final iterate (Sec. 5.3 and
  * 5.4 discrete energies) when options.history is set, else NaN (use
- * psd_energy); status a psd_status. */
+ * psd_energy); status a psd_status.  ls_truncated counts the line searches
+ * of a general-p solve (p other than 2, 4, 6... with no polynomial q) whose
+ * root search stopped at its evaluation cap (graph mode captures a fixed
+ * number of evaluations per iteration) instead of at the root; 0 normally. */
 typedef struct {
     int iters;
     double res_inf, res_l2, energy;
     int status;
+    int ls_truncated;
 } psd_stats;
 
 /* Validate one problem statement on the host (no GPU needed).  Returns

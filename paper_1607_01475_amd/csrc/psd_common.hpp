@@ -57,12 +57,13 @@ struct SolveState {
   int iter;            // updates applied so far
   int done;            // 1: converged / stopped (kernels early-exit)
   int status;          // psd_status
-  int ls_phase;        // general p root rule: 0 expand, 1 newton, 2 finished
+  int ls_phase;        // general p root rule: 1 searching, 2 finished
   int ls_evals;
   int newton_steps;
   double dE;           // energy decrease of the last step (p = 4)
   double mean[3];      // order 6: means of d, e1, e2 removed in the update
-  int pad[2];
+  int ls_trunc;        // general p: line searches stopped by the evaluation cap
+  int pad1;
 };
 
 struct Inst {

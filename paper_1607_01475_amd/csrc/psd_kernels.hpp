@@ -187,9 +187,20 @@ __device__ double poly_root(const double* c) {
 
 // Reduce line-search and spectral partials; mode 0: cubic (p = 4) -> alpha;
 // mode 3: quintic (p = 6) -> alpha; mode 1: general p, first pass at
-// alpha = 0 -> start the root rule; mode 2: general p, one root-rule step
-// after an evaluation at st->x.
-__global__ __launch_bounds__(PSD_FIN_NT) void k_ls_finalize(const Inst* __restrict__ insts, int mode) {
+// alpha = 0 -> start the root search; mode 2: general p, one step of the
+// root search after an evaluation of (q, q') at st->x.
+//
+// General-p root search (q strictly increasing, Sec. 6.1): safeguarded Newton
+// from x0 = -q(0)/q'(0).  Each evaluation narrows the bracket [lo, hi] by the
+// sign of q; a Newton step that leaves the bracket is replaced by bisection
+// (doubling while no upper end is known).  It stops at |q| <= 1e-16 (|q(0)| +
+// q'(0) x), or takes the Newton iterate without evaluating it once the
+// Newton step is below 1e-8 x: with quadratic convergence its error is then
+// at the level of rounding.  After max_evals evaluations it takes its best
+// estimate and counts the search in st->ls_trunc (graph-captured iterations
+// run a fixed number of evaluation passes).
+__global__ __launch_bounds__(PSD_FIN_NT) void k_ls_finalize(const Inst* __restrict__ insts, int mode,
+                                                            int max_evals) {
   __shared__ double scratch[10 * PSD_FIN_NT / PSD_WAVE];
   const Inst& I = insts[blockIdx.x];
   SolveState* st = I.st;
@@ -277,7 +288,7 @@ __global__ __launch_bounds__(PSD_FIN_NT) void k_ls_finalize(const Inst* __restri
       return;
     }
     st->lo = 0.0; st->hi = INFINITY; st->x = -q0 / dq0;
-    st->ls_phase = 0; st->ls_evals = 0; st->newton_steps = 0;
+    st->ls_phase = 1; st->ls_evals = 0; st->newton_steps = 0;
     return;
   }
   // mode 2: evaluation at x finished
@@ -286,27 +297,21 @@ __global__ __launch_bounds__(PSD_FIN_NT) void k_ls_finalize(const Inst* __restri
   const double dq = st->lin + s * acc[1];
   const double c0 = st->c[0], c1 = st->c[1];
   st->ls_evals += 1;
-  if (st->ls_phase == 0) {
-    if (q > 0.0) { st->hi = x; st->ls_phase = 1; }
-    else if (q == 0.0) { st->alpha = x; st->ls_phase = 2; return; }
-    else {
-      st->lo = x; st->x = 2.0 * x;
-      if (st->ls_evals >= 200) { st->alpha = x; st->ls_phase = 2; }
-      return;
-    }
-  } else {
-    if (q > 0.0) st->hi = x;
-    else if (q < 0.0) st->lo = x;
-    else { st->alpha = x; st->ls_phase = 2; return; }
-  }
-  // Newton decision at (x, q, dq)
-  if (fabs(q) <= 1e-16 * (fabs(c0) + c1 * x) || st->newton_steps >= 100) {
-    st->alpha = x; st->ls_phase = 2; return;
-  }
+  if (q > 0.0) st->hi = x;
+  else if (q < 0.0) st->lo = x;
+  else { st->alpha = x; st->ls_phase = 2; return; }
+  if (fabs(q) <= 1e-16 * (fabs(c0) + c1 * x)) { st->alpha = x; st->ls_phase = 2; return; }
   double xn = x - q / dq;
-  if (!(xn > st->lo && xn < st->hi)) xn = 0.5 * (st->lo + st->hi);
-  st->newton_steps += 1;
-  if (fabs(xn - x) <= 1e-15 * x) { st->alpha = xn; st->ls_phase = 2; return; }
+  const bool newton = dq > 0.0 && xn > st->lo && xn < st->hi;
+  if (!newton) xn = isfinite(st->hi) ? 0.5 * (st->lo + st->hi) : 2.0 * x;
+  else st->newton_steps += 1;
+  if (newton && fabs(xn - x) <= 1e-8 * x) { st->alpha = xn; st->ls_phase = 2; return; }
+  if (st->ls_evals >= max_evals) {
+    st->alpha = newton ? xn : x;
+    st->ls_phase = 2;
+    st->ls_trunc += 1;
+    return;
+  }
   st->x = xn;
 }
 
@@ -953,7 +958,7 @@ __global__ void k_reset_state(const Inst* __restrict__ insts, int ninst) {
   SolveState* st = insts[i].st;
   st->alpha = 0.0; st->rinf = 0.0; st->rl2 = 0.0;
   for (int k = 0; k < 4; ++k) st->c[k] = 0.0;
-  st->iter = 0; st->done = 0; st->status = 0; st->ls_phase = 0; st->dE = 0.0;
+  st->iter = 0; st->done = 0; st->status = 0; st->ls_phase = 0; st->dE = 0.0; st->ls_trunc = 0;
   st->mean[0] = st->mean[1] = st->mean[2] = 0.0;
 }
 

@@ -558,8 +558,13 @@ static void run_residual(psd_handle* h, bool upd) {
   k_res_finalize<<<h->batch, PSD_FIN_NT, 0, s>>>(h->dI, upd ? 1 : 0);
 }
 
+// evaluation passes of the general-p root search captured per iteration in
+// graph mode (the search typically needs two to four)
+constexpr int PSD_LS_GRAPH_EVALS = 6;
+constexpr int PSD_LS_HOST_EVALS = 100;
+
 template <typename TD>
-static void run_ls(psd_handle* h, int mode) {
+static void run_ls(psd_handle* h, int mode, int max_evals = PSD_LS_HOST_EVALS) {
   hipStream_t s = h->stream;
   const Task2* t = h->dT + h->ls.off;
   {
@@ -586,7 +591,7 @@ static void run_ls(psd_handle* h, int mode) {
     }
   }
   ProfScope ps(h, PSD_PASS_LS_FIN);
-  k_ls_finalize<<<h->batch, PSD_FIN_NT, 0, s>>>(h->dI, mode);
+  k_ls_finalize<<<h->batch, PSD_FIN_NT, 0, s>>>(h->dI, mode, max_evals);
 }
 
 // one PSD iteration with a polynomial q (p = 4 cubic, p = 6 quintic; Sec.
@@ -613,13 +618,13 @@ static bool all_done(psd_handle* h) {
   return true;
 }
 
-// general p: line search with a host-driven root rule (one grid pass per
-// evaluation of q and q')
+// general p, host-driven loop: the host polls the root search after every
+// evaluation pass (one grid pass per evaluation of q and q')
 template <typename T, typename TD, typename TR>
 static psd_status run_iteration_general(psd_handle* h) {
   run_fft<T, TR, TD>(h, h->fft_solver, h->order == 4 ? OP_PRECOND4 : OP_PRECOND6, true);
   run_ls<TD>(h, 1);
-  for (int step = 0; step < 400; ++step) {
+  for (int step = 0; step < PSD_LS_HOST_EVALS; ++step) {
     run_ls<TD>(h, 2);
     psd_status st = read_states(h);
     if (st != PSD_OK) return st;
@@ -632,10 +637,20 @@ static psd_status run_iteration_general(psd_handle* h) {
   return PSD_OK;
 }
 
+// general p, graph mode: a fixed number of evaluation passes; the blocks of
+// passes after the search has finished return at once
+template <typename T, typename TD, typename TR>
+static void run_iteration_general_fixed(psd_handle* h) {
+  run_fft<T, TR, TD>(h, h->fft_solver, h->order == 4 ? OP_PRECOND4 : OP_PRECOND6, true);
+  run_ls<TD>(h, 1);
+  for (int step = 0; step < PSD_LS_GRAPH_EVALS; ++step) run_ls<TD>(h, 2, PSD_LS_GRAPH_EVALS);
+  run_residual<TD, TR>(h, true);
+}
+
 template <typename T, typename TD, typename TR>
 static psd_status solve_loop(psd_handle* h) {
   const int chunk = h->opt.graph_chunk;
-  if (chunk > 0 && h->poly_ls) {
+  if (chunk > 0) {
     if (!h->gexec || h->gchunk != chunk) {
       if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
       if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
@@ -644,7 +659,8 @@ static psd_status solve_loop(psd_handle* h) {
       HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
       for (int k = 0; k < chunk; ++k) {
         h->prof_iter_slot = k;
-        run_iteration_poly<T, TD, TR>(h);
+        if (h->poly_ls) run_iteration_poly<T, TD, TR>(h);
+        else run_iteration_general_fixed<T, TD, TR>(h);
       }
       h->prof_iter_slot = -1;
       HIPCHK(hipStreamEndCapture(h->stream, &h->graph));
@@ -1211,6 +1227,7 @@ static psd_status solve_impl(psd_handle* h, const double* const* f, const double
       stats[b].res_l2 = S.rl2;
       stats[b].status = status;
       stats[b].energy = NAN;
+      stats[b].ls_truncated = S.ls_trunc;
     }
     if (status < 0 && (worst >= 0 || status < worst)) worst = (psd_status)status;
     else if (status > 0 && worst == PSD_OK) worst = (psd_status)status;

@@ -64,7 +64,7 @@ SCHEMES = {"thinfilm": PSD_SCHEME_THINFILM, "spfc": PSD_SCHEME_SPFC}
 class _Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("res_inf", ctypes.c_double),
                 ("res_l2", ctypes.c_double), ("energy", ctypes.c_double),
-                ("status", ctypes.c_int)]
+                ("status", ctypes.c_int), ("ls_truncated", ctypes.c_int)]
 
 
 _vp = ctypes.c_void_p
@@ -154,6 +154,7 @@ class Stats:
     res_l2: float
     energy: float
     status: int
+    ls_truncated: int = 0
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -226,7 +227,7 @@ class Solver:
                                  _ptr_array(u), _ptr_array(w) if w is not None else None, stats)
         if raise_on_error:
             self._check(st, allow=(PSD_OK, PSD_NOT_CONVERGED))
-        return [Stats(s.iters, s.res_inf, s.res_l2, s.energy, s.status) for s in stats]
+        return [Stats(s.iters, s.res_inf, s.res_l2, s.energy, s.status, s.ls_truncated) for s in stats]
 
     def timestep(self, u: Sequence[torch.Tensor], nsteps: int, scheme: str = "thinfilm",
                  gamma1: float = 0.0, w: Optional[Sequence[torch.Tensor]] = None,
@@ -322,7 +323,7 @@ def solve_noalloc(problem: Problem, f: torch.Tensor, u: torch.Tensor, g: Optiona
                                _ptr(f), _ptr(g), _ptr(u), _ptr(w), ctypes.byref(st))
     if rc not in (PSD_OK, PSD_NOT_CONVERGED):
         raise PSDError(rc, lib.psd_last_error(None).decode())
-    return Stats(st.iters, st.res_inf, st.res_l2, st.energy, st.status)
+    return Stats(st.iters, st.res_inf, st.res_l2, st.energy, st.status, st.ls_truncated)
 
 
 class PSDSolveFn(torch.autograd.Function):

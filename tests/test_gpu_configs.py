@@ -103,7 +103,7 @@ def full_size_parity(psd, name, w, precisions, autotune, chunk_mixed):
             u = torch.zeros_like(f)
             st = S.solve([f], [u])[0]
             tiling = S.tuning()
-        assert st.status == 0 and st.res_inf <= 1e-10
+        assert st.status == 0 and st.res_inf <= 1e-10 and st.ls_truncated == 0
         um = host(u)
         e = sampled_rel(um, G["u_final"], idx)
         print(f"  mixed: iters {st.iters} tiling {tiling} error vs oracle {e}", flush=True)
@@ -116,9 +116,9 @@ def full_size_parity(psd, name, w, precisions, autotune, chunk_mixed):
 @pytest.mark.parametrize("p", [4.0, 3.0])
 def test_config2_1024(psd, p):
     w = psd_inputs.config2(p)
-    # general p runs the host-driven root rule: no graph for the mixed form
-    full_size_parity(psd, f"c2_p{p:g}", w, ("fp64", "mixed"), autotune=False,
-                     chunk_mixed=4 if p == 4.0 else 0)
+    # the mixed form is graph-captured for both p (general p: a fixed number of
+    # root-search passes per captured iteration)
+    full_size_parity(psd, f"c2_p{p:g}", w, ("fp64", "mixed"), autotune=False, chunk_mixed=4)
 
 
 def test_config3_256(psd):
