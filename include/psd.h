@@ -65,6 +65,7 @@ typedef struct {
 } psd_problem;
 
 enum { PSD_FP64 = 0, PSD_MIXED = 1 };
+enum { PSD_METRIC_CONSTANT = 0, PSD_METRIC_VARIABLE = 1 };
 
 /* Solver options.
  *   tol         stop when the absolute max-norm of the residual is <= tol
@@ -98,6 +99,16 @@ typedef struct {
                       32x16; natural or XCD-grouped block order) on this
                       handle's buffers and keep the fastest; results are
                       cached in the file named by PSD_TUNE_CACHE when set */
+    int metric;       /* PSD_METRIC_CONSTANT: d = L_h^{-1} r by FFT (Sec. 5.3 and 6).
+                         PSD_METRIC_VARIABLE (order 4, graph_chunk 0): the metric
+                         of the Remark in Sec. 3, L_k = I - s div_h(|grad_h u^k|^{p-2}
+                         grad_h .) + s eps^2 Delta_h^2 (coefficient frozen at the
+                         current iterate); d = L_k^{-1} r by conjugate gradients
+                         preconditioned with L_h^{-1}, then the same exact line
+                         search and update */
+    double inner_rtol; /* variable metric: stop the inner solve at
+                          ||res||_2 <= inner_rtol ||r||_2 (0: run inner_iters) */
+    int inner_iters;   /* variable metric: iteration cap of the inner solve */
 } psd_options;
 
 /* Per-instance result.  energy is E_h at the final iterate (Sec. 5.3 and

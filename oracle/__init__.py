@@ -390,3 +390,108 @@ def interp_coarse_to_fine(uc: np.ndarray) -> np.ndarray:
         res[tuple(idx)] = odd
         out = res
     return out
+
+
+# ---------------------------------------------------------------------------
+# Variable-metric search direction (Remark in Sec. 3): L_k[nu] = nu - s div_h(
+# |grad_h u^k|^{p-2} grad_h nu) + s eps^2 Delta_h^2 nu, the p-Laplacian's
+# coefficient frozen at the current iterate.  L_k is not diagonal in Fourier
+# space; d^k = L_k^{-1} r^k is computed by conjugate gradients preconditioned
+# with the constant-coefficient operator L_h (FFT, Sec. 5.3).
+# ---------------------------------------------------------------------------
+def apply_Lk(P: "Problem", u, nu) -> np.ndarray:
+    """L_k[nu] with the frozen coefficient R = |grad_h u|^{p-2} at the vertices."""
+    G = P.vgrad(u)
+    R = (G * G).sum(axis=0) ** ((P.p - 2.0) / 2.0) if P.p != 2.0 else np.ones(G.shape[1:])
+    Gn = P.vgrad(nu)
+    return nu - P.s * P.vdiv(R[None] * Gn) + P.s * P.eps ** 2 * P.lap(P.lap(nu))
+
+
+def pcg_Lk(P: "Problem", u, r, rtol: float = 0.0, iters: int = 20):
+    """Preconditioned conjugate gradients for L_k d = r from d = 0 (textbook form,
+    preconditioner L_h^{-1}): stops after `iters` iterations, or earlier when
+    ||res||_2 <= rtol ||r||_2 (rtol > 0).  Returns (d, iterations)."""
+    d = np.zeros_like(r)
+    res = r.copy()
+    z = P.precond(res)
+    pdir = z.copy()
+    rz = P.ip(res, z)
+    r0 = np.sqrt(P.ip(r, r))
+    k = 0
+    while k < iters:
+        Ap = apply_Lk(P, u, pdir)
+        a = rz / P.ip(pdir, Ap)
+        d = d + a * pdir
+        res = res - a * Ap
+        k += 1
+        if rtol > 0 and np.sqrt(P.ip(res, res)) <= rtol * r0:
+            break
+        z = P.precond(res)
+        rz_new = P.ip(res, z)
+        pdir = z + (rz_new / rz) * pdir
+        rz = rz_new
+    return d, k
+
+
+def _root(qfun, c0: float, c1: float) -> float:
+    """Root of the increasing q (Sec. 6.1) by the rule of the oracle's C solve:
+    x = -c0/c1, double until q > 0, then Newton with bisection when a step
+    leaves the bracket; stop at |q| <= 1e-16 (|c0| + c1 x) or |dx| <= 1e-15 x."""
+    lo, hi, x = 0.0, np.inf, -c0 / c1
+    for _ in range(200):
+        q, dq = qfun(x)
+        if q > 0:
+            hi = x
+            break
+        if q == 0:
+            return x
+        lo, x = x, 2 * x
+    for _ in range(100):
+        if abs(q) <= 1e-16 * (abs(c0) + c1 * x):
+            break
+        xn = x - q / dq
+        if not (lo < xn < hi):
+            xn = 0.5 * (lo + hi)
+        if abs(xn - x) <= 1e-15 * x:
+            return xn
+        x = xn
+        q, dq = qfun(x)
+        if q > 0:
+            hi = x
+        elif q < 0:
+            lo = x
+        else:
+            break
+    return x
+
+
+def solve_variable_metric(P: "Problem", f, u0=None, tol: float = 1e-10, max_iter: int = 200,
+                          inner_rtol: float = 0.0, inner_iters: int = 20):
+    """PSD with the variable metric L_k (order 4): d = L_k^{-1} r by PCG (fixed
+    count when inner_rtol = 0), the exact line search of Sec. 6.1, u += alpha d.
+    Returns dict(u, iters, res_inf, alphas, inner, res0, res_hist) with res_hist
+    the max-norm residual after each update and res0 the initial one."""
+    assert P.order == 4
+    f = _arr(f)
+    u = np.zeros_like(f) if u0 is None else _arr(u0).copy()
+    r = P.residual(f, u)
+    res0 = float(np.abs(r).max())
+    alphas, inner, res_hist = [], [], []
+    k = 0
+    while np.abs(r).max() > tol and k < max_iter:
+        d, m = pcg_Lk(P, u, r, inner_rtol, inner_iters)
+        c0 = -P.ip(r, d) / P.hd
+        if P.p == 4.0:
+            c = P.ls_coeffs4(u, d, r)
+            alpha, _ = root_cubic(c)
+        else:
+            _, dq0 = P.q_eval(f, u, d, 0.0)
+            alpha = _root(lambda x: P.q_eval(f, u, d, x), c0, dq0)
+        u = u + alpha * d
+        r = P.residual(f, u)
+        k += 1
+        alphas.append(alpha)
+        inner.append(m)
+        res_hist.append(float(np.abs(r).max()))
+    return dict(u=u, iters=k, res_inf=float(np.abs(r).max()), alphas=np.array(alphas), inner=inner,
+                res0=res0, res_hist=np.array(res_hist))

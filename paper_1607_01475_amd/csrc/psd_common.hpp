@@ -107,6 +107,8 @@ struct Inst {
   int zchunk_res;      // 3D: z-planes marched per residual block (tuned)
   int zchunk_ls;       // 3D: z-planes marched per line-search block (tuned)
   int nblk_vec;        // blocks of the adjoint's vector kernels (and their partials)
+  int adj_frozen;      // 1: the operator of the conjugate gradients is the variable
+                       // metric L_k (frozen p-Laplacian coefficient), not the Hessian
 };
 
 // A block's unit of work: instance and up to three integer coordinates.

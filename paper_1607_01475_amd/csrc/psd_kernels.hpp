@@ -939,6 +939,45 @@ __global__ __launch_bounds__(PSD_NT) void k_ts_rhs(const Inst* __restrict__ inst
   }
 }
 
+// Variable metric: the conjugate-gradient solution x = L_k^{-1} r (FP64, in
+// I.adj_lam) becomes the search direction d (TD), and each block writes the
+// partial sum of r.d (r = I.adj_g, the FP64 residual) into the spectral
+// partial slot the line-search finalize reads for -q(0) (block b of nblk_sp,
+// grid-stride over the cells).
+template <typename TD>
+__global__ __launch_bounds__(PSD_NT) void k_vm_finish(const Inst* __restrict__ insts, int inst) {
+  __shared__ double scratch[2 * PSD_NT / PSD_WAVE];
+  const Inst& I = insts[inst];
+  if (I.st->done) return;
+  TD* d = (TD*)I.d;
+  double acc[2] = {0.0, 0.0};
+  for (long long c = blockIdx.x * (long long)PSD_NT + threadIdx.x; c < I.ncell; c += (long long)gridDim.x * PSD_NT) {
+    const TD dv = (TD)I.adj_lam[c];
+    d[c] = dv;
+    acc[0] += I.adj_g[c] * (double)dv;
+  }
+  block_reduce<2, 0>(acc, scratch);
+  if (threadIdx.x == 0) {
+    I.part_sp[2 * blockIdx.x] = acc[0];
+    I.part_sp[2 * blockIdx.x + 1] = 0.0;
+  }
+}
+
+// Variable metric: FP64 copy of the residual (the right-hand side of the
+// direction solve) and done flags of the finished solves copied to the
+// conjugate-gradient states.
+template <typename TR>
+__global__ __launch_bounds__(PSD_NT) void k_vm_start(const Inst* __restrict__ insts, int inst,
+                                                     const SolveState* __restrict__ psd_st) {
+  const Inst& I = insts[inst];
+  if (blockIdx.x == 0 && threadIdx.x == 0 && psd_st[inst].done) I.st->done = 1;
+  if (psd_st[inst].done) return;
+  const TR* r = (const TR*)I.r;
+  double* g = const_cast<double*>(I.adj_g);
+  for (long long c = blockIdx.x * (long long)PSD_NT + threadIdx.x; c < I.ncell; c += (long long)gridDim.x * PSD_NT)
+    g[c] = (double)r[c];
+}
+
 // mark every instance except `keep` as finished (auxiliary single-instance calls)
 __global__ void k_mark_done(const Inst* __restrict__ insts, int ninst, int keep) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;

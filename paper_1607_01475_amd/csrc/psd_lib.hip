@@ -620,9 +620,8 @@ static bool all_done(psd_handle* h) {
 
 // general p, host-driven loop: the host polls the root search after every
 // evaluation pass (one grid pass per evaluation of q and q')
-template <typename T, typename TD, typename TR>
-static psd_status run_iteration_general(psd_handle* h) {
-  run_fft<T, TR, TD>(h, h->fft_solver, h->order == 4 ? OP_PRECOND4 : OP_PRECOND6, true);
+template <typename TD>
+static psd_status run_ls_general(psd_handle* h) {
   run_ls<TD>(h, 1);
   for (int step = 0; step < PSD_LS_HOST_EVALS; ++step) {
     run_ls<TD>(h, 2);
@@ -633,6 +632,14 @@ static psd_status run_iteration_general(psd_handle* h) {
       if (!h->hState[b].done && h->hState[b].ls_phase != 2) fin = false;
     if (fin) break;
   }
+  return PSD_OK;
+}
+
+template <typename T, typename TD, typename TR>
+static psd_status run_iteration_general(psd_handle* h) {
+  run_fft<T, TR, TD>(h, h->fft_solver, h->order == 4 ? OP_PRECOND4 : OP_PRECOND6, true);
+  psd_status st = run_ls_general<TD>(h);
+  if (st != PSD_OK) return st;
   run_residual<TD, TR>(h, true);
   return PSD_OK;
 }
@@ -650,7 +657,7 @@ static void run_iteration_general_fixed(psd_handle* h) {
 template <typename T, typename TD, typename TR>
 static psd_status solve_loop(psd_handle* h) {
   const int chunk = h->opt.graph_chunk;
-  if (chunk > 0) {
+  if (chunk > 0 && h->opt.metric != PSD_METRIC_VARIABLE) {
     if (!h->gexec || h->gchunk != chunk) {
       if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
       if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
@@ -702,8 +709,18 @@ static psd_status solve_loop(psd_handle* h) {
     return PSD_OK;
   }
   for (int it = 0; it <= h->opt.max_iter; ++it) {
-    if (h->poly_ls) run_iteration_poly<T, TD, TR>(h);
-    else {
+    if (h->opt.metric == PSD_METRIC_VARIABLE) {
+      psd_status st = vm_direction<T, TD, TR>(h);
+      if (st != PSD_OK) return st;
+      if (h->poly_ls) run_ls<TD>(h, h->p_is_6 ? 3 : 0);
+      else {
+        st = run_ls_general<TD>(h);
+        if (st != PSD_OK) return st;
+      }
+      run_residual<TD, TR>(h, true);
+    } else if (h->poly_ls) {
+      run_iteration_poly<T, TD, TR>(h);
+    } else {
       psd_status st = run_iteration_general<T, TD, TR>(h);
       if (st != PSD_OK) return st;
     }
@@ -945,6 +962,15 @@ static psd_status check_create_args(const psd_problem* probs, int batch, const p
   if (!(opt->tol >= 0.0) || opt->max_iter < 0 || (opt->precision != PSD_FP64 && opt->precision != PSD_MIXED) ||
       opt->graph_chunk < 0) {
     msg_out = "bad options";
+    return PSD_ERR_ARG;
+  }
+  if (opt->metric != PSD_METRIC_CONSTANT && opt->metric != PSD_METRIC_VARIABLE) {
+    msg_out = "metric must be PSD_METRIC_CONSTANT or PSD_METRIC_VARIABLE";
+    return PSD_ERR_ARG;
+  }
+  if (opt->metric == PSD_METRIC_VARIABLE &&
+      (probs[0].order != 4 || opt->graph_chunk != 0 || opt->inner_iters < 1 || !(opt->inner_rtol >= 0.0))) {
+    msg_out = "the variable metric needs order 4, graph_chunk 0, inner_iters >= 1 and inner_rtol >= 0";
     return PSD_ERR_ARG;
   }
   return PSD_OK;
@@ -1558,36 +1584,30 @@ extern "C" psd_status psd_history(psd_handle* h, int inst, double* out, int cap,
   return PSD_OK;
 }
 
-template <typename T, typename TD, typename TR>
-static psd_status adjoint_impl(psd_handle* h, const double* const* u_star, const double* const* dJdu,
-                               double* const* dJdf, double* dJds, double* dJdeps, double rtol, int max_iter,
-                               int* cg_iters) {
-  const int B = h->batch;
-  hipStream_t s = h->stream;
-  std::vector<Inst> saved = h->hI;
-  for (int b = 0; b < B; ++b) {
+// Conjugate-gradient buffers (residual, direction, operator times direction),
+// allocated once per handle; shared by the adjoint and the variable metric.
+static psd_status ensure_cg_buffers(psd_handle* h) {
+  if (h->adj_alloc) return PSD_OK;
+  for (int b = 0; b < h->batch; ++b) {
     Inst& I = h->hI[b];
-    if (!h->adj_alloc) {
-      if (dalloc(h, &I.adj_r, I.ncell * 8) || dalloc(h, &I.adj_p, I.ncell * 8) || dalloc(h, &I.adj_Hp, I.ncell * 8)) {
-        h->hI = saved;
-        return set_err(h, PSD_ERR_HIP, "out of device memory");
-      }
-    }
-    I.adj_us = u_star[b];
-    I.adj_g = dJdu[b];
-    I.adj_lam = dJdf[b];
-    I.max_iter = max_iter;
-    I.st = h->dAuxState + b;   // the CG state; the last solve's state stays intact
+    if (dalloc(h, &I.adj_r, I.ncell * 8) || dalloc(h, &I.adj_p, I.ncell * 8) || dalloc(h, &I.adj_Hp, I.ncell * 8))
+      return set_err(h, PSD_ERR_HIP, "out of device memory");
   }
   h->adj_alloc = true;
-  // keep the buffers for later calls
-  for (int b = 0; b < B; ++b) {
-    saved[b].adj_r = h->hI[b].adj_r; saved[b].adj_p = h->hI[b].adj_p; saved[b].adj_Hp = h->hI[b].adj_Hp;
-  }
-  psd_status st = upload_inst(h);
-  if (st != PSD_OK) { h->hI = saved; (void)upload_inst(h); return st; }
-  k_reset_state<<<(B + 63) / 64, 64, 0, s>>>(h->dI, B);
-  const double rtol2 = rtol * rtol;
+  return PSD_OK;
+}
+
+// Flexible conjugate gradients on  A lam = g  for every instance, A the Hessian
+// of E_h at adj_us (second variation, Sec. 5.3) or, with adj_frozen, the
+// variable metric L_k; preconditioned by L_h^{-1} (the FFT passes).  The
+// instance table must point at the auxiliary states (reset, finished
+// instances marked done), adj_g/adj_lam/adj_us at the fields, max_iter at the
+// iteration cap.  Stops at ||res||_2^2 <= rtol2 ||g||_2^2 or the cap; the host
+// reads the states after every iteration.
+template <typename T, typename TD, typename TR>
+static psd_status cg_solve(psd_handle* h, double rtol2, int max_iter) {
+  const int B = h->batch;
+  hipStream_t s = h->stream;
   auto vec = [&](int op) {
     for (int b = 0; b < B; ++b)
       k_cg_vec<TD, TR><<<h->hI[b].nblk_vec, PSD_NT, 0, s>>>(h->dI, b, op);
@@ -1609,15 +1629,39 @@ static psd_status adjoint_impl(psd_handle* h, const double* const* u_star, const
     vec(1);
     fin(3);
     HIPCHK(hipGetLastError());
-    st = read_states(h);
-    if (st != PSD_OK) { h->hI = saved; (void)upload_inst(h); return st; }
+    psd_status st = read_states(h);
+    if (st != PSD_OK) return st;
     if (all_done(h)) break;
     run_fft<T, TR, TD>(h, h->fft_solver, OP_PRECOND4, true);
     vec(2);
     fin(4);
     vec(4);
   }
-  st = read_states(h);
+  return read_states(h);
+}
+
+template <typename T, typename TD, typename TR>
+static psd_status adjoint_impl(psd_handle* h, const double* const* u_star, const double* const* dJdu,
+                               double* const* dJdf, double* dJds, double* dJdeps, double rtol, int max_iter,
+                               int* cg_iters) {
+  const int B = h->batch;
+  hipStream_t s = h->stream;
+  psd_status st = ensure_cg_buffers(h);
+  if (st != PSD_OK) return st;
+  std::vector<Inst> saved = h->hI;
+  for (int b = 0; b < B; ++b) {
+    Inst& I = h->hI[b];
+    I.adj_us = u_star[b];
+    I.adj_g = dJdu[b];
+    I.adj_lam = dJdf[b];
+    I.max_iter = max_iter;
+    I.adj_frozen = 0;
+    I.st = h->dAuxState + b;   // the CG state; the last solve's state stays intact
+  }
+  st = upload_inst(h);
+  if (st != PSD_OK) { h->hI = saved; (void)upload_inst(h); return st; }
+  k_reset_state<<<(B + 63) / 64, 64, 0, s>>>(h->dI, B);
+  st = cg_solve<T, TD, TR>(h, rtol * rtol, max_iter);
   if (st != PSD_OK) { h->hI = saved; (void)upload_inst(h); return st; }
   psd_status worst = PSD_OK;
   // sensitivities to s and eps (one pass per instance)
@@ -1643,6 +1687,51 @@ static psd_status adjoint_impl(psd_handle* h, const double* const* u_star, const
   st = upload_inst(h);
   HIPCHK(hipStreamSynchronize(s));
   return st != PSD_OK ? st : worst;
+}
+
+// Variable-metric search direction (Remark in Sec. 3): d = L_k^{-1} r with
+// L_k = I - s div_h(|grad_h u^k|^{p-2} grad_h .) + s eps^2 Delta_h^2 by the
+// conjugate gradients above (operator flag adj_frozen), on the auxiliary
+// states so the PSD state is untouched.  The FP64 residual goes to tmp, the
+// solution to the iterate buffer the next update overwrites; at the end the
+// solution becomes d and the spectral partial slots receive (r, d) for -q(0).
+// hState must hold the PSD states (iteration parity of each instance).
+template <typename T, typename TD, typename TR>
+static psd_status vm_direction(psd_handle* h) {
+  const int B = h->batch;
+  hipStream_t s = h->stream;
+  psd_status st = ensure_cg_buffers(h);
+  if (st != PSD_OK) return st;
+  std::vector<Inst> saved = h->hI;
+  for (int b = 0; b < B; ++b) {
+    Inst& I = h->hI[b];
+    const int cur = h->hState[b].iter & 1;
+    I.adj_us = I.u[cur];
+    I.adj_g = I.tmp;
+    I.adj_lam = I.u[cur ^ 1];
+    I.max_iter = h->opt.inner_iters;
+    I.adj_frozen = 1;
+    I.st = h->dAuxState + b;
+  }
+  st = upload_inst(h);
+  if (st != PSD_OK) { h->hI = saved; (void)upload_inst(h); return st; }
+  k_reset_state<<<(B + 63) / 64, 64, 0, s>>>(h->dI, B);
+  for (int b = 0; b < B; ++b) k_vm_start<TR><<<h->hI[b].nblk_vec, PSD_NT, 0, s>>>(h->dI, b, h->dState);
+  HIPCHK(hipGetLastError());
+  st = cg_solve<T, TD, TR>(h, h->opt.inner_rtol * h->opt.inner_rtol, h->opt.inner_iters);
+  // back to the PSD states; the CG fields stay bound for the hand-over
+  for (int b = 0; b < B; ++b) {
+    Inst& I = h->hI[b];
+    I.st = saved[b].st;
+    I.max_iter = saved[b].max_iter;
+    I.adj_frozen = 0;
+  }
+  psd_status st2 = upload_inst(h);
+  if (st != PSD_OK) return st;
+  if (st2 != PSD_OK) return st2;
+  for (int b = 0; b < B; ++b) k_vm_finish<TD><<<h->hI[b].nblk_sp, PSD_NT, 0, s>>>(h->dI, b);
+  HIPCHK(hipGetLastError());
+  return PSD_OK;
 }
 
 extern "C" psd_status psd_adjoint(psd_handle* h, const double* const* u_star, const double* const* dJdu,

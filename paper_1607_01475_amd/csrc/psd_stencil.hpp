@@ -36,7 +36,9 @@ __device__ __forceinline__ double flux_r(double g2, double p, int p_is_4, int p_
 
 // Linearised flux of the second variation (Sec. 5.3) at a vertex:
 //   F = |a|^{p-2} b + (p-2) |a|^{p-4} (a.b) a,  a = grad u*, b = grad xi;
-// the second term is 0 where a = 0 (and for p = 2).
+// the second term is 0 where a = 0 (and for p = 2).  With I.adj_frozen set,
+// the flux of the variable metric of the Remark in Sec. 3, F = |a|^{p-2} b
+// (a = grad u^k, the coefficient frozen at the current iterate).
 __device__ __forceinline__ void flux_lin(const Inst& I, double ax, double ay, double az, double bx,
                                          double by, double bz, double& fx, double& fy, double& fz) {
   const double a2 = ax * ax + ay * ay + az * az, ab = ax * bx + ay * by + az * bz;
@@ -46,6 +48,7 @@ __device__ __forceinline__ void flux_lin(const Inst& I, double ax, double ay, do
   else if (I.p_is_6) { r2 = a2 * a2; r4 = 4.0 * a2; }
   else if (a2 == 0.0) { r2 = 0.0; r4 = 0.0; }
   else { r2 = pow(a2, 0.5 * (I.p - 2.0)); r4 = (I.p - 2.0) * r2 / a2; }
+  if (I.adj_frozen) r4 = 0.0;
   fx = r2 * bx + r4 * ab * ax;
   fy = r2 * by + r4 * ab * ay;
   fz = r2 * bz + r4 * ab * az;

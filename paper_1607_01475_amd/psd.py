@@ -48,7 +48,12 @@ class _Options(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("precision", ctypes.c_int), ("graph_chunk", ctypes.c_int),
                 ("history", ctypes.c_int), ("profile", ctypes.c_int),
-                ("autotune", ctypes.c_int)]
+                ("autotune", ctypes.c_int), ("metric", ctypes.c_int),
+                ("inner_rtol", ctypes.c_double), ("inner_iters", ctypes.c_int)]
+
+
+PSD_METRIC_CONSTANT = 0
+PSD_METRIC_VARIABLE = 1
 
 
 class _StepStats(ctypes.Structure):
@@ -178,14 +183,17 @@ class Solver:
     def __init__(self, problems: Union[Problem, List[Problem]], tol: float = 1e-10,
                  max_iter: int = 500, precision: str = "fp64", graph_chunk: int = 0,
                  history: bool = False, profile: bool = False, autotune: bool = False,
-                 stream: Optional[torch.cuda.Stream] = None):
+                 stream: Optional[torch.cuda.Stream] = None, metric: str = "constant",
+                 inner_rtol: float = 0.0, inner_iters: int = 20):
         self._lib = load_library()
         self.problems = [problems] if isinstance(problems, Problem) else list(problems)
         self.batch = len(self.problems)
         arr = (_Problem * self.batch)(*[p.c() for p in self.problems])
         prec = {"fp64": PSD_FP64, "mixed": PSD_MIXED}[precision]
+        met = {"constant": PSD_METRIC_CONSTANT, "variable": PSD_METRIC_VARIABLE}[metric]
         self.opt = _Options(float(tol), int(max_iter), prec, int(graph_chunk), 1 if history else 0,
-                            1 if profile else 0, 1 if autotune else 0)
+                            1 if profile else 0, 1 if autotune else 0, met, float(inner_rtol),
+                            int(inner_iters))
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = _vp()
         st = self._lib.psd_create(arr, self.batch, ctypes.byref(self.opt),
@@ -316,7 +324,7 @@ def solve_noalloc(problem: Problem, f: torch.Tensor, u: torch.Tensor, g: Optiona
     iterate on exit."""
     lib = load_library()
     prec = {"fp64": PSD_FP64, "mixed": PSD_MIXED}[precision]
-    opt = _Options(float(tol), int(max_iter), prec, 0, 1 if history else 0, 0, 0)
+    opt = _Options(float(tol), int(max_iter), prec, 0, 1 if history else 0, 0, 0, PSD_METRIC_CONSTANT, 0.0, 1)
     st = _Stats()
     strm = stream if stream is not None else torch.cuda.current_stream()
     rc = lib.psd_solve_noalloc(ctypes.byref(problem.c()), ctypes.byref(opt), _vp(strm.cuda_stream),

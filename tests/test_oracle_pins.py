@@ -633,3 +633,54 @@ def test_interp_coarse_to_fine_exact_for_linear_in_cell_index():
     xf = (np.arange(16) + 0.5) * 1.0         # fine centres
     fine = oracle.interp_coarse_to_fine(np.tile(xc, (8, 1)))
     assert np.abs(fine[:, 1:-1] - xf[None, 1:-1]).max() < 1e-14
+
+
+# --------------------------------------------------------------------------
+# variable-metric search direction (Remark in Sec. 3)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dim,n,p", [(2, 10, 4.0), (2, 9, 3.0), (3, 6, 4.0)])
+def test_variable_metric_operator_is_spd(dim, n, p):
+    P = Problem(dim, n, 2.0, p=p, s=0.05, eps=0.3)
+    u = rand(P.shape, 1)
+    a, b = rand(P.shape, 2), rand(P.shape, 3)
+    La, Lb = oracle.apply_Lk(P, u, a), oracle.apply_Lk(P, u, b)
+    assert abs(P.ip(La, b) - P.ip(a, Lb)) < 1e-11 * abs(P.ip(La, b))
+    # dense check: symmetric positive definite on a tiny grid (Cholesky succeeds)
+    N = P.n ** dim
+    A = np.stack([oracle.apply_Lk(P, u, np.eye(N)[k].reshape(P.shape)).ravel() for k in range(N)], axis=1)
+    assert np.abs(A - A.T).max() < 1e-10 * np.abs(A).max()
+    x = oracle.cholesky_solve(A, a.ravel())
+    assert np.abs(A @ x - a.ravel()).max() < 1e-10 * np.abs(a).max()
+
+
+def test_variable_metric_is_newton_at_p2():
+    # p = 2: the frozen coefficient is 1, L_k = N_h, so one direction solves the
+    # equation and the exact line search returns alpha = 1
+    P = Problem(2, 32, 6.4, p=2.0, s=0.01, eps=0.1)
+    f = psd_inputs.small_field(2, 32, 6.4, 8, K=5)
+    u = rand(P.shape, 4)
+    assert np.abs(oracle.apply_Lk(P, u, f) - P.N4(f)).max() < 1e-12 * np.abs(P.N4(f)).max()
+    out = oracle.solve_variable_metric(P, f, tol=1e-11, inner_rtol=1e-14, inner_iters=300)
+    assert out["iters"] == 1 and abs(out["alphas"][0] - 1.0) < 1e-10
+
+
+@pytest.mark.parametrize("p", [4.0, 3.0])
+def test_variable_metric_reaches_the_unique_minimiser(p):
+    # strictly convex energy (Sec. 3): both metrics converge to the same u*, the
+    # energy decreases at every step, and the frozen-coefficient metric needs
+    # fewer outer iterations
+    n, L = 32, 6.4
+    P = Problem(2, n, L, p=p, s=0.01, eps=0.1)
+    f = psd_inputs.small_field(2, n, L, 9, K=5)
+    ref = P.solve(f, tol=1e-12, max_iter=400)
+    out = oracle.solve_variable_metric(P, f, tol=1e-12, inner_rtol=1e-13, inner_iters=300)
+    assert np.abs(out["u"] - ref["u"]).max() <= 1e-11 * np.abs(ref["u"]).max()
+    assert out["iters"] < ref["iters"]
+    # energies along a fixed-count run
+    u = np.zeros_like(f)
+    E = [P.energy(f, u)]
+    for _ in range(4):
+        step = oracle.solve_variable_metric(P, f, u0=u, tol=0.0, max_iter=1, inner_iters=8)
+        u = step["u"]
+        E.append(P.energy(f, u))
+    assert (np.diff(E) < 0).all()
