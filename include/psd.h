@@ -51,7 +51,7 @@ typedef enum {
  *   n     cells per axis; supported: 16, 32, 48, 64, 96, 128, 192, 256, 384,
  *         512, 1024 (2D); up to 256 in 3D
  *   L     box side (> 0)
- *   order 4 or 6 (order 6 is supported in 2D)
+ *   order 4 or 6
  *   p     exponent, p >= 2 (p <= 6 in 3D, Sec. 3.1)
  *   s     > 0
  *   eps   0 < eps <= 1

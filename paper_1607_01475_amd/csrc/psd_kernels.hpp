@@ -86,6 +86,23 @@ __global__ __launch_bounds__(PSD_NT) __attribute__((amdgpu_waves_per_eu(RES3D_WA
   }
 }
 
+// 3D sixth-order residual (brick tiles, res3d6_tile)
+template <typename TD, typename TR, bool UPD>
+__global__ __launch_bounds__(PSD_NT) void k_res3d6(const Inst* __restrict__ insts,
+                                                   const Task2* __restrict__ tasks) {
+  extern __shared__ double smem[];
+  const Task2 t = tasks[blockIdx.x];
+  const Inst& I = insts[t.inst];
+  if (I.st->done) return;
+  double acc[2] = {0.0, 0.0};
+  res3d6_tile<TD, TR, UPD>(I, t.a, t.b, t.c, smem, acc);
+  block_reduce<2, 1>(acc, smem + B6_LDS);
+  if (threadIdx.x == 0) {
+    I.part_res[2 * t.slot] = acc[0];
+    I.part_res[2 * t.slot + 1] = acc[1];
+  }
+}
+
 // One block per instance: reduce residual partials, count the update,
 // decide convergence, record history.
 __global__ __launch_bounds__(PSD_FIN_NT) void k_res_finalize(const Inst* __restrict__ insts, int upd) {

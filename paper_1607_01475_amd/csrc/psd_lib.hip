@@ -226,7 +226,6 @@ extern "C" psd_status psd_check_problem(const psd_problem* prob, char* msg, int 
   if (!prob) return fail(PSD_ERR_ARG, "problem is NULL");
   if (prob->dim != 2 && prob->dim != 3) return fail(PSD_ERR_ARG, "dim must be 2 or 3");
   if (prob->order != 4 && prob->order != 6) return fail(PSD_ERR_ARG, "order must be 4 or 6");
-  if (prob->order == 6 && prob->dim != 2) return fail(PSD_ERR_ARG, "order 6 is supported in 2D");
   if (!n_supported(prob->n)) return fail(PSD_ERR_ARG, "unsupported n");
   if (prob->dim == 3 && (prob->n < 32 || prob->n > 256)) return fail(PSD_ERR_ARG, "3D needs 32 <= n <= 256");
   if (!(prob->L > 0.0) || !std::isfinite(prob->L)) return fail(PSD_ERR_RANGE, "L must be > 0");
@@ -383,6 +382,15 @@ static void build_tile_tasks(psd_handle* h) {
             Task2 t{}; t.inst = b; t.a = x0; t.b = y0; t.c = 0; t.slot = slot++;
             h->hT.push_back(t);
           }
+      } else if (pass == 0 && h->order == 6) {
+        // sixth-order residual: bricks of B6X x B6Y x B6Z cells
+        for (int z0 = 0; z0 < I.n; z0 += B6Z)
+          for (int y0 = 0; y0 < I.n; y0 += B6Y)
+            for (int x0 = 0; x0 < I.n; x0 += B6X) {
+              Task2 t{}; t.inst = b; t.a = x0; t.b = y0; t.c = z0; t.slot = slot++;
+              h->hT.push_back(t);
+            }
+        I.zchunk_res = B6Z;
       } else {
         const int z = std::min(zc, I.n);
         const int tx = pass == 0 ? R3_TX : h->ls_tx;   // tile shape tx x ty
@@ -401,6 +409,8 @@ static void build_tile_tasks(psd_handle* h) {
     if (xcd) xcd_permute(h->hT, R.off, R.cnt);
     if (h->dim == 2)
       R.lds = pass == 0 ? (R2_LDS + 16) * sizeof(double) : (L2_LDS + 32) * sizeof(double);
+    else if (pass == 0 && h->order == 6)
+      R.lds = (B6_LDS + 16) * sizeof(double);
     else
       R.lds = pass == 0 ? (R3Shape<R3_TX>::LDS + 16) * sizeof(double)
                         : ((h->ls_tx == L3_TX_WIDE ? L3Shape<L3_TX_WIDE>::LDS : L3Shape<L3_TX_NARROW>::LDS) + 32) *
@@ -547,6 +557,9 @@ static void run_residual(psd_handle* h, bool upd) {
         if (upd) k_res2d<TD, TR, 6, true><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
         else k_res2d<TD, TR, 6, false><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
       }
+    } else if (h->order == 6) {
+      if (upd) k_res3d6<TD, TR, true><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
+      else k_res3d6<TD, TR, false><<<n, PSD_NT, h->res.lds, s>>>(h->dI, t);
     } else {
       // exponent class of the flux (all instances share p) and tile width
       const double p = h->hI[0].p;

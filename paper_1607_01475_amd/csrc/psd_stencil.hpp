@@ -634,6 +634,142 @@ __device__ __forceinline__ void res3d_tile(const Inst& I, int x0, int y0, int z0
 }
 
 // ===========================================================================
+// 3D sixth-order residual (Sec. 5.4 mixed system, carried w) on a brick of
+// B6X x B6Y x B6Z cells, everything staged in LDS:
+//   v = u + alpha (d - dbar),  w' = w + (e1 - e1bar) - alpha (e2 - e2bar),
+//   r1 = g - v + Delta_h w',
+//   r2 = f - (s lam v - s div_h(|grad_h v|^{p-2} grad_h v) + s eps^2 Delta_h^2 v - w'),
+// writing v and w' to the other ping-pong buffers, r2 and r1 (TR) for the
+// FFT, and the block's max(|r1|, |r2|) and sum of r1^2 + r2^2.  HESS: the
+// sixth-order Hessian without its T_h part, xi - ... replaced by
+// s lam xi - s div_h(F_lin) + s eps^2 Delta_h^2 xi (the adjoint adds T_h xi).
+// LDS (doubles): v (B+4)^3-brick | Laplacian (B+2) | Fx, Fy, Fz at the (B+1)
+// vertices | w' (B+2) (HESS: u* there, halo 1 on the low side suffices).
+// ===========================================================================
+constexpr int B6X = 16, B6Y = 8, B6Z = 4;
+constexpr int B6_VX = B6X + 4, B6_VY = B6Y + 4, B6_VZ = B6Z + 4, B6_V = B6_VX * B6_VY * B6_VZ;
+constexpr int B6_LX = B6X + 2, B6_LY = B6Y + 2, B6_LZ = B6Z + 2, B6_L = B6_LX * B6_LY * B6_LZ;
+constexpr int B6_FX = B6X + 1, B6_FY = B6Y + 1, B6_FZ = B6Z + 1, B6_F = B6_FX * B6_FY * B6_FZ;
+constexpr int B6_LDS = B6_V + B6_L + 3 * B6_F + B6_L;
+
+template <typename TD, typename TR, bool UPD, bool HESS = false>
+__device__ void res3d6_tile(const Inst& I, int x0, int y0, int z0, double* lds, double (&acc)[2]) {
+  const int n = I.n;
+  const long long nn = (long long)n * n;
+  const SolveState* st = I.st;
+  const int cur = st->iter & 1;
+  const double alpha = UPD ? st->alpha : 0.0;
+  const double dbar = st->mean[0], e1bar = st->mean[1], e2bar = st->mean[2];
+  const PSD_GLOBAL double* u = gmem(HESS ? (const double*)I.adj_p : (const double*)I.u[cur]);
+  const PSD_GLOBAL TD* d = gmem((const TD*)I.d);
+  double* v = lds;
+  double* lap = v + B6_V;
+  double* Fx = lap + B6_L;
+  double* Fy = Fx + B6_F;
+  double* Fz = Fy + B6_F;
+  double* wl = Fz + B6_F;
+  const double ih = I.inv_h, ih2 = ih * ih, q = 0.25 * ih;
+  const int tid = threadIdx.x;
+  auto gidx = [&](int i, int j, int k) {
+    return (long long)wrapi(i, n) + (long long)n * wrapi(j, n) + nn * wrapi(k, n);
+  };
+  // v on the brick plus a 2-cell shell
+  for (int e = tid; e < B6_V; e += PSD_NT) {
+    const int ex = e % B6_VX, ey = (e / B6_VX) % B6_VY, ez = e / (B6_VX * B6_VY);
+    const long long gi = gidx(x0 - 2 + ex, y0 - 2 + ey, z0 - 2 + ez);
+    v[e] = UPD ? u[gi] + alpha * ((double)d[gi] - dbar) : u[gi];
+  }
+  // w' (or u* in Hessian mode) on the brick plus a 1-cell shell
+  {
+    const PSD_GLOBAL double* w = gmem(HESS ? I.adj_us : (const double*)I.w[cur]);
+    const PSD_GLOBAL TD* e1 = gmem((const TD*)I.e1);
+    const PSD_GLOBAL TD* e2 = gmem((const TD*)I.e2);
+    for (int e = tid; e < B6_L; e += PSD_NT) {
+      const int ex = e % B6_LX, ey = (e / B6_LX) % B6_LY, ez = e / (B6_LX * B6_LY);
+      const long long gi = gidx(x0 - 1 + ex, y0 - 1 + ey, z0 - 1 + ez);
+      wl[e] = (UPD && !HESS) ? w[gi] + (((double)e1[gi] - e1bar) - alpha * ((double)e2[gi] - e2bar)) : w[gi];
+    }
+  }
+  __syncthreads();
+  // Laplacian of v on the brick plus a 1-cell shell
+  for (int e = tid; e < B6_L; e += PSD_NT) {
+    const int lx = e % B6_LX, ly = (e / B6_LX) % B6_LY, lz = e / (B6_LX * B6_LY);
+    const int c = (lx + 1) + B6_VX * ((ly + 1) + B6_VY * (lz + 1));
+    lap[e] = (v[c - 1] + v[c + 1] + v[c - B6_VX] + v[c + B6_VX] + v[c - B6_VX * B6_VY] +
+              v[c + B6_VX * B6_VY] - 6.0 * v[c]) * ih2;
+  }
+  // fluxes at the vertices (i+1/2, j+1/2, k+1/2), i in [x0-1, x0+B6X) etc.
+  for (int e = tid; e < B6_F; e += PSD_NT) {
+    const int fx = e % B6_FX, fy = (e / B6_FX) % B6_FY, fz = e / (B6_FX * B6_FY);
+    const int c = (fx + 1) + B6_VX * ((fy + 1) + B6_VY * (fz + 1));   // cell (i, j, k) of the vertex
+    constexpr int SY = B6_VX, SZ = B6_VX * B6_VY;
+    const double c000 = v[c], c100 = v[c + 1], c010 = v[c + SY], c110 = v[c + SY + 1];
+    const double c001 = v[c + SZ], c101 = v[c + SZ + 1], c011 = v[c + SZ + SY], c111 = v[c + SZ + SY + 1];
+    const double gx = q * ((c100 - c000) + (c110 - c010) + (c101 - c001) + (c111 - c011));
+    const double gy = q * ((c010 - c000) + (c110 - c100) + (c011 - c001) + (c111 - c101));
+    const double gz = q * ((c001 - c000) + (c101 - c100) + (c011 - c010) + (c111 - c110));
+    if (HESS) {
+      // u* at the same 8 cells, from the shell of wl (offset 1 against v's 2)
+      constexpr int TY = B6_LX, TZ = B6_LX * B6_LY;
+      const int cs = fx + B6_LX * (fy + B6_LY * fz);
+      const double s000 = wl[cs], s100 = wl[cs + 1], s010 = wl[cs + TY], s110 = wl[cs + TY + 1];
+      const double s001 = wl[cs + TZ], s101 = wl[cs + TZ + 1], s011 = wl[cs + TZ + TY], s111 = wl[cs + TZ + TY + 1];
+      const double ax = q * ((s100 - s000) + (s110 - s010) + (s101 - s001) + (s111 - s011));
+      const double ay = q * ((s010 - s000) + (s110 - s100) + (s011 - s001) + (s111 - s101));
+      const double az = q * ((s001 - s000) + (s101 - s100) + (s011 - s010) + (s111 - s110));
+      double fxv, fyv, fzv;
+      flux_lin(I, ax, ay, az, gx, gy, gz, fxv, fyv, fzv);
+      Fx[e] = fxv; Fy[e] = fyv; Fz[e] = fzv;
+    } else {
+      const double rr = flux_r(gx * gx + gy * gy + gz * gz, I.p, I.p_is_4, I.p_is_2);
+      Fx[e] = rr * gx; Fy[e] = rr * gy; Fz[e] = rr * gz;
+    }
+  }
+  __syncthreads();
+  const double s = I.s, se2 = I.se2, slam = I.s * I.lam;
+  PSD_GLOBAL double* uo = gmem(I.u[cur ^ 1]);
+  PSD_GLOBAL double* wo = gmem(I.w[cur ^ 1]);
+  constexpr int NO = B6X * B6Y * B6Z / PSD_NT;
+  for (int k = 0; k < NO; ++k) {
+    const int e = tid + k * PSD_NT;
+    const int tx = e % B6X, ty = (e / B6X) % B6Y, tz = e / (B6X * B6Y);
+    const int gx = x0 + tx, gy = y0 + ty, gz = z0 + tz;
+    if (gx >= n || gy >= n || gz >= n) continue;
+    const long long gi = gx + (long long)n * gy + nn * gz;
+    // vertex (i+1/2, j+1/2, k+1/2) of this cell in the flux arrays, and the 7 below / beside it
+    constexpr int FY = B6_FX, FZ = B6_FX * B6_FY;
+    const int f = (tx + 1) + FY * (ty + 1) + FZ * (tz + 1);
+    const double divx = (Fx[f] - Fx[f - 1]) + (Fx[f - FY] - Fx[f - FY - 1]) + (Fx[f - FZ] - Fx[f - FZ - 1]) +
+                        (Fx[f - FZ - FY] - Fx[f - FZ - FY - 1]);
+    const double divy = (Fy[f] - Fy[f - FY]) + (Fy[f - 1] - Fy[f - FY - 1]) + (Fy[f - FZ] - Fy[f - FZ - FY]) +
+                        (Fy[f - FZ - 1] - Fy[f - FZ - FY - 1]);
+    const double divz = (Fz[f] - Fz[f - FZ]) + (Fz[f - 1] - Fz[f - FZ - 1]) + (Fz[f - FY] - Fz[f - FZ - FY]) +
+                        (Fz[f - FY - 1] - Fz[f - FZ - FY - 1]);
+    const double div = q * ((divx + divy) + divz);
+    constexpr int LY = B6_LX, LZ = B6_LX * B6_LY;
+    const int lc = (tx + 1) + LY * (ty + 1) + LZ * (tz + 1);
+    const double l2 = (lap[lc - 1] + lap[lc + 1] + lap[lc - LY] + lap[lc + LY] + lap[lc - LZ] + lap[lc + LZ] -
+                       6.0 * lap[lc]) * ih2;
+    const double vc = v[(tx + 2) + B6_VX * ((ty + 2) + B6_VY * (tz + 2))];
+    if (HESS) {
+      const double hx = slam * vc - s * div + se2 * l2;
+      gmem(I.adj_Hp)[gi] = hx;
+      acc[1] += vc * hx;
+      continue;
+    }
+    const double wc = wl[lc];
+    const double lw = (wl[lc - 1] + wl[lc + 1] + wl[lc - LY] + wl[lc + LY] + wl[lc - LZ] + wl[lc + LZ] - 6.0 * wc) * ih2;
+    const double r1 = gmem(I.g)[gi] - vc + lw;
+    const double r2 = gmem(I.f)[gi] - (slam * vc - s * div + se2 * l2 - wc);
+    gmem((TR*)I.r1)[gi] = (TR)r1;
+    gmem((TR*)I.r)[gi] = (TR)r2;
+    if (UPD) { uo[gi] = vc; wo[gi] = wc; }
+    acc[0] = fmax(acc[0], fmax(fabs(r1), fabs(r2)));
+    acc[1] += r1 * r1 + r2 * r2;
+  }
+}
+
+// ===========================================================================
 // Line-search sums.  MODE 0 (p = 4 cubic): S2 = sum |a|^2|b|^2,
 // S3 = sum (a.b)^2, S4 = sum (a.b)|b|^2, S5 = sum |b|^4 over vertices with
 // a = grad u, b = grad d; P2 = sum d^2, P4 = sum (Delta_h d)^2 over cells.

@@ -44,7 +44,7 @@ def test_exports_every_declared_symbol(psd):
     (dict(dim=4, n=64, L=1.0), -1),
     (dict(dim=2, n=100, L=1.0), -1),
     (dict(dim=3, n=512, L=1.0), -1),
-    (dict(dim=3, n=64, L=1.0, order=6), -1),
+    (dict(dim=3, n=64, L=1.0, order=6, lam=1.0), 0),
     (dict(dim=2, n=64, L=-1.0), -2),
     (dict(dim=2, n=64, L=1.0, s=0.0), -2),
     (dict(dim=2, n=64, L=1.0, eps=0.0), -2),
