@@ -207,6 +207,24 @@ psd_status psd_adjoint(psd_handle* h, const double* const* u_star, const double*
                        double* const* dJdf, double* dJds, double* dJdeps, double rtol,
                        int max_iter, int* cg_iters);
 
+/* Adjoint of the converged order-6 solve (Sec. 4 and 5.4).  With
+ * u = mean(g) + nu (nu mean-zero) the solution satisfies
+ *   F(nu) = P0[s lam u - s div_h(|grad_h u|^{p-2} grad_h u) + s eps^2 Delta_h^2 u
+ *           + T_h(nu - g) - f] = 0,
+ * whose Jacobian H (the Hessian of the sixth-order energy on mean-zero
+ * functions) is symmetric positive definite.  For each instance b: solve
+ * H Lam = P0 dJdu[b] by conjugate gradients preconditioned with the
+ * one-field sixth-order L_h^{-1} (FP64, FFT), then
+ *   dJdf[b] = Lam,  dJdg[b] = sum(dJdu[b])/N + T_h Lam   (device, may be NULL),
+ *   dJds[b] = -Lam.(lam u - div_h(...) + eps^2 Delta_h^2 u),
+ *   dJdeps[b] = -Lam.(2 s eps Delta_h^2 u),  dJdlam[b] = -s Lam.u
+ * (host arrays [batch], each may be NULL).  dJdu are plain partial
+ * derivatives of a loss of u; stops at ||res||_2 <= rtol ||P0 dJdu||_2 or
+ * max_iter (cg_iters, host, may be NULL, receives the counts). */
+psd_status psd_adjoint6(psd_handle* h, const double* const* u_star, const double* const* dJdu,
+                        double* const* dJdf, double* const* dJdg, double* dJds, double* dJdeps,
+                        double* dJdlam, double rtol, int max_iter, int* cg_iters);
+
 /* Convex-splitting time stepping: nsteps time levels, each one PSD solve
  * warm-started from the previous level (the handle's options: tol, max_iter,
  * precision, graph_chunk).  The time step is the problem's s.

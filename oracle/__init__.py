@@ -495,3 +495,63 @@ def solve_variable_metric(P: "Problem", f, u0=None, tol: float = 1e-10, max_iter
         res_hist.append(float(np.abs(r).max()))
     return dict(u=u, iters=k, res_inf=float(np.abs(r).max()), alphas=np.array(alphas), inner=inner,
                 res0=res0, res_hist=np.array(res_hist))
+
+
+# ---------------------------------------------------------------------------
+# Adjoint of the converged sixth-order solve (Sec. 4 and 5.4).  With
+# u = mean(g) + nu (nu mean-zero) the solution satisfies
+#   F(nu) = P0[s lam u - s div_h(|grad_h u|^{p-2} grad_h u) + s eps^2 Delta_h^2 u
+#           + T_h(nu - g) - f] = 0,
+# whose Jacobian H (the Hessian of E_h on mean-zero functions) is symmetric
+# positive definite.  For a loss J(u) with plain partials G = dJ/du:
+#   Lam = H^{-1} P0 G,  dJ/df = Lam,  dJ/dg = sum(G)/N + T_h Lam,
+#   dJ/ds = -Lam.(lam u - div_h(...) + eps^2 Delta_h^2 u),
+#   dJ/deps = -Lam.(2 s eps Delta_h^2 u),  dJ/dlam = -s Lam.u.
+# ---------------------------------------------------------------------------
+def hessvec6(P: "Problem", u, xi) -> np.ndarray:
+    """H xi = P0[s lam xi - s (linearised p-Laplacian at u) xi + s eps^2 Delta_h^2 xi + T_h xi]."""
+    xi = _arr(xi) - float(np.mean(xi))
+    out = (P.s * P.lam * xi - P.s * P.plap_lin(u, xi) + P.s * P.eps ** 2 * P.lap(P.lap(xi)) + P.T(xi))
+    return out - float(np.mean(out))
+
+
+def _precond6(P: "Problem", r) -> np.ndarray:
+    """z = L_h^{-1} r for the sixth-order preconditioner of Sec. 5.4, symbol
+    s lam + s kappa + s eps^2 kappa^2 + 1/kappa (kappa the symbol of -Delta_h),
+    zero mode set to 0 (numpy FFT)."""
+    kap = P.symbol_neglap()
+    sig = np.full_like(kap, np.inf)
+    nz = kap > 0
+    sig[nz] = P.s * P.lam + P.s * kap[nz] + P.s * P.eps ** 2 * kap[nz] ** 2 + 1.0 / kap[nz]
+    return np.fft.ifftn(np.fft.fftn(r) / sig).real
+
+
+def adjoint6(P: "Problem", u, G, rtol: float = 1e-13, max_iter: int = 2000):
+    """Adjoint of the converged sixth-order solve (see above): preconditioned
+    conjugate gradients for H Lam = P0 G.  Returns dict(dJdf, dJdg, dJds,
+    dJdeps, dJdlam, iters)."""
+    assert P.order == 6
+    u, G = _arr(u), _arr(G)
+    b = G - float(np.mean(G))
+    lam_ = np.zeros_like(b)
+    r = b.copy()
+    z = _precond6(P, r)
+    p = z.copy()
+    rz = float((r * z).sum())
+    nb = float(np.sqrt((b * b).sum()))
+    k = 0
+    while k < max_iter and np.sqrt((r * r).sum()) > rtol * nb:
+        Hp = hessvec6(P, u, p)
+        a = rz / float((p * Hp).sum())
+        lam_ += a * p
+        r -= a * Hp
+        z = _precond6(P, r)
+        rz_new = float((r * z).sum())
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+        k += 1
+    d2 = P.lap(P.lap(u))
+    dNds = P.lam * u - P.plap(u) + P.eps ** 2 * d2
+    return dict(dJdf=lam_, dJdg=float(G.sum()) / G.size + P.T(lam_),
+                dJds=-float((lam_ * dNds).sum()), dJdeps=-float((lam_ * 2 * P.s * P.eps * d2).sum()),
+                dJdlam=-P.s * float((lam_ * u).sum()), iters=k)

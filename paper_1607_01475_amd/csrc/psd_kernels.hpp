@@ -460,7 +460,9 @@ __global__ __launch_bounds__(PSD_NT) void k_cols_any(const Inst* __restrict__ in
 //                partials: sum w |rho^|^2/sigma6/Ntot, sum w |d^|^2/K/Ntot
 //   OP_POISSON:  z^ -> z^/K/Ntot (T_h = -Delta_h^{-1}), partial sum w |z^|^2/K/Ntot
 // K = S[kx] + S[ky] (+ S[kz]) is the symbol of -Delta_h (appendix).
-enum SpecOp { OP_PRECOND4 = 0, OP_PRECOND6 = 1, OP_POISSON = 2 };
+//   OP_PRECOND6S: one field, z^ = r^/sigma6/Ntot, k = 0 -> 0 (sixth-order
+//                adjoint); partial sum w |r^|^2/sigma6/Ntot
+enum SpecOp { OP_PRECOND4 = 0, OP_PRECOND6 = 1, OP_POISSON = 2, OP_PRECOND6S = 3 };
 
 // Last-axis pass: lines of length N along the last axis.  Plain block
 // (task.c = 0): columns kx = task.b .. (kx < N/2) of row ky = task.a (3D;
@@ -489,11 +491,16 @@ __device__ __forceinline__ ColSet fused_cols(const Inst& I, const Task2& t) {
 // One-field operators on one spectral value X at symbol K (wgt_inv = w/Ntot).
 template <typename T, int OP>
 __device__ __forceinline__ cx<T> spec_one(cx<T> X, double K, double s, double se2, double inv,
-                                          double wgt_inv, double& acc0) {
-  static_assert(OP == OP_PRECOND4 || OP == OP_POISSON, "one-field operators");
+                                          double wgt_inv, double& acc0, double slam = 0.0) {
+  static_assert(OP == OP_PRECOND4 || OP == OP_POISSON || OP == OP_PRECOND6S, "one-field operators");
   const double x2 = (double)X.x * X.x + (double)X.y * X.y;
   if (OP == OP_PRECOND4) {
     const double rs = rcp_pos(1.0 + s * K + se2 * K * K);   // 1 / sigma
+    acc0 += wgt_inv * x2 * rs;
+    return scale(X, (T)(inv * rs));
+  } else if (OP == OP_PRECOND6S) {
+    if (!(K > 0.0)) return mk(T(0), T(0));
+    const double rs = 1.0 / (slam + s * K + se2 * K * K + 1.0 / K);
     acc0 += wgt_inv * x2 * rs;
     return scale(X, (T)(inv * rs));
   } else {
@@ -542,7 +549,8 @@ __device__ __forceinline__ void fused_col(const Inst& I, const Task2& t, cx<T>* 
     if (W * N % PSD_NT != 0 && tt >= N) break;
     const double K = Kc + Sl[tt];
     if constexpr (OP != OP_PRECOND6) {
-      buf[c * LS + pidx(tt)] = spec_one<T, OP>(buf[c * LS + pidx(tt)], K, s, se2, inv, wgt_inv, acc[0]);
+      buf[c * LS + pidx(tt)] = spec_one<T, OP>(buf[c * LS + pidx(tt)], K, s, se2, inv, wgt_inv, acc[0],
+                                               s * I.lam);
     } else {
       const cx<T> X2 = buf[c * LS + pidx(tt)], X1 = buf[(W + c) * LS + pidx(tt)];
       if (K > 0.0) {
@@ -598,7 +606,8 @@ __device__ __forceinline__ void fused_col_fs(const Inst& I, const Task2& t, cx<T
     const double Kc = Sl[live ? kx : 0] + (I.dim == 3 ? Sl[live ? ky3 : 0] : 0.0);
     double a0 = 0.0;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) x[k] = spec_one<T, OP>(x[k], Kc + Sl[g + N1 * k], s, se2, inv, wgt_inv, a0);
+    for (int k = 0; k < 16; ++k)
+      x[k] = spec_one<T, OP>(x[k], Kc + Sl[g + N1 * k], s, se2, inv, wgt_inv, a0, s * I.lam);
     if (live) acc[0] += a0;
   }
   __syncthreads();   // every thread has read the forward transpose
@@ -733,7 +742,7 @@ __global__ __launch_bounds__(PSD_NT) void k_axpby(double* __restrict__ out, cons
 // SolveState reuse: c[0] = r.z, c[1] = p.Hp, c[2] = r.r, alpha, x = beta,
 // hi = stop threshold on r.r, iter = CG iterations.
 // ===========================================================================
-template <typename TD, typename TR>
+template <typename TD, typename TR, int ORDER = 4>
 __global__ __launch_bounds__(PSD_NT) void k_hess2d(const Inst* __restrict__ insts,
                                                    const Task2* __restrict__ tasks) {
   extern __shared__ double smem[];
@@ -741,7 +750,7 @@ __global__ __launch_bounds__(PSD_NT) void k_hess2d(const Inst* __restrict__ inst
   const Inst& I = insts[t.inst];
   if (I.st->done) return;
   double acc[2] = {0.0, 0.0};
-  res2d_tile<TD, TR, 4, false, true>(I, t.a, t.b, smem, acc);
+  res2d_tile<TD, TR, ORDER, false, true>(I, t.a, t.b, smem, acc);
   block_reduce<2, 1>(acc, smem + R2_LDS);
   if (threadIdx.x == 0) {
     I.part_res[2 * t.slot] = 0.0;
@@ -762,6 +771,113 @@ __global__ __launch_bounds__(PSD_NT) void k_hess3d(const Inst* __restrict__ inst
   if (threadIdx.x == 0) {
     I.part_res[2 * t.slot] = 0.0;
     I.part_res[2 * t.slot + 1] = acc[1];
+  }
+}
+
+// sixth-order Hessian stencil part in 3D (brick tiles): s lam xi - s div(F_lin) + s eps^2 Delta^2 xi
+__global__ __launch_bounds__(PSD_NT) void k_hess3d6(const Inst* __restrict__ insts,
+                                                    const Task2* __restrict__ tasks) {
+  extern __shared__ double smem[];
+  const Task2 t = tasks[blockIdx.x];
+  const Inst& I = insts[t.inst];
+  if (I.st->done) return;
+  double acc[2] = {0.0, 0.0};
+  res3d6_tile<double, double, false, true>(I, t.a, t.b, t.c, smem, acc);
+  block_reduce<2, 1>(acc, smem + B6_LDS);
+  if (threadIdx.x == 0) {
+    I.part_res[2 * t.slot] = 0.0;
+    I.part_res[2 * t.slot + 1] = acc[1];
+  }
+}
+
+// Conjugate gradients of the sixth-order adjoint (mean-zero space, FP64):
+// H Lam = P0 G with H xi = [stencil part] + T_h xi, preconditioned by the
+// one-field sixth-order L_h^{-1}; tmp carries the FFT input/output (z, T_h p).
+// Vector steps (block b: partials part_res[2b], part_res[2b+1]):
+//   op 0: sum G                          op 1: r = G - mean, lam = 0, tmp = r; sum r.r
+//   op 2: sum r.z (z = tmp)              op 3: p = z
+//   op 4: tmp = p                        op 5: Hp += tmp (T_h p); sum p.Hp
+//   op 6: lam += alpha p, r -= alpha Hp, tmp = r; sum r.r
+//   op 7: sum r.z, sum z.Hp              op 8: p = z + beta p
+// State (auxiliary): lo = mean of G, c[0] = r.z, c[1] = p.Hp, c[2] = r.r,
+// hi = stop threshold, alpha, x = beta, iter = CG iterations.
+__global__ __launch_bounds__(PSD_NT) void k_cg6_vec(const Inst* __restrict__ insts, int inst, int op) {
+  __shared__ double scratch[2 * PSD_NT / PSD_WAVE];
+  const Inst& I = insts[inst];
+  const SolveState* st = I.st;
+  if (st->done) return;
+  const long long N = I.ncell;
+  const long long chunk = (N + gridDim.x - 1) / gridDim.x;
+  const long long c0 = blockIdx.x * chunk;
+  const long long c1 = c0 + chunk < N ? c0 + chunk : N;
+  const double alpha = st->alpha, beta = st->x, mean = st->lo;
+  double acc[2] = {0.0, 0.0};
+  double* z = I.tmp;
+  for (long long c = c0 + threadIdx.x; c < c1; c += PSD_NT) {
+    switch (op) {
+      case 0: acc[1] += I.adj_g[c]; break;
+      case 1: {
+        const double r = I.adj_g[c] - mean;
+        I.adj_r[c] = r; I.adj_lam[c] = 0.0; z[c] = r; acc[1] += r * r;
+      } break;
+      case 2: acc[1] += I.adj_r[c] * z[c]; break;
+      case 3: I.adj_p[c] = z[c]; break;
+      case 4: z[c] = I.adj_p[c]; break;
+      case 5: {
+        const double hp = I.adj_Hp[c] + z[c];
+        I.adj_Hp[c] = hp; acc[1] += I.adj_p[c] * hp;
+      } break;
+      case 6: {
+        I.adj_lam[c] += alpha * I.adj_p[c];
+        const double r = I.adj_r[c] - alpha * I.adj_Hp[c];
+        I.adj_r[c] = r; z[c] = r; acc[1] += r * r;
+      } break;
+      case 7: acc[0] += I.adj_r[c] * z[c]; acc[1] += z[c] * I.adj_Hp[c]; break;
+      default: I.adj_p[c] = z[c] + beta * I.adj_p[c]; break;
+    }
+  }
+  if (op == 0 || op == 1 || op == 2 || op == 5 || op == 6 || op == 7) {
+    block_reduce<2, 0>(acc, scratch);
+    if (threadIdx.x == 0) { I.part_res[2 * blockIdx.x] = acc[0]; I.part_res[2 * blockIdx.x + 1] = acc[1]; }
+  }
+}
+
+// One block per instance: reduce the nblk_vec vector partials and update the
+// scalars of k_cg6_vec.  mode 0: mean of G; 1: threshold; 2: r.z; 3: alpha;
+// 4: r.r and stop test; 5: beta and the new r.z.
+__global__ __launch_bounds__(PSD_NT) void k_cg6_fin(const Inst* __restrict__ insts, int mode, double rtol2) {
+  __shared__ double scratch[2 * PSD_NT / PSD_WAVE];
+  const Inst& I = insts[blockIdx.x];
+  SolveState* st = I.st;
+  if (st->done) return;
+  double acc[2] = {0.0, 0.0};
+  for (int b = threadIdx.x; b < I.nblk_vec; b += PSD_NT) {
+    acc[0] += I.part_res[2 * b];
+    acc[1] += I.part_res[2 * b + 1];
+  }
+  block_reduce<2, 0>(acc, scratch);
+  if (threadIdx.x != 0) return;
+  if (mode == 0) {
+    st->lo = acc[1] * I.inv_ntot;
+  } else if (mode == 1) {
+    st->hi = rtol2 * acc[1];
+    st->c[2] = acc[1];
+    if (!(acc[1] > 0.0)) st->done = 1;   // G constant: Lam = 0
+  } else if (mode == 2) {
+    st->c[0] = acc[1];
+  } else if (mode == 3) {
+    st->c[1] = acc[1];
+    if (!(acc[1] > 0.0)) { st->status = -5; st->done = 1; return; }
+    st->alpha = st->c[0] / acc[1];
+  } else if (mode == 4) {
+    st->c[2] = acc[1];
+    st->iter += 1;
+    if (!isfinite(acc[1])) { st->status = -4; st->done = 1; }
+    else if (acc[1] <= st->hi) st->done = 1;
+    else if (st->iter >= I.max_iter) { st->status = 1; st->done = 1; }
+  } else {
+    st->x = -st->alpha * acc[1] / st->c[0];
+    st->c[0] = acc[0];
   }
 }
 
@@ -854,8 +970,8 @@ __global__ __launch_bounds__(PSD_NT) void k_cg_fin(const Inst* __restrict__ inst
 }
 
 // Parameter sensitivities of N_h at u* weighted by lam (one thread per cell,
-// direct reads):  part[2b] = sum lam (-plap u* + eps^2 Delta_h^2 u*),
-// part[2b+1] = sum lam Delta_h^2 u*.
+// direct reads):  part[3b] = sum lam (-plap u* + eps^2 Delta_h^2 u*),
+// part[3b+1] = sum lam Delta_h^2 u*, part[3b+2] = sum lam u*.
 __device__ __forceinline__ double at3(const double* u, int n, int dim, int i, int j, int k) {
   i = wrapi(i, n); j = wrapi(j, n);
   k = dim == 3 ? wrapi(k, n) : 0;
@@ -903,12 +1019,12 @@ __device__ __forceinline__ double div_flux_at(const Inst& I, const double* u, in
 
 __global__ __launch_bounds__(PSD_NT) void k_param_sens(const Inst* __restrict__ insts, int inst,
                                                        double* __restrict__ part) {
-  __shared__ double scratch[2 * PSD_NT / PSD_WAVE];
+  __shared__ double scratch[3 * PSD_NT / PSD_WAVE];
   const Inst& I = insts[inst];
   const double* u = I.adj_us;
   const int n = I.n, dim = I.dim;
   const double ih = I.inv_h, ih2 = ih * ih;
-  double acc[2] = {0.0, 0.0};
+  double acc[3] = {0.0, 0.0, 0.0};
   for (long long c = blockIdx.x * (long long)PSD_NT + threadIdx.x; c < I.ncell; c += (long long)gridDim.x * PSD_NT) {
     const int i = (int)(c % n), j = (int)((c / n) % n), k = dim == 3 ? (int)(c / ((long long)n * n)) : 0;
     auto lap = [&](int a, int b, int e) {
@@ -925,9 +1041,11 @@ __global__ __launch_bounds__(PSD_NT) void k_param_sens(const Inst* __restrict__ 
     const double e2 = I.se2 / I.s;
     acc[0] += lam * (-div + e2 * l2);
     acc[1] += lam * l2;
+    acc[2] += lam * u[c];
   }
-  block_reduce<2, 0>(acc, scratch);
-  if (threadIdx.x == 0) { part[2 * blockIdx.x] = acc[0]; part[2 * blockIdx.x + 1] = acc[1]; }
+  block_reduce<3, 0>(acc, scratch);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 3; ++q) part[3 * blockIdx.x + q] = acc[q];
 }
 
 // Right-hand sides of the convex-splitting time steps from the current time

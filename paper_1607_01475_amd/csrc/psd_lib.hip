@@ -512,6 +512,7 @@ static void run_fft(psd_handle* h, const FftTasks& F, int op, bool solver) {
     ProfScope ps(h, pr ? PSD_PASS_COLS_FUSED : -1);
     if (op == OP_PRECOND4) launch_fused<T, OP_PRECOND4>(F.colz, dI, dT, sv, s);
     else if (op == OP_PRECOND6) launch_fused<T, OP_PRECOND6>(F.colz, dI, dT, sv, s);
+    else if (op == OP_PRECOND6S) launch_fused<T, OP_PRECOND6S>(F.colz, dI, dT, sv, s);
     else launch_fused<T, OP_POISSON>(F.colz, dI, dT, sv, s);
   }
   if (F.coly_i.cnt) {
@@ -1687,10 +1688,10 @@ static psd_status adjoint_impl(psd_handle* h, const double* const* u_star, const
     else if (S.status > 0 && worst == PSD_OK) worst = PSD_NOT_CONVERGED;
     k_param_sens<<<nblk, PSD_NT, 0, s>>>(h->dI, b, h->dAuxPart);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(h->hPart, h->dAuxPart, sizeof(double) * 2 * nblk, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(h->hPart, h->dAuxPart, sizeof(double) * 3 * nblk, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     double a0 = 0.0, a1 = 0.0;
-    for (int k = 0; k < nblk; ++k) { a0 += h->hPart[2 * k]; a1 += h->hPart[2 * k + 1]; }
+    for (int k = 0; k < nblk; ++k) { a0 += h->hPart[3 * k]; a1 += h->hPart[3 * k + 1]; }
     // dN/ds = -plap(u*) + eps^2 Delta_h^2 u*,  dN/deps = 2 s eps Delta_h^2 u*
     const double eps = std::sqrt(I.se2 / I.s);
     if (dJds) dJds[b] = -a0;
@@ -1745,6 +1746,110 @@ static psd_status vm_direction(psd_handle* h) {
   for (int b = 0; b < B; ++b) k_vm_finish<TD><<<h->hI[b].nblk_sp, PSD_NT, 0, s>>>(h->dI, b);
   HIPCHK(hipGetLastError());
   return PSD_OK;
+}
+
+// Adjoint of the converged sixth-order solve on the mean-zero space (Sec. 4,
+// Sec. 5.4): H Lam = P0 G with H = s lam - s (linearised p-Laplacian) +
+// s eps^2 Delta_h^2 + T_h, conjugate gradients preconditioned by the one-field
+// sixth-order L_h^{-1}, in FP64 (T_h and L_h^{-1} on the auxiliary FP64
+// transform of tmp), on the auxiliary states.
+static psd_status adjoint6_impl(psd_handle* h, const double* const* u_star, const double* const* dJdu,
+                                double* const* dJdf, double* const* dJdg, double* dJds, double* dJdeps,
+                                double* dJdlam, double rtol, int max_iter, int* cg_iters) {
+  const int B = h->batch;
+  hipStream_t s = h->stream;
+  psd_status st = ensure_cg_buffers(h);
+  if (st != PSD_OK) return st;
+  std::vector<Inst> saved = h->hI;
+  for (int b = 0; b < B; ++b) {
+    Inst& I = h->hI[b];
+    I.adj_us = u_star[b];
+    I.adj_g = dJdu[b];
+    I.adj_lam = dJdf[b];
+    I.max_iter = max_iter;
+    I.adj_frozen = 0;
+    I.st = h->dAuxState + b;
+  }
+  auto restore = [&]() { h->hI = saved; return upload_inst(h); };
+  st = upload_inst(h);
+  if (st != PSD_OK) { (void)restore(); return st; }
+  k_reset_state<<<(B + 63) / 64, 64, 0, s>>>(h->dI, B);
+  const double rtol2 = rtol * rtol;
+  auto vec = [&](int op) {
+    for (int b = 0; b < B; ++b) k_cg6_vec<<<h->hI[b].nblk_vec, PSD_NT, 0, s>>>(h->dI, b, op);
+  };
+  auto fin = [&](int mode) { k_cg6_fin<<<B, PSD_NT, 0, s>>>(h->dI, mode, rtol2); };
+  auto aux_fft = [&](int op) { run_fft<double, double, double>(h, h->fft_aux, op, false); };
+  const Task2* tt = h->dT + h->res.off;
+  auto hess = [&]() {
+    if (h->dim == 2) k_hess2d<double, double, 6><<<h->res.cnt, PSD_NT, (R2_LDS + 16) * sizeof(double), s>>>(h->dI, tt);
+    else k_hess3d6<<<h->res.cnt, PSD_NT, (B6_LDS + 16) * sizeof(double), s>>>(h->dI, tt);
+  };
+  vec(0); fin(0);                 // mean of G
+  vec(1); fin(1);                 // r = P0 G, threshold
+  aux_fft(OP_PRECOND6S);          // z = L^-1 r in tmp
+  vec(2); fin(2);                 // r.z
+  vec(3);                         // p = z
+  for (int it = 0; it < max_iter; ++it) {
+    hess();                       // stencil part of H p
+    vec(4);                       // tmp = p
+    aux_fft(OP_POISSON);          // tmp = T_h p
+    vec(5); fin(3);               // Hp += T_h p, alpha
+    vec(6); fin(4);               // lam, r, stop test; tmp = r
+    HIPCHK(hipGetLastError());
+    st = read_states(h);
+    if (st != PSD_OK) { (void)restore(); return st; }
+    if (all_done(h)) break;
+    aux_fft(OP_PRECOND6S);        // z = L^-1 r
+    vec(7); fin(5);               // beta, r.z
+    vec(8);                       // p = z + beta p
+  }
+  st = read_states(h);
+  if (st != PSD_OK) { (void)restore(); return st; }
+  psd_status worst = PSD_OK;
+  const int nblk = 1024;
+  for (int b = 0; b < B; ++b) {
+    const Inst& I = h->hI[b];
+    const SolveState& S = h->hState[b];
+    if (cg_iters) cg_iters[b] = S.iter;
+    if (S.status < 0) worst = (psd_status)S.status;
+    else if (S.status > 0 && worst == PSD_OK) worst = PSD_NOT_CONVERGED;
+    // dJ/dg = sum(G)/N + T_h Lam (tmp <- Lam, auxiliary Poisson solve of this instance)
+    HIPCHK(hipMemcpyAsync(I.tmp, I.adj_lam, I.ncell * 8, hipMemcpyDeviceToDevice, s));
+  }
+  aux_fft(OP_POISSON);
+  for (int b = 0; b < B; ++b) {
+    const Inst& I = h->hI[b];
+    const SolveState& S = h->hState[b];
+    if (dJdg && dJdg[b])
+      k_axpby<<<1024, PSD_NT, 0, s>>>(dJdg[b], I.tmp, nullptr, 1.0, 0.0, S.lo, I.ncell);   // S.lo = sum(G)/N
+    k_param_sens<<<nblk, PSD_NT, 0, s>>>(h->dI, b, h->dAuxPart);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(h->hPart, h->dAuxPart, sizeof(double) * 3 * nblk, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int k = 0; k < nblk; ++k) { a0 += h->hPart[3 * k]; a1 += h->hPart[3 * k + 1]; a2 += h->hPart[3 * k + 2]; }
+    // dN/ds = lam u - plap(u) + eps^2 Delta_h^2 u, dN/deps = 2 s eps Delta_h^2 u, dN/dlam = s u
+    const double eps = std::sqrt(I.se2 / I.s);
+    if (dJds) dJds[b] = -(a0 + I.lam * a2);
+    if (dJdeps) dJdeps[b] = -2.0 * I.s * eps * a1;
+    if (dJdlam) dJdlam[b] = -I.s * a2;
+  }
+  st = restore();
+  HIPCHK(hipStreamSynchronize(s));
+  return st != PSD_OK ? st : worst;
+}
+
+extern "C" psd_status psd_adjoint6(psd_handle* h, const double* const* u_star, const double* const* dJdu,
+                                   double* const* dJdf, double* const* dJdg, double* dJds, double* dJdeps,
+                                   double* dJdlam, double rtol, int max_iter, int* cg_iters) {
+  if (!h) return PSD_ERR_ARG;
+  if (h->order != 6) return set_err(h, PSD_ERR_ARG, "psd_adjoint6 needs an order-6 problem");
+  if (!u_star || !dJdu || !dJdf || max_iter <= 0 || !(rtol >= 0.0)) return set_err(h, PSD_ERR_ARG, "bad arguments");
+  for (int b = 0; b < h->batch; ++b)
+    if (!u_star[b] || !dJdu[b] || !dJdf[b]) return set_err(h, PSD_ERR_ARG, "NULL instance pointer");
+  HIPCHK(hipSetDevice(h->device));
+  return adjoint6_impl(h, u_star, dJdu, dJdf, dJdg, dJds, dJdeps, dJdlam, rtol, max_iter, cg_iters);
 }
 
 extern "C" psd_status psd_adjoint(psd_handle* h, const double* const* u_star, const double* const* dJdu,

@@ -197,7 +197,9 @@ __device__ void res2d_tile(const Inst& I, int x0, int y0, double* lds, double (&
     const double l2 = (lap[lc - 1] + lap[lc + 1] + lap[lc - R2_LW] + lap[lc + R2_LW] - 4.0 * lap[lc]) * ih2;
     const double vc = v[(ty + 2) * R2_VW + tx + 2];
     if (HESS) {
-      const double hx = vc - s * div + se2 * l2;
+      // order 4: xi - s div + s eps^2 Delta^2 xi; order 6 without its T_h part:
+      // s lam xi - s div + s eps^2 Delta^2 xi
+      const double hx = (ORDER == 6 ? s * I.lam : 1.0) * vc - s * div + se2 * l2;
       gmem(I.adj_Hp)[gi] = hx;
       acc[1] += vc * hx;
     } else if (ORDER == 4) {

@@ -94,6 +94,9 @@ SIGNATURES = {
     "psd_timestep": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.POINTER(_vp),
                                     ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_StepStats),
                                     ctypes.POINTER(ctypes.c_int)]),
+    "psd_adjoint6": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                    ctypes.POINTER(_vp), _dp, _dp, _dp, ctypes.c_double, ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_int)]),
     "psd_history": (ctypes.c_int, [_vp, ctypes.c_int, _dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "psd_pass_times": (ctypes.c_int, [_vp, _dp, ctypes.POINTER(ctypes.c_int)]),
     "psd_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
@@ -332,6 +335,23 @@ def solve_noalloc(problem: Problem, f: torch.Tensor, u: torch.Tensor, g: Optiona
     if rc not in (PSD_OK, PSD_NOT_CONVERGED):
         raise PSDError(rc, lib.psd_last_error(None).decode())
     return Stats(st.iters, st.res_inf, st.res_l2, st.energy, st.status, st.ls_truncated)
+
+
+def _adjoint6(self, u_star: Sequence[torch.Tensor], dJdu: Sequence[torch.Tensor],
+              rtol: float = 1e-12, max_iter: int = 2000):
+    """Adjoint of the converged sixth-order solves (psd_adjoint6): returns
+    (dJdf, dJdg, dJds, dJdeps, dJdlam, cg_iters)."""
+    B = self.batch
+    dJdf = [torch.empty_like(t) for t in u_star]
+    dJdg = [torch.empty_like(t) for t in u_star]
+    ds, de, dl = (ctypes.c_double * B)(), (ctypes.c_double * B)(), (ctypes.c_double * B)()
+    it = (ctypes.c_int * B)()
+    self._check(self._lib.psd_adjoint6(self._h, _ptr_array(u_star), _ptr_array(dJdu), _ptr_array(dJdf),
+                                       _ptr_array(dJdg), ds, de, dl, float(rtol), int(max_iter), it))
+    return dJdf, dJdg, list(ds), list(de), list(dl), list(it)
+
+
+Solver.adjoint6 = _adjoint6
 
 
 class PSDSolveFn(torch.autograd.Function):

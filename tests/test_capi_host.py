@@ -12,7 +12,7 @@ LIB = os.path.join(ROOT, "paper_1607_01475_amd", "libpsd.so")
 def declared_symbols():
     src = open(os.path.join(ROOT, "include", "psd.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(psd_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(psd_[a-z0-9_]+)\s*\(", src)))
 
 
 @pytest.fixture(scope="module")

@@ -684,3 +684,51 @@ def test_variable_metric_reaches_the_unique_minimiser(p):
         u = step["u"]
         E.append(P.energy(f, u))
     assert (np.diff(E) < 0).all()
+
+
+# --------------------------------------------------------------------------
+# adjoint of the sixth-order solve (Sec. 4, 5.4)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dim,n", [(2, 16), (3, 8)])
+def test_adjoint6_matches_finite_differences(dim, n):
+    L, s, eps, lam = 3.2, 0.05, 0.3, 0.7
+    f = psd_inputs.small_field(dim, n, L, 31, K=3) + 0.2
+    g = psd_inputs.small_field(dim, n, L, 32, K=3) - 0.1
+    ut = psd_inputs.small_field(dim, n, L, 33, K=3)
+    hd = (L / n) ** dim
+
+    def solve(ff, gg, ss, ee, ll):
+        P = Problem(dim, n, L, order=6, p=4.0, s=ss, eps=ee, lam=ll)
+        return P.solve(ff, g=gg, tol=1e-13, max_iter=3000)["u"]
+
+    def J(ff, gg, ss, ee, ll):
+        u = solve(ff, gg, ss, ee, ll)
+        return 0.5 * hd * ((u - ut) ** 2).sum()
+
+    P = Problem(dim, n, L, order=6, p=4.0, s=s, eps=eps, lam=lam)
+    u = solve(f, g, s, eps, lam)
+    adj = oracle.adjoint6(P, u, hd * (u - ut))
+    tau = 1e-5
+    df, dg = rand(P.shape, 34), rand(P.shape, 35)
+    checks = [
+        ((J(f + tau * df, g, s, eps, lam) - J(f - tau * df, g, s, eps, lam)) / (2 * tau), (adj["dJdf"] * df).sum()),
+        ((J(f, g + tau * dg, s, eps, lam) - J(f, g - tau * dg, s, eps, lam)) / (2 * tau), (adj["dJdg"] * dg).sum()),
+        ((J(f, g, s + tau, eps, lam) - J(f, g, s - tau, eps, lam)) / (2 * tau), adj["dJds"]),
+        ((J(f, g, s, eps + tau, lam) - J(f, g, s, eps - tau, lam)) / (2 * tau), adj["dJdeps"]),
+        ((J(f, g, s, eps, lam + tau) - J(f, g, s, eps, lam - tau)) / (2 * tau), adj["dJdlam"]),
+    ]
+    for fd, an in checks:
+        assert abs(fd - an) <= 1e-6 * abs(fd) + 1e-12
+
+
+def test_adjoint6_hessian_is_spd_on_mean_zero():
+    P = Problem(2, 8, 1.6, order=6, p=4.0, s=0.05, eps=0.3, lam=0.7)
+    u = rand(P.shape, 41)
+    N = P.n ** 2
+    # basis of the mean-zero space: e_k - mean
+    E = np.eye(N) - 1.0 / N
+    A = np.stack([oracle.hessvec6(P, u, E[k].reshape(P.shape)).ravel() for k in range(N)], axis=1)
+    assert np.abs(A - A.T).max() < 1e-10 * np.abs(A).max()
+    B = A[:N - 1, :N - 1]     # restriction to N-1 independent mean-zero directions stays SPD
+    x = oracle.cholesky_solve(B + 0.0, np.ones(N - 1))
+    assert np.all(np.isfinite(x))
