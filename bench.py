@@ -313,6 +313,36 @@ def timed(torch, fn, steps, warmup):
     return ts, outs
 
 
+def bench_c1(psd, torch, np, psd_inputs, args):
+    """2D fourth order, 64^2, p = 4 (latency-bound): time to 1e-10 of the FP64
+    form (host-driven loop) and of the FP64 and mixed forms in HIP graphs."""
+    w = psd_inputs.config1()
+    f = torch.from_numpy(w.f).to("cuda")
+    P = psd.Problem(2, w.n, w.L, 4, w.p, w.s, w.eps)
+    out = {}
+    for key, prec, chunk in (("fp64", "fp64", 0), ("fp64_graph", "fp64", args.chunk),
+                             ("mixed_graph", "mixed", args.chunk)):
+        with psd.Solver(P, tol=1e-10, max_iter=500, precision=prec, graph_chunk=chunk) as S:
+            u = torch.zeros_like(f)
+
+            def run():
+                u.zero_()
+                return S.solve([f], [u])[0]
+            ts, sts = timed(torch, run, args.steps, args.warmup)
+        st = sts[-1]
+        if st.status != 0:
+            raise RuntimeError(f"C1 {key}: {st}")
+        out[key] = {"time_to_1e-10_ms": round(1e3 * float(np.median(ts)), 3), "iters": st.iters,
+                    "iters_per_s": round(st.iters / float(np.median(ts)), 1)}
+    head = out["fp64_graph"]
+    return {"metric": "time-to-1e-10 residual & PSD iters/s, 2D 64^2 fourth order (p=4)",
+            "value": head["iters_per_s"], "unit": "PSD iters/s", "ms_per_step": head["time_to_1e-10_ms"],
+            "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "2D fourth-order PSD, 64^2, [0,12.8]^2, s=0.01, eps=0.1, tol 1e-10, "
+                                   "seeded Fourier field |k|<=8"},
+            "forms": out}
+
+
 def bench_c2(psd, torch, np, psd_inputs, args):
     """2D fourth order, 1024^2, p = 4 and p = 3: time to 1e-10 of the FP64
     form (host-driven loop) and the mixed form (HIP graph; general p captures a
@@ -414,26 +444,193 @@ def bench_c5(psd, torch, np, psd_inputs, args):
             "forward_iters": [st.iters for st in sts[-1]], "cg_iters": cg}
 
 
-def cpu_baseline(f_np, n, L, p, s, eps):
-    """Time one PSD iteration of the plain FP64 CPU oracle on the same
-    256^3 workload: preconditioner application, line-search coefficients and
-    the residual of the updated iterate (the three steps of one iteration)."""
+# ---------------------------------------------------------------------------
+# CPU baseline: the plain FP64 oracle (single-threaded C) timed on bounded
+# samples of each workload, in child processes that import neither torch nor
+# the HIP library.  One child gives the single-thread figure; then one child
+# per host core (at most 16) runs the same sample at the same moment (a
+# start barrier over their pipes), which gives the aggregate rate of the
+# host's cores on independent solves.
+# ---------------------------------------------------------------------------
+ORACLE_MAX_PROCS = 16
+
+
+def _golden_iters(name):
+    with open(os.path.join(ROOT, "tests", "golden", f"fullsize_{name}.json")) as fh:
+        return int(json.load(fh)["iters"])
+
+
+def oracle_sample(workload):
+    """Child side: prepare the sample, report ready, wait for the start line,
+    run it, print one JSON line of timings (seconds)."""
     import numpy as np
     import oracle
+    import psd_inputs
     oracle.build(force=False)
-    O = oracle.Problem(3, n, L, p=p, s=s, eps=eps)
-    u = np.zeros_like(f_np)
-    r = O.residual(f_np, u)          # state at the start of the iteration (not timed)
-    t0 = time.perf_counter()
-    d = O.precond(r)
-    c = O.ls_coeffs4(u, d, r)
-    alpha, _ = oracle.root_cubic(c)
-    u = u + alpha * d
-    r = O.residual(f_np, u)
-    dt = time.perf_counter() - t0
-    return dict(value=1.0 / dt, unit="PSD iters/s", cores=1, kind="oracle",
-                sample=f"one PSD iteration (preconditioner, line-search coefficients, update and "
-                       f"residual) of the single-threaded C oracle at {n}^3, {dt:.1f} s")
+    if workload == "c1":
+        w = psd_inputs.config1()
+        O = oracle.Problem(2, w.n, w.L, p=w.p, s=w.s, eps=w.eps)
+
+        def run():
+            t0 = time.perf_counter()
+            res = O.solve(w.f, tol=1e-10, max_iter=500)
+            return {"t_solve": time.perf_counter() - t0, "iters": int(res["iters"])}
+    elif workload == "c3":
+        w = psd_inputs.config3()
+        O = oracle.Problem(3, w.n, w.L, p=w.p, s=w.s, eps=w.eps)
+        u = np.zeros_like(w.f)
+        r = O.residual(w.f, u)          # state at the start of the iteration (not timed)
+
+        def run():
+            t0 = time.perf_counter()
+            d = O.precond(r)
+            c = O.ls_coeffs4(u, d, r)
+            alpha, _ = oracle.root_cubic(c)
+            O.residual(w.f, u + alpha * d)
+            return {"t_iter": time.perf_counter() - t0}
+    elif workload == "c2":
+        w4, w3 = psd_inputs.config2(4.0), psd_inputs.config2(3.0)
+        O4 = oracle.Problem(2, w4.n, w4.L, p=w4.p, s=w4.s, eps=w4.eps)
+        O3 = oracle.Problem(2, w3.n, w3.L, p=w3.p, s=w3.s, eps=w3.eps)
+
+        def run():
+            t0 = time.perf_counter()
+            r4 = O4.solve(w4.f, tol=1e-10, max_iter=500)
+            t1 = time.perf_counter()
+            r3 = O3.solve(w3.f, tol=0.0, max_iter=2)
+            t2 = time.perf_counter()
+            return {"t_solve_p4": t1 - t0, "iters_p4": int(r4["iters"]), "t_iter_p3": (t2 - t1) / r3["iters"]}
+    elif workload == "c4":
+        ws = psd_inputs.config4()
+        w = next(x for x in ws if x.n == 256)
+        O = oracle.Problem(2, w.n, w.L, order=6, p=w.p, s=w.s, eps=w.eps, lam=w.lam)
+
+        def run():
+            t0 = time.perf_counter()
+            res = O.solve(w.f, g=w.g, tol=1e-10, max_iter=500)
+            return {"t_solve": time.perf_counter() - t0, "iters": int(res["iters"]), "n": w.n}
+    elif workload == "c5":
+        w = psd_inputs.config5()[0]
+        O = oracle.Problem(3, w.n, w.L, p=w.p, s=w.s, eps=w.eps)
+
+        def run():
+            t0 = time.perf_counter()
+            res = O.solve(w.f, tol=0.0, max_iter=2)
+            t1 = time.perf_counter()
+            u = res["u"]
+            O.adjoint(u, u - w.u_target, rtol=0.0, max_iter=2)
+            t2 = time.perf_counter()
+            return {"t_iter": (t1 - t0) / 2, "t_cg": (t2 - t1) / 2}
+    else:
+        raise SystemExit(f"unknown workload {workload}")
+    print("ready", flush=True)
+    sys.stdin.readline()
+    print(json.dumps(run()), flush=True)
+
+
+def _host_cores():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, ORACLE_MAX_PROCS))
+
+
+def run_oracle_samples(workload, procs):
+    """Parent side: start `procs` children, release them together, collect."""
+    import subprocess
+    import oracle
+    oracle.build(force=False)       # built once here, not by every child
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    cmd = [sys.executable, os.path.abspath(__file__), "--oracle-sample", workload]
+    kids = [subprocess.Popen(cmd, stdin=subprocess.PIPE, stdout=subprocess.PIPE, text=True, env=env, cwd=ROOT)
+            for _ in range(procs)]
+    try:
+        for k in kids:
+            line = k.stdout.readline()
+            while line and line.strip() != "ready":
+                line = k.stdout.readline()
+            if not line:
+                raise RuntimeError("an oracle sample child ended before its start")
+        t0 = time.perf_counter()
+        for k in kids:
+            k.stdin.write("go\n")
+            k.stdin.flush()
+        outs = []
+        for k in kids:
+            line = k.stdout.readline()
+            while line and not line.startswith("{"):
+                line = k.stdout.readline()
+            if not line:
+                raise RuntimeError("an oracle sample child ended without its timings")
+            outs.append(json.loads(line))
+        wall = time.perf_counter() - t0
+    finally:
+        for k in kids:
+            k.stdin.close()
+            k.wait()
+    if any(k.returncode != 0 for k in kids):
+        raise RuntimeError("an oracle sample child failed")
+    return outs, wall
+
+
+def cpu_baseline(workload, gpu_counts=None, all_cores=True):
+    """The oracle on a bounded sample of `workload`, in the unit of the
+    workload's metric: single-threaded (`value`), and the host's cores running
+    the same sample side by side (`all_cores`, aggregate rate)."""
+    one, _ = run_oracle_samples(workload, 1)
+    one = one[0]
+    procs = _host_cores() if all_cores else 1
+    many, wall = run_oracle_samples(workload, procs) if procs > 1 else ([one], None)
+    out = {"kind": "oracle", "cores": 1}
+    if workload == "c1":
+        out.update(value=one["iters"] / one["t_solve"], unit="PSD iters/s",
+                   sample=f"complete 64^2 p = 4 solve to 1e-10 ({one['iters']} iterations, {one['t_solve']:.3f} s)",
+                   time_to_1e_10_s=round(one["t_solve"], 4))
+        agg = sum(m["iters"] / m["t_solve"] for m in many)
+    elif workload == "c3":
+        iters = _golden_iters("c3")
+        out.update(value=1.0 / one["t_iter"], unit="PSD iters/s",
+                   sample=f"one PSD iteration (preconditioner, cubic coefficients, root, update, residual) of "
+                          f"the 256^3 solve from u = 0: {one['t_iter']:.1f} s",
+                   time_to_1e_10_s_est=round(iters * one["t_iter"], 1),
+                   time_to_1e_10_note=f"{iters} oracle iterations (tests/golden/fullsize_c3.json) x the sampled "
+                                      "iteration time")
+        agg = sum(1.0 / m["t_iter"] for m in many)
+    elif workload == "c2":
+        it3 = _golden_iters("c2_p3")
+        out.update(value=one["iters_p4"] / one["t_solve_p4"], unit="PSD iters/s",
+                   sample=f"complete p = 4 solve at 1024^2 to 1e-10 ({one['iters_p4']} iterations, "
+                          f"{one['t_solve_p4']:.1f} s) and two p = 3 iterations",
+                   p4_time_to_1e_10_s=round(one["t_solve_p4"], 2),
+                   p3_iters_per_s=round(1.0 / one["t_iter_p3"], 3),
+                   p3_time_to_1e_10_s_est=round(it3 * one["t_iter_p3"], 1))
+        agg = sum(m["iters_p4"] / m["t_solve_p4"] for m in many)
+    elif workload == "c4":
+        cps = one["iters"] * one["n"] ** 2 / one["t_solve"]
+        out.update(value=one["iters"] / one["t_solve"], unit="instance PSD iters/s (256^2 instance)",
+                   sample=f"complete solve of one 256^2 sixth-order instance of the batch to 1e-10 "
+                          f"({one['iters']} iterations, {one['t_solve']:.1f} s)",
+                   cell_iters_per_s=round(cps, 1))
+        agg = sum(m["iters"] / m["t_solve"] for m in many)
+    else:   # c5: time per gradient, scaled from sampled unit costs
+        fi, cg = (gpu_counts or {}).get("forward_iters"), (gpu_counts or {}).get("cg_iters")
+        out.update(value=None, unit="ms",
+                   sample=f"two PSD iterations ({one['t_iter']:.1f} s each) and two adjoint CG iterations "
+                          f"({one['t_cg']:.1f} s each, setup included) of one 128^3 instance",
+                   t_psd_iter_s=round(one["t_iter"], 2), t_cg_iter_s=round(one["t_cg"], 2))
+        if fi and cg:
+            est = sum(a * one["t_iter"] + b * one["t_cg"] for a, b in zip(fi, cg))
+            out["value"] = round(1e3 * est, 1)
+            out["value_note"] = "per-instance iteration and CG counts of the GPU run x the sampled unit costs"
+        agg = None
+    if procs > 1 and agg is not None:
+        out["all_cores"] = {"cores": procs, "value": round(agg, 4 if agg < 100 else 1),
+                            "note": f"{procs} single-threaded oracle processes running the same sample "
+                                    f"side by side (wall {wall:.1f} s); aggregate rate of independent solves"}
+        if workload == "c4":
+            out["all_cores"]["cell_iters_per_s"] = round(agg * one["n"] ** 2, 1)
+    return out
 
 
 def oracle_check(u, w, iters):
@@ -461,11 +658,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-single", action="store_true", help="CPU baseline on one core only")
+    ap.add_argument("--oracle-sample", choices=["c1", "c2", "c3", "c4", "c5"], help=argparse.SUPPRESS)
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--chunk", type=int, default=4, help="PSD iterations per HIP graph replay")
-    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "c5"],
-                    help="c3: the 256^3 line (default); c2: 2D 1024^2; c4: 64-instance sixth-order "
-                         "batch; c5: adjoint of 8 x 128^3")
+    ap.add_argument("--workload", default="c3", choices=["c3", "c1", "c2", "c4", "c5"],
+                    help="c3: the 256^3 line (default); c1: 2D 64^2; c2: 2D 1024^2; c4: 64-instance "
+                         "sixth-order batch; c5: adjoint of 8 x 128^3")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 512 MiB device copy (reference for HBM counters)")
     ap.add_argument("--summarize-trace", nargs=4, metavar=("STATS_CSV", "OUT_MD", "TITLE", "COMMAND"),
@@ -475,6 +674,9 @@ def main():
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
                     help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) into HBM bytes per launch")
     args = ap.parse_args()
+    if args.oracle_sample:
+        oracle_sample(args.oracle_sample)
+        return
     if args.summarize_pmc:
         rec = summarize_pmc(*args.summarize_pmc)
         print(json.dumps(rec))
@@ -500,9 +702,12 @@ def main():
         raise SystemExit("no GPU visible")
     psd.load_library()
     if args.workload != "c3":
-        fn = {"c2": bench_c2, "c4": bench_c4, "c5": bench_c5}[args.workload]
+        fn = {"c1": bench_c1, "c2": bench_c2, "c4": bench_c4, "c5": bench_c5}[args.workload]
         out = fn(psd, torch, np, psd_inputs, args)
         out.update({"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "vs_baseline": None})
+        if not args.no_cpu_baseline:
+            log(f"bench: CPU oracle baseline ({args.workload})")
+            out["cpu_baseline"] = cpu_baseline(args.workload, gpu_counts=out, all_cores=not args.cpu_single)
         print(json.dumps(out), flush=True)
         return
     if args.copy_calibration:
@@ -576,8 +781,8 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("bench: CPU oracle baseline (one iteration at full size)")
-        cpu = cpu_baseline(w.f, w.n, w.L, w.p, w.s, w.eps)
+        log("bench: CPU oracle baseline (one iteration at full size; one core, then all cores)")
+        cpu = cpu_baseline("c3", all_cores=not args.cpu_single)
         if head_mixed and w.n == 256:
             log("bench: oracle check of the mixed answer (FP64 residual, fixture samples)")
             cpu["check"] = oracle_check(res["mixed"]["u"].cpu().numpy(), w, res["mixed"]["iters"][-1])

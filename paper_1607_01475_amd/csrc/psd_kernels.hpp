@@ -22,9 +22,12 @@ struct Task2 {  // residual / line-search / col tiles
 // lengths of the 3D grids (y-axis column passes exist in 3D only)
 #define PSD_FOR_EACH_N3(X) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
 
+#ifndef PSD_ROW_BYTES
+#define PSD_ROW_BYTES 32768
+#endif
 template <typename T, int N>
 constexpr int row_lines() {
-  int nl = 32768 / (fft_ls(N) * (int)sizeof(cx<T>));  // plus N twiddles
+  int nl = PSD_ROW_BYTES / (fft_ls(N) * (int)sizeof(cx<T>));  // plus N twiddles
   int p = 1;
   while (p * 2 <= nl && p < 32) p *= 2;
   return p;

@@ -852,15 +852,20 @@ static psd_status autotune_impl(psd_handle* h) {
     build_all_tasks(h, nsp_aux);
     return upload_tasks(h);
   }
-  // scratch bindings: u[0] -> tmp (zeroed), f -> tmp; d, r zeroed
+  // scratch bindings: u[0] -> tmp, f -> u[1] (a buffer of its own, as in a
+  // solve; every residual block reads f only at the cells whose new iterate
+  // it writes, and both stay zero); d, r zeroed
   std::vector<Inst> saved = h->hI;
   for (int b = 0; b < h->batch; ++b) {
     Inst& I = h->hI[b];
+    const size_t tds = h->mixed ? 4 : 8;
     HIPCHK(hipMemsetAsync(I.tmp, 0, I.ncell * 8, h->stream));
-    HIPCHK(hipMemsetAsync(I.d, 0, I.ncell * (h->mixed ? 4 : 8), h->stream));
+    HIPCHK(hipMemsetAsync(I.d, 0, I.ncell * tds, h->stream));
+    HIPCHK(hipMemsetAsync(I.r, 0, I.ncell * tds, h->stream));
     HIPCHK(hipMemsetAsync(I.u[1], 0, I.ncell * 8, h->stream));
+    if (h->order == 6) HIPCHK(hipMemsetAsync(I.r1, 0, I.ncell * tds, h->stream));
     I.u[0] = I.tmp;
-    I.f = I.tmp;
+    I.f = I.u[1];
     if (h->order == 6) {
       HIPCHK(hipMemsetAsync(I.w[0], 0, I.ncell * 8, h->stream));
       HIPCHK(hipMemsetAsync(I.w[1], 0, I.ncell * 8, h->stream));
@@ -927,8 +932,11 @@ static psd_status autotune_impl(psd_handle* h) {
       psd_status st = upload_tasks(h);
       if (st != PSD_OK) return st;
       for (int k = 0; k < PSD_NPASS; ++k) { h->pass_ms[k] = 0.0; h->pass_n[k] = 0; }
+      // the launch sequence of an iteration (the transforms leave the caches
+      // as they are when the line search starts); stencil passes timed
       for (int rep = 0; rep < 4; ++rep) {
         k_reset_state<<<(h->batch + 63) / 64, 64, 0, h->stream>>>(h->dI, h->batch);
+        run_fft<TD, TR, TD>(h, h->fft_solver, h->order == 4 ? OP_PRECOND4 : OP_PRECOND6, true);
         run_ls<TD>(h, 0);
         k_reset_state<<<(h->batch + 63) / 64, 64, 0, h->stream>>>(h->dI, h->batch);
         run_residual<TD, TR>(h, true);

@@ -516,8 +516,11 @@ struct Res3March {
       acc1 += v * hx;
     } else {
       const double rr = fval - (v - s * div + se2 * l2);
-      r[gi] = (TR)rr;
-      if (UPD) uo[gi] = v;
+      // streaming stores: r and the new iterate are read again only after
+      // other passes, so they are not kept in the caches, which then still
+      // hold u and d for the line search and this pass
+      __builtin_nontemporal_store((TR)rr, &r[gi]);
+      if (UPD) __builtin_nontemporal_store(v, &uo[gi]);
       acc0 = fmax(acc0, fabs(rr));
       acc1 += rr * rr;
     }
@@ -531,8 +534,8 @@ struct Res3March {
     if (j + 2 < z1) fetch<P0>(j + 4);
     // f of output plane j: issued here, used after the second barrier
     if (!HESS && j >= z0 && j < z1) {
-      fv[0] = f[own0 + nn * j];
-      fv[1] = f[own1 + nn * j];
+      fv[0] = __builtin_nontemporal_load(&f[own0 + nn * j]);   // read once per iteration
+      fv[1] = __builtin_nontemporal_load(&f[own1 + nn * j]);
     }
     __syncthreads();
     const double* v0 = vb + S0 * VP;

@@ -1,6 +1,7 @@
 """Host-side logic of bench.py (no GPU): the one-GPU guard, the algorithmic
-byte table, and the conversion of rocprofv3 counter files into HBM bytes per
-launch (checked on synthetic counter files with known values)."""
+byte table, the conversion of rocprofv3 counter files into HBM bytes per
+launch (checked on synthetic counter files with known values), and the CPU
+baseline's child processes (on the 64^2 workload)."""
 import csv
 import json
 import os
@@ -85,3 +86,14 @@ def test_source_hash_ignores_comments_only(tmp_path):
     assert bench.source_hash(str(tmp_path)) == h0
     k.write_text(text.replace("PSD_COL_BYTES 128", "PSD_COL_BYTES 64"))
     assert bench.source_hash(str(tmp_path)) != h0
+
+
+def test_oracle_baseline_children():
+    """Single-thread and two side-by-side oracle children on the 64^2 solve:
+    both report the oracle's own iteration count and positive rates."""
+    out = bench.cpu_baseline("c1", all_cores=False)
+    assert out["kind"] == "oracle" and out["cores"] == 1 and out["value"] > 0
+    assert "all_cores" not in out
+    many, wall = bench.run_oracle_samples("c1", 2)
+    assert len(many) == 2 and wall > 0
+    assert all(m["iters"] == many[0]["iters"] > 0 for m in many)
