@@ -101,13 +101,15 @@ PASS_KERNELS = {
 COPY_BYTES = 512 * 1024 * 1024   # the --copy-calibration device copy
 
 
-def summarize_pmc(fetch_dir: str, write_dir: str, out: str, workload: str = "c3_256") -> dict:
+def summarize_pmc(fetch_dir: str, write_dir: str, out: str, md_out: str | None = None,
+                  workload: str = "c3_256") -> dict:
     """HBM bytes per launch of every pass from two rocprofv3 --pmc runs of
     `bench.py --steps 1 --warmup 0 --no-cpu-baseline --forms mixed
     --copy-calibration` (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).
     Each counter is scaled by what it reads for the 512 MiB calibration copy;
     the median over the last ten launches of a kernel (the ten iterations of
-    the final host-driven solve) is kept.  Writes `out` (JSON)."""
+    the final host-driven solve) is kept.  Writes `out` (JSON) and, given
+    `md_out`, a markdown table with the commands."""
     import csv
     import statistics
 
@@ -127,7 +129,9 @@ def summarize_pmc(fetch_dir: str, write_dir: str, out: str, workload: str = "c3_
     wscale = COPY_BYTES / (1024.0 * max(v for _, v in write[copy]))
     rec = {"_calibration": {"copy_bytes": COPY_BYTES, "fetch_scale": round(fscale, 4),
                             "write_scale": round(wscale, 4)}}
-    src = source_hash()
+    rh = recorded_hash(os.path.join(fetch_dir, "x"))
+    src = rh.split()[0]
+
     def launches(per, prefix):
         out = []
         for name, vals in per.items():
@@ -150,6 +154,31 @@ def summarize_pmc(fetch_dir: str, write_dir: str, out: str, workload: str = "c3_
                                       "source_hash": src}
     with open(out, "w") as fh:
         json.dump(rec, fh, indent=1)
+    if md_out:
+        run = "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --forms mixed --copy-calibration"
+        lines = ["# HBM traffic per launch, 3D p=4 256^3 mixed form", "",
+                 f"Kernel sources: comment-insensitive hash `{rh}` (bench.source_hash).", "",
+                 "Commands (run from the repository root on the MI355X box), one counter per pass, then this "
+                 "summary:", "", "```",
+                 f"PSD_TUNE_CACHE=gpurun_out/tune.txt rocprofv3 --pmc FETCH_SIZE --output-format csv "
+                 f"-d {fetch_dir} -o pmc -- {run}",
+                 f"PSD_TUNE_CACHE=gpurun_out/tune.txt rocprofv3 --pmc WRITE_SIZE --output-format csv "
+                 f"-d {write_dir} -o pmc -- {run}",
+                 f"python bench.py --summarize-pmc {fetch_dir} {write_dir} {out} {md_out}", "```", "",
+                 f"Calibration: the 512 MiB device copy issued by `--copy-calibration` reads FETCH_SIZE scaled by "
+                 f"{fscale:.4f} and WRITE_SIZE scaled by {wscale:.4f} to its bytes; every kernel's counters are "
+                 "scaled by these factors. Values are medians over the ten launches of the final host-driven "
+                 "solve. FETCH_SIZE counts the L2's reads from the fabric (Infinity Cache hits included), so it "
+                 "bounds the HBM reads from above.", "",
+                 "| pass | kernel | fetched (MB) | written (MB) | total / algorithmic |",
+                 "|---|---|---:|---:|---:|"]
+        for key, r in rec.items():
+            if key.startswith("_"):
+                continue
+            lines.append(f"| {key.split(':')[1]} | `{r['kernel']}` | {r['fetch_bytes'] / 1e6:.1f} | "
+                         f"{r['write_bytes'] / 1e6:.1f} | {r['ratio']:.3f} |")
+        with open(md_out, "w") as fh:
+            fh.write("\n".join(lines) + "\n")
     return rec
 
 
@@ -248,19 +277,44 @@ def recorded_hash(path: str) -> str:
     return source_hash() + " (current tree)"
 
 
+EARLY_EXIT_US = 8.0   # launches shorter than this: every block found its instance done
+
+
 def summarize_trace(stats_csv: str, out: str, title: str, command: str, top: int = 25) -> list:
     """Markdown table of a rocprofv3 --kernel-trace --stats kernel_stats.csv
-    (calls, average and total duration, share of GPU time), top kernels first."""
+    (calls, average and total duration, share of GPU time), top kernels first.
+    With the per-launch kernel_trace.csv beside it, also the launches that did
+    work (at least EARLY_EXIT_US) and their average duration: launches of a
+    converged instance inside a replayed graph return at once."""
     import csv
     rows = list(csv.DictReader(open(stats_csv)))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    trace_csv = stats_csv.replace("kernel_stats.csv", "kernel_trace.csv")
+    working = {}
+    if trace_csv != stats_csv and os.path.exists(trace_csv):
+        launches = sorted(csv.DictReader(open(trace_csv)), key=lambda t: int(t["Start_Timestamp"]))
+        for t in launches:
+            us = (int(t["End_Timestamp"]) - int(t["Start_Timestamp"])) / 1e3
+            if us >= EARLY_EXIT_US:
+                working.setdefault(t["Kernel_Name"], []).append(us)
     lines = [f"# {title}", "", f"Kernel sources: comment-insensitive hash `{recorded_hash(stats_csv)}` (bench.source_hash).",
              "", "Commands (kernel trace, then this summary):", "", "```", command,
              f"python bench.py --summarize-trace {stats_csv} {out} '{title}' \"{command}\"", "```", "",
-             "| kernel | calls | avg us | total ms | % |", "|---|---:|---:|---:|---:|"]
+             "Durations from the profiler's kernel trace (not HIP events). `working`: launches of at least "
+             f"{EARLY_EXIT_US:g} us (shorter ones are launches in a replayed graph whose instance had already "
+             "converged); `avg working` is their mean, `avg last 10` the mean of the last ten of them (in a "
+             "bench.py run: the ten iterations of its final host-driven solve, the launches its HIP events "
+             "time).", "",
+             "| kernel | calls | avg us | working | avg working us | avg last 10 us | total ms | % |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|"]
     for r in rows[:top]:
         name = r["Name"].replace("void ", "").split("(")[0]
-        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+        w = working.get(r["Name"])
+        if w:
+            wc, wa, wl = str(len(w)), f"{sum(w) / len(w):.2f}", f"{sum(w[-10:]) / len(w[-10:]):.2f}"
+        else:
+            wc = wa = wl = "—"
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | {wc} | {wa} | {wl} | "
                      f"{float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['Percentage']):.1f} |")
     with open(out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
@@ -574,14 +628,22 @@ def run_oracle_samples(workload, procs):
     return outs, wall
 
 
-def cpu_baseline(workload, gpu_counts=None, all_cores=True):
+def oracle_timings(workload, all_cores=True):
+    """Run the oracle samples of `workload`: one child alone, then (all_cores)
+    one child per host core side by side.  Called before this process touches
+    the GPU, so the children start from a process without a GPU context."""
+    one, _ = run_oracle_samples(workload, 1)
+    procs = _host_cores() if all_cores else 1
+    many, wall = run_oracle_samples(workload, procs) if procs > 1 else (one, None)
+    return {"one": one[0], "many": many, "wall": wall, "procs": procs}
+
+
+def cpu_baseline(workload, gpu_counts=None, all_cores=True, timings=None):
     """The oracle on a bounded sample of `workload`, in the unit of the
     workload's metric: single-threaded (`value`), and the host's cores running
     the same sample side by side (`all_cores`, aggregate rate)."""
-    one, _ = run_oracle_samples(workload, 1)
-    one = one[0]
-    procs = _host_cores() if all_cores else 1
-    many, wall = run_oracle_samples(workload, procs) if procs > 1 else ([one], None)
+    tm = timings or oracle_timings(workload, all_cores)
+    one, many, wall, procs = tm["one"], tm["many"], tm["wall"], tm["procs"]
     out = {"kind": "oracle", "cores": 1}
     if workload == "c1":
         out.update(value=one["iters"] / one["t_solve"], unit="PSD iters/s",
@@ -671,13 +733,16 @@ def main():
                     help="turn a rocprofv3 --stats kernel_stats.csv into a markdown summary")
     ap.add_argument("--summarize-sq", nargs=3, metavar=("DIR_A", "DIR_B", "OUT_MD"),
                     help="turn the two SQ counter passes (SQ_PASSES) into a markdown summary")
-    ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
-                    help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) into HBM bytes per launch")
+    ap.add_argument("--summarize-pmc", nargs="+", metavar="PATH",
+                    help="FETCH_DIR WRITE_DIR OUT_JSON [OUT_MD]: turn two rocprofv3 --pmc runs (FETCH_SIZE, "
+                         "WRITE_SIZE) into HBM bytes per launch")
     args = ap.parse_args()
     if args.oracle_sample:
         oracle_sample(args.oracle_sample)
         return
     if args.summarize_pmc:
+        if len(args.summarize_pmc) not in (3, 4):
+            raise SystemExit("--summarize-pmc takes FETCH_DIR WRITE_DIR OUT_JSON [OUT_MD]")
         rec = summarize_pmc(*args.summarize_pmc)
         print(json.dumps(rec))
         return
@@ -698,16 +763,30 @@ def main():
     import psd_inputs
     from paper_1607_01475_amd import psd
 
+    # the oracle's timing children start before anything here touches the GPU
+    timings = None
+    if not args.no_cpu_baseline:
+        log(f"bench: CPU oracle samples ({args.workload}; one core, then "
+            f"{'all cores' if not args.cpu_single else 'no more'})")
+        timings = oracle_timings(args.workload, all_cores=not args.cpu_single)
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
     psd.load_library()
+    if not os.environ.get("PSD_TUNE_CACHE"):
+        # one tiling per precision for the whole run: the event-timed run uses
+        # the tiling the autotuner picked for the timed graph run
+        import atexit
+        import tempfile
+        fd, tune_path = tempfile.mkstemp(prefix="psd_tune_", suffix=".txt")
+        os.close(fd)
+        os.environ["PSD_TUNE_CACHE"] = tune_path
+        atexit.register(lambda: os.path.exists(tune_path) and os.remove(tune_path))
     if args.workload != "c3":
         fn = {"c1": bench_c1, "c2": bench_c2, "c4": bench_c4, "c5": bench_c5}[args.workload]
         out = fn(psd, torch, np, psd_inputs, args)
         out.update({"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "vs_baseline": None})
-        if not args.no_cpu_baseline:
-            log(f"bench: CPU oracle baseline ({args.workload})")
-            out["cpu_baseline"] = cpu_baseline(args.workload, gpu_counts=out, all_cores=not args.cpu_single)
+        if timings is not None:
+            out["cpu_baseline"] = cpu_baseline(args.workload, gpu_counts=out, timings=timings)
         print(json.dumps(out), flush=True)
         return
     if args.copy_calibration:
@@ -781,8 +860,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("bench: CPU oracle baseline (one iteration at full size; one core, then all cores)")
-        cpu = cpu_baseline("c3", all_cores=not args.cpu_single)
+        cpu = cpu_baseline("c3", timings=timings)
         if head_mixed and w.n == 256:
             log("bench: oracle check of the mixed answer (FP64 residual, fixture samples)")
             cpu["check"] = oracle_check(res["mixed"]["u"].cpu().numpy(), w, res["mixed"]["iters"][-1])

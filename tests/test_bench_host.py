@@ -97,3 +97,25 @@ def test_oracle_baseline_children():
     many, wall = bench.run_oracle_samples("c1", 2)
     assert len(many) == 2 and wall > 0
     assert all(m["iters"] == many[0]["iters"] > 0 for m in many)
+
+
+def test_trace_summary_separates_early_exits(tmp_path):
+    """Kernel-trace summary on synthetic profiler files: launches under the
+    early-exit threshold are left out of the working average."""
+    stats = tmp_path / "kt_kernel_stats.csv"
+    trace = tmp_path / "kt_kernel_trace.csv"
+
+    def write(path, header, rows):
+        with open(path, "w", newline="") as fh:
+            w = csv.writer(fh)
+            w.writerow(header)
+            w.writerows(rows)
+    write(stats, ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage"],
+          [["void k_res(int)", "3", "244000", "81333", "100.0"]])
+    write(trace, ["Kernel_Name", "Start_Timestamp", "End_Timestamp"],
+          [["void k_res(int)", "0", "120000"], ["void k_res(int)", "200000", "320000"],
+           ["void k_res(int)", "400000", "404000"]])
+    out = tmp_path / "summary.md"
+    bench.summarize_trace(str(stats), str(out), "t", "cmd")
+    text = out.read_text()
+    assert "| `k_res` | 3 | 81.33 | 2 | 120.00 | 120.00 |" in text

@@ -146,20 +146,22 @@ def test_solve_parity_fp64(psd, dim, n, p, L, s, eps):
     assert np.abs(O.residual(f, ug)).max() <= 1.5e-10
 
 
-def test_p6_wide_tiles_matched_count(psd):
-    """p = 6 in 3D at n = 64 (64-wide line-search tiles): six FP64 updates and
-    their step sizes against six oracle updates (the oracle's general-p root
-    rule at 64^3 takes minutes to convergence, so the count is fixed)."""
-    n, L, s, eps, k = 64, 12.8, 0.01, 0.1, 6
+@pytest.mark.parametrize("p,k", [(6.0, 6), (3.0, 4)])
+def test_wide_tiles_general_p_matched_count(psd, p, k):
+    """p = 6 (quintic) and p = 3 (root search by (q, q') passes) in 3D at
+    n = 64 (64-wide line-search tiles): k FP64 updates and their step sizes
+    against k oracle updates (the oracle's general-p root rule at 64^3 takes
+    minutes to convergence, so the count is fixed)."""
+    n, L, s, eps = 64, 12.8, 0.01, 0.1
     f = psd_inputs.small_field(3, n, L, 31, K=6)
-    O = oracle.Problem(3, n, L, p=6.0, s=s, eps=eps)
+    O = oracle.Problem(3, n, L, p=p, s=s, eps=eps)
     ref = O.solve(f, tol=0.0, max_iter=k, history=True)
-    P = psd.Problem(3, n, L, 4, 6.0, s, eps)
+    P = psd.Problem(3, n, L, 4, p, s, eps)
     with psd.Solver(P, tol=0.0, max_iter=k, history=True) as S:
         u = torch.zeros_like(dev(f))
         st = S.solve([dev(f)], [u])[0]
         hist = S.history(0)
-    log(f"case p6 3D n={n}: {st.iters} updates, rel {rel(host(u), ref['u']):.2e}")
+    log(f"case p={p:g} 3D n={n}: {st.iters} updates, rel {rel(host(u), ref['u']):.2e}")
     assert st.iters == k
     assert rel(host(u), ref["u"]) <= 1e-11
     check_alphas(hist[:, 0], ref["hist"][:, 0], ref["hist"][:, 1], np.abs(f).max(),
@@ -280,10 +282,12 @@ def test_mixed_precision_reaches_fp64_answer(psd, dim, n, p):
 # p = 3 and 2.5: general p, the root search runs a fixed number of evaluation
 # passes per captured iteration; while none is cut short the graph replays
 # give the host-driven loop's iterates bit for bit
-@pytest.mark.parametrize("precision,p,dim", [("fp64", 4.0, 3), ("mixed", 4.0, 3), ("mixed", 6.0, 3),
-                                            ("fp64", 3.0, 3), ("mixed", 2.5, 2)])
-def test_graph_mode_matches_stream_mode(psd, precision, p, dim):
-    n, L = 48, 12.8
+@pytest.mark.parametrize("precision,p,dim,n", [("fp64", 4.0, 3, 48), ("mixed", 4.0, 3, 48), ("mixed", 6.0, 3, 48),
+                                              ("fp64", 3.0, 3, 48), ("mixed", 2.5, 2, 48),
+                                              # 64-wide line-search tiles
+                                              ("mixed", 4.0, 3, 64), ("mixed", 3.0, 3, 64)])
+def test_graph_mode_matches_stream_mode(psd, precision, p, dim, n):
+    L = 12.8
     f = psd_inputs.small_field(dim, n, L, 61, K=6)
     P = psd.Problem(dim, n, L, 4, p, 0.01, 0.1)
     out = []
