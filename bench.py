@@ -190,7 +190,7 @@ SQ_PASSES = {
     "B": ["SQ_WAVES", "SQ_WAIT_ANY", "SQ_ACTIVE_INST_ANY", "SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM",
           "SQ_WAIT_INST_LDS", "SQ_LDS_IDX_ACTIVE", "GRBM_GUI_ACTIVE"],
 }
-SQ_KERNELS = "k_res3d|k_ls3d"
+SQ_KERNELS = "k_res3d|k_ls3d|k_rows"
 
 
 def sq_command(tag: str) -> str:
@@ -201,7 +201,7 @@ def sq_command(tag: str) -> str:
 
 def summarize_sq(dir_a: str, dir_b: str, out: str) -> dict:
     """Markdown summary of the two SQ counter passes (SQ_PASSES) of the
-    residual and line-search kernels: per kernel, the median over its last
+    residual, line-search and row-transform kernels: per kernel, the median over its last
     ten launches (the final host-driven solve) of every counter, and the
     per-wave fractions of time spent issuing VALU / LDS / VMEM instructions
     and waiting (counter / SQ_WAVE_CYCLES), LDS bank-conflict cycles per LDS
@@ -226,7 +226,7 @@ def summarize_sq(dir_a: str, dir_b: str, out: str) -> dict:
         return statistics.median(x for _, x in v) if v else float("nan")
 
     A, B = load(dir_a), load(dir_b)
-    lines = ["# SQ counters of the 3D stencil kernels (256^3, p = 4, mixed form)", "",
+    lines = ["# SQ counters of the 3D stencil and row-transform kernels (256^3, p = 4, mixed form)", "",
              f"Kernel sources: comment-insensitive hash `{recorded_hash(dir_a + '/x')}` (bench.source_hash).", "",
              "Commands (counter passes, then this summary):", "", "```"]
     lines += [sq_command("A"), sq_command("B"),
