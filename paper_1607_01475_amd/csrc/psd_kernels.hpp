@@ -145,8 +145,8 @@ __global__ __launch_bounds__(PSD_NT) void k_ls2d(const Inst* __restrict__ insts,
   const Inst& I = insts[t.inst];
   if (I.st->done || (MODE == 2 && I.st->ls_phase == 2)) return;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  ls2d_tile<TD, MODE>(I, t.a, t.b, smem, acc);
-  block_reduce<8, 0>(acc, smem + L2_LDS);
+  ls2d_wave_tile<TD, MODE>(I, t.a, t.b, acc);
+  block_reduce<8, 0>(acc, smem);
   if (threadIdx.x == 0)
     for (int k = 0; k < 8; ++k) I.part_ls[8 * t.slot + k] = acc[k];
 }
@@ -224,8 +224,12 @@ __global__ __launch_bounds__(PSD_FIN_NT) void k_ls_finalize(const Inst* __restri
   __shared__ double scratch[10 * PSD_FIN_NT / PSD_WAVE];
   const Inst& I = insts[blockIdx.x];
   SolveState* st = I.st;
-  // state, line-search and spectral partials are loaded together
-  const bool skip = st->done || (mode == 2 && st->ls_phase == 2);
+  // modes 0, 1, 3: state, line-search and spectral partials are loaded
+  // together (one memory round trip; the pass almost always has work).
+  // Mode 2: the passes captured after the root search has finished are the
+  // common case, so the state is read first and the partials only if needed.
+  if (mode == 2 && (st->done || st->ls_phase == 2)) return;
+  const bool skip = st->done;
   double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   {
     double a8[8] = {0, 0, 0, 0, 0, 0, 0, 0};

@@ -377,8 +377,10 @@ static void build_tile_tasks(psd_handle* h) {
       Inst& I = h->hI[b];
       int slot = 0;
       if (h->dim == 2) {
-        for (int y0 = 0; y0 < I.n; y0 += T2Y)
-          for (int x0 = 0; x0 < I.n; x0 += T2X) {
+        // residual: 64 x 8 LDS tiles; line search: 64 x 32 tiles walked by rows
+        const int tyh = pass == 0 ? T2Y : L2W_Y, txw = pass == 0 ? T2X : L2W_X;
+        for (int y0 = 0; y0 < I.n; y0 += tyh)
+          for (int x0 = 0; x0 < I.n; x0 += txw) {
             Task2 t{}; t.inst = b; t.a = x0; t.b = y0; t.c = 0; t.slot = slot++;
             h->hT.push_back(t);
           }
@@ -408,7 +410,7 @@ static void build_tile_tasks(psd_handle* h) {
     R.cnt = (int)h->hT.size() - R.off;
     if (xcd) xcd_permute(h->hT, R.off, R.cnt);
     if (h->dim == 2)
-      R.lds = pass == 0 ? (R2_LDS + 16) * sizeof(double) : (L2_LDS + 32) * sizeof(double);
+      R.lds = pass == 0 ? (R2_LDS + 16) * sizeof(double) : 32 * sizeof(double);
     else if (pass == 0 && h->order == 6)
       R.lds = (B6_LDS + 16) * sizeof(double);
     else

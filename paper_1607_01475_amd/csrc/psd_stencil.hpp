@@ -820,54 +820,84 @@ __device__ __forceinline__ void ls_vertex(double p, double alpha, double ax, dou
   }
 }
 
-constexpr int L2_W = T2X + 2, L2_H = T2Y + 2;
-constexpr int L2_LDS = 2 * L2_W * L2_H;
+// 2D line-search sums by rows: each wave owns 64 columns x L2W_R rows of a
+// 64 x (4 L2W_R) block tile and walks its rows in order, so the rows y - 1,
+// y, y + 1 a cell needs are in registers (one load per row and field), the
+// x-neighbours come from the neighbouring lanes (cross-lane shuffles) and the
+// halo columns x0 - 1, x0 + 64 from one extra load per row that every lane
+// issues (two addresses per wave).  No LDS and no barrier until the block's
+// reduction.  Each cell (x, y) contributes its vertex (x+1/2, y+1/2) (the
+// averaged gradients of u and d over the 2 x 2 cells around it, Sec. 5.1)
+// and its d and 5-point Laplacian of d.
+constexpr int L2W_R = 8;                  // rows per wave
+constexpr int L2W_X = PSD_WAVE, L2W_Y = (PSD_NT / PSD_WAVE) * L2W_R;   // block tile
+
+template <typename TD>
+struct L2wRow {
+  double u, ue;       // u at the own column and at the halo column
+  TD d, de;           // d likewise
+};
 
 template <typename TD, int MODE>
-__device__ void ls2d_tile(const Inst& I, int x0, int y0, double* lds, double (&acc)[8]) {
+__device__ void ls2d_wave_tile(const Inst& I, int x0, int y0, double (&acc)[8]) {
   const int n = I.n;
-  const bool small = n < T2X + 2;   // else every tile index lies in [-n, 2n)
   const SolveState* st = I.st;
   const PSD_GLOBAL double* u = gmem((const double*)I.u[st->iter & 1]);
   const PSD_GLOBAL TD* d = gmem((const TD*)I.d);
   const double alpha = (MODE == 2) ? st->x : 0.0;
-  double* ul = lds;
-  double* dl = lds + L2_W * L2_H;
-  {
-    constexpr int NV = L2_W * L2_H, IT = (NV + PSD_NT - 1) / PSD_NT;
-    double uv[IT];
-    TD dv[IT];
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int e = threadIdx.x + it * PSD_NT;
-      if (e < NV) {
-        const int ey = e / L2_W, ex = e - ey * L2_W;
-        const long long gi = wrap2(x0 - 1 + ex, n, small) + (long long)n * wrap2(y0 - 1 + ey, n, small);
-        uv[it] = u[gi];
-        dv[it] = d[gi];
-      }
-    }
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int e = threadIdx.x + it * PSD_NT;
-      if (e < NV) { ul[e] = uv[it]; dl[e] = (double)dv[it]; }
-    }
-  }
-  __syncthreads();
+  const int lane = threadIdx.x & (PSD_WAVE - 1), w = threadIdx.x / PSD_WAVE;
+  const int ya = y0 + w * L2W_R, yb = min(ya + L2W_R, n);
+  if (ya >= n) return;
+  const bool okx = x0 + lane < n;
+  const long long xs = posmod(x0 + lane, n);
+  // halo column: x0 - 1 (lanes 0..31; lane 0 uses it), x0 + 64 (lanes 32..63; lane 63)
+  const long long xe = posmod(lane < PSD_WAVE / 2 ? x0 - 1 : x0 + PSD_WAVE, n);
   const double hh = 0.5 * I.inv_h, ih2 = I.inv_h * I.inv_h;
-  for (int e = threadIdx.x; e < T2X * T2Y; e += PSD_NT) {
-    const int ty = e / T2X, tx = e - ty * T2X;
-    if (x0 + tx >= n || y0 + ty >= n) continue;
-    const int c = (ty + 1) * L2_W + tx + 1;
-    const double a00 = ul[c], a10 = ul[c + 1], a01 = ul[c + L2_W], a11 = ul[c + L2_W + 1];
-    const double b00 = dl[c], b10 = dl[c + 1], b01 = dl[c + L2_W], b11 = dl[c + L2_W + 1];
-    const double ax = hh * ((a10 - a00) + (a11 - a01)), ay = hh * ((a01 - a00) + (a11 - a10));
-    const double bx = hh * ((b10 - b00) + (b11 - b01)), by = hh * ((b01 - b00) + (b11 - b10));
-    ls_vertex<MODE>(I.p, alpha, ax, ay, 0.0, bx, by, 0.0, acc);
-    const double ld = (dl[c - 1] + dl[c + 1] + dl[c - L2_W] + dl[c + L2_W] - 4.0 * b00) * ih2;
-    if (MODE == 0) { acc[4] += b00 * b00; acc[5] += ld * ld; }
-    else if (MODE == 3) { acc[5] += b00 * b00; acc[6] += ld * ld; }
-    else { acc[2] += b00 * b00; acc[3] += ld * ld; }
+  auto load = [&](int y, L2wRow<TD>& r) {
+    const long long ro = (long long)n * wrapi(y, n);   // y in [-1, n + 1]
+    r.u = u[ro + xs];
+    r.ue = u[ro + xe];
+    r.d = d[ro + xs];
+    r.de = d[ro + xe];
+  };
+  auto right = [&](double v, double edge) {
+    const double t = __shfl_down(v, 1, PSD_WAVE);
+    return lane == PSD_WAVE - 1 ? edge : t;
+  };
+  auto left = [&](double v, double edge) {
+    const double t = __shfl_up(v, 1, PSD_WAVE);
+    return lane == 0 ? edge : t;
+  };
+  // row values: own, x + 1 (u and d), x - 1 (d)
+  double cu, cux, cd, cdx, cdl;       // row y
+  double dm = (double)d[(long long)n * wrapi(ya - 1, n) + xs];   // d at row y - 1
+  L2wRow<TD> ra, rb;
+  load(ya, ra);
+  load(ya + 1, rb);
+  cu = ra.u; cd = (double)ra.d;
+  cux = right(cu, ra.ue);
+  cdx = right(cd, (double)ra.de);
+  cdl = left(cd, (double)ra.de);
+  for (int y = ya; y < yb; ++y) {
+    const L2wRow<TD> r1 = rb;
+    if (y + 1 < yb) load(y + 2, rb);   // next row in flight while this one is summed
+    const double nu = r1.u, nd = (double)r1.d;
+    const double nux = right(nu, r1.ue);
+    const double ndx = right(nd, (double)r1.de);
+    const double ndl = left(nd, (double)r1.de);
+    if (okx) {
+      const double a00 = cu, a10 = cux, a01 = nu, a11 = nux;
+      const double b00 = cd, b10 = cdx, b01 = nd, b11 = ndx;
+      const double ax = hh * ((a10 - a00) + (a11 - a01)), ay = hh * ((a01 - a00) + (a11 - a10));
+      const double bx = hh * ((b10 - b00) + (b11 - b01)), by = hh * ((b01 - b00) + (b11 - b10));
+      ls_vertex<MODE>(I.p, alpha, ax, ay, 0.0, bx, by, 0.0, acc);
+      const double ld = (cdl + cdx + dm + nd - 4.0 * b00) * ih2;
+      if (MODE == 0) { acc[4] += b00 * b00; acc[5] += ld * ld; }
+      else if (MODE == 3) { acc[5] += b00 * b00; acc[6] += ld * ld; }
+      else { acc[2] += b00 * b00; acc[3] += ld * ld; }
+    }
+    dm = cd;
+    cu = nu; cux = nux; cd = nd; cdx = ndx; cdl = ndl;
   }
 }
 
