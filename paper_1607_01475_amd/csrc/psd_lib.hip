@@ -670,6 +670,11 @@ static void run_iteration_general_fixed(psd_handle* h) {
   run_residual<TD, TR>(h, true);
 }
 
+// search direction of the variable metric (defined with the adjoint's
+// conjugate-gradient machinery below)
+template <typename T, typename TD, typename TR>
+static psd_status vm_direction(psd_handle* h);
+
 template <typename T, typename TD, typename TR>
 static psd_status solve_loop(psd_handle* h) {
   const int chunk = h->opt.graph_chunk;
