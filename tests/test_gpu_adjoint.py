@@ -102,3 +102,38 @@ def test_adjoint_full_size_defining_equation(psd):
     Hl = O.hessvec(host(us[0]), host(lam[0]))
     g = host(gs[0])
     assert np.linalg.norm(Hl - g) <= 1e-10 * np.linalg.norm(g)
+
+
+def test_adjoint_full_size_finite_differences(psd):
+    """Config C5 shape (one 128^3 instance): dJ/df along a random direction,
+    dJ/ds and dJ/deps from psd_adjoint against central differences of J
+    through FP64 forward solves to 1e-13 (relative steps 1e-4)."""
+    w = psd_inputs.config5(batch=1)[0]
+    h3 = (w.L / w.n) ** 3
+    f = dev(w.f)
+    ut = dev(w.u_target)
+
+    def J_of(ff, ss, ee):
+        with psd.Solver(psd.Problem(3, w.n, w.L, 4, w.p, ss, ee), tol=1e-13, max_iter=500) as S:
+            u = torch.zeros_like(ff)
+            st = S.solve([ff], [u])[0]
+            assert st.status == 0
+        return 0.5 * h3 * float(((u - ut) ** 2).sum())
+
+    P = psd.Problem(3, w.n, w.L, 4, w.p, w.s, w.eps)
+    with psd.Solver(P, tol=1e-13, max_iter=500) as S:
+        u = torch.zeros_like(f)
+        st = S.solve([f], [u])[0]
+        assert st.status == 0
+        lam, ds, de, it = S.adjoint([u], [h3 * (u - ut)], rtol=1e-13, max_iter=500)
+    tau = 1e-4
+    dirn = dev(psd_inputs.white_noise(w.f.shape, 94))
+    fd_f = (J_of(f + tau * dirn, w.s, w.eps) - J_of(f - tau * dirn, w.s, w.eps)) / (2 * tau)
+    an_f = float((lam[0] * dirn).sum())
+    fd_s = (J_of(f, w.s * (1 + tau), w.eps) - J_of(f, w.s * (1 - tau), w.eps)) / (2 * tau * w.s)
+    fd_e = (J_of(f, w.s, w.eps * (1 + tau)) - J_of(f, w.s, w.eps * (1 - tau))) / (2 * tau * w.eps)
+    print(f"C5 shape: cg {it[0]}; f {fd_f:.10e} {an_f:.10e}; s {fd_s:.10e} {ds[0]:.10e}; "
+          f"eps {fd_e:.10e} {de[0]:.10e}", flush=True)
+    assert abs(an_f - fd_f) <= 1e-6 * abs(fd_f)
+    assert abs(ds[0] - fd_s) <= 1e-6 * abs(fd_s)
+    assert abs(de[0] - fd_e) <= 1e-6 * abs(fd_e)
