@@ -376,7 +376,7 @@ def bench_c1(psd, torch, np, psd_inputs, args):
     out = {}
     for key, prec, chunk in (("fp64", "fp64", 0), ("fp64_graph", "fp64", args.chunk),
                              ("mixed_graph", "mixed", args.chunk)):
-        with psd.Solver(P, tol=1e-10, max_iter=500, precision=prec, graph_chunk=chunk) as S:
+        with psd.Solver(P, tol=1e-10, max_iter=500, precision=prec, graph_chunk=chunk, autotune=True) as S:
             u = torch.zeros_like(f)
 
             def run():
@@ -408,8 +408,10 @@ def bench_c2(psd, torch, np, psd_inputs, args):
         P = psd.Problem(2, w.n, w.L, 4, w.p, w.s, w.eps)
         for prec in ("fp64", "mixed"):
             chunk = args.chunk if prec == "mixed" else 0
-            with psd.Solver(P, tol=1e-10, max_iter=500, precision=prec, graph_chunk=chunk) as S:
+            with psd.Solver(P, tol=1e-10, max_iter=500, precision=prec, graph_chunk=chunk,
+                            autotune=True) as S:
                 u = torch.zeros_like(f)
+                tiling = S.tuning()
 
                 def run():
                     u.zero_()
@@ -420,7 +422,7 @@ def bench_c2(psd, torch, np, psd_inputs, args):
                 raise RuntimeError(f"C2 p={p} {prec}: {st}")
             key = f"p{p:g}_{prec}"
             out[key] = {"time_to_1e-10_ms": round(1e3 * float(np.median(ts)), 3), "iters": st.iters,
-                        "iters_per_s": round(st.iters / float(np.median(ts)), 1)}
+                        "iters_per_s": round(st.iters / float(np.median(ts)), 1), "row_layout": tiling[5]}
     head = out["p4_mixed"]
     return {"metric": "time-to-1e-10 residual & PSD iters/s, 2D 1024^2 fourth order (p=4, p=3)",
             "value": head["iters_per_s"], "unit": "PSD iters/s", "ms_per_step": head["time_to_1e-10_ms"],
@@ -856,7 +858,8 @@ def main():
         extra[f"{k}_time_to_1e-10_ms"] = round(1e3 * float(np.median(r["times"])), 3)
         extra[f"{k}_iters"] = int(np.median(r["iters"]))
         extra[f"{k}_iters_per_s"] = round(float(np.sum(r["iters"]) / np.sum(r["times"])), 2)
-        extra[f"{k}_tiling"] = dict(zip(("zchunk_res", "zchunk_ls", "xcd_res", "xcd_ls", "ls_tile_x"), r["tuning"]))
+        extra[f"{k}_tiling"] = dict(zip(("zchunk_res", "zchunk_ls", "xcd_res", "xcd_ls", "ls_tile_x", "row_layout"),
+                                        r["tuning"]))
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -96,8 +96,9 @@ typedef struct {
                       (residual z-chunk 16/28/40/64, line-search z-chunk
                       12/24/36/60, plus per kernel the chunk at which all its
                       blocks are resident at once; line-search tile 64x8 or
-                      32x16; natural or XCD-grouped block order) on this
-                      handle's buffers and keep the fastest; results are
+                      32x16; natural or XCD-grouped block order) and the
+                      row-transform layout (lines per block, 2D and 3D) on
+                      this handle's buffers and keep the fastest; results are
                       cached in the file named by PSD_TUNE_CACHE when set */
     int metric;       /* PSD_METRIC_CONSTANT: d = L_h^{-1} r by FFT (Sec. 5.3 and 6).
                          PSD_METRIC_VARIABLE (order 4, graph_chunk 0): the metric
@@ -282,12 +283,14 @@ enum {
  * graph mode).  Arrays of PSD_NPASS entries, host memory. */
 psd_status psd_pass_times(psd_handle* h, double* ms, int* launches);
 
-/* Tiling chosen for the stencil kernels (after autotuning or defaults):
- * out[0..4] = z-chunk of the residual, z-chunk of the line search,
- * XCD-grouped order of the residual (0/1), of the line search (0/1),
- * 3D line-search tile width (32 or 64 cells).  out5 is host memory of five
- * ints.  The z-chunks and tile width matter in 3D only. */
-psd_status psd_tuning(const psd_handle* h, int* out5);
+/* Tiling chosen for the stencil kernels and layout of the row transforms
+ * (after autotuning or defaults): out[0..5] = z-chunk of the residual,
+ * z-chunk of the line search, XCD-grouped order of the residual (0/1), of the
+ * line search (0/1), 3D line-search tile width (32 or 64 cells), row-pass
+ * layout (0, 1, 2: the lines per block of the x-axis transforms fill about
+ * 16, 32 or 64 KB of LDS; default 1).  out6 is host memory of six ints.  The
+ * z-chunks and tile width matter in 3D only. */
+psd_status psd_tuning(const psd_handle* h, int* out6);
 
 /* Destroy the handle and free its workspace. */
 psd_status psd_destroy(psd_handle* h);

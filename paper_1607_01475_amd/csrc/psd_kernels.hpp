@@ -22,12 +22,16 @@ struct Task2 {  // residual / line-search / col tiles
 // lengths of the 3D grids (y-axis column passes exist in 3D only)
 #define PSD_FOR_EACH_N3(X) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
 
+// Lines per block of the row passes (LDS layout of the row transform): the
+// largest power of two whose lines fit in about PSD_ROW_BYTES of LDS scaled
+// by 2^(SEL-1); the autotuner picks SEL in 0..PSD_ROW_SELS-1 per handle.
 #ifndef PSD_ROW_BYTES
 #define PSD_ROW_BYTES 32768
 #endif
-template <typename T, int N>
+constexpr int PSD_ROW_SELS = 3;
+template <typename T, int N, int SEL = 1>
 constexpr int row_lines() {
-  int nl = PSD_ROW_BYTES / (fft_ls(N) * (int)sizeof(cx<T>));  // plus N twiddles
+  int nl = ((PSD_ROW_BYTES << SEL) / 2) / (fft_ls(N) * (int)sizeof(cx<T>));  // plus N twiddles
   int p = 1;
   while (p * 2 <= nl && p < 32) p *= 2;
   return p;
@@ -364,14 +368,14 @@ __device__ __forceinline__ RowArgs<T> row_args(const Inst& I, int fs, cx<T>* spe
 // row pass kernels: task.a = first global row (over fields), task.b = field
 // set, task.c = number of fields.  One kernel per row length N: every block
 // of a launch works on instances with n = N.
-template <typename T, typename TIO, bool FWD, int N>
+template <typename T, typename TIO, bool FWD, int N, int SEL>
 __device__ __forceinline__ void rows_body(const Inst& I, const Task2& t, double* smem, int solver) {
   cx<T>* buf = (cx<T>*)smem;
   const cx<T>* tw = (const cx<T>*)(sizeof(T) == 8 ? I.tw64 : I.tw32);
   RowArgs<T> A = row_args<T>(I, t.b, (cx<T>*)I.spec, t.c);
   double fsum[3] = {0.0, 0.0, 0.0};
-  if (FWD) r2c_rows<T, TIO, N, row_lines<T, N>()>(A, t.a, buf, tw);
-  else c2r_rows<T, TIO, N, row_lines<T, N>()>(A, t.a, buf, tw, fsum);
+  if (FWD) r2c_rows<T, TIO, N, row_lines<T, N, SEL>()>(A, t.a, buf, tw);
+  else c2r_rows<T, TIO, N, row_lines<T, N, SEL>()>(A, t.a, buf, tw, fsum);
   if (!FWD && solver && I.order == 6) {   // field sums of the solver's inverse transform
     __syncthreads();
     block_reduce<3, 0>(fsum, smem);
@@ -380,18 +384,18 @@ __device__ __forceinline__ void rows_body(const Inst& I, const Task2& t, double*
   }
 }
 
-template <typename T, typename TIO, bool FWD, int N>
+template <typename T, typename TIO, bool FWD, int N, int SEL>
 __global__ __launch_bounds__(PSD_NT) void k_rows(const Inst* __restrict__ insts,
                                                  const Task2* __restrict__ tasks, int solver) {
   extern __shared__ double smem[];
   const Task2 t = tasks[blockIdx.x];
   const Inst& I = insts[t.inst];
   if (solver && I.st->done) return;
-  rows_body<T, TIO, FWD, N>(I, t, smem, solver);
+  rows_body<T, TIO, FWD, N, SEL>(I, t, smem, solver);
 }
 
 // Batches of several grid sizes: one launch, the length chosen per block.
-template <typename T, typename TIO, bool FWD>
+template <typename T, typename TIO, bool FWD, int SEL>
 __global__ __launch_bounds__(PSD_NT) void k_rows_any(const Inst* __restrict__ insts,
                                                      const Task2* __restrict__ tasks, int solver) {
   extern __shared__ double smem[];
@@ -399,7 +403,7 @@ __global__ __launch_bounds__(PSD_NT) void k_rows_any(const Inst* __restrict__ in
   const Inst& I = insts[t.inst];
   if (solver && I.st->done) return;
   switch (I.n) {
-#define PSD_C(NN) case NN: rows_body<T, TIO, FWD, NN>(I, t, smem, solver); break;
+#define PSD_C(NN) case NN: rows_body<T, TIO, FWD, NN, SEL>(I, t, smem, solver); break;
     PSD_FOR_EACH_N(PSD_C)
 #undef PSD_C
     default: break;

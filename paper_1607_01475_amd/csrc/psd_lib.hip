@@ -61,9 +61,10 @@ bool n_supported(int n) {
 }
 
 template <typename T>
-int host_row_lines(int n) {
+int host_row_lines(int n, int sel) {
   switch (n) {
-#define C(NN) case NN: return row_lines<T, NN>();
+#define C(NN) \
+  case NN: return sel == 0 ? row_lines<T, NN, 0>() : (sel == 2 ? row_lines<T, NN, 2>() : row_lines<T, NN, 1>());
     PSD_FOR_EACH_N(C)
 #undef C
   }
@@ -115,6 +116,7 @@ struct psd_handle_s {
   // tuning (autotuner or defaults)
   int tune_zc_res = T3Z_RES, tune_zc_ls = T3Z_LS;
   int ls_tx = L3_TX_NARROW;   // 3D line-search tile width (wide when every n >= 64)
+  int row_sel = 1;            // row-pass layout (lines per block), 0..PSD_ROW_SELS-1
   bool tune_xcd_res = false, tune_xcd_ls = false;
   size_t dT_cap = 0;
   std::string err;
@@ -276,7 +278,7 @@ static void build_fft_tasks(psd_handle* h, FftTasks& F, int nfi, int nfo, bool w
     R.off = (int)h->hT.size();
     for (int n : ns) {
       open_part(R, n);
-      const int nl = host_row_lines<T>(n);
+      const int nl = host_row_lines<T>(n, h->row_sel);
       for (int b = 0; b < h->batch; ++b) {
         const Inst& I = h->hI[b];
         if (I.n != n) continue;
@@ -442,21 +444,29 @@ static void build_all_tasks(psd_handle* h, std::vector<int>& nsp_aux) {
 // ---------------------------------------------------------------------------
 // One launch per pass: the kernel specialised to the transform length when
 // the batch has one grid size, else the kernel that switches per block.
-template <typename T, typename TIO, bool FWD>
-static void launch_rows(const Range& R, const Inst* dI, const Task2* dT, int sv, hipStream_t s) {
+template <typename T, typename TIO, bool FWD, int SEL>
+static void launch_rows_sel(const Range& R, const Inst* dI, const Task2* dT, int sv, hipStream_t s) {
   if (R.parts.size() > 1) {
-    k_rows_any<T, TIO, FWD><<<R.cnt, PSD_NT, R.lds, s>>>(dI, dT + R.off, sv);
+    k_rows_any<T, TIO, FWD, SEL><<<R.cnt, PSD_NT, R.lds, s>>>(dI, dT + R.off, sv);
     return;
   }
   for (const NPart& p : R.parts) {
     switch (p.n) {
 #define PSD_L(NN) \
-      case NN: k_rows<T, TIO, FWD, NN><<<p.cnt, PSD_NT, p.lds, s>>>(dI, dT + p.off, sv); break;
+      case NN: k_rows<T, TIO, FWD, NN, SEL><<<p.cnt, PSD_NT, p.lds, s>>>(dI, dT + p.off, sv); break;
       PSD_FOR_EACH_N(PSD_L)
 #undef PSD_L
       default: break;
     }
   }
+}
+
+// row-pass layout `sel` (lines per block, see row_lines) as built into the tasks
+template <typename T, typename TIO, bool FWD>
+static void launch_rows(const Range& R, const Inst* dI, const Task2* dT, int sv, hipStream_t s, int sel) {
+  if (sel == 0) launch_rows_sel<T, TIO, FWD, 0>(R, dI, dT, sv, s);
+  else if (sel == 2) launch_rows_sel<T, TIO, FWD, 2>(R, dI, dT, sv, s);
+  else launch_rows_sel<T, TIO, FWD, 1>(R, dI, dT, sv, s);
 }
 
 template <typename T, int NF, int DIR>
@@ -502,7 +512,7 @@ static void run_fft(psd_handle* h, const FftTasks& F, int op, bool solver) {
   const bool pr = solver;  // auxiliary transforms are not profiled
   if (F.r2c.cnt) {
     ProfScope ps(h, pr ? PSD_PASS_ROWS_R2C : -1);
-    launch_rows<T, TIN, true>(F.r2c, dI, dT, sv, s);
+    launch_rows<T, TIN, true>(F.r2c, dI, dT, sv, s, h->row_sel);
   }
   const int nfi = op == OP_PRECOND6 ? 2 : 1, nfo = op == OP_PRECOND6 ? 3 : 1;
   if (F.coly_f.cnt) {
@@ -524,7 +534,7 @@ static void run_fft(psd_handle* h, const FftTasks& F, int op, bool solver) {
   }
   if (F.c2r.cnt) {
     ProfScope ps(h, pr ? PSD_PASS_ROWS_C2R : -1);
-    launch_rows<T, TOUT, false>(F.c2r, dI, dT, sv, s);
+    launch_rows<T, TOUT, false>(F.c2r, dI, dT, sv, s, h->row_sel);
   }
 }
 
@@ -819,13 +829,16 @@ static bool tune_cache_read(psd_handle* h, const std::string& key) {
     std::string l(line);
     const size_t bar = l.find('|');
     if (bar == std::string::npos || l.substr(0, bar) != key) continue;
-    int a, b, c, d, e;
+    int a, b, c, d, e, rs = 1;
     // chunks below T3Z_MIN would need more partial slots than were allocated;
-    // a wide line-search tile needs every n >= 64
-    if (std::sscanf(l.c_str() + bar + 1, "%d %d %d %d %d", &a, &b, &c, &d, &e) == 5 && a >= T3Z_MIN &&
-        b >= T3Z_MIN && (e == L3_TX_NARROW || (e == L3_TX_WIDE && h->ls_tx == L3_TX_WIDE))) {
+    // a wide line-search tile needs every n >= 64; the row layout is the
+    // sixth value (lines without it keep the default layout)
+    const int nv = std::sscanf(l.c_str() + bar + 1, "%d %d %d %d %d %d", &a, &b, &c, &d, &e, &rs);
+    if (nv >= 5 && a >= T3Z_MIN && b >= T3Z_MIN && (e == L3_TX_NARROW || (e == L3_TX_WIDE && h->ls_tx == L3_TX_WIDE)) &&
+        rs >= 0 && rs < PSD_ROW_SELS) {
       h->tune_zc_res = a; h->tune_zc_ls = b; h->tune_xcd_res = c != 0; h->tune_xcd_ls = d != 0;
       h->ls_tx = e;
+      h->row_sel = rs;
       found = true;
     }
   }
@@ -838,8 +851,8 @@ static void tune_cache_write(psd_handle* h, const std::string& key) {
   if (!path) return;
   FILE* fp = std::fopen(path, "a");
   if (!fp) return;
-  std::fprintf(fp, "%s|%d %d %d %d %d\n", key.c_str(), h->tune_zc_res, h->tune_zc_ls, (int)h->tune_xcd_res,
-               (int)h->tune_xcd_ls, h->ls_tx);
+  std::fprintf(fp, "%s|%d %d %d %d %d %d\n", key.c_str(), h->tune_zc_res, h->tune_zc_ls, (int)h->tune_xcd_res,
+               (int)h->tune_xcd_ls, h->ls_tx, h->row_sel);
   std::fclose(fp);
 }
 
@@ -957,10 +970,32 @@ static psd_status autotune_impl(psd_handle* h) {
       if (tl < best_ls) { best_ls = tl; bz_ls = zls[zi]; bx_ls = xcd != 0; btx_ls = tx; }
     }
   }
-  h->opt.profile = save_prof;
   h->tune_zc_res = bz_res; h->tune_zc_ls = bz_ls;
   h->tune_xcd_res = bx_res; h->tune_xcd_ls = bx_ls;
   h->ls_tx = btx_ls;
+  // row-pass layout (lines per block of the LDS row transform): both row
+  // passes of the solver's transform timed for every layout
+  double best_rows = 1e300;
+  int bsel = 1;
+  for (int sel = 0; sel < PSD_ROW_SELS; ++sel) {
+    h->row_sel = sel;
+    build_all_tasks(h, nsp_aux);
+    psd_status st = upload_tasks(h);
+    if (st != PSD_OK) return st;
+    for (int k = 0; k < PSD_NPASS; ++k) { h->pass_ms[k] = 0.0; h->pass_n[k] = 0; }
+    for (int rep = 0; rep < 4; ++rep) {
+      k_reset_state<<<(h->batch + 63) / 64, 64, 0, h->stream>>>(h->dI, h->batch);
+      run_fft<TD, TR, TD>(h, h->fft_solver, h->order == 4 ? OP_PRECOND4 : OP_PRECOND6, true);
+      HIPCHK(hipStreamSynchronize(h->stream));
+      if (rep == 0) { h->prof.clear(); h->ev_used = 0; continue; }  // warm-up
+      prof_collect(h, -1, false);
+    }
+    HIPCHK(hipGetLastError());
+    const double trow = h->pass_ms[PSD_PASS_ROWS_R2C] + h->pass_ms[PSD_PASS_ROWS_C2R];
+    if (trow < best_rows) { best_rows = trow; bsel = sel; }
+  }
+  h->row_sel = bsel;
+  h->opt.profile = save_prof;
   h->hI = saved;
   build_all_tasks(h, nsp_aux);
   for (int k = 0; k < PSD_NPASS; ++k) { h->pass_ms[k] = 0.0; h->pass_n[k] = 0; }
@@ -1109,12 +1144,14 @@ static psd_status setup_handle(psd_handle* h, const psd_problem* probs, int batc
       I.hist_cap = opt->max_iter;
     }
   }
-  // task tables: capacities from the finest z-chunk and every line-search
-  // tile width any tuning may pick
+  // task tables: capacities from the finest z-chunk, every line-search tile
+  // width and the row layout with the most blocks (fewest lines per block)
+  // that any tuning may pick
   std::vector<int> nsp_aux;
-  std::vector<int> cap_res(batch, 0), cap_ls(batch, 0);
+  std::vector<int> cap_res(batch, 0), cap_ls(batch, 0), cap_c2r(batch, 0);
   const int ls_tx0 = h->ls_tx;
   h->dT_cap = 0;
+  h->row_sel = 0;
   for (int tx : {L3_TX_NARROW, ls_tx0}) {
     h->ls_tx = tx;
     h->tune_zc_res = h->tune_zc_ls = T3Z_MIN;
@@ -1123,8 +1160,10 @@ static psd_status setup_handle(psd_handle* h, const psd_problem* probs, int batc
     for (int b = 0; b < batch; ++b) {
       cap_res[b] = std::max(cap_res[b], h->hI[b].nblk_res);
       cap_ls[b] = std::max(cap_ls[b], h->hI[b].nblk_ls);
+      cap_c2r[b] = std::max(cap_c2r[b], h->hI[b].nblk_c2r);
     }
   }
+  h->row_sel = 1;
   h->ls_tx = ls_tx0;
   h->tune_zc_res = T3Z_RES;
   h->tune_zc_ls = T3Z_LS;
@@ -1140,7 +1179,7 @@ static psd_status setup_handle(psd_handle* h, const psd_problem* probs, int batc
     I.nblk_vec = (int)std::min<long long>(1024, std::max<long long>(64, I.ncell / 2048));
     const int nres = std::max(cap_res[b], I.nblk_vec);
     if (dalloc(h, &I.part_res, (size_t)nres * 2 * 8) || dalloc(h, &I.part_ls, (size_t)cap_ls[b] * 8 * 8) ||
-        dalloc(h, &I.part_sp, (size_t)nsp_max * 2 * 8) || dalloc(h, &I.part_c2r, (size_t)I.nblk_c2r * 3 * 8))
+        dalloc(h, &I.part_sp, (size_t)nsp_max * 2 * 8) || dalloc(h, &I.part_c2r, (size_t)cap_c2r[b] * 3 * 8))
       return oom();
     I.st = h->dState + b;
   }
@@ -1200,11 +1239,12 @@ extern "C" psd_status psd_create(const psd_problem* probs, int batch, const psd_
   return PSD_OK;
 }
 
-extern "C" psd_status psd_tuning(const psd_handle* h, int* out5) {
-  if (!h || !out5) return PSD_ERR_ARG;
-  out5[0] = h->tune_zc_res; out5[1] = h->tune_zc_ls;
-  out5[2] = h->tune_xcd_res ? 1 : 0; out5[3] = h->tune_xcd_ls ? 1 : 0;
-  out5[4] = h->ls_tx;
+extern "C" psd_status psd_tuning(const psd_handle* h, int* out6) {
+  if (!h || !out6) return PSD_ERR_ARG;
+  out6[0] = h->tune_zc_res; out6[1] = h->tune_zc_ls;
+  out6[2] = h->tune_xcd_res ? 1 : 0; out6[3] = h->tune_xcd_ls ? 1 : 0;
+  out6[4] = h->ls_tx;
+  out6[5] = h->row_sel;
   return PSD_OK;
 }
 

@@ -294,8 +294,8 @@ class Solver:
 
     def tuning(self):
         """(z-chunk residual, z-chunk line search, XCD order residual, XCD order line search,
-        3D line-search tile width)."""
-        out = (ctypes.c_int * 5)()
+        3D line-search tile width, row-transform layout)."""
+        out = (ctypes.c_int * 6)()
         self._check(self._lib.psd_tuning(self._h, out))
         return tuple(out)
 
