@@ -88,13 +88,14 @@ def traffic_for(kernel: str, workload: str):
 
 
 # kernels of the passes of the mixed 256^3 p=4 form (prefixes of rocprofv3
-# kernel names; the line-search tile width is a trailing template argument)
+# kernel names; the line-search tile width and the row layout are trailing
+# template arguments)
 PASS_KERNELS = {
-    "rows_r2c": "psd::k_rows<float, float, true, 256>",
+    "rows_r2c": "psd::k_rows<float, float, true, 256, ",
     "cols_fwd": "psd::k_cols<float, 1, -1, 256>",
     "cols_fused": "psd::k_cols_fused<float, 0, 256>",
     "cols_inv": "psd::k_cols<float, 1, 1, 256>",
-    "rows_c2r": "psd::k_rows<float, float, false, 256>",
+    "rows_c2r": "psd::k_rows<float, float, false, 256, ",
     "ls": "psd::k_ls3d<float, 0, ",
     "res": "psd::k_res3d<float, float, true, 4, ",
 }
