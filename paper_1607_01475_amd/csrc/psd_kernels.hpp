@@ -812,14 +812,16 @@ __global__ __launch_bounds__(PSD_NT) void k_hess3d6(const Inst* __restrict__ ins
 //   op 7: sum r.z, sum z.Hp              op 8: p = z + beta p
 // State (auxiliary): lo = mean of G, c[0] = r.z, c[1] = p.Hp, c[2] = r.r,
 // hi = stop threshold, alpha, x = beta, iter = CG iterations.
-__global__ __launch_bounds__(PSD_NT) void k_cg6_vec(const Inst* __restrict__ insts, int inst, int op) {
+__global__ __launch_bounds__(PSD_NT) void k_cg6_vec(const Inst* __restrict__ insts, int nmax, int op) {
   __shared__ double scratch[2 * PSD_NT / PSD_WAVE];
+  // one launch for every instance: block (inst, j), j < nblk_vec of the instance
+  const int inst = blockIdx.x / nmax, j = blockIdx.x - inst * nmax;
   const Inst& I = insts[inst];
   const SolveState* st = I.st;
-  if (st->done) return;
+  if (st->done || j >= I.nblk_vec) return;
   const long long N = I.ncell;
-  const long long chunk = (N + gridDim.x - 1) / gridDim.x;
-  const long long c0 = blockIdx.x * chunk;
+  const long long chunk = (N + I.nblk_vec - 1) / I.nblk_vec;
+  const long long c0 = j * chunk;
   const long long c1 = c0 + chunk < N ? c0 + chunk : N;
   const double alpha = st->alpha, beta = st->x, mean = st->lo;
   double acc[2] = {0.0, 0.0};
@@ -849,7 +851,7 @@ __global__ __launch_bounds__(PSD_NT) void k_cg6_vec(const Inst* __restrict__ ins
   }
   if (op == 0 || op == 1 || op == 2 || op == 5 || op == 6 || op == 7) {
     block_reduce<2, 0>(acc, scratch);
-    if (threadIdx.x == 0) { I.part_res[2 * blockIdx.x] = acc[0]; I.part_res[2 * blockIdx.x + 1] = acc[1]; }
+    if (threadIdx.x == 0) { I.part_res[2 * j] = acc[0]; I.part_res[2 * j + 1] = acc[1]; }
   }
 }
 
@@ -899,14 +901,16 @@ __global__ __launch_bounds__(PSD_NT) void k_cg6_fin(const Inst* __restrict__ ins
 //   op 2: partial z.Hp
 //   op 3: p = z (first) ; op 4: p = z + beta p
 template <typename TD, typename TR>
-__global__ __launch_bounds__(PSD_NT) void k_cg_vec(const Inst* __restrict__ insts, int inst, int op) {
+__global__ __launch_bounds__(PSD_NT) void k_cg_vec(const Inst* __restrict__ insts, int nmax, int op) {
   __shared__ double scratch[2 * PSD_NT / PSD_WAVE];
+  // one launch for every instance: block (inst, j), j < nblk_vec of the instance
+  const int inst = blockIdx.x / nmax, j = blockIdx.x - inst * nmax;
   const Inst& I = insts[inst];
   const SolveState* st = I.st;
-  if (st->done) return;
+  if (st->done || j >= I.nblk_vec) return;
   const long long N = I.ncell;
-  const long long chunk = (N + gridDim.x - 1) / gridDim.x;
-  const long long c0 = blockIdx.x * chunk;
+  const long long chunk = (N + I.nblk_vec - 1) / I.nblk_vec;
+  const long long c0 = j * chunk;
   const long long c1 = c0 + chunk < N ? c0 + chunk : N;
   const double alpha = st->alpha, beta = st->x;
   double acc[2] = {0.0, 0.0};
@@ -935,7 +939,7 @@ __global__ __launch_bounds__(PSD_NT) void k_cg_vec(const Inst* __restrict__ inst
   }
   if (op <= 2) {
     block_reduce<2, 1>(acc, scratch);
-    if (threadIdx.x == 0) I.part_res[2 * blockIdx.x + 1] = acc[1];
+    if (threadIdx.x == 0) I.part_res[2 * j + 1] = acc[1];
   }
 }
 

@@ -1677,10 +1677,9 @@ template <typename T, typename TD, typename TR>
 static psd_status cg_solve(psd_handle* h, double rtol2, int max_iter) {
   const int B = h->batch;
   hipStream_t s = h->stream;
-  auto vec = [&](int op) {
-    for (int b = 0; b < B; ++b)
-      k_cg_vec<TD, TR><<<h->hI[b].nblk_vec, PSD_NT, 0, s>>>(h->dI, b, op);
-  };
+  int nmax = 1;
+  for (int b = 0; b < B; ++b) nmax = std::max(nmax, h->hI[b].nblk_vec);
+  auto vec = [&](int op) { k_cg_vec<TD, TR><<<B * nmax, PSD_NT, 0, s>>>(h->dI, nmax, op); };
   auto fin = [&](int mode) {
     // vector partials: nblk_vec per instance (read from the instance table)
     k_cg_fin<<<B, PSD_NT, 0, s>>>(h->dI, mode, -1, rtol2);
@@ -1830,9 +1829,9 @@ static psd_status adjoint6_impl(psd_handle* h, const double* const* u_star, cons
   if (st != PSD_OK) { (void)restore(); return st; }
   k_reset_state<<<(B + 63) / 64, 64, 0, s>>>(h->dI, B);
   const double rtol2 = rtol * rtol;
-  auto vec = [&](int op) {
-    for (int b = 0; b < B; ++b) k_cg6_vec<<<h->hI[b].nblk_vec, PSD_NT, 0, s>>>(h->dI, b, op);
-  };
+  int nmax = 1;
+  for (int b = 0; b < B; ++b) nmax = std::max(nmax, h->hI[b].nblk_vec);
+  auto vec = [&](int op) { k_cg6_vec<<<B * nmax, PSD_NT, 0, s>>>(h->dI, nmax, op); };
   auto fin = [&](int mode) { k_cg6_fin<<<B, PSD_NT, 0, s>>>(h->dI, mode, rtol2); };
   auto aux_fft = [&](int op) { run_fft<double, double, double>(h, h->fft_aux, op, false); };
   const Task2* tt = h->dT + h->res.off;
