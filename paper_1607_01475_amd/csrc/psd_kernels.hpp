@@ -1032,31 +1032,65 @@ __device__ __forceinline__ double div_flux_at(const Inst& I, const double* u, in
   return div;
 }
 
+// Parameter sensitivities of the adjoint: with lam = H^{-1} dJ/du,
+//   part[0] = sum_c lam (-div_h F(u*) + eps^2 Delta_h^2 u*),  F = |grad u|^{p-2} grad u,
+//   part[1] = sum_c lam Delta_h^2 u*,  part[2] = sum_c lam u*,
+// evaluated by summation by parts (the vertex gradient is minus the adjoint
+// of the divergence, Delta_h is self-adjoint): sum_c lam (-div F) =
+// sum_v grad lam . F and sum_c lam Delta_h^2 u = sum_c Delta_h lam Delta_h u.
+// Each cell contributes its upper vertex (i+1/2, j+1/2[, k+1/2]) and its own
+// Laplacians: 16 (3D) loads of u and lam for the vertex, 12 for the
+// Laplacians.
 __global__ __launch_bounds__(PSD_NT) void k_param_sens(const Inst* __restrict__ insts, int inst,
                                                        double* __restrict__ part) {
   __shared__ double scratch[3 * PSD_NT / PSD_WAVE];
   const Inst& I = insts[inst];
   const double* u = I.adj_us;
+  const double* lm = I.adj_lam;
   const int n = I.n, dim = I.dim;
   const double ih = I.inv_h, ih2 = ih * ih;
+  const double e2 = I.se2 / I.s;
   double acc[3] = {0.0, 0.0, 0.0};
   for (long long c = blockIdx.x * (long long)PSD_NT + threadIdx.x; c < I.ncell; c += (long long)gridDim.x * PSD_NT) {
     const int i = (int)(c % n), j = (int)((c / n) % n), k = dim == 3 ? (int)(c / ((long long)n * n)) : 0;
-    auto lap = [&](int a, int b, int e) {
-      double v = at3(u, n, dim, a + 1, b, e) + at3(u, n, dim, a - 1, b, e) + at3(u, n, dim, a, b + 1, e) +
-                 at3(u, n, dim, a, b - 1, e) - 4.0 * at3(u, n, dim, a, b, e);
-      if (dim == 3) v += at3(u, n, dim, a, b, e + 1) + at3(u, n, dim, a, b, e - 1) - 2.0 * at3(u, n, dim, a, b, e);
-      return v * ih2;
+    double gx, gy, gz = 0.0, hx, hy, hz = 0.0;   // grad u*, grad lam at the vertex
+    if (dim == 2) {
+      const double c00 = at3(u, n, 2, i, j, 0), c10 = at3(u, n, 2, i + 1, j, 0);
+      const double c01 = at3(u, n, 2, i, j + 1, 0), c11 = at3(u, n, 2, i + 1, j + 1, 0);
+      gx = 0.5 * ih * ((c10 - c00) + (c11 - c01));
+      gy = 0.5 * ih * ((c01 - c00) + (c11 - c10));
+      const double l00 = at3(lm, n, 2, i, j, 0), l10 = at3(lm, n, 2, i + 1, j, 0);
+      const double l01 = at3(lm, n, 2, i, j + 1, 0), l11 = at3(lm, n, 2, i + 1, j + 1, 0);
+      hx = 0.5 * ih * ((l10 - l00) + (l11 - l01));
+      hy = 0.5 * ih * ((l01 - l00) + (l11 - l10));
+    } else {
+      const double q = 0.25 * ih;
+      const double c000 = at3(u, n, 3, i, j, k), c100 = at3(u, n, 3, i + 1, j, k);
+      const double c010 = at3(u, n, 3, i, j + 1, k), c110 = at3(u, n, 3, i + 1, j + 1, k);
+      const double c001 = at3(u, n, 3, i, j, k + 1), c101 = at3(u, n, 3, i + 1, j, k + 1);
+      const double c011 = at3(u, n, 3, i, j + 1, k + 1), c111 = at3(u, n, 3, i + 1, j + 1, k + 1);
+      gx = q * ((c100 - c000) + (c110 - c010) + (c101 - c001) + (c111 - c011));
+      gy = q * ((c010 - c000) + (c110 - c100) + (c011 - c001) + (c111 - c101));
+      gz = q * ((c001 - c000) + (c101 - c100) + (c011 - c010) + (c111 - c110));
+      const double l000 = at3(lm, n, 3, i, j, k), l100 = at3(lm, n, 3, i + 1, j, k);
+      const double l010 = at3(lm, n, 3, i, j + 1, k), l110 = at3(lm, n, 3, i + 1, j + 1, k);
+      const double l001 = at3(lm, n, 3, i, j, k + 1), l101 = at3(lm, n, 3, i + 1, j, k + 1);
+      const double l011 = at3(lm, n, 3, i, j + 1, k + 1), l111 = at3(lm, n, 3, i + 1, j + 1, k + 1);
+      hx = q * ((l100 - l000) + (l110 - l010) + (l101 - l001) + (l111 - l011));
+      hy = q * ((l010 - l000) + (l110 - l100) + (l011 - l001) + (l111 - l101));
+      hz = q * ((l001 - l000) + (l101 - l100) + (l011 - l010) + (l111 - l110));
+    }
+    const double rr = flux_r(gx * gx + gy * gy + gz * gz, I.p, I.p_is_4, I.p_is_2);
+    auto lap = [&](const double* v) {
+      double t = at3(v, n, dim, i + 1, j, k) + at3(v, n, dim, i - 1, j, k) + at3(v, n, dim, i, j + 1, k) +
+                 at3(v, n, dim, i, j - 1, k) - 4.0 * at3(v, n, dim, i, j, k);
+      if (dim == 3) t += at3(v, n, dim, i, j, k + 1) + at3(v, n, dim, i, j, k - 1) - 2.0 * at3(v, n, dim, i, j, k);
+      return t * ih2;
     };
-    double l2 = lap(i + 1, j, k) + lap(i - 1, j, k) + lap(i, j + 1, k) + lap(i, j - 1, k) - 4.0 * lap(i, j, k);
-    if (dim == 3) l2 += lap(i, j, k + 1) + lap(i, j, k - 1) - 2.0 * lap(i, j, k);
-    l2 *= ih2;
-    const double div = div_flux_at(I, u, i, j, k, false);
-    const double lam = I.adj_lam[c];
-    const double e2 = I.se2 / I.s;
-    acc[0] += lam * (-div + e2 * l2);
-    acc[1] += lam * l2;
-    acc[2] += lam * u[c];
+    const double ll = lap(lm) * lap(u);
+    acc[0] += rr * (hx * gx + hy * gy + hz * gz) + e2 * ll;
+    acc[1] += ll;
+    acc[2] += lm[c] * u[c];
   }
   block_reduce<3, 0>(acc, scratch);
   if (threadIdx.x == 0)
