@@ -189,6 +189,11 @@ __device__ __forceinline__ cx<T> gld(const cx<T>* p) {
   const gvec<T, 2> v = *(const PSD_GLOBAL gvec<T, 2>*)gmem(p);
   return mk(v.x, v.y);
 }
+// global load of a table entry, complex or real
+template <typename T>
+__device__ __forceinline__ cx<T> gld_any(const cx<T>* p) { return gld(p); }
+__device__ __forceinline__ double gld_any(const double* p) { return *gmem(p); }
+
 template <typename T>
 __device__ __forceinline__ void gst(cx<T>* p, const cx<T>& a) {
   gvec<T, 2> v;

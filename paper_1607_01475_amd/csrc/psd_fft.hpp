@@ -160,12 +160,36 @@ __device__ __forceinline__ void dftR(cx<T>* a) {
 constexpr int fft_ls(int N) { return N + N / 16 + 1; }
 __device__ __forceinline__ int pidx(int t) { return t + (t >> 4); }
 
-// Copy the twiddle table exp(-2 pi i m/N), m < N, into LDS (dst); the
-// caller's next barrier publishes it.
-template <typename T, int N>
-__device__ __forceinline__ void stage_twiddles(cx<T>* dst, const cx<T>* __restrict__ tw) {
-  for (int i = threadIdx.x; i < N; i += PSD_NT) dst[i] = gld(tw + i);
-}
+// Copy a table of N entries (the twiddles exp(-2 pi i m/N), m < N, or the
+// fused pass's symbol) into LDS in two steps: load() issues the global loads
+// into registers, store() writes them to LDS; the caller's next barrier
+// publishes them.  A block issues its data loads first, then the table's,
+// then stores both: the table's latency overlaps the data's instead of
+// adding to it (an LDS store has to wait for its load), and the data
+// requests reach memory first.
+template <typename U, int N>
+struct TableStage {
+  static constexpr int K = (N + PSD_NT - 1) / PSD_NT;
+  U v[K];
+  __device__ __forceinline__ void load(const U* __restrict__ src) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = (int)threadIdx.x + k * PSD_NT;
+      if (N % PSD_NT == 0 || i < N) v[k] = gld_any(src + i);
+    }
+    // keep the arithmetic on the block's data (which may start before the
+    // next barrier) from being scheduled above these loads: it would wait
+    // for the data before the table's loads are issued
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  __device__ __forceinline__ void store(U* dst) const {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = (int)threadIdx.x + k * PSD_NT;
+      if (N % PSD_NT == 0 || i < N) dst[i] = v[k];
+    }
+  }
+};
 
 template <int S, int NSTG, typename F>
 __device__ __forceinline__ void stage_loop(F&& f) {
@@ -281,7 +305,6 @@ __device__ __forceinline__ void r2c_rows(const RowArgs<T>& A, long long row0, cx
   static_assert(N % VEC == 0, "row length must be a multiple of the vector width");
   struct alignas(16) V { TIN x[VEC]; };
   cx<T>* twl = buf + NL * LS;
-  stage_twiddles<T, N>(twl, tw);
   V regs[IT];
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
@@ -300,6 +323,9 @@ __device__ __forceinline__ void r2c_rows(const RowArgs<T>& A, long long row0, cx
       for (int q = 0; q < VEC; ++q) regs[it].x[q] = TIN(0);
     }
   }
+  TableStage<cx<T>, N> tws;
+  tws.load(tw);
+  tws.store(twl);
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int e = threadIdx.x + it * PSD_NT;
@@ -340,25 +366,28 @@ __device__ __forceinline__ void c2r_rows(const RowArgs<T>& A, long long row0, cx
   constexpr int NE = NL * NC;
   constexpr int IT = (NE + PSD_NT - 1) / PSD_NT;
   cx<T>* twl = buf + NL * LS;
-  stage_twiddles<T, N>(twl, tw);
   cx<T> ra[IT], rb[IT];
+  // entries past the block's rows read its first entry, so that no branch
+  // surrounds the loads (a branch splits them into separately waited
+  // groups); entries past NE are not stored to LDS, and lines past the last
+  // row are transformed but never written out
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int e = threadIdx.x + it * PSD_NT;
-    const int l = e / NC, k = e - l * NC;
-    const long long gr = row0 + 2 * l;
-    ra[it] = mk(T(0), T(0));
-    rb[it] = mk(T(0), T(0));
-    if ((NE % PSD_NT == 0 || e < NE) && gr < A.nrows) {
-      long long row;
-      const int fld = row_field(gr, A.rpf, row);
-      const cx<T>* in = A.spec + fld * A.nspec;
-      const long long oa = (k < N / 2) ? row * A.ncp + k : A.nyq + row;
-      const long long ob = (k < N / 2) ? oa + A.ncp : oa + 1;
-      ra[it] = gld(in + oa);
-      rb[it] = gld(in + ob);
-    }
+    const int l0 = e / NC, k0 = e - l0 * NC;
+    const bool ok = (NE % PSD_NT == 0 || e < NE) && row0 + 2 * l0 < A.nrows;
+    const int l = ok ? l0 : 0, k = ok ? k0 : 0;
+    long long row;
+    const int fld = row_field(row0 + 2 * l, A.rpf, row);
+    const cx<T>* in = A.spec + fld * A.nspec;
+    const long long oa = (k < N / 2) ? row * A.ncp + k : A.nyq + row;
+    const long long ob = (k < N / 2) ? oa + A.ncp : oa + 1;
+    ra[it] = gld(in + oa);
+    rb[it] = gld(in + ob);
   }
+  TableStage<cx<T>, N> tws;
+  tws.load(tw);
+  tws.store(twl);
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int e = threadIdx.x + it * PSD_NT;
@@ -404,17 +433,20 @@ struct ColSet {
 };
 
 // Load NF fields of the block's columns of length N into LDS lines
-// (f*W + c), every load of the block issued before the first LDS store.
-template <typename T, int N, int W, int NF>
+// (f*W + c), every load of the block issued before the first LDS store;
+// mid() runs between the loads and the stores (table staging).
+template <typename T, int N, int W, int NF, typename Mid>
 __device__ __forceinline__ void col_load(const cx<T>* base, const ColSet& cs, long long fstride,
-                                         cx<T>* buf) {
+                                         cx<T>* buf, Mid&& mid) {
   constexpr int LS = fft_ls(N);
   constexpr int NE = NF * W * N;
   constexpr int IT = (NE + PSD_NT - 1) / PSD_NT;
   static_assert(PSD_NT % W == 0, "a thread keeps one column");
   const int c = threadIdx.x % W;
-  const long long coff = cs.cbase + c * cs.cstride;
   const bool live = c < cs.ncols;
+  // columns past the block's last one read its first column (no branch
+  // around the loads), and are zeroed afterwards
+  const long long coff = cs.cbase + (live ? c : 0) * cs.cstride;
   cx<T> regs[IT];
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
@@ -422,8 +454,12 @@ __device__ __forceinline__ void col_load(const cx<T>* base, const ColSet& cs, lo
     const int ft = e / W;
     const int t = ft % N, f = ft / N;
     regs[it] = mk(T(0), T(0));
-    if ((NE % PSD_NT == 0 || e < NE) && live) regs[it] = gld(base + f * fstride + coff + t * cs.lstride);
+    if (NE % PSD_NT == 0 || e < NE) regs[it] = gld(base + f * fstride + coff + t * cs.lstride);
   }
+  if (!live)
+#pragma unroll
+    for (int it = 0; it < IT; ++it) regs[it] = mk(T(0), T(0));
+  mid();
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int e = threadIdx.x + it * PSD_NT;
@@ -503,10 +539,15 @@ __device__ __forceinline__ void four_step(cx<T>* x, int g, int c, cx<T>* buf, co
 template <int N, typename T>
 __device__ __forceinline__ void col_fs_load(const cx<T>* base, const ColSet& cs, int c, int g, bool live,
                                             cx<T>* x) {
-  const cx<T>* col = base + cs.cbase + c * cs.cstride + g * cs.lstride;
+  // columns past the block's last one read its first column, so that the
+  // loads need no branch (a branch splits them into separately waited groups)
+  const cx<T>* col = base + cs.cbase + (live ? c : 0) * cs.cstride + g * cs.lstride;
   const long long step = (N / 16) * cs.lstride;
 #pragma unroll
-  for (int j = 0; j < 16; ++j) x[j] = live ? gld(col + j * step) : mk(T(0), T(0));
+  for (int j = 0; j < 16; ++j) x[j] = gld(col + j * step);
+  if (!live)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) x[j] = mk(T(0), T(0));
 }
 
 template <int N, typename T>
@@ -530,7 +571,9 @@ __device__ __forceinline__ void col_pass(cx<T>* base, const ColSet& cs, long lon
     cx<T> x[16];
     col_fs_load<N>(base, cs, c, g, live, x);
     cx<T>* twl = buf + 16 * FS_RS;
-    stage_twiddles<T, N>(twl, tw);
+    TableStage<cx<T>, N> tws;
+    tws.load(tw);
+    tws.store(twl);
     __syncthreads();
     four_step<N, DIR>(x, g, c, buf, twl);
     if (live) col_fs_store<N>(base, cs, c, g, x);
@@ -538,8 +581,8 @@ __device__ __forceinline__ void col_pass(cx<T>* base, const ColSet& cs, long lon
   }
   constexpr int LS = fft_ls(N);
   cx<T>* twl = buf + NF * W * LS;
-  stage_twiddles<T, N>(twl, tw);
-  col_load<T, N, W, NF>(base, cs, fstride, buf);
+  TableStage<cx<T>, N> tws;
+  col_load<T, N, W, NF>(base, cs, fstride, buf, [&] { tws.load(tw); tws.store(twl); });
   __syncthreads();
   lds_fft<T, N, NF * W, LS, DIR>(buf, twl);
   col_store<T, N, W, NF>(base, cs, fstride, buf);

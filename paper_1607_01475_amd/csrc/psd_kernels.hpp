@@ -535,12 +535,16 @@ __device__ __forceinline__ void fused_col(const Inst& I, const Task2& t, cx<T>* 
   const ColSet cs = fused_cols<T, N, W>(I, t);
   constexpr int NLMAX = (NFI > NFO ? NFI : NFO) * W;
   cx<T>* twl = buf + NLMAX * LS;
-  stage_twiddles<T, N>(twl, tw);
   // the symbol S(k) of the last axis, staged with the twiddles
   double* Sl = (double*)(twl + N);
-  const PSD_GLOBAL double* S = gmem(I.S);
-  for (int e = threadIdx.x; e < N; e += PSD_NT) Sl[e] = S[e];
-  col_load<T, N, W, NFI>(base, cs, fstride, buf);
+  TableStage<cx<T>, N> tws;
+  TableStage<double, N> sst;
+  col_load<T, N, W, NFI>(base, cs, fstride, buf, [&] {
+    tws.load(tw);
+    sst.load(I.S);
+    tws.store(twl);
+    sst.store(Sl);
+  });
   __syncthreads();
   lds_fft<T, N, NFI * W, LS, -1>(buf, twl);
   const double s = I.s, se2 = I.se2, inv = I.inv_ntot;
@@ -602,9 +606,12 @@ __device__ __forceinline__ void fused_col_fs(const Inst& I, const Task2& t, cx<T
   col_fs_load<N>(base, cs, c, g, live, x);
   cx<T>* twl = buf + 16 * FS_RS;
   double* Sl = (double*)(twl + N);
-  stage_twiddles<T, N>(twl, tw);
-  const PSD_GLOBAL double* S = gmem(I.S);
-  if (threadIdx.x < N) Sl[threadIdx.x] = S[threadIdx.x];
+  TableStage<cx<T>, N> tws;
+  TableStage<double, N> sst;
+  tws.load(tw);
+  sst.load(I.S);
+  tws.store(twl);
+  sst.store(Sl);
   __syncthreads();
   four_step<N, -1>(x, g, c, buf, twl);   // x[k] = frequency g + N1 k
   {

@@ -98,21 +98,22 @@ __device__ void res2d_tile(const Inst& I, int x0, int y0, double* lds, double (&
     fo[k] = HESS ? 0.0 : gmem(I.f)[gi];
     go[k] = (ORDER == 6 && !HESS) ? gmem(I.g)[gi] : 0.0;
   }
-  // v = u + alpha d on the tile plus a 2-cell ring: all loads issued first
+  // v = u + alpha d on the tile plus a 2-cell ring: all loads issued first,
+  // with no branch around them (threads past the ring reload its last cell;
+  // a branch would split the loads into separately waited groups)
   {
     constexpr int NV = R2_VW * R2_VH, IT = (NV + PSD_NT - 1) / PSD_NT;
     double uv[IT];
     TD dv[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-      const int e = tid + it * PSD_NT;
-      if (e < NV) {
-        const int ey = e / R2_VW, ex = e - ey * R2_VW;
-        const long long gi = wrap2(x0 - 2 + ex, n, small) + (long long)n * wrap2(y0 - 2 + ey, n, small);
-        uv[it] = u[gi];
-        if (UPD) dv[it] = d[gi];
-      }
+      const int e = min(tid + it * PSD_NT, NV - 1);
+      const int ey = e / R2_VW, ex = e - ey * R2_VW;
+      const long long gi = wrap2(x0 - 2 + ex, n, small) + (long long)n * wrap2(y0 - 2 + ey, n, small);
+      uv[it] = u[gi];
+      if (UPD) dv[it] = d[gi];
     }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int e = tid + it * PSD_NT;
@@ -136,14 +137,13 @@ __device__ void res2d_tile(const Inst& I, int x0, int y0, double* lds, double (&
     TD e1v[IT], e2v[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-      const int e = tid + it * PSD_NT;
-      if (e < NW) {
-        const int ey = e / R2_LW, ex = e - ey * R2_LW;
-        const long long gi = wrap2(x0 - 1 + ex, n, small) + (long long)n * wrap2(y0 - 1 + ey, n, small);
-        wv[it] = w[gi];
-        if (UPD) { e1v[it] = e1[gi]; e2v[it] = e2[gi]; }
-      }
+      const int e = min(tid + it * PSD_NT, NW - 1);   // as above: no branch around the loads
+      const int ey = e / R2_LW, ex = e - ey * R2_LW;
+      const long long gi = wrap2(x0 - 1 + ex, n, small) + (long long)n * wrap2(y0 - 1 + ey, n, small);
+      wv[it] = w[gi];
+      if (UPD) { e1v[it] = e1[gi]; e2v[it] = e2[gi]; }
     }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int e = tid + it * PSD_NT;
@@ -380,7 +380,8 @@ struct Res3March {
   // rotating registers: [plane slot][cell]
   double vc[3][2], sc[3][2], lap[3][2];
   VPart po[2][2], pr[2], so[2][2], sr[2];
-  double Pq[2], Qq[2], fv[2];   // per cell: divergence terms of the vertex plane below, f
+  double Pq[2], Qq[2];   // per cell: divergence terms of the vertex plane below
+  double fq[3][2];       // f of the output planes j, j+1, j+2: [plane slot][cell]
   R3Prefetch<TD> pf[2];
   double acc0, acc1;
 
@@ -438,13 +439,13 @@ struct Res3March {
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
-      for (int e = 0; e < 2; ++e) vc[k][e] = sc[k][e] = lap[k][e] = 0.0;
+      for (int e = 0; e < 2; ++e) vc[k][e] = sc[k][e] = lap[k][e] = fq[k][e] = 0.0;
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       pr[k] = sr[k] = VPart{0.0, 0.0, 0.0};
 #pragma unroll
       for (int e = 0; e < 2; ++e) po[k][e] = so[k][e] = VPart{0.0, 0.0, 0.0};
-      Pq[k] = Qq[k] = fv[k] = 0.0;
+      Pq[k] = Qq[k] = 0.0;
     }
   }
 
@@ -457,10 +458,10 @@ struct Res3March {
       pf[B].d0 = d[zo + own0];
       pf[B].d1 = d[zo + own1];
     }
-    if (tid < VRING) {
-      pf[B].u_ring = u[zo + ring_xy];
-      if (LOADD) pf[B].d_ring = d[zo + ring_xy];
-    }
+    // every thread loads a halo value (threads past the ring read a cell of
+    // the tile), so that no branch surrounds the loads
+    pf[B].u_ring = u[zo + ring_xy];
+    if (LOADD) pf[B].d_ring = d[zo + ring_xy];
   }
 
   // the plane prefetched in buffer B into v slot S (and u* slot S)
@@ -530,13 +531,19 @@ struct Res3March {
   __device__ __forceinline__ void step(int j) {
     constexpr int S0 = Q % 3, S1 = (Q + 1) % 3, S2 = (Q + 2) % 3;   // planes j, j+1, j+2
     constexpr int P0 = Q & 1, P1 = (Q + 1) & 1;                      // planes j, j+1
-    put<S2, P0>();
-    if (j + 2 < z1) fetch<P0>(j + 4);
-    // f of output plane j: issued here, used after the second barrier
-    if (!HESS && j >= z0 && j < z1) {
-      fv[0] = __builtin_nontemporal_load(&f[own0 + nn * j]);   // read once per iteration
-      fv[1] = __builtin_nontemporal_load(&f[own1 + nn * j]);
+    // f of output plane j+2, used two steps later.  The memory counter that
+    // a wait for a load tests retires loads in issue order, so f is issued
+    // before the prefetch of plane j+4: the emit of plane j then waits only
+    // for loads issued two steps back.  Loads are unconditional (branches
+    // around them make the waits assume the worst); planes outside the
+    // chunk are clamped to its last needed plane, which the caches hold.
+    if (!HESS) {
+      const long long fz = nn * (long long)min(j + 2, z1 - 1);
+      fq[S2][0] = __builtin_nontemporal_load(&f[own0 + fz]);   // read once per iteration
+      fq[S2][1] = __builtin_nontemporal_load(&f[own1 + fz]);
     }
+    put<S2, P0>();
+    fetch<P0>(min(j + 4, z1 + 1));
     __syncthreads();
     const double* v0 = vb + S0 * VP;
     const double* v1 = vb + S1 * VP;
@@ -599,12 +606,12 @@ struct Res3March {
         if (ok0) {
           const double l2 = (lc[l0 - 1] + lc[l0 + 1] + lc[l0 - LW] + lap[S0][1] + lap[S2][0] + lap[S1][0] -
                              6.0 * lap[S0][0]) * ih2;
-          emit(gi, vc[S0][0], qhp * (P_0 + Pq[0] + Q_0 - Qq[0]), l2, fv[0]);
+          emit(gi, vc[S0][0], qhp * (P_0 + Pq[0] + Q_0 - Qq[0]), l2, fq[S0][0]);
         }
         if (ok1) {
           const double l2 = (lc[l1 - 1] + lc[l1 + 1] + lap[S0][0] + lc[l1 + LW] + lap[S2][1] + lap[S1][1] -
                              6.0 * lap[S0][1]) * ih2;
-          emit(gi + n, vc[S0][1], qhp * (P_1 + Pq[1] + Q_1 - Qq[1]), l2, fv[1]);
+          emit(gi + n, vc[S0][1], qhp * (P_1 + Pq[1] + Q_1 - Qq[1]), l2, fq[S0][1]);
         }
       }
       Pq[0] = P_0; Qq[0] = Q_0;
@@ -678,22 +685,43 @@ __device__ void res3d6_tile(const Inst& I, int x0, int y0, int z0, double* lds, 
   auto gidx = [&](int i, int j, int k) {
     return (long long)wrapi(i, n) + (long long)n * wrapi(j, n) + nn * wrapi(k, n);
   };
-  // v on the brick plus a 2-cell shell
-  for (int e = tid; e < B6_V; e += PSD_NT) {
+  // v on the brick plus a 2-cell shell and w' (or u* in Hessian mode) on
+  // the brick plus a 1-cell shell: every load is issued before the first
+  // LDS store, with no branch around the loads (threads past a region
+  // reload its last cell), so the block waits for memory once
+  constexpr int ITV = (B6_V + PSD_NT - 1) / PSD_NT, ITW = (B6_L + PSD_NT - 1) / PSD_NT;
+  constexpr bool WUPD = UPD && !HESS;
+  const PSD_GLOBAL double* w = gmem(HESS ? I.adj_us : (const double*)I.w[cur]);
+  const PSD_GLOBAL TD* e1 = gmem((const TD*)I.e1);
+  const PSD_GLOBAL TD* e2 = gmem((const TD*)I.e2);
+  double uv[ITV], wv[ITW];
+  TD dv[ITV], e1v[ITW], e2v[ITW];
+#pragma unroll
+  for (int it = 0; it < ITV; ++it) {
+    const int e = min(tid + it * PSD_NT, B6_V - 1);
     const int ex = e % B6_VX, ey = (e / B6_VX) % B6_VY, ez = e / (B6_VX * B6_VY);
     const long long gi = gidx(x0 - 2 + ex, y0 - 2 + ey, z0 - 2 + ez);
-    v[e] = UPD ? u[gi] + alpha * ((double)d[gi] - dbar) : u[gi];
+    uv[it] = u[gi];
+    if (UPD) dv[it] = d[gi];
   }
-  // w' (or u* in Hessian mode) on the brick plus a 1-cell shell
-  {
-    const PSD_GLOBAL double* w = gmem(HESS ? I.adj_us : (const double*)I.w[cur]);
-    const PSD_GLOBAL TD* e1 = gmem((const TD*)I.e1);
-    const PSD_GLOBAL TD* e2 = gmem((const TD*)I.e2);
-    for (int e = tid; e < B6_L; e += PSD_NT) {
-      const int ex = e % B6_LX, ey = (e / B6_LX) % B6_LY, ez = e / (B6_LX * B6_LY);
-      const long long gi = gidx(x0 - 1 + ex, y0 - 1 + ey, z0 - 1 + ez);
-      wl[e] = (UPD && !HESS) ? w[gi] + (((double)e1[gi] - e1bar) - alpha * ((double)e2[gi] - e2bar)) : w[gi];
-    }
+#pragma unroll
+  for (int it = 0; it < ITW; ++it) {
+    const int e = min(tid + it * PSD_NT, B6_L - 1);
+    const int ex = e % B6_LX, ey = (e / B6_LX) % B6_LY, ez = e / (B6_LX * B6_LY);
+    const long long gi = gidx(x0 - 1 + ex, y0 - 1 + ey, z0 - 1 + ez);
+    wv[it] = w[gi];
+    if (WUPD) { e1v[it] = e1[gi]; e2v[it] = e2[gi]; }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int it = 0; it < ITV; ++it) {
+    const int e = tid + it * PSD_NT;
+    if (e < B6_V) v[e] = UPD ? uv[it] + alpha * ((double)dv[it] - dbar) : uv[it];
+  }
+#pragma unroll
+  for (int it = 0; it < ITW; ++it) {
+    const int e = tid + it * PSD_NT;
+    if (e < B6_L) wl[e] = WUPD ? wv[it] + (((double)e1v[it] - e1bar) - alpha * ((double)e2v[it] - e2bar)) : wv[it];
   }
   __syncthreads();
   // Laplacian of v on the brick plus a 1-cell shell
