@@ -303,19 +303,27 @@ __device__ __forceinline__ void flat_reduce2(const double* __restrict__ p1, int 
   if (lane < K1) scratch[wid * K1 + lane] = a;
   if (lane < K2) scratch[NW * K1 + wid * K2 + lane] = b;
   __syncthreads();
+  // thread k < K1 + K2 adds entry k over the waves in wave order (in
+  // parallel rather than all in thread 0; the order of the additions is the
+  // same), then thread 0 collects the results
+  static_assert(K1 + K2 <= NT, "one thread per entry");
+  double r = 0.0;
+  if (tid < K1) {
+    r = scratch[tid];
+    for (int w2 = 1; w2 < NW; ++w2) r += scratch[w2 * K1 + tid];
+  } else if (tid < K1 + K2) {
+    const int k = tid - K1;
+    r = scratch[NW * K1 + k];
+    for (int w2 = 1; w2 < NW; ++w2) r += scratch[NW * K1 + w2 * K2 + k];
+  }
+  __syncthreads();
+  if (tid < K1 + K2) scratch[tid] = r;
+  __syncthreads();
   if (tid == 0) {
 #pragma unroll
-    for (int k = 0; k < K1; ++k) {
-      double r = scratch[k];
-      for (int w2 = 1; w2 < NW; ++w2) r += scratch[w2 * K1 + k];
-      o1[k] = r;
-    }
+    for (int k = 0; k < K1; ++k) o1[k] = scratch[k];
 #pragma unroll
-    for (int k = 0; k < K2; ++k) {
-      double r = scratch[NW * K1 + k];
-      for (int w2 = 1; w2 < NW; ++w2) r += scratch[NW * K1 + w2 * K2 + k];
-      o2[k] = r;
-    }
+    for (int k = 0; k < K2; ++k) o2[k] = scratch[K1 + k];
   }
   __syncthreads();
 }

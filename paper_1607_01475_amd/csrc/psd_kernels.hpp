@@ -228,12 +228,19 @@ __global__ __launch_bounds__(PSD_FIN_NT) void k_ls_finalize(const Inst* __restri
   __shared__ double scratch[10 * PSD_FIN_NT / PSD_WAVE];
   const Inst& I = insts[blockIdx.x];
   SolveState* st = I.st;
-  // modes 0, 1, 3: state, line-search and spectral partials are loaded
-  // together (one memory round trip; the pass almost always has work).
   // Mode 2: the passes captured after the root search has finished are the
   // common case, so the state is read first and the partials only if needed.
-  if (mode == 2 && (st->done || st->ls_phase == 2)) return;
-  const bool skip = st->done;
+  // Modes 0, 1, 3 (the pass almost always has work): the state's flag is
+  // loaded with the partials and tested only after their reduction, so that
+  // both arrive in one memory round trip (the empty asm statement below keeps
+  // the compiler from comparing the flag, and so waiting for its load, before
+  // the partials' loads are issued).
+  int skip = 0;
+  if (mode == 2) {
+    if (st->done || st->ls_phase == 2) return;
+  } else {
+    skip = st->done;
+  }
   double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   {
     double a8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -245,6 +252,7 @@ __global__ __launch_bounds__(PSD_FIN_NT) void k_ls_finalize(const Inst* __restri
     acc[8] = a2[0];
     acc[9] = a2[1];
   }
+  __asm__ volatile("" : "+v"(skip));
   if (skip) return;
   if (I.order == 6 && mode != 2) {
     // means of d, e1, e2 (FP32 round-off of the inverse transform leaves a
