@@ -78,9 +78,12 @@ enum { PSD_METRIC_CONSTANT = 0, PSD_METRIC_VARIABLE = 1 };
  *               reductions, step and update stay FP64 (iterative refinement)
  *   graph_chunk 0: host-driven loop, the host reads the convergence flag
  *               after every iteration.  k > 0: k iterations are captured once
- *               in a HIP graph and replayed until the device flag says done
- *               (general p: each captured iteration runs up to 6 evaluation
- *               passes of the root search; see psd_stats.ls_truncated)
+ *               in a HIP graph and replayed until the device flag says done;
+ *               the host reads the flags of one batch of replays while the
+ *               next batch runs (two pinned state buffers and two events,
+ *               allocated on first use) (general p: each captured iteration
+ *               runs up to 6 evaluation passes of the root search; see
+ *               psd_stats.ls_truncated)
  *   history     non-zero: record per-update (alpha, ||r||_inf, ||r||_2, dE)
  *   profile     non-zero: per-pass kernel timing of psd_solve (psd_pass_times)
  *   autotune    non-zero: pick stencil tilings by timing at creation */

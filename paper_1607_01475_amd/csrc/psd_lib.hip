@@ -104,6 +104,10 @@ struct psd_handle_s {
   SolveState* dState = nullptr;
   SolveState* dAuxState = nullptr;  // states of auxiliary evaluations (keep dState intact)
   SolveState* hState = nullptr;  // pinned
+  // graph-mode solves: two pinned slots for the states copied after each
+  // queued batch of replays, each with an event (created on first use)
+  SolveState* hStateQ[2] = {nullptr, nullptr};
+  hipEvent_t ev_state[2] = {nullptr, nullptr};
   double* hPart = nullptr;       // pinned scratch for auxiliary partials
   size_t hPartCap = 0;
   double* dAuxPart = nullptr;
@@ -705,37 +709,74 @@ static psd_status solve_loop(psd_handle* h) {
       HIPCHK(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
       h->gchunk = chunk;
     }
-    // Replays are queued back to back and the host checks the device flag
-    // only after each batch.  The batch size comes from the residual decay
-    // observed so far (PSD converges linearly, Sec. 2.3): enough chunks to
-    // reach tol at the measured rate.  Extra replays cost only early exits.
+    // Replays are queued in batches.  After the initial residual and after
+    // each batch the device states are copied to a pinned slot and an event
+    // is recorded; the host queues the next batch before it waits for the
+    // previous one's states, so the GPU does not idle while the host decides
+    // (at most two batches are outstanding).  The batch size comes from the
+    // residual decay observed so far (PSD converges linearly, Sec. 2.3):
+    // enough replays to reach tol at the measured rate counting those already
+    // queued.  Replays past convergence cost only early exits.
+    for (int k = 0; k < 2; ++k) {
+      if (!h->hStateQ[k] &&
+          hipHostMalloc((void**)&h->hStateQ[k], sizeof(SolveState) * h->batch, hipHostMallocDefault) != hipSuccess)
+        return set_err(h, PSD_ERR_HIP, "pinned allocation failed");
+      if (!h->ev_state[k] && hipEventCreateWithFlags(&h->ev_state[k], hipEventDisableTiming) != hipSuccess)
+        return set_err(h, PSD_ERR_HIP, "event creation failed");
+    }
     const int max_launch = h->opt.max_iter / chunk + 2;
-    std::vector<double> r_prev(h->batch);
-    std::vector<int> k_prev(h->batch);
-    for (int b = 0; b < h->batch; ++b) { r_prev[b] = h->hState[b].rinf; k_prev[b] = h->hState[b].iter; }
-    int launched = 0, nrep = 1;
-    while (launched < max_launch) {
-      for (int k = 0; k < nrep && launched < max_launch; ++k, ++launched)
-        HIPCHK(hipGraphLaunch(h->gexec, h->stream));
-      psd_status st = read_states(h);
-      if (st != PSD_OK) return st;
-      if (all_done(h)) break;
+    struct Batch { int slot, chunks; };
+    Batch q[2];
+    int nq = 0, next_slot = 0, launched = 0;
+    auto enqueue = [&](int nrep) -> psd_status {
+      int c = 0;
+      for (; c < nrep && launched < max_launch; ++c, ++launched) HIPCHK(hipGraphLaunch(h->gexec, h->stream));
+      const int sl = next_slot;
+      next_slot ^= 1;
+      HIPCHK(hipMemcpyAsync(h->hStateQ[sl], h->hI[0].st, sizeof(SolveState) * h->batch, hipMemcpyDeviceToHost,
+                            h->stream));
+      HIPCHK(hipEventRecord(h->ev_state[sl], h->stream));
+      q[nq++] = Batch{sl, c};
+      return PSD_OK;
+    };
+    psd_status st = enqueue(0);   // the initial residual's states
+    if (st == PSD_OK) st = enqueue(1);
+    if (st != PSD_OK) return st;
+    std::vector<double> r_prev(h->batch, 0.0);
+    std::vector<int> k_prev(h->batch, -1);
+    while (nq > 0) {
+      const Batch bt = q[0];
+      q[0] = q[1];
+      --nq;
+      HIPCHK(hipEventSynchronize(h->ev_state[bt.slot]));
+      const SolveState* S = h->hStateQ[bt.slot];
+      bool done = true, rate_known = true;
       double k_rem = 0.0;
       for (int b = 0; b < h->batch; ++b) {
-        const SolveState& S = h->hState[b];
-        if (S.done) continue;
-        const int dk = S.iter - k_prev[b];
+        if (S[b].done) continue;
+        done = false;
+        const int dk = k_prev[b] < 0 ? 0 : S[b].iter - k_prev[b];
         double need = chunk;
-        if (dk > 0 && S.rinf > 0.0 && r_prev[b] > S.rinf) {
-          const double rate = std::pow(S.rinf / r_prev[b], 1.0 / dk);   // per iteration
-          need = std::log(h->hI[b].tol / S.rinf) / std::log(rate);
+        if (dk > 0 && S[b].rinf > 0.0 && r_prev[b] > S[b].rinf) {
+          const double rate = std::pow(S[b].rinf / r_prev[b], 1.0 / dk);   // per iteration
+          need = std::log(h->hI[b].tol / S[b].rinf) / std::log(rate);
+        } else {
+          rate_known = false;
         }
         k_rem = std::max(k_rem, need);
-        r_prev[b] = S.rinf;
-        k_prev[b] = S.iter;
+        r_prev[b] = S[b].rinf;
+        k_prev[b] = S[b].iter;
       }
-      nrep = (int)std::ceil(std::min(k_rem, (double)h->opt.max_iter) / chunk);
-      nrep = std::max(1, std::min(nrep, 8));
+      if (done) break;
+      int ahead = 0;   // replays still queued
+      for (int k = 0; k < nq; ++k) ahead += q[k].chunks;
+      int nrep = (int)std::ceil((std::min(k_rem, (double)h->opt.max_iter) - ahead * chunk) / chunk);
+      nrep = std::max(0, std::min(nrep, 8));
+      if (nq == 0 || !rate_known) nrep = std::max(nrep, 1);
+      if (nrep > 0 && launched < max_launch) {
+        st = enqueue(nrep);
+        if (st != PSD_OK) return st;
+      }
     }
     return PSD_OK;
   }
@@ -1317,12 +1358,16 @@ static psd_status solve_impl(psd_handle* h, const double* const* f, const double
   }
   for (int b = 0; b < B; ++b)
     if (pre_status[b]) k_set_status<<<1, 64, 0, h->stream>>>(h->dI, b, pre_status[b]);
-  // initial residual (no update)
+  // initial residual (no update); graph-mode solves read its states with
+  // the first queued replays in flight
   run_residual<TD, TR>(h, false);
   HIPCHK(hipGetLastError());
-  st = read_states(h);
-  if (st != PSD_OK) return st;
-  if (!all_done(h)) {
+  const bool graph_mode = h->opt.graph_chunk > 0 && h->opt.metric != PSD_METRIC_VARIABLE;
+  if (!graph_mode) {
+    st = read_states(h);
+    if (st != PSD_OK) return st;
+  }
+  if (graph_mode || !all_done(h)) {
     st = solve_loop<T, TD, TR>(h);
     if (st != PSD_OK) return st;
   }
@@ -1958,6 +2003,10 @@ extern "C" psd_status psd_destroy(psd_handle* h) {
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   if (h->hState) (void)hipHostFree(h->hState);
   if (h->hPart) (void)hipHostFree(h->hPart);
+  for (int k = 0; k < 2; ++k) {
+    if (h->hStateQ[k]) (void)hipHostFree(h->hStateQ[k]);
+    if (h->ev_state[k]) (void)hipEventDestroy(h->ev_state[k]);
+  }
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
   return PSD_OK;
