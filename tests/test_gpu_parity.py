@@ -386,6 +386,41 @@ def test_degenerate_inputs(psd, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_mode_edge_cases(psd, precision):
+    """Graph-mode solves read the device states of one batch of replays while
+    the next batch runs: a zero residual at the start (no update, the iterate
+    untouched), a restart from a converged answer, and a stop at max_iter in
+    the middle of a captured chunk (status PSD_NOT_CONVERGED, the same
+    iterate as the host-driven loop after max_iter updates, bit for bit)."""
+    n, L = 48, 9.6
+    P = psd.Problem(2, n, L, 4, 4.0, 0.01, 0.1)
+    log(f"case graph edge {precision}")
+    with psd.Solver(P, tol=1e-10, max_iter=50, precision=precision, graph_chunk=4) as S:
+        z = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        u = torch.zeros_like(z)
+        st = S.solve([z], [u])[0]
+        assert st.status == 0 and st.iters == 0 and st.res_inf == 0.0
+        assert not bool(u.abs().max() > 0)
+    f = psd_inputs.small_field(2, n, L, 73, K=5)
+    with psd.Solver(P, tol=1e-10, max_iter=300, precision=precision, graph_chunk=4) as S:
+        u = torch.zeros_like(dev(f))
+        st = S.solve([dev(f)], [u])[0]
+        assert st.status == 0 and st.res_inf <= 1e-10
+        u_conv = host(u).copy()
+        st2 = S.solve([dev(f)], [u])[0]
+        assert st2.status == 0 and st2.iters == 0
+        assert np.array_equal(host(u), u_conv)
+    out = []
+    for chunk in (0, 4):
+        with psd.Solver(P, tol=1e-30, max_iter=7, precision=precision, graph_chunk=chunk) as S:
+            u = torch.zeros_like(dev(f))
+            st = S.solve([dev(f)], [u])[0]
+            assert st.status == 1 and st.iters == 7
+            out.append(host(u))
+    assert np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_batched_3d_sizes_match_oracle(psd, precision):
     """3D instances of different n in one handle: every FFT pass runs as one
     launch over both sizes (per-block length switch); narrow line-search tiles."""
