@@ -200,13 +200,13 @@ __device__ __forceinline__ void stage_loop(F&& f) {
 }
 
 // Transform NL lines of length N held in LDS (line l at buf + l*LS, element
-// t at pidx(t)), in place, unnormalised.  tw[m] = exp(-2 pi i m / N), staged
-// in LDS by the caller.
-// Must be called by all PSD_NT threads of the block; ends with a barrier.
-template <typename T, int N, int NL, int LS, int DIR>
+// t at pidx(t)), in place, unnormalised: stages S0 .. S1-1 of the plan (all
+// by default).  tw[m] = exp(-2 pi i m / N), staged in LDS by the caller.
+// Must be called by all PSD_NT threads of the block; each stage ends with a
+// barrier.
+template <typename T, int N, int NL, int LS, int DIR, int S0 = 0, int S1 = plan_stages(N)>
 __device__ __forceinline__ void lds_fft(cx<T>* buf, const cx<T>* __restrict__ tw) {
-  constexpr int NSTG = plan_stages(N);
-  stage_loop<0, NSTG>([&](auto sc) {
+  stage_loop<S0, S1>([&](auto sc) {
     constexpr int s = decltype(sc)::value;
     constexpr int R = plan_radix(N, s);
     constexpr int Ns = plan_span(N, s);
@@ -400,24 +400,45 @@ __device__ __forceinline__ void c2r_rows(const RowArgs<T>& A, long long row0, cx
     if (k != 0 && k != N / 2) buf[l * LS + pidx(N - k)] = conj(a) + mul_i<1>(conj(b));
   }
   __syncthreads();
-  lds_fft<T, N, NL, LS, 1>(buf, twl);
-  constexpr int VEC = 16 / (int)sizeof(TOUT);
-  constexpr int NV = 2 * NL * N / VEC;
-  for (int e = threadIdx.x; e < NV; e += PSD_NT) {
-    const int rr = (e * VEC) / N, col = e * VEC - rr * N;
-    const long long gr = row0 + rr;
+  constexpr int SL = plan_stages(N) - 1;
+  lds_fft<T, N, NL, LS, 1, 0, SL>(buf, twl);
+  // The last stage of the plan (span M = N / R) keeps its results in
+  // registers and writes them straight to memory: butterfly j of line l
+  // holds the points j + r M (real part: row 2l, imaginary part: row 2l + 1)
+  constexpr int R = plan_radix(N, SL), M = N / R, NB = NL * M;
+  static_assert(plan_span(N, SL) == M, "last stage spans N / R");
+  constexpr int ITL = (NB + PSD_NT - 1) / PSD_NT;
+#pragma unroll
+  for (int it = 0; it < ITL; ++it) {
+    const int b = threadIdx.x + it * PSD_NT;
+    if (!(NB % PSD_NT == 0 || b < NB)) continue;
+    const int l = b / M, j = b - l * M;
+    const cx<T>* src = buf + l * LS;
+    cx<T> v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = src[pidx(j + r * M)];
+    if constexpr (M > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        cx<T> w = twl[r * j];
+        w.y = -w.y;   // inverse transform: exp(+2 pi i r j / N)
+        v[r] = v[r] * w;
+      }
+    }
+    dftR<R, 1>(v);
+    const long long gr = row0 + 2 * l;
     if (gr >= A.nrows) continue;
     long long row;
     const int fld = row_field(gr, A.rpf, row);
-    const T* src = (const T*)(buf + (rr >> 1) * LS + pidx(col)) + (rr & 1);
-    gvec<TOUT, VEC> out;
+    PSD_GLOBAL TOUT* pa = gmem((TOUT*)A.out(fld)) + row * N + j;
     double part = 0.0;
 #pragma unroll
-    for (int q = 0; q < VEC; ++q) {
-      out[q] = (TOUT)src[2 * q];
-      part += (double)out[q];
+    for (int r = 0; r < R; ++r) {
+      const TOUT xa = (TOUT)v[r].x, xb = (TOUT)v[r].y;
+      pa[r * M] = xa;
+      pa[N + r * M] = xb;
+      part += (double)xa + (double)xb;
     }
-    *(PSD_GLOBAL gvec<TOUT, VEC>*)(gmem((TOUT*)A.out(fld)) + row * N + col) = out;
     fsum[0] += fld == 0 ? part : 0.0;
     fsum[1] += fld == 1 ? part : 0.0;
     fsum[2] += fld == 2 ? part : 0.0;
