@@ -157,13 +157,14 @@ def summarize_pmc(fetch_dir: str, write_dir: str, out: str, md_out: str | None =
         json.dump(rec, fh, indent=1)
     if md_out:
         run = "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --forms mixed --copy-calibration"
+        tune = os.path.join(os.path.dirname(os.path.normpath(fetch_dir)), "tune.txt")
         lines = ["# HBM traffic per launch, 3D p=4 256^3 mixed form", "",
                  f"Kernel sources: comment-insensitive hash `{rh}` (bench.source_hash).", "",
                  "Commands (run from the repository root on the MI355X box), one counter per pass, then this "
                  "summary:", "", "```",
-                 f"PSD_TUNE_CACHE=gpurun_out/tune.txt rocprofv3 --pmc FETCH_SIZE --output-format csv "
+                 f"PSD_TUNE_CACHE={tune} rocprofv3 --pmc FETCH_SIZE --output-format csv "
                  f"-d {fetch_dir} -o pmc -- {run}",
-                 f"PSD_TUNE_CACHE=gpurun_out/tune.txt rocprofv3 --pmc WRITE_SIZE --output-format csv "
+                 f"PSD_TUNE_CACHE={tune} rocprofv3 --pmc WRITE_SIZE --output-format csv "
                  f"-d {write_dir} -o pmc -- {run}",
                  f"python bench.py --summarize-pmc {fetch_dir} {write_dir} {out} {md_out}", "```", "",
                  f"Calibration: the 512 MiB device copy issued by `--copy-calibration` reads FETCH_SIZE scaled by "
@@ -194,9 +195,11 @@ SQ_PASSES = {
 SQ_KERNELS = "k_res3d|k_ls3d|k_rows"
 
 
-def sq_command(tag: str) -> str:
-    return (f"PSD_TUNE_CACHE=gpurun_out/tune.txt rocprofv3 --pmc {' '.join(SQ_PASSES[tag])} "
-            f"--kernel-include-regex '{SQ_KERNELS}' --output-format csv -d gpurun_out/sq{tag} -o pmc "
+def sq_command(tag: str, root: str = "prof_out") -> str:
+    """The rocprofv3 command of SQ counter pass `tag`, writing under `root`
+    (the tiling cache of the counted runs in root/tune.txt)."""
+    return (f"PSD_TUNE_CACHE={root}/tune.txt rocprofv3 --pmc {' '.join(SQ_PASSES[tag])} "
+            f"--kernel-include-regex '{SQ_KERNELS}' --output-format csv -d {root}/sq{tag} -o pmc "
             "-- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --forms mixed")
 
 
@@ -230,8 +233,9 @@ def summarize_sq(dir_a: str, dir_b: str, out: str) -> dict:
     lines = ["# SQ counters of the 3D stencil and row-transform kernels (256^3, p = 4, mixed form)", "",
              f"Kernel sources: comment-insensitive hash `{recorded_hash(dir_a + '/x')}` (bench.source_hash).", "",
              "Commands (counter passes, then this summary):", "", "```"]
-    lines += [sq_command("A"), sq_command("B"),
-              f"python bench.py --summarize-sq gpurun_out/sqA gpurun_out/sqB {out}", "```", "",
+    root = os.path.dirname(os.path.normpath(dir_a))
+    lines += [sq_command("A", root), sq_command("B", root),
+              f"python bench.py --summarize-sq {dir_a} {dir_b} {out}", "```", "",
               "Medians over the last ten launches of each kernel (the ten iterations of the final",
               "host-driven solve).  Fractions are per wave: counter / SQ_WAVE_CYCLES.", ""]
     res = {}
