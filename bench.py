@@ -271,8 +271,8 @@ def summarize_sq(dir_a: str, dir_b: str, out: str) -> dict:
 
 def recorded_hash(path: str) -> str:
     """Kernel-source hash recorded beside profiler output (source_hash.txt,
-    written on the GPU machine when the profile was taken, in the output folder
-    or one of its parents), else the current tree's."""
+    written on the GPU machine when the profile was taken, in the output
+    folder or one of its parents), else the current tree's."""
     d = os.path.dirname(os.path.abspath(path))
     for _ in range(3):
         f = os.path.join(d, "source_hash.txt")
@@ -761,8 +761,8 @@ def main():
         print(json.dumps({k: v["derived"] for k, v in rec.items()}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this solver runs on one GPU; multi-GPU runs are not part of "
-                                   "this build (run with --gpus 1)"}))
+        print(json.dumps({"error": "this solver runs on one GPU: each instance's fields live in one "
+                                   "GPU's memory and no path spans several GPUs (run with --gpus 1)"}))
         sys.exit(2)
 
     import numpy as np
